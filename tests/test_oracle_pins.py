@@ -1,0 +1,325 @@
+"""Pins of the CPU oracle against what the paper and mathematics fix.
+
+Each test checks the oracle against something other than itself: closed-form
+integrals, order conditions, exact invariants of the ALE/GCL discretisation,
+central finite differences, the duality theorem of the paper's appendix
+(d lambda^(0) / d lambda_Nt = Phi^T) and the agreement of two different ways
+of computing the same gradient.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from paper_1512_00616_amd import inputs
+
+MU = np.array(inputs.MU_NOMINAL)
+
+
+def make(O, **kw):
+    base = dict(Nr=2, Nth=6, p=1, Nt=4)
+    base.update(kw)
+    return O.Oracle(**base)
+
+
+# ---------------------------------------------------------------- reference element
+@pytest.mark.parametrize("p", [1, 2, 3, 4])
+def test_volume_quadrature_exact_on_monomials(oracle_mod, p):
+    """int_T xi^a eta^b = a! b! / (a+b+2)! on the unit right triangle, a+b <= 2p+2."""
+    o = make(oracle_mod, p=p)
+    xq, wq, _, _ = o.ref_tables()
+    for a in range(2 * p + 3):
+        for b in range(2 * p + 3 - a):
+            exact = math.factorial(a) * math.factorial(b) / math.factorial(a + b + 2)
+            got = np.sum(wq * xq[:, 0] ** a * xq[:, 1] ** b)
+            assert abs(got - exact) <= 1e-14 * max(1.0, exact) + 1e-16, (a, b, got, exact)
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_basis_partition_of_unity_and_polynomial_reproduction(oracle_mod, p):
+    """Lagrange basis on equispaced nodes (s/p, t/p), t outer, s inner: sums to
+    one and reproduces every polynomial of degree <= p from its nodal values."""
+    o = make(oracle_mod, p=p)
+    xq, _, ph, _ = o.ref_tables()
+    assert np.allclose(ph.sum(axis=1), 1.0, atol=1e-13)
+    nodes = [(s / p, t / p) for t in range(p + 1) for s in range(p + 1 - t)]
+    for a in range(p + 1):
+        for b in range(p + 1 - a):
+            nodal = np.array([x ** a * y ** b for x, y in nodes])
+            assert np.allclose(ph @ nodal, xq[:, 0] ** a * xq[:, 1] ** b, atol=1e-13)
+
+
+def test_p1_mass_matrix_closed_form(oracle_mod):
+    """P1 mass matrix of a triangle of area |T|: |T|/12 [[2,1,1],[1,2,1],[1,1,2]]."""
+    o = make(oracle_mod, p=1)
+    _, _, _, mh = o.ref_tables()
+    exact = (0.5 / 12.0) * np.array([[2, 1, 1], [1, 2, 1], [1, 1, 2]])
+    assert np.allclose(mh, exact, atol=1e-16)
+
+
+# ---------------------------------------------------------------- DIRK tableau
+def test_dirk3_order_conditions(oracle_mod):
+    A, b, c = oracle_mod.dirk_tableau()
+    assert np.allclose(A.sum(axis=1), c, atol=1e-15)
+    assert abs(b.sum() - 1) < 1e-15
+    assert abs(b @ c - 0.5) < 1e-15
+    assert abs(b @ c ** 2 - 1 / 3) < 1e-15
+    assert abs(b @ A @ c - 1 / 6) < 1e-15
+    # stiffly accurate, L-stable: b equals the last row, diagonal alpha solves
+    # x^3 - 3x^2 + 3x/2 - 1/6 = 0
+    assert np.allclose(A[2], b, atol=0)
+    al = A[0, 0]
+    assert abs(al ** 3 - 3 * al ** 2 + 1.5 * al - 1 / 6) < 1e-15
+    assert np.allclose(np.diag(A), al) and np.allclose(np.triu(A, 1), 0)
+
+
+# ---------------------------------------------------------------- mesh
+def test_mesh_connectivity_and_orientation(oracle_mod):
+    o = make(oracle_mod, Nr=8, Nth=24)
+    ev, en, tw, vxy = o.mesh()
+    _, area = o.nodes()
+    assert (area > 0).all()  # every triangle counter-clockwise
+    r = np.hypot(vxy[:, 0], vxy[:, 1]).reshape(9, 24)
+    assert np.allclose(r[0], 1.0) and np.allclose(r[-1], 10.0)
+    # stretching: per-cell ratio 1.3 at Nr = 8
+    dr = np.diff(r[:, 0])
+    assert np.allclose(dr[1:] / dr[:-1], 1.3, rtol=1e-12)
+    nwall = nfar = 0
+    for K in range(o.Ne):
+        for f in range(3):
+            nb = en[K, f]
+            if nb == -1:
+                nwall += 1
+                a, b = vxy[ev[K, f]], vxy[ev[K, (f + 1) % 3]]
+                assert abs(np.hypot(*a) - 1) < 1e-14 and abs(np.hypot(*b) - 1) < 1e-14
+            elif nb == -2:
+                nfar += 1
+            else:
+                t = tw[K, f]
+                assert en[nb, t] == K and tw[nb, t] == f
+                # shared edge traversed in opposite directions
+                assert ev[K, f] == ev[nb, (t + 1) % 3] and ev[K, (f + 1) % 3] == ev[nb, t]
+    assert nwall == 24 and nfar == 24
+
+
+# ---------------------------------------------------------------- ALE + GCL
+def _freestream_vector(o, g):
+    u0 = o.freestream()
+    Uinf = np.array([1.0, 1.0, 0.0, u0[3] / o.gbar(0, 0)[0]])
+    return np.repeat(g, 4) * np.tile(Uinf, o.Ne * o.np), Uinf
+
+
+def test_rigid_motion_gives_unit_gbar(oracle_mod):
+    """With the blend moved outside the domain the map is a rigid motion:
+    det G = 1 and the GCL right-hand side vanishes."""
+    o = make(oracle_mod, p=2, r_blend0=100.0, r_blend1=200.0)
+    o.set_params(MU)
+    for n, i in [(0, 0), (1, 2), (3, 3)]:
+        assert np.abs(o.gbar(n, i) - 1).max() < 1e-13
+    assert np.abs(o.gcl_rhs(2, 1)).max() < 1e-13
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_freestream_residual_equals_gcl_source(oracle_mod, p):
+    """Discrete GCL: r(gbar U_inf) = U_inf r_g at every stage time, on the
+    deforming (blended, non-rigid) mesh with the body boundary as far field."""
+    o = make(oracle_mod, Nr=3, Nth=8, p=p, wall_is_farfield=True)
+    o.set_params(MU)
+    for n, i in [(1, 1), (2, 3), (4, 2)]:
+        u, Uinf = _freestream_vector(o, o.gbar(n, i))
+        r = o.residual(n, i, u)
+        expect = np.repeat(o.gcl_rhs(n, i), 4) * np.tile(Uinf, o.Ne * o.np)
+        assert np.abs(r - expect).max() <= 1e-13 * np.abs(r).max()
+
+
+def test_freestream_preserved_over_a_period(oracle_mod):
+    """A uniform free stream is preserved by a full DIRK period on the
+    deforming mesh: U_X / gbar = U_inf at every node of every step."""
+    o = make(oracle_mod, Nr=3, Nth=8, p=2, Nt=4, wall_is_farfield=True, lin_solver=0,
+             newton_atol=1e-12)
+    o.set_params(MU)
+    u0 = o.freestream()
+    o.primal_period(u0)
+    for n in range(o.Nt + 1):
+        un = o.traj(2, n)
+        g = o.gbar(n, 3) if n else o.gbar(0, 0)
+        U = (un.reshape(-1, 4) / g[:, None])
+        _, Uinf = _freestream_vector(o, g)
+        assert np.abs(U - Uinf).max() <= 1e-12 * np.abs(Uinf).max()
+
+
+def test_gcl_field_third_order_in_time(oracle_mod):
+    """gbar integrates M dgbar/dt = r_g with the DIRK; r_g is the exact time
+    derivative of the projection of det G, so gbar at t = T/2 converges to the
+    projection of det G(T/2) at third order.  The latter equals gbar(0) of the
+    phase-shifted parameters (-h0, theta0, phi + pi)."""
+    shifted = np.array([-MU[0], MU[1], MU[2] + math.pi])
+    errs = []
+    for Nt in (4, 8, 16):
+        o = make(oracle_mod, Nr=2, Nth=6, p=2, Nt=Nt)
+        o.set_params(shifted)
+        ref = o.gbar(0, 0)
+        o.set_params(MU)
+        errs.append(np.abs(o.gbar(Nt // 2, 3) - ref).max())
+    rates = np.log2(np.array(errs[:-1]) / np.array(errs[1:]))
+    assert (rates > 2.7).all(), (errs, rates)
+
+
+# ---------------------------------------------------------------- conservation, force
+def test_mass_conservation(oracle_mod):
+    """Interior fluxes cancel and the wall is impermeable: for any state equal
+    to the free stream on the outer ring of elements, the sum of all density
+    residual rows is zero."""
+    o = make(oracle_mod, Nr=3, Nth=8, p=2)
+    o.set_params(MU)
+    u, _ = _freestream_vector(o, o.gbar(1, 2))
+    pert = inputs.perturbation(o.Nu, seed=3, sigma=1e-2).reshape(o.Ne, -1)
+    inner = 2 * 2 * 8  # elements of the two inner rings
+    u = u.reshape(o.Ne, -1)
+    u[:inner] += pert[:inner]
+    r = o.residual(1, 2, u.ravel()).reshape(o.Ne, o.np, 4)
+    assert abs(r[:, :, 0].sum()) <= 1e-12 * np.abs(r[:, :, 0]).max()
+
+
+def test_force_on_closed_body_at_rest_is_zero(oracle_mod):
+    """Fluid at rest with uniform pressure around a motionless body: the
+    pressure integrates to zero over the closed polygonal wall."""
+    o = make(oracle_mod, Nr=2, Nth=12, p=2)
+    o.set_params(np.zeros(3))
+    g = o.gbar(0, 0)
+    U = np.array([1.0, 0.0, 0.0, 30.0])
+    u = np.repeat(g, 4) * np.tile(U, o.Ne * o.np)
+    f = o.qoi(1, 1, u)
+    assert np.abs(f).max() < 1e-12
+
+
+# ---------------------------------------------------------------- derivatives
+@pytest.mark.parametrize("p", [1, 3])
+def test_jacobian_matches_central_differences(oracle_mod, p):
+    o = make(oracle_mod, Nr=2, Nth=6, p=p)
+    o.set_params(MU)
+    u = o.freestream(inputs.perturbation(o.Nu, seed=5, sigma=1e-2))
+    J = o.jacobian(1, 2, u)
+    v, w = inputs.random_vectors(o.Nu, 2, seed=7)
+    Jv = o.bsr_apply(J, v)
+    h = 1e-5
+    fd = (o.residual(1, 2, u + h * v) - o.residual(1, 2, u - h * v)) / (2 * h)
+    assert np.linalg.norm(Jv - fd) <= 1e-7 * np.linalg.norm(Jv)
+    # transpose apply agrees with the forward apply
+    assert abs(w @ Jv - v @ o.bsr_apply(J, w, True)) <= 1e-13 * abs(w @ Jv)
+
+
+def test_dr_dmu_and_dqoi_match_central_differences(oracle_mod):
+    o = make(oracle_mod, Nr=2, Nth=6, p=2)
+    o.set_params(MU)
+    u = o.freestream(inputs.perturbation(o.Nu, seed=5, sigma=1e-2))
+    n, i = 2, 2
+    drdmu = o.dr_dmu(n, i, u)
+    f, dfdu, dfdmu = o.qoi(n, i, u, derivs=True)
+    tau = 1e-5
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = tau
+        o.set_params(MU + e)
+        rp, fp = o.residual(n, i, u), o.qoi(n, i, u)
+        o.set_params(MU - e)
+        rm, fm = o.residual(n, i, u), o.qoi(n, i, u)
+        fd = (rp - rm) / (2 * tau)
+        assert np.linalg.norm(drdmu[k] - fd) <= 1e-6 * np.linalg.norm(drdmu[k]) + 1e-8
+        assert np.allclose(dfdmu[:, k], (fp - fm) / (2 * tau), rtol=1e-6, atol=1e-7 * np.abs(dfdmu).max())
+    o.set_params(MU)
+    v = inputs.random_vectors(o.Nu, 1, seed=9)[0]
+    h = 1e-6
+    fdq = (o.qoi(n, i, u + h * v) - o.qoi(n, i, u - h * v)) / (2 * h)
+    assert np.allclose(dfdu @ v, fdq, rtol=1e-6, atol=1e-9)
+
+
+# ---------------------------------------------------------------- sweeps
+@pytest.fixture(scope="module")
+def tiny_periodic(oracle_mod):
+    """2x6 O-grid, p=1, 4 steps, exact (dense LU) stage solves, shot to a
+    periodic state at 1e-12."""
+    o = make(oracle_mod, Nr=2, Nth=6, p=1, Nt=4, lin_solver=0, newton_atol=1e-12)
+    o.set_params(MU)
+    u0 = o.freestream(inputs.perturbation(o.Nu, seed=1))
+    us, rep = o.shoot(u0, tol=1e-11, eta=1e-10, maxit=20, max_krylov=300)
+    return o, us, rep
+
+
+def test_tangent_sweep_is_derivative_of_flow_map(oracle_mod):
+    o = make(oracle_mod, Nr=2, Nth=6, p=1, Nt=4, lin_solver=0, newton_atol=1e-12)
+    o.set_params(MU)
+    u0 = o.freestream(inputs.perturbation(o.Nu, seed=1))
+    v = inputs.random_vectors(o.Nu, 1, seed=7)[0]
+    o.primal_period(u0)
+    Pv = o.tangent(v)
+    h = 1e-5
+    a, _, _ = o.primal_period(u0 + h * v)
+    b, _, _ = o.primal_period(u0 - h * v)
+    assert np.linalg.norm((a - b) / (2 * h) - Pv) <= 1e-8 * np.linalg.norm(Pv)
+
+
+def test_adjoint_sweep_is_transpose_of_tangent_sweep(tiny_periodic):
+    """Appendix theorem: d lambda^(0) / d lambda_Nt = Phi^T, so
+    <w, Phi v> = <Phi^T w, v> for the unforced adjoint sweep."""
+    o, us, _ = tiny_periodic
+    o.primal_period(us)
+    v, w = inputs.random_vectors(o.Nu, 2, seed=7)
+    lhs = w @ o.tangent(v)
+    rhs = o.adjoint(w) @ v
+    assert abs(lhs - rhs) <= 1e-12 * abs(lhs)
+
+
+def test_shooting_converges(tiny_periodic):
+    o, us, rep = tiny_periodic
+    assert rep.final_res <= 1e-11
+    _, _, res = o.primal_period(us)
+    assert res <= 1e-11
+
+
+def test_periodic_adjoint_matches_dense_solve(tiny_periodic):
+    """Alg. 3 against a dense direct solve: Phi formed column by column from
+    tangent sweeps, then (Phi^T - I) lambda_Nt = -g_F solved by LU."""
+    o, us, _ = tiny_periodic
+    o.primal_period(us)
+    Phi = np.stack([o.tangent(e) for e in np.eye(o.Nu)], axis=1)
+    for q in (0, 1):
+        g, lam, _ = o.periodic_adjoint(q, rtol=1e-13)
+        gF, _ = o.adjoint(np.zeros(o.Nu), forced_qoi=q)
+        lam_dense = np.linalg.solve(Phi.T - np.eye(o.Nu), -gF)
+        assert np.linalg.norm(lam - lam_dense) <= 1e-10 * np.linalg.norm(lam_dense)
+
+
+def test_adjoint_gradient_equals_tangent_gradient(tiny_periodic):
+    """lambda^T (tangent) = dJ/dmu: the periodic adjoint gradient of both QoIs
+    equals the direct (periodic tangent) gradient."""
+    o, us, _ = tiny_periodic
+    o.primal_period(us)
+    G = np.stack([o.periodic_adjoint(q, rtol=1e-13)[0] for q in (0, 1)])
+    T = o.tangent_gradient(rtol=1e-13)
+    assert np.abs(G - T).max() <= 1e-9 * np.abs(G).max()
+
+
+@pytest.mark.slow
+def test_adjoint_gradient_matches_central_differences(oracle_mod, tiny_periodic):
+    """Sec. 5.1 verification: central differences with tau = 1e-6 of the
+    periodic QoIs, periodic solves to 1e-12 warm-started from u0*."""
+    o, us, _ = tiny_periodic
+    o.set_params(MU)
+    o.primal_period(us)
+    G = np.stack([o.periodic_adjoint(q, rtol=1e-13)[0] for q in (0, 1)])
+    tau = 1e-6
+
+    def J(m):
+        o.set_params(m)
+        u, _ = o.shoot(us, tol=1e-12, eta=1e-11, maxit=20, max_krylov=300)
+        return o.primal_period(u)[1]
+
+    FD = np.zeros((2, 3))
+    for k in range(3):
+        e = np.zeros(3)
+        e[k] = tau
+        FD[:, k] = (J(MU + e) - J(MU - e)) / (2 * tau)
+    o.set_params(MU)
+    o.primal_period(us)
+    assert np.linalg.norm(G - FD) <= 1e-6 * np.linalg.norm(FD), (G, FD)
