@@ -1,0 +1,182 @@
+/*
+ * pa.h -- C ABI of the MI355X periodic-adjoint library (libpa.so).
+ *
+ * The library computes time-periodic solutions of a DG discretisation of the
+ * 2-D compressible Navier-Stokes equations on a deforming domain, and the
+ * gradients of time-averaged quantities of interest on the manifold of
+ * periodic solutions, with the fully discrete adjoint method of Zahr, Persson
+ * and Wilkening (arXiv:1512.00616).  The calls follow the paper's statement
+ * of the problem (Alg. 4): set the mesh and the kinematic parameters mu, run
+ * the primal period, shoot to periodicity, return the QoIs and dJ/dmu.
+ *
+ * Conventions
+ *  - All integers are fixed width; all floating point is IEEE double.
+ *  - Host pointers: every array argument of this header is HOST memory owned
+ *    by the caller; the library copies in or out synchronously and keeps no
+ *    pointer after the call returns.  Device memory is owned by the context.
+ *  - State ordering: u[(K*np + a)*4 + m], element K, node a of the element's
+ *    equispaced nodal set (t outer, s inner), conserved variable m of the
+ *    reference-domain state U_X (Sec. 5 eq. transform1-nogcl with gbar).
+ *  - Block layout of dr/du: blk[((K*4 + s)*b + row)*b + col], b = 4*np, slot
+ *    s = 0 the diagonal block, s = 1 + f the block coupling element K to its
+ *    neighbour across local face f (zero where f lies on the boundary).
+ *  - Stage (n, i), n = 1..Nt, i = 1..3 is the DIRK stage at
+ *    t = (n - 1 + c_i) dt (Sec. 2.2 eq. dirk); (0, 0) means t = 0.
+ *  - Errors: every call returns pa_status; no exception crosses the ABI.
+ *    pa_last_error() describes the last failure.  After PA_EDEVICE the
+ *    context must be destroyed; after any other error it stays usable.
+ *  - Threading: one context per host thread; contexts share nothing.
+ */
+#ifndef PA_H
+#define PA_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum pa_status {
+    PA_OK = 0,
+    PA_EINVAL = -1,     /* bad argument */
+    PA_ENOMEM = -2,     /* device allocation failed */
+    PA_EDEVICE = -3,    /* HIP runtime error */
+    PA_ENOCONV = -4,    /* Newton / Krylov iteration did not converge */
+    PA_ENUMERIC = -5,   /* NaN or Inf, or a singular block */
+    PA_ESTATE = -6      /* call out of order (no parameters, no trajectory) */
+} pa_status;
+
+typedef struct pa_ctx pa_ctx;
+
+typedef struct pa_config {
+    int32_t Nr, Nth;            /* O-grid: radial x angular quads (2 triangles each) */
+    int32_t p;                  /* DG polynomial degree, 1..3 */
+    int32_t Nt;                 /* DIRK steps per period */
+    double  r_far;              /* far-field radius (body radius 1) */
+    double  stretch;            /* radial growth ratio at Nr = 8 (refines as stretch^(8/Nr)) */
+    double  mach, re, gamma, pr;
+    double  T;                  /* period */
+    double  r_blend0, r_blend1; /* mesh motion rigid inside r_blend0, at rest beyond r_blend1 */
+    int32_t wall_is_farfield;   /* 1: treat the body boundary as far field (GCL checks) */
+    int32_t gmres_restart;      /* stage GMRES restart length (<= 64) */
+    double  lin_rtol;           /* stage linear solve relative tolerance */
+    double  newton_atol;        /* stage Newton tolerance on ||M k - dt r||_2 */
+    int32_t newton_maxit;
+    int32_t max_krylov;         /* outer Krylov basis size (shooting, periodic adjoint) */
+    int32_t device;             /* HIP device ordinal */
+} pa_config;
+
+/* defaults: 8x24 O-grid, p = 1, Nt = 20, r_far 10, stretch 1.3, M 0.2,
+ * Re 1000, gamma 1.4, Pr 0.72, T 1, blend 2..8, GMRES(30) 1e-10,
+ * Newton 1e-10 / 20, outer basis 100 */
+void pa_default_config(pa_config* cfg);
+
+/* Builds the mesh, the reference tables and every device buffer the method
+ * needs (including the on-device trajectory checkpoints of a whole period).
+ * *out is NULL on failure. */
+pa_status pa_create(const pa_config* cfg, pa_ctx** out);
+void      pa_destroy(pa_ctx* ctx);                /* NULL-safe */
+const char* pa_last_error(const pa_ctx* ctx);
+
+int64_t pa_num_dofs(const pa_ctx* ctx);
+int32_t pa_num_elems(const pa_ctx* ctx);
+int32_t pa_block_size(const pa_ctx* ctx);
+/* device bytes held by the context */
+int64_t pa_device_bytes(const pa_ctx* ctx);
+
+/* mesh connectivity: elem_vert[Ne*3], elem_nbr[Ne*3] (-1 wall, -2 far field),
+ * twin[Ne*3] (neighbour's local face, -1 on the boundary), vert_xy[Nv*2];
+ * any pointer may be NULL */
+pa_status pa_get_mesh(const pa_ctx* ctx, int32_t* elem_vert, int32_t* elem_nbr, int8_t* twin, double* vert_xy);
+
+/* kinematic parameters mu = (h0, theta0 [rad], phi [rad]) of heave
+ * h0 sin(2 pi t/T) and pitch theta0 sin(2 pi t/T + phi) (Sec. 5.1 eq.
+ * defmap with one Fourier mode).  Recomputes the GCL field gbar and its
+ * mu-derivatives for every stage; invalidates the trajectory. */
+pa_status pa_set_params(pa_ctx* ctx, const double mu[3]);
+
+/* initial state u0 [Nu] (host) */
+pa_status pa_set_state(pa_ctx* ctx, const double* u0, int64_t n);
+/* u0 = gbar(0) U_inf (+ perturb[Nu] if not NULL) */
+pa_status pa_set_freestream(pa_ctx* ctx, const double* perturb);
+/* which = 0: current u0, 1: u^(Nt) of the last primal period */
+pa_status pa_get_state(pa_ctx* ctx, int32_t which, double* out, int64_t n);
+
+/* One primal period from u0 (Sec. 2.3 eq. dirk2): Newton per stage, stores
+ * the trajectory (u^(n), k_i^(n), u_i^(n), dr/du and the block-Jacobi
+ * inverses of every stage) on the device.  qoi[2] = time-averaged
+ * (power, x-force); res = ||u^(Nt) - u0||_2.  Either output may be NULL. */
+pa_status pa_primal_period(pa_ctx* ctx, double qoi[2], double* res);
+
+typedef struct pa_shoot_report {
+    int32_t newton_its;         /* outer Newton iterations */
+    int32_t krylov_its;         /* total tangent sweeps used as matvecs */
+    int32_t primal_sweeps;
+    int32_t stage_newton_its;   /* summed over all primal sweeps */
+    int64_t stage_gmres_its;    /* summed over all stage solves */
+    double  res0, res;          /* initial and final ||u^(Nt) - u0||_2 */
+    double  ms;                 /* wall time */
+} pa_shoot_report;
+
+/* Newton-Krylov shooting (Alg. 2 with the Jacobian Phi - I of eq. jac-prim)
+ * from the current u0 to ||u^(Nt) - u0||_2 <= tol, inexact Newton with
+ * relative GMRES forcing eta.  On success u0 is periodic and the stored
+ * trajectory belongs to it.  PA_ENOCONV leaves the last iterate and report. */
+pa_status pa_shoot(pa_ctx* ctx, double tol, double eta, int32_t maxit, pa_shoot_report* rep);
+
+typedef struct pa_adjoint_report {
+    int32_t krylov_its[2];      /* outer GMRES iterations per QoI */
+    int32_t sweeps;             /* backward sweeps in total */
+    int64_t stage_gmres_its;
+    double  rel_res[2];
+    double  ms;
+} pa_adjoint_report;
+
+/* Periodic adjoint (Alg. 3) for both QoIs about the stored periodic
+ * trajectory, and the gradient of eq. funcl-grad-nosens-dirk (Alg. 4).
+ * qoi[2] (may be NULL), dJdmu[2*3] (QoI-major). */
+pa_status pa_adjoint_gradient(pa_ctx* ctx, double rtol, double qoi[2], double dJdmu[6], pa_adjoint_report* rep);
+
+/* Sweeps about the stored trajectory (host vectors of length Nu):
+ * tangent: out = Phi v (eq. dirk-sens-mvp);
+ * adjoint: lam0 = lambda^(0) from lambda^(Nt) = lamNt (eq.
+ * uns-disc-adj-dirk-sens-mvp when forced_qoi < 0, eq. uns-disc-adj-dirk2
+ * forced by QoI forced_qoi otherwise, then grad[3] receives dJ/dmu). */
+pa_status pa_tangent_sweep(pa_ctx* ctx, const double* v, double* out);
+pa_status pa_adjoint_sweep(pa_ctx* ctx, const double* lamNt, int32_t forced_qoi, double* lam0, double* grad);
+
+/* ---- unit-level entry points for parity checks (host in, host out) ---- */
+pa_status pa_dbg_gbar(pa_ctx* ctx, int32_t n, int32_t i, double* out /*[Ne*np]*/);
+pa_status pa_dbg_dgbar(pa_ctx* ctx, int32_t n, int32_t i, double* out /*[3*Ne*np]*/);
+pa_status pa_dbg_residual(pa_ctx* ctx, int32_t n, int32_t i, const double* u, double* r);
+pa_status pa_dbg_jacobian(pa_ctx* ctx, int32_t n, int32_t i, const double* u, double* blk);
+pa_status pa_dbg_dr_dmu(pa_ctx* ctx, int32_t n, int32_t i, const double* u, double* out /*[3*Nu]*/);
+/* instantaneous QoIs, df/du [2*Nu] and df/dmu [2*3]; outputs may be NULL */
+pa_status pa_dbg_qoi(pa_ctx* ctx, int32_t n, int32_t i, const double* u, double f[2], double* dfdu, double* dfdmu);
+/* y = alpha M x + beta op(J) x with J given in the block layout above */
+pa_status pa_dbg_bsr_apply(pa_ctx* ctx, const double* blk, double alpha, double beta, int32_t transpose,
+                           const double* x, double* y);
+/* inverses of the diagonal blocks of M - a_dt J: out[Ne*b*b] */
+pa_status pa_dbg_blockinv(pa_ctx* ctx, const double* blk, double a_dt, double* out);
+/* solve (M - a_dt J) x = rhs (transposed if transpose != 0) with
+ * block-Jacobi GMRES; *iters receives the iteration count */
+pa_status pa_dbg_stage_solve(pa_ctx* ctx, const double* blk, double a_dt, int32_t transpose, const double* rhs,
+                             double* x, int32_t* iters);
+/* trajectory: which = 0 stage state u_i^(n), 1 stage k_i^(n), 2 step state u^(n) */
+pa_status pa_dbg_traj(pa_ctx* ctx, int32_t which, int32_t n, int32_t i, double* out);
+
+/* ---- measurement ---- */
+/* kernel ids for pa_kernel_time */
+enum { PA_K_SPMV = 0, PA_K_PRECOND = 1, PA_K_JACOBIAN = 2, PA_K_RESIDUAL = 3, PA_K_BLOCKINV = 4, PA_K_COUNT = 5 };
+/* when on, every 8th launch of each listed kernel is bracketed by HIP events
+ * on the library's stream; pa_kernel_time returns the launch count since
+ * timing was switched on and the sampled mean duration times that count */
+pa_status pa_set_timing(pa_ctx* ctx, int32_t on);
+pa_status pa_kernel_time(pa_ctx* ctx, int32_t kernel, double* total_ms, int64_t* launches);
+/* averaged over reps launches of the stage-operator SpMV y = (M - c J_1) x on
+ * the stored first-stage Jacobian (timed with HIP events, library stream) */
+pa_status pa_bench_spmv(pa_ctx* ctx, int32_t reps, int32_t transpose, double* avg_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

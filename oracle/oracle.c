@@ -693,8 +693,10 @@ static void face_interior(const pao_ctx* c, const Stage* S, int L, int fL, int R
 
 /* Boundary face of K.  Far field (reading of the characteristic free-stream
  * condition): Lax-Friedrichs flux against U_inf plus the interior viscous
- * flux.  Wall (no-slip, adiabatic; reading): pressure flux of the state
- * moving with the wall, interior viscous stress with zero heat flux, and an
+ * flux.  Wall (no-slip, adiabatic; reading): the Lax-Friedrichs flux
+ * against the reflected state U_b (interior density and pressure, velocity
+ * 2 v_G - u, so that the mass flux vanishes and the average velocity is the
+ * wall's), interior viscous stress with zero heat flux, and an
  * interior-penalty term mu C11 rho (u - v_G) on the momentum with
  * C11 = 10 / h, h = 2|K| / |e|.  Fh [nf][4] is Fhat . N_K. */
 static void face_boundary(const pao_ctx* c, const Stage* S, int K, int f, int wall, const cplx* u, cplx* Fh)
@@ -723,10 +725,11 @@ static void face_boundary(const pao_ctx* c, const Stage* S, int K, int f, int wa
             for (int m = 0; m < 4; ++m) Fh[j * 4 + m] = jf * Fi[m] - (Fv[m][0] * cn[0] + Fv[m][1] * cn[1]);
         } else {
             cplx r = U[0], ux = U[1] / r, uy = U[2] / r;
-            cplx Ub[4] = { r, r * vG[0], r * vG[1],
-                           U[3] - 0.5 * r * (ux * ux + uy * uy) + 0.5 * r * (vG[0] * vG[0] + vG[1] * vG[1]) };
+            /* reflected state: interior density and pressure, velocity 2 v_G - u */
+            cplx bx = 2.0 * vG[0] - ux, by = 2.0 * vG[1] - uy;
+            cplx Ub[4] = { r, r * bx, r * by, U[3] - 0.5 * r * (ux * ux + uy * uy) + 0.5 * r * (bx * bx + by * by) };
             cplx H[4], Fv[4][2];
-            flux_H(c, Ub, nn, vn, H);
+            flux_lf(c, U, Ub, nn, vn, H);
             flux_vis(c, U, dU, Fv, 0);
             cplx tn0 = Fv[1][0] * nn[0] + Fv[1][1] * nn[1];
             cplx tn1 = Fv[2][0] * nn[0] + Fv[2][1] * nn[1];
@@ -1441,9 +1444,6 @@ int pao_primal_period(pao_ctx* c, const double* u0, double* uNt, double qoi[2], 
                 for (int j = 1; j < i; ++j) acc += c->A[i - 1][j - 1] * c->tk[(int64_t)(s - i + j) * Nu + q];
                 ubase[q] = acc;
             }
-            /* predictor */
-            if (s > 0) memcpy(k, c->tk + (int64_t)(s - 1) * Nu, sizeof(double) * Nu);
-            else memset(k, 0, sizeof(double) * Nu);
             double aii = c->A[i - 1][i - 1];
 #define EVAL_R(kk, out_norm)                                                         \
     do {                                                                             \
@@ -1453,8 +1453,23 @@ int pao_primal_period(pao_ctx* c, const double* u0, double* uNt, double qoi[2], 
         for (int64_t q = 0; q < Nu; ++q) R[q] -= c->dt * r[q];                       \
         out_norm = nrm2(Nu, R);                                                      \
     } while (0)
+            /* predictor (reading; the paper fixes none): the previous stage's
+             * slope k_{i-1}, or the slope that puts u_i at the previous stage
+             * state; the one with the smaller Newton residual is kept (the
+             * slope on ties).  The first stage of the period starts from 0. */
             double nR;
-            EVAL_R(k, nR);
+            if (s > 0) {
+                const double* uprv = c->tui + (int64_t)(s - 1) * Nu;
+                double n2;
+                for (int64_t q = 0; q < Nu; ++q) kt[q] = (uprv[q] - ubase[q]) / aii;
+                EVAL_R(kt, n2);
+                memcpy(k, c->tk + (int64_t)(s - 1) * Nu, sizeof(double) * Nu);
+                EVAL_R(k, nR);
+                if (!(nR <= n2)) { memcpy(k, kt, sizeof(double) * Nu); EVAL_R(k, nR); }
+            } else {
+                memset(k, 0, sizeof(double) * Nu);
+                EVAL_R(k, nR);
+            }
             int it = 0;
             while (!(nR <= c->cfg.newton_atol)) {
                 if (!isfinite(nR)) { rc = fail(c, -3, "NaN in stage (%d,%d)", n, i); break; }
@@ -1465,13 +1480,16 @@ int pao_primal_period(pao_ctx* c, const double* u0, double* uNt, double qoi[2], 
                 pao_jacobian(c, n, i, ui, Jt);
                 int li = pao_stage_solve(c, Jt, c->dt * aii, 0, R, dk);
                 if (li < 0) { rc = li; break; }
+                /* backtracking: halve until ||R|| decreases (NaN counts as no decrease) */
                 double lam = 1.0, nT = 0;
                 for (;;) {
                     for (int64_t q = 0; q < Nu; ++q) kt[q] = k[q] - lam * dk[q];
                     EVAL_R(kt, nT);
-                    if (nT < nR || lam < 1e-3) break;
+                    if (nT < nR) break;
                     lam *= 0.5;
+                    if (lam < 1e-4) { rc = fail(c, -2, "line search failed at stage (%d,%d)", n, i); break; }
                 }
+                if (rc) break;
                 memcpy(k, kt, sizeof(double) * Nu);
                 nR = nT;
                 ++it;

@@ -1,0 +1,1515 @@
+// Host orchestration and C ABI of the periodic-adjoint library (gfx950).
+//
+// Implements, on one MI355X, the fully discrete time-periodic adjoint method
+// of arXiv:1512.00616:
+//   primal period (Sec. 2.3 eq. dirk2): per DIRK stage a Newton solve with
+//     the exact Jacobian and block-Jacobi GMRES;
+//   tangent sweep (eq. dirk-sens-mvp) = matvec of Newton-Krylov shooting
+//     (Alg. 2, Jacobian Phi - I of eq. jac-prim);
+//   backward adjoint sweep (eqs. uns-disc-adj-dirk2 and
+//     uns-disc-adj-dirk-sens-mvp) with transposed stage solves;
+//   periodic adjoint GMRES (Alg. 3) and the gradient (eq.
+//     funcl-grad-nosens-dirk, Alg. 4).
+// Every stage state, stage slope, Jacobian and block-Jacobi inverse of the
+// period is checkpointed in HBM during the primal sweep, so the tangent and
+// adjoint sweeps only stream stored operators.
+#include "../../include/pa.h"
+#include "pa_kernels.hpp"
+#include "pa_linalg.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <functional>
+#include <string>
+#include <vector>
+
+using namespace pa;
+
+namespace {
+
+struct PaError {
+    pa_status code;
+    std::string msg;
+};
+
+[[noreturn]] void raise(pa_status c, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    throw PaError{ c, buf };
+}
+
+#define HIPCHK(expr)                                                                                 \
+    do {                                                                                             \
+        hipError_t e_ = (expr);                                                                      \
+        if (e_ != hipSuccess) raise(PA_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));      \
+    } while (0)
+
+#define LAUNCHCHK()                                                                                  \
+    do {                                                                                             \
+        hipError_t e_ = hipGetLastError();                                                           \
+        if (e_ != hipSuccess) raise(PA_EDEVICE, "kernel launch failed: %s", hipGetErrorString(e_));   \
+    } while (0)
+
+double now_ms()
+{
+    return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+// ------------------------------------------------------------------ reference element (host)
+// Gauss-Legendre rule on [0, 1] by Newton's method on P_n
+void gauss_legendre01(int n, std::vector<double>& x, std::vector<double>& w)
+{
+    x.assign(n, 0.0);
+    w.assign(n, 0.0);
+    for (int k = 0; k < n; ++k) {
+        double z = -std::cos(M_PI * (k + 0.75) / (n + 0.5));   // ascending
+        double dpn = 1.0;
+        for (int it = 0; it < 100; ++it) {
+            double pm = 1.0, pc = z;   // P_0, P_1
+            for (int l = 2; l <= n; ++l) {
+                double pn = ((2 * l - 1) * z * pc - (l - 1) * pm) / l;
+                pm = pc;
+                pc = pn;
+            }
+            dpn = n * (pm - z * pc) / (1.0 - z * z);
+            double step = pc / dpn;
+            z -= step;
+            if (std::fabs(step) < 1e-17) break;
+        }
+        double pm = 1.0, pc = z;
+        for (int l = 2; l <= n; ++l) {
+            double pn = ((2 * l - 1) * z * pc - (l - 1) * pm) / l;
+            pm = pc;
+            pc = pn;
+        }
+        dpn = n * (pm - z * pc) / (1.0 - z * z);
+        x[k] = 0.5 * (z + 1.0);
+        w[k] = 1.0 / ((1.0 - z * z) * dpn * dpn);
+    }
+}
+
+// Lagrange basis on the equispaced nodal set via a monomial Vandermonde
+// matrix inverted by Gauss-Jordan elimination
+struct Basis {
+    int p, np;
+    std::vector<int> ex, ey;
+    std::vector<double> coef;   // coef[k*np + a]: phi_a = sum_k coef * monomial_k
+    explicit Basis(int p_) : p(p_), np((p_ + 1) * (p_ + 2) / 2)
+    {
+        for (int i = 0; i <= p; ++i)
+            for (int j = 0; i + j <= p; ++j) { ex.push_back(i); ey.push_back(j); }
+        std::vector<double> nodes;
+        for (int t = 0; t <= p; ++t)
+            for (int s = 0; s + t <= p; ++s) { nodes.push_back((double)s / p); nodes.push_back((double)t / p); }
+        // augmented [V | I], V[b][k] = monomial_k(node_b)
+        int n = np;
+        std::vector<double> a(n * 2 * n, 0.0);
+        for (int b = 0; b < n; ++b) {
+            for (int k = 0; k < n; ++k) a[b * 2 * n + k] = std::pow(nodes[2 * b], ex[k]) * std::pow(nodes[2 * b + 1], ey[k]);
+            a[b * 2 * n + n + b] = 1.0;
+        }
+        for (int c = 0; c < n; ++c) {
+            int piv = c;
+            for (int r = c + 1; r < n; ++r)
+                if (std::fabs(a[r * 2 * n + c]) > std::fabs(a[piv * 2 * n + c])) piv = r;
+            if (piv != c)
+                for (int k = 0; k < 2 * n; ++k) std::swap(a[c * 2 * n + k], a[piv * 2 * n + k]);
+            double d = a[c * 2 * n + c];
+            for (int k = 0; k < 2 * n; ++k) a[c * 2 * n + k] /= d;
+            for (int r = 0; r < n; ++r) {
+                if (r == c) continue;
+                double f = a[r * 2 * n + c];
+                if (f != 0.0)
+                    for (int k = 0; k < 2 * n; ++k) a[r * 2 * n + k] -= f * a[c * 2 * n + k];
+            }
+        }
+        // V^{-1} = right half; coef[k][a] = Vinv[k][a]
+        coef.assign(n * n, 0.0);
+        for (int k = 0; k < n; ++k)
+            for (int b = 0; b < n; ++b) coef[k * n + b] = a[k * 2 * n + n + b];
+    }
+    void eval(double x, double y, double* phi, double (*dphi)[2]) const
+    {
+        for (int a = 0; a < np; ++a) { phi[a] = 0.0; dphi[a][0] = dphi[a][1] = 0.0; }
+        for (int k = 0; k < np; ++k) {
+            double m = std::pow(x, ex[k]) * std::pow(y, ey[k]);
+            double mx = ex[k] ? ex[k] * std::pow(x, ex[k] - 1) * std::pow(y, ey[k]) : 0.0;
+            double my = ey[k] ? ey[k] * std::pow(x, ex[k]) * std::pow(y, ey[k] - 1) : 0.0;
+            for (int a = 0; a < np; ++a) {
+                double c = coef[k * np + a];
+                phi[a] += c * m;
+                dphi[a][0] += c * mx;
+                dphi[a][1] += c * my;
+            }
+        }
+    }
+};
+
+template <int P>
+void build_ref(Ref<P>& R)
+{
+    constexpr int NP = Sz<P>::NP, NF = Sz<P>::NF;
+    Basis bs(P);
+    std::vector<double> gx, gw;
+    gauss_legendre01(P + 2, gx, gw);
+    int q = 0;
+    for (int l = 0; l < P + 2; ++l)
+        for (int k = 0; k < P + 2; ++k) {
+            double xi = gx[k] * (1.0 - gx[l]), eta = gx[l];
+            bs.eval(xi, eta, R.phq[q], R.dphq[q]);
+            R.wq[q] = gw[k] * gw[l] * (1.0 - gx[l]);
+            ++q;
+        }
+    const double rv[3][2] = { { 0, 0 }, { 1, 0 }, { 0, 1 } };
+    for (int f = 0; f < 3; ++f)
+        for (int j = 0; j < NF; ++j) {
+            const double *a = rv[f], *b = rv[(f + 1) % 3];
+            double s = gx[j], sr = 1.0 - gx[j];
+            bs.eval(a[0] + s * (b[0] - a[0]), a[1] + s * (b[1] - a[1]), R.phf[f][j], R.dphf[f][j]);
+            bs.eval(a[0] + sr * (b[0] - a[0]), a[1] + sr * (b[1] - a[1]), R.phr[f][j], R.dphr[f][j]);
+        }
+    for (int j = 0; j < NF; ++j) R.wf[j] = gw[j];
+    for (int a = 0; a < NP; ++a)
+        for (int b = 0; b < NP; ++b) {
+            double s = 0.0;
+            for (int qq = 0; qq < Sz<P>::NQ; ++qq) s += R.wq[qq] * R.phq[qq][a] * R.phq[qq][b];
+            R.mh[a][b] = s;
+        }
+    // inverse of the mass matrix (Gauss-Jordan)
+    int n = NP;
+    std::vector<double> a(n * 2 * n, 0.0);
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j < n; ++j) a[i * 2 * n + j] = R.mh[i][j];
+        a[i * 2 * n + n + i] = 1.0;
+    }
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(a[r * 2 * n + c]) > std::fabs(a[piv * 2 * n + c])) piv = r;
+        if (piv != c)
+            for (int k = 0; k < 2 * n; ++k) std::swap(a[c * 2 * n + k], a[piv * 2 * n + k]);
+        double d = a[c * 2 * n + c];
+        for (int k = 0; k < 2 * n; ++k) a[c * 2 * n + k] /= d;
+        for (int r = 0; r < n; ++r) {
+            if (r == c) continue;
+            double f = a[r * 2 * n + c];
+            for (int k = 0; k < 2 * n; ++k) a[r * 2 * n + k] -= f * a[c * 2 * n + k];
+        }
+    }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) R.mhi[i][j] = a[i * 2 * n + n + j];
+}
+
+// Alexander's three-stage, L-stable, stiffly accurate DIRK of order 3
+// (reading of the third-order DIRK of Sec. 5.1; the paper gives no tableau)
+struct Dirk3 {
+    double A[3][3], b[3], c[3];
+    Dirk3()
+    {
+        // alpha: root in (1/6, 1/2) of x^3 - 3x^2 + 3x/2 - 1/6, by bisection
+        double lo = 1.0 / 6.0, hi = 0.5;
+        for (int it = 0; it < 200; ++it) {
+            double mid = 0.5 * (lo + hi);
+            double f = ((mid - 3.0) * mid + 1.5) * mid - 1.0 / 6.0;
+            double flo = ((lo - 3.0) * lo + 1.5) * lo - 1.0 / 6.0;
+            if ((f < 0) == (flo < 0)) lo = mid; else hi = mid;
+        }
+        double al = 0.5 * (lo + hi), t2 = 0.5 * (1.0 + al);
+        double b1 = -(6 * al * al - 16 * al + 1) / 4.0, b2 = (6 * al * al - 20 * al + 5) / 4.0;
+        std::memset(A, 0, sizeof A);
+        A[0][0] = al;
+        A[1][0] = t2 - al; A[1][1] = al;
+        A[2][0] = b1; A[2][1] = b2; A[2][2] = al;
+        b[0] = b1; b[1] = b2; b[2] = al;
+        c[0] = al; c[1] = t2; c[2] = 1.0;
+    }
+};
+
+inline int grid1(int64_t n, int bs = 256) { return (int)((n + bs - 1) / bs); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ context
+struct pa_ctx {
+    pa_config cfg;
+    std::string err;
+    virtual ~pa_ctx() {}
+    virtual int64_t num_dofs() const = 0;
+    virtual int32_t num_elems() const = 0;
+    virtual int32_t block_size() const = 0;
+    virtual int64_t device_bytes() const = 0;
+    virtual void get_mesh(int32_t*, int32_t*, int8_t*, double*) const = 0;
+    virtual void set_params(const double mu[3]) = 0;
+    virtual void set_state(const double* u0, int64_t n) = 0;
+    virtual void set_freestream(const double* pert) = 0;
+    virtual void get_state(int which, double* out, int64_t n) = 0;
+    virtual void primal_period(double qoi[2], double* res) = 0;
+    virtual void shoot(double tol, double eta, int maxit, pa_shoot_report* rep) = 0;
+    virtual void adjoint_gradient(double rtol, double qoi[2], double dJ[6], pa_adjoint_report* rep) = 0;
+    virtual void tangent_sweep_h(const double* v, double* out) = 0;
+    virtual void adjoint_sweep_h(const double* lam, int fq, double* lam0, double* grad) = 0;
+    virtual void dbg_gbar(int n, int i, double* out, bool deriv) = 0;
+    virtual void dbg_residual(int n, int i, const double* u, double* r, bool dmu) = 0;
+    virtual void dbg_jacobian(int n, int i, const double* u, double* blk) = 0;
+    virtual void dbg_qoi(int n, int i, const double* u, double f[2], double* dfdu, double* dfdmu) = 0;
+    virtual void dbg_bsr_apply(const double* blk, double alpha, double beta, int tr, const double* x, double* y) = 0;
+    virtual void dbg_blockinv(const double* blk, double adt, double* out) = 0;
+    virtual int dbg_stage_solve(const double* blk, double adt, int tr, const double* rhs, double* x) = 0;
+    virtual void dbg_traj(int which, int n, int i, double* out) = 0;
+    virtual void set_timing(bool on) = 0;
+    virtual void kernel_time(int k, double* ms, int64_t* cnt) = 0;
+    virtual double bench_spmv(int reps, int tr) = 0;
+};
+
+namespace {
+
+template <int P>
+struct Solver final : pa_ctx {
+    static constexpr int NP = Sz<P>::NP, NQ = Sz<P>::NQ, NF = Sz<P>::NF, B = Sz<P>::B, BB = B * B;
+
+    int Ne = 0, Nt = 0, nst = 0, nwall = 0;
+    int64_t Nu = 0, nn = 0, Jsz = 0, Isz = 0;
+    double dt = 0;
+    Dirk3 rk;
+    Phys ph{};
+    double mu[3] = { 0, 0, 0 };
+    bool have_params = false, have_traj = false;
+    int restart = 30, max_kry = 100;
+    bool verbose = false;   // PA_VERBOSE=1: per-stage Newton history on stderr
+    int64_t bytes = 0;
+
+    // host mesh
+    std::vector<int32_t> ev, enb, wall;
+    std::vector<int8_t> etw;
+    std::vector<double> vxy, area, jit, xn, wbl, elen, enrm;
+    Ref<P> href{};
+
+    hipStream_t st = nullptr;
+    DevMesh dm{};
+    Ref<P>* dref = nullptr;
+    double* dmh = nullptr;
+    int32_t* dwall = nullptr;
+    int* dstatus = nullptr;
+    std::vector<void*> allocs;
+
+    double *gb = nullptr, *dgb = nullptr;                          // [(nst+1)][nn], [(nst+1)][3][nn]
+    double *tu = nullptr, *tk = nullptr, *tui = nullptr;           // trajectory
+    double *tJ = nullptr, *tAi = nullptr;                          // stage operators
+    double *qh = nullptr;                                          // [nst][nwall][2]
+    double *u0 = nullptr;
+    // work vectors
+    double *wa = nullptr, *wb = nullptr, *wc = nullptr, *wd = nullptr, *we = nullptr, *wf = nullptr;
+    double *sk3 = nullptr;                                         // 3 * Nu
+    double *fp3 = nullptr;                                         // 3 * Nu (QoI derivatives)
+    double *drm = nullptr;                                         // 3 * Nu (dr/dmu)
+    double *V = nullptr, *Vo = nullptr;                            // stage / outer Krylov bases
+    double *part = nullptr, *hdev = nullptr;
+    double *qtmp = nullptr, *qdu = nullptr, *qdmu = nullptr;
+    double *rg4 = nullptr, *kg4 = nullptr;                         // GCL work [3][4][nn]
+    int64_t cnt_newton = 0, cnt_gmres = 0;
+
+    // timing
+    bool timing = false;
+    struct EvPair { hipEvent_t a, b; int k; };
+    std::vector<EvPair> evpool;
+    size_t evused = 0;
+    double ktime[PA_K_COUNT] = { 0 };
+    int64_t kcount[PA_K_COUNT] = { 0 };
+
+    template <class T>
+    T* dalloc(int64_t n)
+    {
+        void* p = nullptr;
+        if (n <= 0) n = 1;
+        hipError_t e = hipMalloc(&p, sizeof(T) * (size_t)n);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            raise(PA_ENOMEM, "hipMalloc of %.3f GB failed: %s", sizeof(T) * (double)n / 1e9, hipGetErrorString(e));
+        }
+        allocs.push_back(p);
+        bytes += sizeof(T) * n;
+        return static_cast<T*>(p);
+    }
+
+    explicit Solver(const pa_config& c)
+    {
+        cfg = c;
+        HIPCHK(hipSetDevice(c.device));
+        HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        Nt = c.Nt;
+        nst = 3 * Nt;
+        dt = c.T / c.Nt;
+        restart = c.gmres_restart;
+        max_kry = c.max_krylov;
+        ph.gam = c.gamma;
+        ph.muv = 1.0 / c.re;
+        ph.pr = c.pr;
+        double pinf = 1.0 / (c.gamma * c.mach * c.mach);
+        ph.Uinf[0] = 1.0; ph.Uinf[1] = 1.0; ph.Uinf[2] = 0.0; ph.Uinf[3] = pinf / (c.gamma - 1.0) + 0.5;
+        ph.lf_delta = 1e-2;
+        ph.wall_eta = 10.0;
+        const char* ve = std::getenv("PA_VERBOSE");
+        verbose = ve && ve[0] == '1';
+        build_mesh();
+        build_ref(href);
+        upload();
+    }
+
+    ~Solver() override
+    {
+        if (st) (void)hipStreamSynchronize(st);
+        for (auto& e : evpool) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
+        for (void* p : allocs) (void)hipFree(p);
+        if (st) (void)hipStreamDestroy(st);
+    }
+
+    // O-grid around the unit circle: radii 1 + (r_far - 1)(q^i - 1)/(q^Nr - 1),
+    // q = stretch^(8/Nr); quad (i, j) -> triangles (a, b, c), (a, c, d)
+    void build_mesh()
+    {
+        const int Nr = cfg.Nr, Nth = cfg.Nth;
+        Ne = 2 * Nr * Nth;
+        nn = (int64_t)Ne * NP;
+        Nu = nn * 4;
+        Jsz = (int64_t)Ne * 4 * BB;
+        Isz = (int64_t)Ne * BB;
+        vxy.resize(2 * (Nr + 1) * Nth);
+        const double q = std::pow(cfg.stretch, 8.0 / Nr), qN = std::pow(q, Nr);
+        for (int i = 0; i <= Nr; ++i) {
+            double r = 1.0 + (cfg.r_far - 1.0) * (std::pow(q, i) - 1.0) / (qN - 1.0);
+            for (int j = 0; j < Nth; ++j) {
+                double th = 2.0 * M_PI * j / Nth;
+                vxy[2 * (i * Nth + j)] = r * std::cos(th);
+                vxy[2 * (i * Nth + j) + 1] = r * std::sin(th);
+            }
+        }
+        ev.assign(3 * Ne, 0);
+        enb.assign(3 * Ne, 0);
+        etw.assign(3 * Ne, 0);
+        auto wrap = [&](int j) { return ((j % Nth) + Nth) % Nth; };
+        auto vid = [&](int i, int j) { return i * Nth + wrap(j); };
+        auto eA = [&](int i, int j) { return 2 * (i * Nth + wrap(j)); };
+        for (int i = 0; i < Nr; ++i)
+            for (int j = 0; j < Nth; ++j) {
+                int A = eA(i, j), Bt = A + 1;
+                int a = vid(i, j), b = vid(i + 1, j), cc = vid(i + 1, j + 1), d = vid(i, j + 1);
+                int* eA3 = &ev[3 * A];
+                int* eB3 = &ev[3 * Bt];
+                eA3[0] = a; eA3[1] = b; eA3[2] = cc;
+                eB3[0] = a; eB3[1] = cc; eB3[2] = d;
+                // triangle A: faces a-b, b-c, c-a
+                enb[3 * A + 0] = eA(i, j - 1) + 1; etw[3 * A + 0] = 1;
+                if (i + 1 < Nr) { enb[3 * A + 1] = eA(i + 1, j) + 1; etw[3 * A + 1] = 2; }
+                else { enb[3 * A + 1] = -2; etw[3 * A + 1] = -1; }
+                enb[3 * A + 2] = Bt; etw[3 * A + 2] = 0;
+                // triangle B: faces a-c, c-d, d-a
+                enb[3 * Bt + 0] = A; etw[3 * Bt + 0] = 2;
+                enb[3 * Bt + 1] = eA(i, j + 1); etw[3 * Bt + 1] = 0;
+                if (i > 0) { enb[3 * Bt + 2] = eA(i - 1, j); etw[3 * Bt + 2] = 1; }
+                else { enb[3 * Bt + 2] = -1; etw[3 * Bt + 2] = -1; }
+            }
+        area.resize(Ne);
+        jit.resize(4 * Ne);
+        xn.resize(2 * nn);
+        wbl.resize(nn);
+        elen.resize(3 * Ne);
+        enrm.resize(6 * Ne);
+        for (int K = 0; K < Ne; ++K) {
+            const double* p0 = &vxy[2 * ev[3 * K]];
+            const double* p1 = &vxy[2 * ev[3 * K + 1]];
+            const double* p2 = &vxy[2 * ev[3 * K + 2]];
+            double j00 = p1[0] - p0[0], j01 = p2[0] - p0[0], j10 = p1[1] - p0[1], j11 = p2[1] - p0[1];
+            double det = j00 * j11 - j01 * j10;
+            area[K] = 0.5 * det;
+            // J^{-T} = [[j11, -j10], [-j01, j00]] / det
+            jit[4 * K + 0] = j11 / det;
+            jit[4 * K + 1] = -j10 / det;
+            jit[4 * K + 2] = -j01 / det;
+            jit[4 * K + 3] = j00 / det;
+            int a = 0;
+            for (int t = 0; t <= P; ++t)
+                for (int s = 0; s + t <= P; ++s) {
+                    double X = p0[0] + (double(s) / P) * (p1[0] - p0[0]) + (double(t) / P) * (p2[0] - p0[0]);
+                    double Y = p0[1] + (double(s) / P) * (p1[1] - p0[1]) + (double(t) / P) * (p2[1] - p0[1]);
+                    int64_t na = (int64_t)K * NP + a;
+                    xn[2 * na] = X;
+                    xn[2 * na + 1] = Y;
+                    double r = std::sqrt(X * X + Y * Y), w;
+                    if (r <= cfg.r_blend0) w = 1.0;
+                    else if (r >= cfg.r_blend1) w = 0.0;
+                    else {
+                        double z = (r - cfg.r_blend0) / (cfg.r_blend1 - cfg.r_blend0);
+                        w = 1.0 - z * z * (3.0 - 2.0 * z);
+                    }
+                    wbl[na] = w;
+                    ++a;
+                }
+            const double* pv[3] = { p0, p1, p2 };
+            for (int f = 0; f < 3; ++f) {
+                const double* u = pv[f];
+                const double* v = pv[(f + 1) % 3];
+                double tx = v[0] - u[0], ty = v[1] - u[1], l = std::sqrt(tx * tx + ty * ty);
+                elen[3 * K + f] = l;
+                enrm[6 * K + 2 * f] = ty / l;
+                enrm[6 * K + 2 * f + 1] = -tx / l;
+            }
+            if (!cfg.wall_is_farfield)
+                for (int f = 0; f < 3; ++f)
+                    if (enb[3 * K + f] == -1) { wall.push_back(K); break; }
+        }
+        nwall = (int)wall.size();
+    }
+
+    template <class T>
+    T* upload_vec(const std::vector<T>& h)
+    {
+        T* d = dalloc<T>((int64_t)h.size());
+        HIPCHK(hipMemcpy(d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
+        return d;
+    }
+
+    void upload()
+    {
+        dm.Ne = Ne;
+        dm.wall_is_far = cfg.wall_is_farfield;
+        dm.enb = upload_vec(enb);
+        dm.etw = upload_vec(etw);
+        dm.area = upload_vec(area);
+        dm.jit = upload_vec(jit);
+        dm.xn = upload_vec(xn);
+        dm.wbl = upload_vec(wbl);
+        dm.elen = upload_vec(elen);
+        dm.enrm = upload_vec(enrm);
+        dref = dalloc<Ref<P>>(1);
+        HIPCHK(hipMemcpy(dref, &href, sizeof(Ref<P>), hipMemcpyHostToDevice));
+        std::vector<double> mhf(NP * NP);
+        for (int a = 0; a < NP; ++a)
+            for (int b = 0; b < NP; ++b) mhf[a * NP + b] = href.mh[a][b];
+        dmh = upload_vec(mhf);
+        std::vector<int32_t> w = wall;
+        if (w.empty()) w.push_back(0);
+        dwall = upload_vec(w);
+        dstatus = dalloc<int>(1);
+        gb = dalloc<double>((nst + 1) * nn);
+        dgb = dalloc<double>((nst + 1) * 3 * nn);
+        tu = dalloc<double>((Nt + 1) * Nu);
+        tk = dalloc<double>(nst * Nu);
+        tui = dalloc<double>(nst * Nu);
+        tJ = dalloc<double>(nst * Jsz);
+        tAi = dalloc<double>(nst * Isz);
+        qh = dalloc<double>((int64_t)nst * std::max(nwall, 1) * 2);
+        u0 = dalloc<double>(Nu);
+        wa = dalloc<double>(Nu); wb = dalloc<double>(Nu); wc = dalloc<double>(Nu);
+        wd = dalloc<double>(Nu); we = dalloc<double>(Nu); wf = dalloc<double>(Nu);
+        sk3 = dalloc<double>(3 * Nu);
+        fp3 = dalloc<double>(3 * Nu);
+        drm = dalloc<double>(3 * Nu);
+        V = dalloc<double>((int64_t)(restart + 1) * Nu);
+        Vo = dalloc<double>((int64_t)(max_kry + 1) * Nu);
+        part = dalloc<double>((int64_t)RED_BLOCKS * (std::max(restart, max_kry) + 2));
+        hdev = dalloc<double>(std::max(restart, max_kry) + 2);
+        qtmp = dalloc<double>((int64_t)std::max(nwall, 1) * 2);
+        qdu = dalloc<double>((int64_t)std::max(nwall, 1) * 2 * B);
+        qdmu = dalloc<double>((int64_t)std::max(nwall, 1) * 8);
+        rg4 = dalloc<double>(4 * nn);
+        kg4 = dalloc<double>(3 * 4 * nn);
+        outer_x = dalloc<double>(Nu);
+        outer_w = dalloc<double>(Nu);
+        outer_z = dalloc<double>(Nu);
+        outer_rhs = dalloc<double>(Nu);
+        lam_buf = dalloc<double>(Nu);
+        set_jacobian_smem();
+    }
+
+    void set_jacobian_smem()
+    {
+        size_t smem = sizeof(JacSmem<P>);
+        if (smem > 48 * 1024)
+            HIPCHK(hipFuncSetAttribute((const void*)k_jacobian<P>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem));
+    }
+
+    // ---------------------------------------------------------------- timing
+    // every TSTRIDE-th launch of a kernel is bracketed by events (an unbiased
+    // sample of the launch durations with little host overhead)
+    static constexpr int TSTRIDE = 8;
+    int64_t tseen[PA_K_COUNT] = { 0 };
+    void tstart(int k, hipEvent_t* out)
+    {
+        *out = nullptr;
+        if (!timing) return;
+        if ((tseen[k]++ % TSTRIDE) != 0) return;
+        if (evused >= 4096) harvest();   // every recorded pair is closed here
+        if (evused == evpool.size()) {
+            EvPair e;
+            HIPCHK(hipEventCreate(&e.a));
+            HIPCHK(hipEventCreate(&e.b));
+            evpool.push_back(e);
+        }
+        EvPair& e = evpool[evused];
+        e.k = k;
+        HIPCHK(hipEventRecord(e.a, st));
+        *out = e.b;
+        ++evused;
+    }
+    void tstop(hipEvent_t b)
+    {
+        if (!timing || !b) return;
+        HIPCHK(hipEventRecord(b, st));
+    }
+    void harvest()
+    {
+        if (!evused) return;
+        HIPCHK(hipStreamSynchronize(st));
+        for (size_t i = 0; i < evused; ++i) {
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, evpool[i].a, evpool[i].b));
+            ktime[evpool[i].k] += ms;
+            kcount[evpool[i].k] += 1;
+        }
+        evused = 0;
+    }
+    void set_timing(bool on) override
+    {
+        harvest();
+        timing = on;
+        for (int k = 0; k < PA_K_COUNT; ++k) { ktime[k] = 0; kcount[k] = 0; tseen[k] = 0; }
+    }
+    void kernel_time(int k, double* ms, int64_t* cnt) override
+    {
+        if (k < 0 || k >= PA_K_COUNT) raise(PA_EINVAL, "bad kernel id %d", k);
+        // finish pending measurements without disturbing the counters
+        bool t = timing;
+        timing = false;
+        harvest();
+        timing = t;
+        // sampled launches: scale the summed time to every launch seen
+        double avg = kcount[k] ? ktime[k] / (double)kcount[k] : 0.0;
+        if (ms) *ms = avg * (double)tseen[k];
+        if (cnt) *cnt = tseen[k];
+    }
+
+    // ---------------------------------------------------------------- motion
+    Motion<double> motion(double t) const
+    {
+        double w = 2.0 * M_PI / cfg.T;
+        Motion<double> m;
+        m.h = mu[0] * std::sin(w * t);
+        m.hd = mu[0] * w * std::cos(w * t);
+        m.th = mu[1] * std::sin(w * t + mu[2]);
+        m.thd = mu[1] * w * std::cos(w * t + mu[2]);
+        return m;
+    }
+    Motion<Dual<3>> motion_d(double t) const
+    {
+        double w = 2.0 * M_PI / cfg.T, s = std::sin(w * t), c = std::cos(w * t);
+        double sp = std::sin(w * t + mu[2]), cp = std::cos(w * t + mu[2]);
+        Motion<Dual<3>> m;
+        m.h = { mu[0] * s, { s, 0, 0 } };
+        m.hd = { mu[0] * w * c, { w * c, 0, 0 } };
+        m.th = { mu[1] * sp, { 0, sp, mu[1] * cp } };
+        m.thd = { mu[1] * w * cp, { 0, w * cp, -mu[1] * w * sp } };
+        return m;
+    }
+    double stage_time(int n, int i) const { return n == 0 ? 0.0 : (n - 1 + rk.c[i - 1]) * dt; }
+    int gidx(int n, int i) const { return n == 0 ? 0 : 1 + (n - 1) * 3 + (i - 1); }
+    const double* gbs(int n, int i) const { return gb + (int64_t)gidx(n, i) * nn; }
+    const double* dgbs(int n, int i) const { return dgb + (int64_t)gidx(n, i) * 3 * nn; }
+    void check_stage(int n, int i) const
+    {
+        if (!have_params) raise(PA_ESTATE, "parameters not set");
+        if (!((n == 0 && i == 0) || (n >= 1 && n <= Nt && i >= 1 && i <= 3))) raise(PA_EINVAL, "bad stage (%d,%d)", n, i);
+    }
+
+    // ---------------------------------------------------------------- kernels
+    void residual(int n, int i, const double* u, double* r)
+    {
+        hipEvent_t e;
+        tstart(PA_K_RESIDUAL, &e);
+        k_residual<P, double><<<Ne, 64, 0, st>>>(dm, dref, ph, motion(stage_time(n, i)), u, gbs(n, i), nullptr, r, Nu);
+        LAUNCHCHK();
+        tstop(e);
+    }
+    void dr_dmu(int n, int i, const double* u, double* out)
+    {
+        k_residual<P, Dual<3>><<<Ne, 64, 0, st>>>(dm, dref, ph, motion_d(stage_time(n, i)), u, gbs(n, i), dgbs(n, i),
+                                                   out, Nu);
+        LAUNCHCHK();
+    }
+    void jacobian(int n, int i, const double* u, double* J)
+    {
+        hipEvent_t e;
+        tstart(PA_K_JACOBIAN, &e);
+        k_jacobian<P><<<Ne, 256, sizeof(JacSmem<P>), st>>>(dm, dref, ph, motion(stage_time(n, i)), u, gbs(n, i), J);
+        LAUNCHCHK();
+        tstop(e);
+    }
+    void blockinv(const double* J, double c, double* Ai)
+    {
+        hipEvent_t e;
+        tstart(PA_K_BLOCKINV, &e);
+        k_blockinv<NP><<<Ne, 64, 0, st>>>(Ne, dm.area, dmh, J, c, Ai, dstatus);
+        LAUNCHCHK();
+        tstop(e);
+    }
+    // y = alpha M x + beta op(J) x
+    void bsr(const double* J, double alpha, double beta, int tr, const double* x, double* y)
+    {
+        hipEvent_t e;
+        tstart(PA_K_SPMV, &e);
+        k_bsr_apply<NP><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, dm.area, dmh, J, x, y, alpha, beta, tr);
+        LAUNCHCHK();
+        tstop(e);
+    }
+    void prec(const double* Ai, int tr, const double* x, double* z)
+    {
+        hipEvent_t e;
+        tstart(PA_K_PRECOND, &e);
+        k_block_apply<NP><<<Ne, 64, 0, st>>>(Ne, Ai, x, z, tr);
+        LAUNCHCHK();
+        tstop(e);
+    }
+    void axpby(double a, const double* x, double b, double* y)
+    {
+        k_axpby<<<grid1(Nu), 256, 0, st>>>(a, x, b, y, Nu);
+        LAUNCHCHK();
+    }
+    void lincomb(double a, const double* x, double b, const double* y, double* z)
+    {
+        k_lincomb<<<grid1(Nu), 256, 0, st>>>(a, x, b, y, z, Nu);
+        LAUNCHCHK();
+    }
+    void copy(const double* x, double* y)
+    {
+        HIPCHK(hipMemcpyAsync(y, x, sizeof(double) * Nu, hipMemcpyDeviceToDevice, st));
+    }
+    void zero(double* y, int64_t n = -1)
+    {
+        HIPCHK(hipMemsetAsync(y, 0, sizeof(double) * (n < 0 ? Nu : n), st));
+    }
+    // host h[c] = <V_c, w>, c < ncols (V_c = V + c*ldv); one synchronisation
+    void dots(const double* Vb, int64_t ldv, int ncols, const double* w, double* h)
+    {
+        k_multidot<<<RED_BLOCKS, RED_THREADS, 0, st>>>(Vb, ldv, ncols, w, Nu, part);
+        LAUNCHCHK();
+        k_reduce_partials<<<1, 128, 0, st>>>(part, RED_BLOCKS, ncols, hdev);
+        LAUNCHCHK();
+        HIPCHK(hipMemcpyAsync(h, hdev, sizeof(double) * ncols, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    double norm(const double* w)
+    {
+        double h;
+        dots(w, 0, 1, w, &h);
+        return std::sqrt(h);
+    }
+    // w += sign * sum_c h[c] V_c  (h host)
+    void vupdate(const double* Vb, int64_t ldv, int ncols, const double* h, double sign, double* w)
+    {
+        HIPCHK(hipMemcpyAsync(hdev, h, sizeof(double) * ncols, hipMemcpyHostToDevice, st));
+        k_vupdate<<<grid1(Nu), 256, 0, st>>>(Vb, ldv, ncols, hdev, sign, w, Nu);
+        LAUNCHCHK();
+    }
+
+    // ---------------------------------------------------------------- GMRES
+    // Generic GMRES (Arnoldi with classical Gram-Schmidt and one
+    // reorthogonalisation, Givens rotations, zero initial guess).
+    // A(v, out), Pc(v, out) or empty for no preconditioner (right
+    // preconditioning).  Basis storage Vb with room for m+1 vectors.
+    // Returns iterations; throws PA_ENOCONV when maxit is reached and
+    // require_conv is set.
+    int gmres(const std::function<void(const double*, double*)>& A,
+              const std::function<void(const double*, double*)>& Pc, const double* b, double* x, double rtol,
+              int m, int maxit, double* Vb, double* wk, double* zk, double* relres, bool require_conv)
+    {
+        std::vector<double> H((m + 1) * m, 0.0), cs(m), sn(m), g(m + 1), y(m), h(m + 2), h2(m + 2);
+        double bn = norm(b);
+        zero(x);
+        if (relres) *relres = 0.0;
+        if (bn == 0.0) return 0;
+        int total = 0;
+        bool first = true;
+        double res = bn;
+        for (;;) {
+            // r = b - A x
+            if (first) copy(b, wk);
+            else { A(x, wk); lincomb(1.0, b, -1.0, wk, wk); }
+            double beta = first ? bn : norm(wk);
+            first = false;
+            res = beta;
+            if (beta <= rtol * bn) break;
+            if (total >= maxit) break;
+            lincomb(1.0 / beta, wk, 0.0, wk, Vb);
+            std::fill(g.begin(), g.end(), 0.0);
+            g[0] = beta;
+            int j = 0;
+            bool done = false;
+            for (; j < m && total < maxit; ++j) {
+                ++total;
+                double* vj = Vb + (int64_t)j * Nu;
+                if (Pc) { Pc(vj, zk); A(zk, wk); } else A(vj, wk);
+                dots(Vb, Nu, j + 1, wk, h.data());
+                vupdate(Vb, Nu, j + 1, h.data(), -1.0, wk);
+                // second pass; the last column returns |w|^2 for the norm
+                {
+                    k_multidot<<<RED_BLOCKS, RED_THREADS, 0, st>>>(Vb, Nu, j + 1, wk, Nu, part);
+                    LAUNCHCHK();
+                    k_multidot<<<RED_BLOCKS, RED_THREADS, 0, st>>>(wk, 0, 1, wk, Nu, part + RED_BLOCKS * (j + 1));
+                    LAUNCHCHK();
+                    k_reduce_partials<<<1, 128, 0, st>>>(part, RED_BLOCKS, j + 1, hdev);
+                    LAUNCHCHK();
+                    k_reduce_partials<<<1, 128, 0, st>>>(part + RED_BLOCKS * (j + 1), RED_BLOCKS, 1, hdev + j + 1);
+                    LAUNCHCHK();
+                    HIPCHK(hipMemcpyAsync(h2.data(), hdev, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, st));
+                    HIPCHK(hipStreamSynchronize(st));
+                }
+                double ww = h2[j + 1], corr = 0.0;
+                for (int i = 0; i <= j; ++i) corr += h2[i] * h2[i];
+                vupdate(Vb, Nu, j + 1, h2.data(), -1.0, wk);
+                for (int i = 0; i <= j; ++i) H[i * m + j] = h[i] + h2[i];
+                double hn = std::sqrt(std::max(ww - corr, 0.0));
+                if (!std::isfinite(hn)) raise(PA_ENUMERIC, "NaN in GMRES");
+                H[(j + 1) * m + j] = hn;
+                for (int i = 0; i < j; ++i) {
+                    double a = H[i * m + j], bb = H[(i + 1) * m + j];
+                    H[i * m + j] = cs[i] * a + sn[i] * bb;
+                    H[(i + 1) * m + j] = -sn[i] * a + cs[i] * bb;
+                }
+                double a = H[j * m + j], bb = H[(j + 1) * m + j];
+                double rr = std::sqrt(a * a + bb * bb);
+                cs[j] = a / rr;
+                sn[j] = bb / rr;
+                H[j * m + j] = rr;
+                H[(j + 1) * m + j] = 0.0;
+                g[j + 1] = -sn[j] * g[j];
+                g[j] = cs[j] * g[j];
+                res = std::fabs(g[j + 1]);
+                if (res <= rtol * bn || hn == 0.0) { ++j; done = true; break; }
+                lincomb(1.0 / hn, wk, 0.0, wk, Vb + (int64_t)(j + 1) * Nu);
+            }
+            for (int i = j - 1; i >= 0; --i) {
+                double s = g[i];
+                for (int k = i + 1; k < j; ++k) s -= H[i * m + k] * y[k];
+                y[i] = s / H[i * m + i];
+            }
+            zero(wk);
+            vupdate(Vb, Nu, j, y.data(), 1.0, wk);
+            if (Pc) { Pc(wk, zk); axpby(1.0, zk, 1.0, x); }
+            else axpby(1.0, wk, 1.0, x);
+            if (done) break;
+        }
+        if (relres) *relres = res / bn;
+        if (res > rtol * bn && require_conv) raise(PA_ENOCONV, "GMRES did not converge: rel. residual %.3e", res / bn);
+        return total;
+    }
+
+    // stage solve: (M - c J) x = rhs, or its transpose, with the stored
+    // block-Jacobi inverse Ai
+    int stage_solve(const double* J, const double* Ai, double c, int tr, const double* rhs, double* x)
+    {
+        auto A = [&](const double* v, double* out) { bsr(J, 1.0, -c, tr, v, out); };
+        auto Pc = [&](const double* v, double* out) { prec(Ai, tr, v, out); };
+        int its = gmres(A, Pc, rhs, x, cfg.lin_rtol, restart, 20 * restart, V, we, wf, nullptr, true);
+        cnt_gmres += its;
+        return its;
+    }
+
+    // ---------------------------------------------------------------- setup
+    void set_params(const double m[3]) override
+    {
+        std::memcpy(mu, m, sizeof mu);
+        have_params = true;
+        have_traj = false;
+        // gbar(0) and its mu-derivatives
+        k_gbar0<P, Dual<3>><<<Ne, 64, 0, st>>>(dm, dref, motion_d(0.0), rg4, nn);
+        LAUNCHCHK();
+        HIPCHK(hipMemcpyAsync(gb, rg4, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipMemcpyAsync(dgb, rg4 + nn, sizeof(double) * 3 * nn, hipMemcpyDeviceToDevice, st));
+        for (int n = 1; n <= Nt; ++n) {
+            const int prev = gidx(n - 1, n - 1 == 0 ? 0 : 3);
+            for (int i = 1; i <= 3; ++i) {
+                k_gcl_rhs<P, Dual<3>><<<Ne, 64, 0, st>>>(dm, dref, motion_d(stage_time(n, i)), rg4, nn);
+                LAUNCHCHK();
+                k_gcl_kstage<P><<<grid1(4 * nn), 256, 0, st>>>(dm, dref, rg4, dt, kg4 + (int64_t)(i - 1) * 4 * nn, 4, nn);
+                LAUNCHCHK();
+                const int cur = gidx(n, i);
+                // value field and the three derivative fields
+                for (int fld = 0; fld < 4; ++fld) {
+                    double* dst = fld == 0 ? gb + (int64_t)cur * nn : dgb + ((int64_t)cur * 3 + fld - 1) * nn;
+                    const double* src = fld == 0 ? gb + (int64_t)prev * nn : dgb + ((int64_t)prev * 3 + fld - 1) * nn;
+                    HIPCHK(hipMemcpyAsync(dst, src, sizeof(double) * nn, hipMemcpyDeviceToDevice, st));
+                    for (int j = 1; j <= i; ++j) {
+                        k_axpby<<<grid1(nn), 256, 0, st>>>(rk.A[i - 1][j - 1], kg4 + ((int64_t)(j - 1) * 4 + fld) * nn,
+                                                            1.0, dst, nn);
+                        LAUNCHCHK();
+                    }
+                }
+            }
+        }
+        HIPCHK(hipStreamSynchronize(st));
+    }
+
+    void set_state(const double* h, int64_t n) override
+    {
+        if (n != Nu) raise(PA_EINVAL, "state length %lld != %lld", (long long)n, (long long)Nu);
+        HIPCHK(hipMemcpy(u0, h, sizeof(double) * Nu, hipMemcpyHostToDevice));
+        have_traj = false;
+    }
+    void set_freestream(const double* pert) override
+    {
+        if (!have_params) raise(PA_ESTATE, "parameters not set");
+        std::vector<double> g(nn), u(Nu);
+        HIPCHK(hipMemcpy(g.data(), gb, sizeof(double) * nn, hipMemcpyDeviceToHost));
+        for (int64_t k = 0; k < nn; ++k)
+            for (int m = 0; m < 4; ++m) u[4 * k + m] = g[k] * ph.Uinf[m] + (pert ? pert[4 * k + m] : 0.0);
+        set_state(u.data(), Nu);
+    }
+    void get_state(int which, double* out, int64_t n) override
+    {
+        if (n != Nu) raise(PA_EINVAL, "bad length");
+        if (which == 0) HIPCHK(hipMemcpy(out, u0, sizeof(double) * Nu, hipMemcpyDeviceToHost));
+        else if (which == 1) {
+            if (!have_traj) raise(PA_ESTATE, "no trajectory");
+            HIPCHK(hipMemcpy(out, tu + (int64_t)Nt * Nu, sizeof(double) * Nu, hipMemcpyDeviceToHost));
+        } else raise(PA_EINVAL, "bad which");
+    }
+
+    // ---------------------------------------------------------------- sweeps
+    // stage QoI values of all wall elements into qh[s]
+    void qoi_values(int n, int i, const double* u, double* fval)
+    {
+        if (!nwall) return;
+        k_qoi_du<P><<<grid1((int64_t)nwall * B, 64), 64, 0, st>>>(dm, dref, ph, motion(stage_time(n, i)), dwall, nwall,
+                                                                  u, gbs(n, i), fval, qdu);
+        LAUNCHCHK();
+    }
+    // dense df_q/du [Nu] of QoI q at stage (n, i) into out
+    void qoi_grad(int n, int i, const double* u, int q, double* out, double* fval)
+    {
+        zero(out);
+        if (!nwall) return;
+        k_qoi_du<P><<<grid1((int64_t)nwall * B, 64), 64, 0, st>>>(dm, dref, ph, motion(stage_time(n, i)), dwall, nwall,
+                                                                  u, gbs(n, i), fval, qdu);
+        LAUNCHCHK();
+        for (int w = 0; w < nwall; ++w)
+            HIPCHK(hipMemcpyAsync(out + (int64_t)wall[w] * B, qdu + ((int64_t)w * 2 + q) * B, sizeof(double) * B,
+                                  hipMemcpyDeviceToDevice, st));
+    }
+    // explicit mu-derivative of the QoIs at a stage, host out[2][3] (and values)
+    void qoi_dmu(int n, int i, const double* u, double out[6], double val[2])
+    {
+        for (int k = 0; k < 6; ++k) out[k] = 0.0;
+        if (val) val[0] = val[1] = 0.0;
+        if (!nwall) return;
+        k_qoi_dmu<P><<<grid1(nwall, 64), 64, 0, st>>>(dm, dref, ph, motion_d(stage_time(n, i)), dwall, nwall, u, gbs(n, i),
+                                                      dgbs(n, i), qdmu, nn);
+        LAUNCHCHK();
+        std::vector<double> h((size_t)nwall * 8);
+        HIPCHK(hipMemcpyAsync(h.data(), qdmu, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int w = 0; w < nwall; ++w)
+            for (int q = 0; q < 2; ++q) {
+                if (val) val[q] += h[8 * w + 4 * q];
+                for (int k = 0; k < 3; ++k) out[3 * q + k] += h[8 * w + 4 * q + 1 + k];
+            }
+    }
+
+    double* stJ(int s) { return tJ + (int64_t)s * Jsz; }
+    double* stA(int s) { return tAi + (int64_t)s * Isz; }
+    double* stK(int s) { return tk + (int64_t)s * Nu; }
+    double* stU(int s) { return tui + (int64_t)s * Nu; }
+
+    // primal period from u0 (device), Newton per stage
+    void primal_sweep(double qoi[2], double* res)
+    {
+        if (!have_params) raise(PA_ESTATE, "parameters not set");
+        have_traj = false;
+        copy(u0, tu);
+        done_stages = 0;
+        double* ubase = wa;
+        double* R = wb;
+        double* dk = wc;
+        double* r = wd;
+        for (int n = 1; n <= Nt; ++n) {
+            const double* uprev = tu + (int64_t)(n - 1) * Nu;
+            for (int i = 1; i <= 3; ++i) {
+                const int s = (n - 1) * 3 + (i - 1);
+                const double aii = rk.A[i - 1][i - 1], c = dt * aii;
+                copy(uprev, ubase);
+                for (int j = 1; j < i; ++j) axpby(rk.A[i - 1][j - 1], stK(s - i + j), 1.0, ubase);
+                double* k = stK(s);
+                double* ui = stU(s);
+                double* kt = we;   // trial slope; the stage GMRES is idle while it is live
+                auto evalR = [&](const double* kk) {
+                    lincomb(1.0, ubase, aii, kk, ui);
+                    residual(n, i, ui, r);
+                    k_stage_residual<NP><<<grid1(Nu), 256, 0, st>>>(Ne, dm.area, dmh, kk, r, dt, R);
+                    LAUNCHCHK();
+                    return norm(R);
+                };
+                // predictor: previous stage slope, or the slope that places u_i
+                // at the previous stage state -- whichever has the smaller
+                // Newton residual (the slope on ties); zero at the first stage
+                double nR;
+                if (s > 0) {
+                    lincomb(1.0 / aii, stU(s - 1), -1.0 / aii, ubase, kt);
+                    double n2 = evalR(kt);
+                    copy(stK(s - 1), k);
+                    nR = evalR(k);
+                    if (!(nR <= n2)) { copy(kt, k); nR = evalR(k); }
+                } else {
+                    zero(k);
+                    nR = evalR(k);
+                }
+                if (verbose) fprintf(stderr, "[pa] stage (%d,%d) predictor |R| = %.3e\n", n, i, nR);
+                int it = 0;
+                while (!(nR <= cfg.newton_atol)) {
+                    if (!std::isfinite(nR)) raise(PA_ENUMERIC, "NaN at stage (%d,%d)", n, i);
+                    if (it >= cfg.newton_maxit)
+                        raise(PA_ENOCONV, "stage Newton did not converge at (%d,%d): |R| = %.3e", n, i, nR);
+                    jacobian(n, i, ui, stJ(s));
+                    blockinv(stJ(s), c, stA(s));
+                    stage_solve(stJ(s), stA(s), c, 0, R, dk);
+                    // backtracking on ||R||: halve until it decreases (NaN counts as no decrease)
+                    double lam = 1.0, nT;
+                    for (;;) {
+                        lincomb(1.0, k, -lam, dk, kt);
+                        nT = evalR(kt);
+                        if (nT < nR) break;
+                        lam *= 0.5;
+                        if (lam < 1e-4) raise(PA_ENOCONV, "line search failed at stage (%d,%d), |R| = %.3e", n, i, nR);
+                    }
+                    copy(kt, k);
+                    nR = nT;
+                    ++it;
+                    ++cnt_newton;
+                    if (verbose) fprintf(stderr, "[pa] stage (%d,%d) it %d lam %.3g |R| = %.3e\n", n, i, it, lam, nR);
+                }
+                // exact linearisation at the converged stage state
+                jacobian(n, i, ui, stJ(s));
+                blockinv(stJ(s), c, stA(s));
+                qoi_values(n, i, ui, qh + (int64_t)s * std::max(nwall, 1) * 2);
+                done_stages = s + 1 - (i == 3 ? 1 : 0);   // u^(n) is written after the step
+            }
+            double* un = tu + (int64_t)n * Nu;
+            copy(uprev, un);
+            for (int i = 0; i < 3; ++i) axpby(rk.b[i], stK((n - 1) * 3 + i), 1.0, un);
+            done_stages = 3 * n;
+        }
+        // time-averaged QoIs (fixed-order host sum)
+        std::vector<double> h((size_t)nst * std::max(nwall, 1) * 2);
+        HIPCHK(hipMemcpyAsync(h.data(), qh, sizeof(double) * h.size(), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        double J0 = 0, J1 = 0;
+        for (int s = 0; s < nst; ++s) {
+            double f0 = 0, f1 = 0;
+            for (int w = 0; w < nwall; ++w) { f0 += h[((size_t)s * nwall + w) * 2]; f1 += h[((size_t)s * nwall + w) * 2 + 1]; }
+            J0 += dt * rk.b[s % 3] * f0 / cfg.T;
+            J1 += dt * rk.b[s % 3] * f1 / cfg.T;
+        }
+        if (qoi) { qoi[0] = J0; qoi[1] = J1; }
+        lincomb(1.0, tu + (int64_t)Nt * Nu, -1.0, u0, wa);
+        double rn = norm(wa);
+        if (res) *res = rn;
+        have_traj = true;
+    }
+
+    void primal_period(double qoi[2], double* res) override { primal_sweep(qoi, res); }
+
+    // tangent sweep: out = Phi v (device vectors; out may alias nothing used here)
+    void tangent(const double* v, double* out)
+    {
+        if (!have_traj) raise(PA_ESTATE, "no trajectory");
+        double* du = wa;
+        double* w = wb;
+        double* rhs = wc;
+        copy(v, du);
+        for (int n = 1; n <= Nt; ++n) {
+            for (int i = 1; i <= 3; ++i) {
+                const int s = (n - 1) * 3 + (i - 1);
+                copy(du, w);
+                for (int j = 1; j < i; ++j) axpby(rk.A[i - 1][j - 1], sk3 + (int64_t)(j - 1) * Nu, 1.0, w);
+                bsr(stJ(s), 0.0, dt, 0, w, rhs);
+                stage_solve(stJ(s), stA(s), dt * rk.A[i - 1][i - 1], 0, rhs, sk3 + (int64_t)(i - 1) * Nu);
+            }
+            for (int i = 0; i < 3; ++i) axpby(rk.b[i], sk3 + (int64_t)i * Nu, 1.0, du);
+        }
+        copy(du, out);
+    }
+
+    // backward adjoint sweep from lamNt; forced by QoI fq >= 0 (then grad[3])
+    void adjoint(const double* lamNt, int fq, double* lam0, double* grad)
+    {
+        if (!have_traj) raise(PA_ESTATE, "no trajectory");
+        double* lam = wa;
+        double* rhs = wb;
+        double* kap = wc;
+        copy(lamNt, lam);
+        double g[3] = { 0, 0, 0 };
+        const double sc = dt / cfg.T;
+        for (int n = Nt; n >= 1; --n) {
+            if (fq >= 0)
+                for (int i = 1; i <= 3; ++i) {
+                    const int s = (n - 1) * 3 + (i - 1);
+                    qoi_grad(n, i, stU(s), fq, fp3 + (int64_t)(i - 1) * Nu, qtmp);
+                    double fm[6];
+                    qoi_dmu(n, i, stU(s), fm, nullptr);
+                    for (int k = 0; k < 3; ++k) g[k] += sc * rk.b[i - 1] * fm[3 * fq + k];
+                }
+            for (int i = 3; i >= 1; --i) {
+                const int s = (n - 1) * 3 + (i - 1);
+                lincomb(rk.b[i - 1], lam, 0.0, lam, rhs);
+                for (int j = i + 1; j <= 3; ++j) axpby(rk.A[j - 1][i - 1], sk3 + (int64_t)(j - 1) * Nu, 1.0, rhs);
+                if (fq >= 0)
+                    for (int j = i; j <= 3; ++j)
+                        axpby(sc * rk.b[j - 1] * rk.A[j - 1][i - 1], fp3 + (int64_t)(j - 1) * Nu, 1.0, rhs);
+                stage_solve(stJ(s), stA(s), dt * rk.A[i - 1][i - 1], 1, rhs, kap);
+                bsr(stJ(s), 0.0, dt, 1, kap, sk3 + (int64_t)(i - 1) * Nu);
+                if (fq >= 0) {
+                    dr_dmu(n, i, stU(s), drm);
+                    double d[3];
+                    dots(drm, Nu, 3, kap, d);
+                    for (int k = 0; k < 3; ++k) g[k] += dt * d[k];
+                }
+            }
+            for (int i = 0; i < 3; ++i) axpby(1.0, sk3 + (int64_t)i * Nu, 1.0, lam);
+            if (fq >= 0)
+                for (int i = 0; i < 3; ++i) axpby(sc * rk.b[i], fp3 + (int64_t)i * Nu, 1.0, lam);
+        }
+        copy(lam, lam0);
+        if (grad) for (int k = 0; k < 3; ++k) grad[k] = g[k];
+    }
+
+    // ---------------------------------------------------------------- outer solvers
+    void shoot(double tol, double eta, int maxit, pa_shoot_report* rep) override
+    {
+        double t0 = now_ms();
+        pa_shoot_report r{};
+        cnt_newton = cnt_gmres = 0;
+        for (;;) {
+            double qoi[2], res;
+            primal_sweep(qoi, &res);
+            ++r.primal_sweeps;
+            if (r.primal_sweeps == 1) r.res0 = res;
+            r.res = res;
+            if (res <= tol) break;
+            if (r.newton_its >= maxit) {
+                r.stage_newton_its = (int32_t)cnt_newton;
+                r.stage_gmres_its = cnt_gmres;
+                r.ms = now_ms() - t0;
+                if (rep) *rep = r;
+                raise(PA_ENOCONV, "shooting did not converge: |R| = %.3e after %d Newton steps", res, r.newton_its);
+            }
+            // R = u^(Nt) - u0;  (Phi - I) Delta = R;  u0 <- u0 - Delta
+            lincomb(1.0, tu + (int64_t)Nt * Nu, -1.0, u0, wd);
+            int k0 = r.krylov_its;
+            outer_gmres(true, wd, eta, r.krylov_its);
+            axpby(-1.0, wf, 1.0, u0);
+            ++r.newton_its;
+            if (verbose)
+                fprintf(stderr, "[pa] shoot it %d |R| = %.3e krylov %d (rel %.2e) %.1f s\n", r.newton_its, res,
+                        r.krylov_its - k0, last_outer_rel, (now_ms() - t0) / 1e3);
+        }
+        r.stage_newton_its = (int32_t)cnt_newton;
+        r.stage_gmres_its = cnt_gmres;
+        r.ms = now_ms() - t0;
+        if (rep) *rep = r;
+    }
+
+    // Outer matrix-free GMRES on (Phi - I) (tangent_op) or (Phi^T - I), zero
+    // initial guess, no restart; rhs copied first, solution written to wf.
+    // The sweeps' work vectors are disjoint from the outer buffers.
+    void outer_gmres(bool tangent_op, const double* rhs, double rtol, int32_t& its_acc)
+    {
+        copy(rhs, outer_rhs);
+        auto A = [&](const double* v, double* out) {
+            if (tangent_op) tangent(v, out);
+            else adjoint(v, -1, out, nullptr);
+            axpby(-1.0, v, 1.0, out);
+        };
+        double rr;
+        int its = gmres(A, nullptr, outer_rhs, outer_x, rtol, max_kry, max_kry, Vo, outer_w, outer_z, &rr, false);
+        its_acc += its;
+        last_outer_rel = rr;
+        copy(outer_x, wf);
+    }
+    double *outer_x = nullptr, *outer_w = nullptr, *outer_z = nullptr, *outer_rhs = nullptr, *lam_buf = nullptr;
+    double last_outer_rel = 0;
+
+    void adjoint_gradient(double rtol, double qoi[2], double dJ[6], pa_adjoint_report* rep) override
+    {
+        if (!have_traj) raise(PA_ESTATE, "no trajectory (run pa_primal_period or pa_shoot first)");
+        double t0 = now_ms();
+        int64_t g0 = cnt_gmres;
+        pa_adjoint_report r{};
+        double* lamN = lam_buf;
+        for (int q = 0; q < 2; ++q) {
+            double grad[3];
+            // g_F: forced sweep from zero
+            zero(lamN);
+            adjoint(lamN, q, wd, grad);
+            ++r.sweeps;
+            axpby(-1.0, wd, 0.0, wd);   // b = -g_F  (dF/du^(Nt) = 0)
+            int its = 0;
+            outer_gmres(false, wd, rtol, its);
+            r.krylov_its[q] = its;
+            r.rel_res[q] = last_outer_rel;
+            if (verbose)
+                fprintf(stderr, "[pa] adjoint qoi %d: %d krylov its, rel res %.2e, %.1f s\n", q, its, last_outer_rel,
+                        (now_ms() - t0) / 1e3);
+            r.sweeps += its + 1;
+            copy(wf, lamN);
+            adjoint(lamN, q, wd, grad);
+            ++r.sweeps;
+            for (int k = 0; k < 3; ++k) dJ[3 * q + k] = grad[k];
+        }
+        if (qoi) {
+            // time-averaged QoIs of the stored trajectory
+            std::vector<double> h((size_t)nst * std::max(nwall, 1) * 2);
+            HIPCHK(hipMemcpy(h.data(), qh, sizeof(double) * h.size(), hipMemcpyDeviceToHost));
+            double J0 = 0, J1 = 0;
+            for (int s = 0; s < nst; ++s) {
+                double f0 = 0, f1 = 0;
+                for (int w = 0; w < nwall; ++w) { f0 += h[((size_t)s * nwall + w) * 2]; f1 += h[((size_t)s * nwall + w) * 2 + 1]; }
+                J0 += dt * rk.b[s % 3] * f0 / cfg.T;
+                J1 += dt * rk.b[s % 3] * f1 / cfg.T;
+            }
+            qoi[0] = J0;
+            qoi[1] = J1;
+        }
+        r.stage_gmres_its = cnt_gmres - g0;
+        r.ms = now_ms() - t0;
+        if (rep) *rep = r;
+    }
+
+    // ---------------------------------------------------------------- host-vector wrappers
+    void tangent_sweep_h(const double* v, double* out) override
+    {
+        HIPCHK(hipMemcpy(wd, v, sizeof(double) * Nu, hipMemcpyHostToDevice));
+        tangent(wd, wf);
+        HIPCHK(hipMemcpy(out, wf, sizeof(double) * Nu, hipMemcpyDeviceToHost));
+    }
+    void adjoint_sweep_h(const double* lamh, int fq, double* lam0, double* grad) override
+    {
+        HIPCHK(hipMemcpy(wd, lamh, sizeof(double) * Nu, hipMemcpyHostToDevice));
+        adjoint(wd, fq, wf, grad);
+        HIPCHK(hipMemcpy(lam0, wf, sizeof(double) * Nu, hipMemcpyDeviceToHost));
+    }
+
+    // ---------------------------------------------------------------- debug entry points
+    void dbg_gbar(int n, int i, double* out, bool deriv) override
+    {
+        check_stage(n, i);
+        if (deriv) HIPCHK(hipMemcpy(out, dgbs(n, i), sizeof(double) * 3 * nn, hipMemcpyDeviceToHost));
+        else HIPCHK(hipMemcpy(out, gbs(n, i), sizeof(double) * nn, hipMemcpyDeviceToHost));
+    }
+    void dbg_residual(int n, int i, const double* u, double* r, bool dmu) override
+    {
+        check_stage(n, i);
+        HIPCHK(hipMemcpy(wd, u, sizeof(double) * Nu, hipMemcpyHostToDevice));
+        if (dmu) {
+            dr_dmu(n, i, wd, drm);
+            HIPCHK(hipStreamSynchronize(st));
+            HIPCHK(hipMemcpy(r, drm, sizeof(double) * 3 * Nu, hipMemcpyDeviceToHost));
+        } else {
+            residual(n, i, wd, wf);
+            HIPCHK(hipStreamSynchronize(st));
+            HIPCHK(hipMemcpy(r, wf, sizeof(double) * Nu, hipMemcpyDeviceToHost));
+        }
+    }
+    void dbg_jacobian(int n, int i, const double* u, double* blk) override
+    {
+        check_stage(n, i);
+        HIPCHK(hipMemcpy(wd, u, sizeof(double) * Nu, hipMemcpyHostToDevice));
+        jacobian(n, i, wd, tJ);
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipMemcpy(blk, tJ, sizeof(double) * Jsz, hipMemcpyDeviceToHost));
+        have_traj = false;
+    }
+    void dbg_qoi(int n, int i, const double* u, double f[2], double* dfdu, double* dfdmu) override
+    {
+        check_stage(n, i);
+        HIPCHK(hipMemcpy(wd, u, sizeof(double) * Nu, hipMemcpyHostToDevice));
+        double fv[2] = { 0, 0 };
+        if (dfdu) {
+            for (int q = 0; q < 2; ++q) {
+                qoi_grad(n, i, wd, q, wf, qtmp);
+                HIPCHK(hipStreamSynchronize(st));
+                HIPCHK(hipMemcpy(dfdu + (int64_t)q * Nu, wf, sizeof(double) * Nu, hipMemcpyDeviceToHost));
+            }
+        }
+        double fm[6];
+        qoi_dmu(n, i, wd, fm, fv);
+        if (f) { f[0] = fv[0]; f[1] = fv[1]; }
+        if (dfdmu) std::memcpy(dfdmu, fm, sizeof fm);
+    }
+    void dbg_bsr_apply(const double* blk, double alpha, double beta, int tr, const double* x, double* y) override
+    {
+        HIPCHK(hipMemcpy(tJ, blk, sizeof(double) * Jsz, hipMemcpyHostToDevice));
+        HIPCHK(hipMemcpy(wd, x, sizeof(double) * Nu, hipMemcpyHostToDevice));
+        bsr(tJ, alpha, beta, tr, wd, wf);
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipMemcpy(y, wf, sizeof(double) * Nu, hipMemcpyDeviceToHost));
+        have_traj = false;
+    }
+    void dbg_blockinv(const double* blk, double adt, double* out) override
+    {
+        HIPCHK(hipMemcpy(tJ, blk, sizeof(double) * Jsz, hipMemcpyHostToDevice));
+        HIPCHK(hipMemsetAsync(dstatus, 0, sizeof(int), st));
+        blockinv(tJ, adt, tAi);
+        int stt = 0;
+        HIPCHK(hipMemcpyAsync(&stt, dstatus, sizeof(int), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        if (stt) raise(PA_ENUMERIC, "singular diagonal block");
+        HIPCHK(hipMemcpy(out, tAi, sizeof(double) * Isz, hipMemcpyDeviceToHost));
+        have_traj = false;
+    }
+    int dbg_stage_solve(const double* blk, double adt, int tr, const double* rhs, double* x) override
+    {
+        HIPCHK(hipMemcpy(tJ, blk, sizeof(double) * Jsz, hipMemcpyHostToDevice));
+        blockinv(tJ, adt, tAi);
+        HIPCHK(hipMemcpy(wd, rhs, sizeof(double) * Nu, hipMemcpyHostToDevice));
+        int its = stage_solve(tJ, tAi, adt, tr, wd, wc);
+        HIPCHK(hipStreamSynchronize(st));
+        HIPCHK(hipMemcpy(x, wc, sizeof(double) * Nu, hipMemcpyDeviceToHost));
+        have_traj = false;
+        return its;
+    }
+    int done_stages = 0;   // stages completed by the last (possibly failed) primal sweep
+    void dbg_traj(int which, int n, int i, double* out) override
+    {
+        // stages of a sweep that stopped early stay readable (diagnostics)
+        int need = which == 2 ? 3 * n : (n - 1) * 3 + i;
+        if (!have_traj && need > done_stages) raise(PA_ESTATE, "no trajectory");
+        const double* src;
+        if (which == 2) {
+            if (n < 0 || n > Nt) raise(PA_EINVAL, "bad step");
+            src = tu + (int64_t)n * Nu;
+        } else {
+            if (n < 1 || n > Nt || i < 1 || i > 3) raise(PA_EINVAL, "bad stage");
+            int s = (n - 1) * 3 + (i - 1);
+            src = which == 0 ? stU(s) : stK(s);
+        }
+        HIPCHK(hipMemcpy(out, src, sizeof(double) * Nu, hipMemcpyDeviceToHost));
+    }
+    double bench_spmv(int reps, int tr) override
+    {
+        if (!have_traj) raise(PA_ESTATE, "no trajectory");
+        hipEvent_t a, b;
+        HIPCHK(hipEventCreate(&a));
+        HIPCHK(hipEventCreate(&b));
+        double c = dt * rk.A[0][0];
+        bsr(stJ(0), 1.0, -c, tr, u0, wf);
+        HIPCHK(hipEventRecord(a, st));
+        for (int r = 0; r < reps; ++r) k_bsr_apply<NP><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, dm.area, dmh, stJ(0), u0, wf, 1.0, -c, tr);
+        LAUNCHCHK();
+        HIPCHK(hipEventRecord(b, st));
+        HIPCHK(hipEventSynchronize(b));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, a, b));
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        return ms / reps;
+    }
+
+    int64_t num_dofs() const override { return Nu; }
+    int32_t num_elems() const override { return Ne; }
+    int32_t block_size() const override { return B; }
+    int64_t device_bytes() const override { return bytes; }
+    void get_mesh(int32_t* a, int32_t* b, int8_t* c, double* d) const override
+    {
+        if (a) std::memcpy(a, ev.data(), sizeof(int32_t) * ev.size());
+        if (b) std::memcpy(b, enb.data(), sizeof(int32_t) * enb.size());
+        if (c) std::memcpy(c, etw.data(), sizeof(int8_t) * etw.size());
+        if (d) std::memcpy(d, vxy.data(), sizeof(double) * vxy.size());
+    }
+};
+
+pa_status guard(pa_ctx* c, const std::function<void()>& f)
+{
+    if (!c) return PA_EINVAL;
+    try {
+        f();
+        return PA_OK;
+    } catch (const PaError& e) {
+        c->err = e.msg;
+        return e.code;
+    } catch (const std::exception& e) {
+        c->err = e.what();
+        return PA_EDEVICE;
+    }
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+void pa_default_config(pa_config* c)
+{
+    std::memset(c, 0, sizeof *c);
+    c->Nr = 8; c->Nth = 24; c->p = 1; c->Nt = 20;
+    c->r_far = 10.0; c->stretch = 1.3;
+    c->mach = 0.2; c->re = 1000.0; c->gamma = 1.4; c->pr = 0.72;
+    c->T = 1.0; c->r_blend0 = 2.0; c->r_blend1 = 8.0;
+    c->wall_is_farfield = 0;
+    c->gmres_restart = 30; c->lin_rtol = 1e-10;
+    c->newton_atol = 1e-10; c->newton_maxit = 20;
+    c->max_krylov = 100;
+    c->device = 0;
+}
+
+static thread_local std::string g_create_err;
+
+pa_status pa_create(const pa_config* cfg, pa_ctx** out)
+{
+    if (!out) return PA_EINVAL;
+    *out = nullptr;
+    if (!cfg || cfg->Nr < 1 || cfg->Nth < 3 || cfg->p < 1 || cfg->p > 3 || cfg->Nt < 1 || cfg->gmres_restart < 1 ||
+        cfg->gmres_restart > 64 || cfg->max_krylov < 1 || cfg->max_krylov > 126 || !(cfg->r_far > 1.0) ||
+        !(cfg->stretch > 0.0) || !(cfg->T > 0.0)) {
+        g_create_err = "invalid configuration";
+        return PA_EINVAL;
+    }
+    try {
+        pa_ctx* c = nullptr;
+        switch (cfg->p) {
+        case 1: c = new Solver<1>(*cfg); break;
+        case 2: c = new Solver<2>(*cfg); break;
+        default: c = new Solver<3>(*cfg); break;
+        }
+        *out = c;
+        return PA_OK;
+    } catch (const PaError& e) {
+        g_create_err = e.msg;
+        return e.code;
+    } catch (const std::exception& e) {
+        g_create_err = e.what();
+        return PA_EDEVICE;
+    }
+}
+
+void pa_destroy(pa_ctx* c) { delete c; }
+const char* pa_last_error(const pa_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
+int64_t pa_num_dofs(const pa_ctx* c) { return c ? c->num_dofs() : -1; }
+int32_t pa_num_elems(const pa_ctx* c) { return c ? c->num_elems() : -1; }
+int32_t pa_block_size(const pa_ctx* c) { return c ? c->block_size() : -1; }
+int64_t pa_device_bytes(const pa_ctx* c) { return c ? c->device_bytes() : -1; }
+
+pa_status pa_get_mesh(const pa_ctx* c, int32_t* a, int32_t* b, int8_t* t, double* v)
+{
+    if (!c) return PA_EINVAL;
+    c->get_mesh(a, b, t, v);
+    return PA_OK;
+}
+pa_status pa_set_params(pa_ctx* c, const double mu[3])
+{
+    return guard(c, [&] { if (!mu) raise(PA_EINVAL, "null mu"); c->set_params(mu); });
+}
+pa_status pa_set_state(pa_ctx* c, const double* u0, int64_t n)
+{
+    return guard(c, [&] { if (!u0) raise(PA_EINVAL, "null state"); c->set_state(u0, n); });
+}
+pa_status pa_set_freestream(pa_ctx* c, const double* pert) { return guard(c, [&] { c->set_freestream(pert); }); }
+pa_status pa_get_state(pa_ctx* c, int32_t which, double* out, int64_t n)
+{
+    return guard(c, [&] { if (!out) raise(PA_EINVAL, "null output"); c->get_state(which, out, n); });
+}
+pa_status pa_primal_period(pa_ctx* c, double qoi[2], double* res)
+{
+    return guard(c, [&] { c->primal_period(qoi, res); });
+}
+pa_status pa_shoot(pa_ctx* c, double tol, double eta, int32_t maxit, pa_shoot_report* rep)
+{
+    return guard(c, [&] {
+        if (!(tol > 0) || !(eta > 0) || maxit < 0) raise(PA_EINVAL, "bad shooting options");
+        c->shoot(tol, eta, maxit, rep);
+    });
+}
+pa_status pa_adjoint_gradient(pa_ctx* c, double rtol, double qoi[2], double dJ[6], pa_adjoint_report* rep)
+{
+    return guard(c, [&] {
+        if (!dJ || !(rtol > 0)) raise(PA_EINVAL, "bad arguments");
+        c->adjoint_gradient(rtol, qoi, dJ, rep);
+    });
+}
+pa_status pa_tangent_sweep(pa_ctx* c, const double* v, double* out)
+{
+    return guard(c, [&] { if (!v || !out) raise(PA_EINVAL, "null vector"); c->tangent_sweep_h(v, out); });
+}
+pa_status pa_adjoint_sweep(pa_ctx* c, const double* lam, int32_t fq, double* lam0, double* grad)
+{
+    return guard(c, [&] {
+        if (!lam || !lam0 || fq > 1 || (fq >= 0 && !grad)) raise(PA_EINVAL, "bad arguments");
+        c->adjoint_sweep_h(lam, fq, lam0, grad);
+    });
+}
+pa_status pa_dbg_gbar(pa_ctx* c, int32_t n, int32_t i, double* out)
+{
+    return guard(c, [&] { c->dbg_gbar(n, i, out, false); });
+}
+pa_status pa_dbg_dgbar(pa_ctx* c, int32_t n, int32_t i, double* out)
+{
+    return guard(c, [&] { c->dbg_gbar(n, i, out, true); });
+}
+pa_status pa_dbg_residual(pa_ctx* c, int32_t n, int32_t i, const double* u, double* r)
+{
+    return guard(c, [&] { c->dbg_residual(n, i, u, r, false); });
+}
+pa_status pa_dbg_jacobian(pa_ctx* c, int32_t n, int32_t i, const double* u, double* blk)
+{
+    return guard(c, [&] { c->dbg_jacobian(n, i, u, blk); });
+}
+pa_status pa_dbg_dr_dmu(pa_ctx* c, int32_t n, int32_t i, const double* u, double* out)
+{
+    return guard(c, [&] { c->dbg_residual(n, i, u, out, true); });
+}
+pa_status pa_dbg_qoi(pa_ctx* c, int32_t n, int32_t i, const double* u, double f[2], double* dfdu, double* dfdmu)
+{
+    return guard(c, [&] { c->dbg_qoi(n, i, u, f, dfdu, dfdmu); });
+}
+pa_status pa_dbg_bsr_apply(pa_ctx* c, const double* blk, double alpha, double beta, int32_t tr, const double* x,
+                           double* y)
+{
+    return guard(c, [&] { c->dbg_bsr_apply(blk, alpha, beta, tr, x, y); });
+}
+pa_status pa_dbg_blockinv(pa_ctx* c, const double* blk, double adt, double* out)
+{
+    return guard(c, [&] { c->dbg_blockinv(blk, adt, out); });
+}
+pa_status pa_dbg_stage_solve(pa_ctx* c, const double* blk, double adt, int32_t tr, const double* rhs, double* x,
+                             int32_t* iters)
+{
+    return guard(c, [&] {
+        int its = c->dbg_stage_solve(blk, adt, tr, rhs, x);
+        if (iters) *iters = its;
+    });
+}
+pa_status pa_dbg_traj(pa_ctx* c, int32_t which, int32_t n, int32_t i, double* out)
+{
+    return guard(c, [&] { c->dbg_traj(which, n, i, out); });
+}
+pa_status pa_set_timing(pa_ctx* c, int32_t on) { return guard(c, [&] { c->set_timing(on != 0); }); }
+pa_status pa_kernel_time(pa_ctx* c, int32_t k, double* ms, int64_t* cnt)
+{
+    return guard(c, [&] { c->kernel_time(k, ms, cnt); });
+}
+pa_status pa_bench_spmv(pa_ctx* c, int32_t reps, int32_t tr, double* avg)
+{
+    return guard(c, [&] {
+        if (reps < 1 || !avg) raise(PA_EINVAL, "bad arguments");
+        *avg = c->bench_spmv(reps, tr);
+    });
+}
+
+}  // extern "C"

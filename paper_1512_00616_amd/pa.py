@@ -1,0 +1,298 @@
+"""Python binding of libpa.so (the HIP library).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels and its C++ orchestrator.  There is no CPU fallback -- importing
+this module without a built ``libpa.so`` raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpa.so")
+
+PA_OK, PA_EINVAL, PA_ENOMEM, PA_EDEVICE, PA_ENOCONV, PA_ENUMERIC, PA_ESTATE = 0, -1, -2, -3, -4, -5, -6
+PA_K_SPMV, PA_K_PRECOND, PA_K_JACOBIAN, PA_K_RESIDUAL, PA_K_BLOCKINV = range(5)
+
+EXPORTED = [
+    "pa_default_config", "pa_create", "pa_destroy", "pa_last_error", "pa_num_dofs", "pa_num_elems",
+    "pa_block_size", "pa_device_bytes", "pa_get_mesh", "pa_set_params", "pa_set_state", "pa_set_freestream",
+    "pa_get_state", "pa_primal_period", "pa_shoot", "pa_adjoint_gradient", "pa_tangent_sweep",
+    "pa_adjoint_sweep", "pa_dbg_gbar", "pa_dbg_dgbar", "pa_dbg_residual", "pa_dbg_jacobian", "pa_dbg_dr_dmu",
+    "pa_dbg_qoi", "pa_dbg_bsr_apply", "pa_dbg_blockinv", "pa_dbg_stage_solve", "pa_dbg_traj", "pa_set_timing",
+    "pa_kernel_time", "pa_bench_spmv",
+]
+
+
+class pa_config(C.Structure):
+    _fields_ = [
+        ("Nr", C.c_int32), ("Nth", C.c_int32), ("p", C.c_int32), ("Nt", C.c_int32),
+        ("r_far", C.c_double), ("stretch", C.c_double),
+        ("mach", C.c_double), ("re", C.c_double), ("gamma", C.c_double), ("pr", C.c_double),
+        ("T", C.c_double), ("r_blend0", C.c_double), ("r_blend1", C.c_double),
+        ("wall_is_farfield", C.c_int32), ("gmres_restart", C.c_int32), ("lin_rtol", C.c_double),
+        ("newton_atol", C.c_double), ("newton_maxit", C.c_int32), ("max_krylov", C.c_int32),
+        ("device", C.c_int32),
+    ]
+
+
+class pa_shoot_report(C.Structure):
+    _fields_ = [("newton_its", C.c_int32), ("krylov_its", C.c_int32), ("primal_sweeps", C.c_int32),
+                ("stage_newton_its", C.c_int32), ("stage_gmres_its", C.c_int64), ("res0", C.c_double),
+                ("res", C.c_double), ("ms", C.c_double)]
+
+
+class pa_adjoint_report(C.Structure):
+    _fields_ = [("krylov_its", C.c_int32 * 2), ("sweeps", C.c_int32), ("stage_gmres_its", C.c_int64),
+                ("rel_res", C.c_double * 2), ("ms", C.c_double)]
+
+
+class PaError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("libpa error %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+
+
+def lib():
+    """Load libpa.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("HIP library not built: %s -- run __graft_entry__.build()" % LIB_PATH)
+        L = C.CDLL(LIB_PATH)
+        P = C.c_void_p
+        L.pa_default_config.argtypes = [C.POINTER(pa_config)]
+        L.pa_create.argtypes = [C.POINTER(pa_config), C.POINTER(C.c_void_p)]
+        L.pa_destroy.argtypes = [P]
+        L.pa_last_error.argtypes = [P]
+        L.pa_last_error.restype = C.c_char_p
+        for fn in ("pa_num_dofs", "pa_device_bytes"):
+            getattr(L, fn).argtypes = [P]
+            getattr(L, fn).restype = C.c_int64
+        for fn in ("pa_num_elems", "pa_block_size"):
+            getattr(L, fn).argtypes = [P]
+            getattr(L, fn).restype = C.c_int32
+        sig = {
+            "pa_create": None,
+            "pa_get_mesh": [P, P, P, P, P],
+            "pa_set_params": [P, P],
+            "pa_set_state": [P, P, C.c_int64],
+            "pa_set_freestream": [P, P],
+            "pa_get_state": [P, C.c_int32, P, C.c_int64],
+            "pa_primal_period": [P, P, P],
+            "pa_shoot": [P, C.c_double, C.c_double, C.c_int32, P],
+            "pa_adjoint_gradient": [P, C.c_double, P, P, P],
+            "pa_tangent_sweep": [P, P, P],
+            "pa_adjoint_sweep": [P, P, C.c_int32, P, P],
+            "pa_dbg_gbar": [P, C.c_int32, C.c_int32, P],
+            "pa_dbg_dgbar": [P, C.c_int32, C.c_int32, P],
+            "pa_dbg_residual": [P, C.c_int32, C.c_int32, P, P],
+            "pa_dbg_jacobian": [P, C.c_int32, C.c_int32, P, P],
+            "pa_dbg_dr_dmu": [P, C.c_int32, C.c_int32, P, P],
+            "pa_dbg_qoi": [P, C.c_int32, C.c_int32, P, P, P, P],
+            "pa_dbg_bsr_apply": [P, P, C.c_double, C.c_double, C.c_int32, P, P],
+            "pa_dbg_blockinv": [P, P, C.c_double, P],
+            "pa_dbg_stage_solve": [P, P, C.c_double, C.c_int32, P, P, P],
+            "pa_dbg_traj": [P, C.c_int32, C.c_int32, C.c_int32, P],
+            "pa_set_timing": [P, C.c_int32],
+            "pa_kernel_time": [P, C.c_int32, P, P],
+            "pa_bench_spmv": [P, C.c_int32, C.c_int32, P],
+        }
+        for fn, args in sig.items():
+            f = getattr(L, fn)
+            if args is not None:
+                f.argtypes = args
+            f.restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _ptr(a):
+    if a is None:
+        return None
+    assert a.flags["C_CONTIGUOUS"]
+    return a.ctypes.data_as(C.c_void_p)
+
+
+def default_config(**kw):
+    cfg = pa_config()
+    lib().pa_default_config(C.byref(cfg))
+    for k, v in kw.items():
+        if not hasattr(cfg, k):
+            raise KeyError(k)
+        setattr(cfg, k, v)
+    return cfg
+
+
+class Solver:
+    """One discretised problem on one GPU (a ``pa_ctx``)."""
+
+    def __init__(self, **kw):
+        self.cfg = default_config(**kw)
+        h = C.c_void_p()
+        rc = lib().pa_create(C.byref(self.cfg), C.byref(h))
+        if rc != PA_OK:
+            raise PaError(rc, lib().pa_last_error(None).decode())
+        self._c = h
+        self.Nu = lib().pa_num_dofs(h)
+        self.Ne = lib().pa_num_elems(h)
+        self.b = lib().pa_block_size(h)
+        self.np = self.b // 4
+        self.Nt = self.cfg.Nt
+
+    def close(self):
+        if getattr(self, "_c", None):
+            lib().pa_destroy(self._c)
+            self._c = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _chk(self, rc):
+        if rc != PA_OK:
+            raise PaError(rc, lib().pa_last_error(self._c).decode())
+
+    def _vec(self, x, n=None):
+        x = np.ascontiguousarray(x, dtype=np.float64)
+        assert x.size == (self.Nu if n is None else n)
+        return x
+
+    @property
+    def device_bytes(self):
+        return lib().pa_device_bytes(self._c)
+
+    def mesh(self):
+        ev = np.zeros(self.Ne * 3, np.int32)
+        en = np.zeros(self.Ne * 3, np.int32)
+        tw = np.zeros(self.Ne * 3, np.int8)
+        vxy = np.zeros((self.cfg.Nr + 1) * self.cfg.Nth * 2)
+        self._chk(lib().pa_get_mesh(self._c, _ptr(ev), _ptr(en), _ptr(tw), _ptr(vxy)))
+        return ev.reshape(-1, 3), en.reshape(-1, 3), tw.reshape(-1, 3), vxy.reshape(-1, 2)
+
+    def set_params(self, mu):
+        self._chk(lib().pa_set_params(self._c, _ptr(self._vec(mu, 3))))
+
+    def set_state(self, u0):
+        u0 = self._vec(u0)
+        self._chk(lib().pa_set_state(self._c, _ptr(u0), self.Nu))
+
+    def set_freestream(self, perturb=None):
+        pp = None if perturb is None else self._vec(perturb)
+        self._chk(lib().pa_set_freestream(self._c, _ptr(pp)))
+
+    def get_state(self, which=0):
+        out = np.zeros(self.Nu)
+        self._chk(lib().pa_get_state(self._c, which, _ptr(out), self.Nu))
+        return out
+
+    def primal_period(self):
+        q = np.zeros(2)
+        r = np.zeros(1)
+        self._chk(lib().pa_primal_period(self._c, _ptr(q), _ptr(r)))
+        return q, float(r[0])
+
+    def shoot(self, tol=1e-8, eta=1e-3, maxit=30):
+        rep = pa_shoot_report()
+        self._chk(lib().pa_shoot(self._c, tol, eta, maxit, C.byref(rep)))
+        return rep
+
+    def adjoint_gradient(self, rtol=1e-8):
+        q = np.zeros(2)
+        g = np.zeros(6)
+        rep = pa_adjoint_report()
+        self._chk(lib().pa_adjoint_gradient(self._c, rtol, _ptr(q), _ptr(g), C.byref(rep)))
+        return q, g.reshape(2, 3), rep
+
+    def tangent_sweep(self, v):
+        v = self._vec(v)
+        out = np.zeros(self.Nu)
+        self._chk(lib().pa_tangent_sweep(self._c, _ptr(v), _ptr(out)))
+        return out
+
+    def adjoint_sweep(self, lam, forced_qoi=-1):
+        lam = self._vec(lam)
+        out = np.zeros(self.Nu)
+        g = np.zeros(3)
+        self._chk(lib().pa_adjoint_sweep(self._c, _ptr(lam), forced_qoi, _ptr(out), _ptr(g)))
+        return (out, g) if forced_qoi >= 0 else out
+
+    # unit-level parity entry points
+    def gbar(self, n, i):
+        out = np.zeros(self.Ne * self.np)
+        self._chk(lib().pa_dbg_gbar(self._c, n, i, _ptr(out)))
+        return out
+
+    def dgbar(self, n, i):
+        out = np.zeros(3 * self.Ne * self.np)
+        self._chk(lib().pa_dbg_dgbar(self._c, n, i, _ptr(out)))
+        return out.reshape(3, -1)
+
+    def residual(self, n, i, u):
+        r = np.zeros(self.Nu)
+        self._chk(lib().pa_dbg_residual(self._c, n, i, _ptr(self._vec(u)), _ptr(r)))
+        return r
+
+    def jacobian(self, n, i, u):
+        blk = np.zeros(self.Ne * 4 * self.b * self.b)
+        self._chk(lib().pa_dbg_jacobian(self._c, n, i, _ptr(self._vec(u)), _ptr(blk)))
+        return blk.reshape(self.Ne, 4, self.b, self.b)
+
+    def dr_dmu(self, n, i, u):
+        out = np.zeros(3 * self.Nu)
+        self._chk(lib().pa_dbg_dr_dmu(self._c, n, i, _ptr(self._vec(u)), _ptr(out)))
+        return out.reshape(3, self.Nu)
+
+    def qoi(self, n, i, u):
+        f = np.zeros(2)
+        dfdu = np.zeros(2 * self.Nu)
+        dfdmu = np.zeros(6)
+        self._chk(lib().pa_dbg_qoi(self._c, n, i, _ptr(self._vec(u)), _ptr(f), _ptr(dfdu), _ptr(dfdmu)))
+        return f, dfdu.reshape(2, self.Nu), dfdmu.reshape(2, 3)
+
+    def bsr_apply(self, blk, x, alpha=0.0, beta=1.0, transpose=False):
+        blk = self._vec(blk, self.Ne * 4 * self.b * self.b)
+        y = np.zeros(self.Nu)
+        self._chk(lib().pa_dbg_bsr_apply(self._c, _ptr(blk), alpha, beta, int(transpose), _ptr(self._vec(x)),
+                                         _ptr(y)))
+        return y
+
+    def blockinv(self, blk, a_dt):
+        blk = self._vec(blk, self.Ne * 4 * self.b * self.b)
+        out = np.zeros(self.Ne * self.b * self.b)
+        self._chk(lib().pa_dbg_blockinv(self._c, _ptr(blk), a_dt, _ptr(out)))
+        return out.reshape(self.Ne, self.b, self.b)
+
+    def stage_solve(self, blk, a_dt, rhs, transpose=False):
+        blk = self._vec(blk, self.Ne * 4 * self.b * self.b)
+        x = np.zeros(self.Nu)
+        its = C.c_int32()
+        self._chk(lib().pa_dbg_stage_solve(self._c, _ptr(blk), a_dt, int(transpose), _ptr(self._vec(rhs)),
+                                           _ptr(x), C.byref(its)))
+        return x, its.value
+
+    def traj(self, which, n, i=1):
+        out = np.zeros(self.Nu)
+        self._chk(lib().pa_dbg_traj(self._c, which, n, i, _ptr(out)))
+        return out
+
+    # measurement
+    def set_timing(self, on):
+        self._chk(lib().pa_set_timing(self._c, int(on)))
+
+    def kernel_time(self, k):
+        ms = C.c_double()
+        cnt = C.c_int64()
+        self._chk(lib().pa_kernel_time(self._c, k, C.byref(ms), C.byref(cnt)))
+        return ms.value, cnt.value
+
+    def bench_spmv(self, reps=50, transpose=False):
+        ms = C.c_double()
+        self._chk(lib().pa_bench_spmv(self._c, reps, int(transpose), C.byref(ms)))
+        return ms.value

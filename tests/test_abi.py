@@ -1,0 +1,33 @@
+"""The C-ABI library loads and exports every symbol its header declares
+(no compute calls: runs without a GPU)."""
+import ctypes
+import os
+import re
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    src = open(os.path.join(ROOT, "include", "pa.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(pa_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_the_binding_surface():
+    from paper_1512_00616_amd import pa
+    assert sorted(pa.EXPORTED) == header_symbols()
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_1512_00616_amd import pa
+    lib = ctypes.CDLL(pa.LIB_PATH)
+    missing = [s for s in header_symbols() if not hasattr(lib, s)]
+    assert not missing, missing
+
+
+def test_oracle_library_exports_its_header():
+    src = open(os.path.join(ROOT, "oracle", "oracle.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    syms = sorted(set(re.findall(r"\b(pao_[a-z_0-9]+)\s*\(", src)))
+    lib = ctypes.CDLL(os.path.join(ROOT, "oracle", "liboracle.so"))
+    assert [s for s in syms if not hasattr(lib, s)] == []

@@ -1,0 +1,212 @@
+"""Parity of the HIP library (through its C ABI) against the CPU oracle.
+
+Every comparison feeds both sides the same seeded inputs; the oracle computes
+its own mesh, GCL field, residuals and derivatives.  Bars: integer
+connectivity bit-exact; floating point within the stated relative tolerance
+(max abs difference over max abs value).
+"""
+import numpy as np
+import pytest
+
+from paper_1512_00616_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+MU = np.array(inputs.MU_NOMINAL)
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def libs():
+    from paper_1512_00616_amd import pa
+    from oracle import oracle as O
+    pa.lib()
+    O.lib()
+    return pa, O
+
+
+def make_pair(libs, gpu_kw=None, orc_kw=None, **kw):
+    pa, O = libs
+    g = pa.Solver(**dict(kw, **(gpu_kw or {})))
+    o = O.Oracle(**dict(kw, **(orc_kw or {})))
+    g.set_params(MU)
+    o.set_params(MU)
+    return g, o
+
+
+# ---------------------------------------------------------------- mesh
+@pytest.mark.parametrize("Nr,Nth,p", [(8, 24, 1), (32, 96, 3), (3, 7, 2)])
+def test_mesh_connectivity_bit_exact(libs, Nr, Nth, p):
+    pa, O = libs
+    g = pa.Solver(Nr=Nr, Nth=Nth, p=p, Nt=1)
+    o = O.Oracle(Nr=Nr, Nth=Nth, p=p, Nt=1)
+    for a, b in zip(g.mesh()[:3], o.mesh()[:3]):
+        assert a.dtype == b.dtype and np.array_equal(a, b)
+    assert np.abs(g.mesh()[3] - o.mesh()[3]).max() <= 1e-14
+
+
+# ---------------------------------------------------------------- GCL field
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_gbar_parity(libs, p):
+    g, o = make_pair(libs, Nr=3, Nth=8, p=p, Nt=4)
+    for n, i in [(0, 0), (1, 1), (2, 3), (4, 3)]:
+        assert rel(g.gbar(n, i), o.gbar(n, i)) <= 1e-12
+
+
+# ---------------------------------------------------------------- residual and derivatives
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_residual_parity(libs, p):
+    g, o = make_pair(libs, Nr=3, Nth=8, p=p, Nt=4)
+    u = o.freestream(inputs.perturbation(o.Nu, seed=11, sigma=1e-2))
+    for n, i in [(0, 0), (1, 1), (3, 2)]:
+        assert rel(g.residual(n, i, u), o.residual(n, i, u)) <= 1e-12
+
+
+def test_residual_parity_wall_as_farfield(libs):
+    g, o = make_pair(libs, Nr=3, Nth=8, p=2, Nt=4, wall_is_farfield=1)
+    u = o.freestream(inputs.perturbation(o.Nu, seed=12, sigma=1e-2))
+    assert rel(g.residual(2, 2, u), o.residual(2, 2, u)) <= 1e-12
+
+
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_jacobian_parity(libs, p):
+    g, o = make_pair(libs, Nr=3, Nth=8, p=p, Nt=4)
+    u = o.freestream(inputs.perturbation(o.Nu, seed=13, sigma=1e-2))
+    Jg = g.jacobian(2, 1, u)
+    Jo = o.jacobian(2, 1, u)
+    assert rel(Jg, Jo) <= 1e-11
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_dr_dmu_parity(libs, p):
+    g, o = make_pair(libs, Nr=3, Nth=8, p=p, Nt=4)
+    u = o.freestream(inputs.perturbation(o.Nu, seed=14, sigma=1e-2))
+    dg = g.dr_dmu(1, 3, u)
+    do = o.dr_dmu(1, 3, u)
+    for k in range(3):
+        assert rel(dg[k], do[k]) <= 1e-10
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_qoi_parity(libs, p):
+    g, o = make_pair(libs, Nr=3, Nth=8, p=p, Nt=4)
+    u = o.freestream(inputs.perturbation(o.Nu, seed=15, sigma=1e-2))
+    fg, dug, dmg = g.qoi(2, 2, u)
+    fo, duo, dmo = o.qoi(2, 2, u, derivs=True)
+    # the net force is a small difference of O(p_inf |wall|) pressure terms
+    assert np.abs(fg - fo).max() <= 1e-12 * 20.0 * 2 * np.pi
+    assert rel(dug, duo) <= 1e-11
+    assert rel(dmg, dmo) <= 1e-9
+
+
+# ---------------------------------------------------------------- linear algebra
+@pytest.mark.parametrize("p", [1, 2, 3])
+def test_bsr_apply_parity(libs, p):
+    g, o = make_pair(libs, Nr=4, Nth=10, p=p, Nt=2)
+    u = o.freestream(inputs.perturbation(o.Nu, seed=16, sigma=1e-2))
+    J = o.jacobian(1, 1, u)
+    x, w = inputs.random_vectors(o.Nu, 2, seed=7)
+    for tr in (False, True):
+        yo = o.bsr_apply(J, x, transpose=tr)
+        assert rel(g.bsr_apply(J, x, transpose=tr), yo) <= 1e-13
+    c = 0.37
+    A = o.mass(x) - c * o.bsr_apply(J, x)
+    assert rel(g.bsr_apply(J, x, alpha=1.0, beta=-c), A) <= 1e-13
+    # transpose gather: <w, J x> = <J^T w, x>
+    lhs = w @ g.bsr_apply(J, x)
+    rhs = x @ g.bsr_apply(J, w, transpose=True)
+    assert abs(lhs - rhs) <= 1e-13 * abs(lhs)
+
+
+@pytest.mark.parametrize("p", [1, 3])
+def test_blockinv_inverts_diagonal_blocks(libs, p):
+    g, o = make_pair(libs, Nr=3, Nth=8, p=p, Nt=2)
+    u = o.freestream(inputs.perturbation(o.Nu, seed=17, sigma=1e-2))
+    J = o.jacobian(1, 1, u)
+    c = 0.01 * 0.4358665215084590
+    inv = g.blockinv(J, c)
+    _, _, _, mh = o.ref_tables()
+    _, area = o.nodes()
+    b = o.b
+    eye = np.eye(b)
+    for K in range(o.Ne):
+        M = 2 * area[K] * np.kron(mh, np.eye(4))
+        D = M - c * J[K, 0]
+        assert np.abs(D @ inv[K] - eye).max() <= 1e-11
+
+
+@pytest.mark.parametrize("tr", [False, True])
+def test_stage_solve_parity(libs, tr):
+    g, o = make_pair(libs, Nr=3, Nth=8, p=2, Nt=2, gpu_kw=dict(lin_rtol=1e-13), orc_kw=dict(lin_solver=0))
+    u = o.freestream(inputs.perturbation(o.Nu, seed=18, sigma=1e-2))
+    J = o.jacobian(1, 2, u)
+    c = 0.5 * 0.4358665215084590
+    rhs = inputs.random_vectors(o.Nu, 1, seed=19)[0]
+    xg, its = g.stage_solve(J, c, rhs, transpose=tr)
+    xo = o.stage_solve(J, c, rhs, transpose=tr)
+    assert its > 0
+    assert rel(xg, xo) <= 1e-10
+
+
+# ---------------------------------------------------------------- sweeps
+TIGHT_G = dict(lin_rtol=1e-13, newton_atol=1e-12)
+TIGHT_O = dict(lin_solver=0, newton_atol=1e-12)
+
+
+@pytest.fixture(scope="module")
+def period_pair(libs):
+    g, o = make_pair(libs, gpu_kw=TIGHT_G, orc_kw=TIGHT_O, Nr=2, Nth=6, p=2, Nt=8)
+    pert = inputs.perturbation(g.Nu, seed=1)
+    g.set_freestream(pert)
+    u0 = o.freestream(pert)
+    qg, rg = g.primal_period()
+    uNt, qo, ro = o.primal_period(u0)
+    return g, o, u0, (qg, rg), (uNt, qo, ro)
+
+
+def test_primal_period_parity(period_pair):
+    g, o, u0, (qg, rg), (uNt, qo, ro) = period_pair
+    assert rel(g.get_state(0), u0) <= 1e-14
+    assert rel(g.get_state(1), uNt) <= 1e-10
+    assert rel(qg, qo) <= 1e-10
+    assert abs(rg - ro) <= 1e-10 * ro
+    for n, i in [(1, 1), (2, 3), (8, 2)]:
+        assert rel(g.traj(0, n, i), o.traj(0, n, i)) <= 1e-10
+        assert rel(g.traj(1, n, i), o.traj(1, n, i)) <= 1e-9
+
+
+def test_tangent_and_adjoint_sweep_parity(period_pair):
+    g, o, *_ = period_pair
+    v, w = inputs.random_vectors(g.Nu, 2, seed=7)
+    tg = g.tangent_sweep(v)
+    assert rel(tg, o.tangent(v)) <= 1e-10
+    ag = g.adjoint_sweep(w)
+    assert rel(ag, o.adjoint(w)) <= 1e-10
+    # duality on the GPU alone: <w, Phi v> = <Phi^T w, v>
+    assert abs(w @ tg - ag @ v) <= 1e-11 * abs(w @ tg)
+    for q in (0, 1):
+        lg, gg = g.adjoint_sweep(w, forced_qoi=q)
+        lo, go = o.adjoint(w, forced_qoi=q)
+        assert rel(lg, lo) <= 1e-10
+        assert rel(gg, go) <= 1e-9
+
+
+def test_shoot_and_periodic_gradient_parity(libs):
+    g, o = make_pair(libs, gpu_kw=TIGHT_G, orc_kw=TIGHT_O, Nr=2, Nth=6, p=1, Nt=4)
+    pert = inputs.perturbation(g.Nu, seed=1)
+    g.set_freestream(pert)
+    rep = g.shoot(tol=1e-11, eta=1e-10, maxit=20)
+    assert rep.res <= 1e-11
+    us, orep = o.shoot(o.freestream(pert), tol=1e-11, eta=1e-10, maxit=20, max_krylov=300)
+    assert rel(g.get_state(0), us) <= 1e-9
+    qg, dJ, arep = g.adjoint_gradient(rtol=1e-12)
+    o.primal_period(us)
+    go = np.stack([o.periodic_adjoint(q, rtol=1e-13)[0] for q in (0, 1)])
+    assert rel(dJ, go) <= 1e-8
+    # and against the oracle's independent direct (tangent) gradient
+    assert rel(dJ, o.tangent_gradient(rtol=1e-13)) <= 1e-8
