@@ -122,6 +122,14 @@ typedef struct pa_shoot_report {
  * relative GMRES forcing eta.  On success u0 is periodic and the stored
  * trajectory belongs to it.  PA_ENOCONV leaves the last iterate and report. */
 pa_status pa_shoot(pa_ctx* ctx, double tol, double eta, int32_t maxit, pa_shoot_report* rep);
+/* (The Newton step u0 - lam Delta is globalised by backtracking, lam = 1,
+ * 1/2, ..., 1/64: a trial is accepted when its primal period succeeds and
+ * lowers ||u^(Nt) - u0||_2.) */
+
+/* Fixed-point iteration (Alg. 1) as a warm start: `periods` primal periods
+ * with u0 <- u^(Nt)(u0).  res (may be NULL) receives ||u^(Nt) - u0||_2 of
+ * the last period.  The stored trajectory is invalidated. */
+pa_status pa_fixed_point(pa_ctx* ctx, int32_t periods, double* res);
 
 typedef struct pa_adjoint_report {
     int32_t krylov_its[2];      /* outer GMRES iterations per QoI */

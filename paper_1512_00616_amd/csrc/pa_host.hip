@@ -256,6 +256,7 @@ struct pa_ctx {
     virtual void get_state(int which, double* out, int64_t n) = 0;
     virtual void primal_period(double qoi[2], double* res) = 0;
     virtual void shoot(double tol, double eta, int maxit, pa_shoot_report* rep) = 0;
+    virtual void fixed_point(int periods, double* res) = 0;
     virtual void adjoint_gradient(double rtol, double qoi[2], double dJ[6], pa_adjoint_report* rep) = 0;
     virtual void tangent_sweep_h(const double* v, double* out) = 0;
     virtual void adjoint_sweep_h(const double* lam, int fq, double* lam0, double* grad) = 0;
@@ -286,7 +287,7 @@ struct Solver final : pa_ctx {
     double mu[3] = { 0, 0, 0 };
     bool have_params = false, have_traj = false;
     int restart = 30, max_kry = 100;
-    bool verbose = false;   // PA_VERBOSE=1: per-stage Newton history on stderr
+    int verbose = 0;   // PA_VERBOSE=1: solver progress on stderr, 2: also per-stage Newton history
     int64_t bytes = 0;
 
     // host mesh
@@ -360,7 +361,7 @@ struct Solver final : pa_ctx {
         ph.lf_delta = 1e-2;
         ph.wall_eta = 10.0;
         const char* ve = std::getenv("PA_VERBOSE");
-        verbose = ve && ve[0] == '1';
+        verbose = ve ? std::atoi(ve) : 0;
         build_mesh();
         build_ref(href);
         upload();
@@ -371,6 +372,7 @@ struct Solver final : pa_ctx {
         if (st) (void)hipStreamSynchronize(st);
         for (auto& e : evpool) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
         for (void* p : allocs) (void)hipFree(p);
+        if (hstat) (void)hipHostFree(hstat);
         if (st) (void)hipStreamDestroy(st);
     }
 
@@ -471,11 +473,24 @@ struct Solver final : pa_ctx {
         nwall = (int)wall.size();
     }
 
+    // host <-> device copies are ordered on the library stream (which does not
+    // synchronise with the null stream) and complete before returning
+    void h2d(void* dst, const void* src, size_t bytes)
+    {
+        HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+    void d2h(void* dst, const void* src, size_t bytes)
+    {
+        HIPCHK(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+    }
+
     template <class T>
     T* upload_vec(const std::vector<T>& h)
     {
         T* d = dalloc<T>((int64_t)h.size());
-        HIPCHK(hipMemcpy(d, h.data(), sizeof(T) * h.size(), hipMemcpyHostToDevice));
+        h2d(d, h.data(), sizeof(T) * h.size());
         return d;
     }
 
@@ -492,7 +507,7 @@ struct Solver final : pa_ctx {
         dm.elen = upload_vec(elen);
         dm.enrm = upload_vec(enrm);
         dref = dalloc<Ref<P>>(1);
-        HIPCHK(hipMemcpy(dref, &href, sizeof(Ref<P>), hipMemcpyHostToDevice));
+        h2d(dref, &href, sizeof(Ref<P>));
         std::vector<double> mhf(NP * NP);
         for (int a = 0; a < NP; ++a)
             for (int b = 0; b < NP; ++b) mhf[a * NP + b] = href.mh[a][b];
@@ -529,6 +544,10 @@ struct Solver final : pa_ctx {
         outer_z = dalloc<double>(Nu);
         outer_rhs = dalloc<double>(Nu);
         lam_buf = dalloc<double>(Nu);
+        nk_delta = dalloc<double>(Nu);
+        nk_save = dalloc<double>(Nu);
+        gms = dalloc<GmState>(1);
+        HIPCHK(hipHostMalloc((void**)&hstat, sizeof(GmHost), hipHostMallocDefault));
         set_jacobian_smem();
     }
 
@@ -663,19 +682,19 @@ struct Solver final : pa_ctx {
         tstop(e);
     }
     // y = alpha M x + beta op(J) x
-    void bsr(const double* J, double alpha, double beta, int tr, const double* x, double* y)
+    void bsr(const double* J, double alpha, double beta, int tr, const double* x, double* y, const int* skip = nullptr)
     {
         hipEvent_t e;
         tstart(PA_K_SPMV, &e);
-        k_bsr_apply<NP><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, dm.area, dmh, J, x, y, alpha, beta, tr);
+        k_bsr_apply<NP><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, dm.area, dmh, J, x, y, alpha, beta, tr, skip);
         LAUNCHCHK();
         tstop(e);
     }
-    void prec(const double* Ai, int tr, const double* x, double* z)
+    void prec(const double* Ai, int tr, const double* x, double* z, const int* skip = nullptr)
     {
         hipEvent_t e;
         tstart(PA_K_PRECOND, &e);
-        k_block_apply<NP><<<Ne, 64, 0, st>>>(Ne, Ai, x, z, tr);
+        k_block_apply<NP><<<Ne, 64, 0, st>>>(Ne, Ai, x, z, tr, skip);
         LAUNCHCHK();
         tstop(e);
     }
@@ -702,7 +721,7 @@ struct Solver final : pa_ctx {
     {
         k_multidot<<<RED_BLOCKS, RED_THREADS, 0, st>>>(Vb, ldv, ncols, w, Nu, part);
         LAUNCHCHK();
-        k_reduce_partials<<<1, 128, 0, st>>>(part, RED_BLOCKS, ncols, hdev);
+        k_reduce_partials<<<1, PRED_THREADS, 0, st>>>(part, RED_BLOCKS, ncols, hdev);
         LAUNCHCHK();
         HIPCHK(hipMemcpyAsync(h, hdev, sizeof(double) * ncols, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -766,9 +785,9 @@ struct Solver final : pa_ctx {
                     LAUNCHCHK();
                     k_multidot<<<RED_BLOCKS, RED_THREADS, 0, st>>>(wk, 0, 1, wk, Nu, part + RED_BLOCKS * (j + 1));
                     LAUNCHCHK();
-                    k_reduce_partials<<<1, 128, 0, st>>>(part, RED_BLOCKS, j + 1, hdev);
+                    k_reduce_partials<<<1, PRED_THREADS, 0, st>>>(part, RED_BLOCKS, j + 1, hdev);
                     LAUNCHCHK();
-                    k_reduce_partials<<<1, 128, 0, st>>>(part + RED_BLOCKS * (j + 1), RED_BLOCKS, 1, hdev + j + 1);
+                    k_reduce_partials<<<1, PRED_THREADS, 0, st>>>(part + RED_BLOCKS * (j + 1), RED_BLOCKS, 1, hdev + j + 1);
                     LAUNCHCHK();
                     HIPCHK(hipMemcpyAsync(h2.data(), hdev, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, st));
                     HIPCHK(hipStreamSynchronize(st));
@@ -815,14 +834,74 @@ struct Solver final : pa_ctx {
 
     // stage solve: (M - c J) x = rhs, or its transpose, with the stored
     // block-Jacobi inverse Ai
+    // Right-preconditioned GMRES(m) with the Arnoldi state on the device:
+    // no host round trip inside an iteration; the host reads the pinned
+    // status every GM_CHECK iterations and then only enqueues early-exiting
+    // launches if the cycle converged in between.
+    static constexpr int GM_CHECK = 5;
     int stage_solve(const double* J, const double* Ai, double c, int tr, const double* rhs, double* x)
     {
-        auto A = [&](const double* v, double* out) { bsr(J, 1.0, -c, tr, v, out); };
-        auto Pc = [&](const double* v, double* out) { prec(Ai, tr, v, out); };
-        int its = gmres(A, Pc, rhs, x, cfg.lin_rtol, restart, 20 * restart, V, we, wf, nullptr, true);
-        cnt_gmres += its;
-        return its;
+        const int m = restart, maxit = 20 * restart;
+        const int* skip = &gms->done;
+        const double bn = norm(rhs);
+        zero(x);
+        if (bn == 0.0) return 0;
+        const double tol = cfg.lin_rtol * bn;
+        double* r = we;
+        double* w = we;
+        double* z = wf;
+        int total = 0;
+        copy(rhs, r);
+        for (;;) {
+            k_multidot<<<RED_BLOCKS, RED_THREADS, 0, st>>>(r, 0, 1, r, Nu, part);
+            LAUNCHCHK();
+            k_gm_start<<<1, PRED_THREADS, 0, st>>>(part, RED_BLOCKS, tol, gms);
+            LAUNCHCHK();
+            k_gm_scale0<<<grid1(Nu), 256, 0, st>>>(r, V, Nu, gms);
+            LAUNCHCHK();
+            bool done = false;
+            int jend = m;
+            for (int j = 0; j < m; ++j) {
+                double* vj = V + (int64_t)j * Nu;
+                prec(Ai, tr, vj, z, skip);
+                bsr(J, 1.0, -c, tr, z, w, skip);
+                k_gm_dot<<<RED_BLOCKS, RED_THREADS, 0, st>>>(V, Nu, j + 1, 0, w, Nu, part, gms);
+                k_gm_red1<<<1, PRED_THREADS, 0, st>>>(part, RED_BLOCKS, j + 1, gms);
+                k_gm_upd1<<<grid1(Nu), 256, 0, st>>>(V, Nu, j + 1, w, Nu, gms);
+                k_gm_dot<<<RED_BLOCKS, RED_THREADS, 0, st>>>(V, Nu, j + 1, 1, w, Nu, part, gms);
+                k_gm_red2<<<1, PRED_THREADS, 0, st>>>(part, RED_BLOCKS, j, m, gms);
+                k_gm_upd2<<<grid1(Nu), 256, 0, st>>>(V, Nu, j + 1, w, V + (int64_t)(j + 1) * Nu, Nu, gms);
+                LAUNCHCHK();
+                if ((j + 1) % GM_CHECK == 0 || j == m - 1) {
+                    HIPCHK(hipMemcpyAsync(hstat, &gms->res, 16, hipMemcpyDeviceToHost, st));
+                    HIPCHK(hipStreamSynchronize(st));
+                    if (hstat->done) { done = true; jend = hstat->its; break; }
+                }
+            }
+            // x += P^{-1} V y
+            k_gm_solve<<<1, 64, 0, st>>>(m, gms);
+            k_gm_combine<<<grid1(Nu), 256, 0, st>>>(V, Nu, m, w, Nu, gms);
+            LAUNCHCHK();
+            prec(Ai, tr, w, z);
+            axpby(1.0, z, 1.0, x);
+            total += done ? jend : m;
+            if (done) {
+                if (!std::isfinite(hstat->res)) raise(PA_ENUMERIC, "NaN in stage GMRES");
+                if (hstat->res <= tol) break;
+            }
+            if (total >= maxit)
+                raise(PA_ENOCONV, "stage GMRES did not converge in %d iterations: rel. residual %.3e", total,
+                      hstat->res / bn);
+            // restart from the true residual r = b - A x
+            bsr(J, 1.0, -c, tr, x, w);
+            lincomb(1.0, rhs, -1.0, w, r);
+        }
+        cnt_gmres += total;
+        return total;
     }
+    struct GmHost { double res; int done; int its; };
+    GmState* gms = nullptr;
+    GmHost* hstat = nullptr;
 
     // ---------------------------------------------------------------- setup
     void set_params(const double m[3]) override
@@ -862,14 +941,14 @@ struct Solver final : pa_ctx {
     void set_state(const double* h, int64_t n) override
     {
         if (n != Nu) raise(PA_EINVAL, "state length %lld != %lld", (long long)n, (long long)Nu);
-        HIPCHK(hipMemcpy(u0, h, sizeof(double) * Nu, hipMemcpyHostToDevice));
+        h2d(u0, h, sizeof(double) * Nu);
         have_traj = false;
     }
     void set_freestream(const double* pert) override
     {
         if (!have_params) raise(PA_ESTATE, "parameters not set");
         std::vector<double> g(nn), u(Nu);
-        HIPCHK(hipMemcpy(g.data(), gb, sizeof(double) * nn, hipMemcpyDeviceToHost));
+        d2h(g.data(), gb, sizeof(double) * nn);
         for (int64_t k = 0; k < nn; ++k)
             for (int m = 0; m < 4; ++m) u[4 * k + m] = g[k] * ph.Uinf[m] + (pert ? pert[4 * k + m] : 0.0);
         set_state(u.data(), Nu);
@@ -877,10 +956,10 @@ struct Solver final : pa_ctx {
     void get_state(int which, double* out, int64_t n) override
     {
         if (n != Nu) raise(PA_EINVAL, "bad length");
-        if (which == 0) HIPCHK(hipMemcpy(out, u0, sizeof(double) * Nu, hipMemcpyDeviceToHost));
+        if (which == 0) d2h(out, u0, sizeof(double) * Nu);
         else if (which == 1) {
             if (!have_traj) raise(PA_ESTATE, "no trajectory");
-            HIPCHK(hipMemcpy(out, tu + (int64_t)Nt * Nu, sizeof(double) * Nu, hipMemcpyDeviceToHost));
+            d2h(out, tu + (int64_t)Nt * Nu, sizeof(double) * Nu);
         } else raise(PA_EINVAL, "bad which");
     }
 
@@ -971,7 +1050,7 @@ struct Solver final : pa_ctx {
                     zero(k);
                     nR = evalR(k);
                 }
-                if (verbose) fprintf(stderr, "[pa] stage (%d,%d) predictor |R| = %.3e\n", n, i, nR);
+                if (verbose > 1) fprintf(stderr, "[pa] stage (%d,%d) predictor |R| = %.3e\n", n, i, nR);
                 int it = 0;
                 while (!(nR <= cfg.newton_atol)) {
                     if (!std::isfinite(nR)) raise(PA_ENUMERIC, "NaN at stage (%d,%d)", n, i);
@@ -993,7 +1072,7 @@ struct Solver final : pa_ctx {
                     nR = nT;
                     ++it;
                     ++cnt_newton;
-                    if (verbose) fprintf(stderr, "[pa] stage (%d,%d) it %d lam %.3g |R| = %.3e\n", n, i, it, lam, nR);
+                    if (verbose > 1) fprintf(stderr, "[pa] stage (%d,%d) it %d lam %.3g |R| = %.3e\n", n, i, it, lam, nR);
                 }
                 // exact linearisation at the converged stage state
                 jacobian(n, i, ui, stJ(s));
@@ -1091,39 +1170,82 @@ struct Solver final : pa_ctx {
     }
 
     // ---------------------------------------------------------------- outer solvers
+    // Newton-Krylov shooting with a backtracking line search on ||R||: the
+    // step u0 - lam Delta is accepted when its primal period succeeds and
+    // lowers the periodicity residual (lam = 1, 1/2, ... 1/64)
     void shoot(double tol, double eta, int maxit, pa_shoot_report* rep) override
     {
         double t0 = now_ms();
         pa_shoot_report r{};
         cnt_newton = cnt_gmres = 0;
-        for (;;) {
-            double qoi[2], res;
-            primal_sweep(qoi, &res);
-            ++r.primal_sweeps;
-            if (r.primal_sweeps == 1) r.res0 = res;
-            r.res = res;
-            if (res <= tol) break;
+        auto finish = [&]() {
+            r.stage_newton_its = (int32_t)cnt_newton;
+            r.stage_gmres_its = cnt_gmres;
+            r.ms = now_ms() - t0;
+            if (rep) *rep = r;
+        };
+        double qoi[2], res;
+        primal_sweep(qoi, &res);
+        ++r.primal_sweeps;
+        r.res0 = r.res = res;
+        if (verbose) fprintf(stderr, "[pa] shoot start |R| = %.3e  %.1f s\n", res, (now_ms() - t0) / 1e3);
+        while (!(res <= tol)) {
             if (r.newton_its >= maxit) {
-                r.stage_newton_its = (int32_t)cnt_newton;
-                r.stage_gmres_its = cnt_gmres;
-                r.ms = now_ms() - t0;
-                if (rep) *rep = r;
+                finish();
                 raise(PA_ENOCONV, "shooting did not converge: |R| = %.3e after %d Newton steps", res, r.newton_its);
             }
-            // R = u^(Nt) - u0;  (Phi - I) Delta = R;  u0 <- u0 - Delta
+            // R = u^(Nt) - u0;  (Phi - I) Delta = R
             lincomb(1.0, tu + (int64_t)Nt * Nu, -1.0, u0, wd);
             int k0 = r.krylov_its;
             outer_gmres(true, wd, eta, r.krylov_its);
-            axpby(-1.0, wf, 1.0, u0);
+            copy(wf, nk_delta);
+            copy(u0, nk_save);
+            double lam = 1.0, rnew = 0.0;
+            bool ok = false;
+            for (int trial = 0; trial < 7 && !ok; ++trial, lam *= 0.5) {
+                lincomb(1.0, nk_save, -lam, nk_delta, u0);
+                try {
+                    primal_sweep(qoi, &rnew);
+                    ++r.primal_sweeps;
+                    ok = rnew < res;
+                } catch (const PaError& e) {
+                    if (e.code != PA_ENOCONV && e.code != PA_ENUMERIC) throw;
+                    ++r.primal_sweeps;
+                    ok = false;
+                }
+                if (verbose)
+                    fprintf(stderr, "[pa] shoot it %d lam %.4g |R| = %.3e -> %s  %.1f s\n", r.newton_its + 1, lam,
+                            res, ok ? "accepted" : "rejected", (now_ms() - t0) / 1e3);
+                if (ok) break;
+            }
+            if (!ok) {
+                copy(nk_save, u0);
+                primal_sweep(qoi, &res);
+                ++r.primal_sweeps;
+                finish();
+                raise(PA_ENOCONV, "shooting line search failed at |R| = %.3e", res);
+            }
+            res = rnew;
+            r.res = res;
             ++r.newton_its;
             if (verbose)
-                fprintf(stderr, "[pa] shoot it %d |R| = %.3e krylov %d (rel %.2e) %.1f s\n", r.newton_its, res,
+                fprintf(stderr, "[pa] shoot it %d |R| = %.3e (krylov %d, rel %.2e)  %.1f s\n", r.newton_its, res,
                         r.krylov_its - k0, last_outer_rel, (now_ms() - t0) / 1e3);
         }
-        r.stage_newton_its = (int32_t)cnt_newton;
-        r.stage_gmres_its = cnt_gmres;
-        r.ms = now_ms() - t0;
-        if (rep) *rep = r;
+        finish();
+    }
+
+    // Alg. 1: m fixed-point periods u0 <- u^(Nt)(u0)
+    void fixed_point(int periods, double* res_out) override
+    {
+        double res = 0.0, qoi[2];
+        for (int k = 0; k < periods; ++k) {
+            primal_sweep(qoi, &res);
+            copy(tu + (int64_t)Nt * Nu, u0);
+            have_traj = false;   // the stored trajectory starts from the previous u0
+            if (verbose) fprintf(stderr, "[pa] fixed-point period %d |R| = %.3e\n", k + 1, res);
+        }
+        if (res_out) *res_out = res;
     }
 
     // Outer matrix-free GMRES on (Phi - I) (tangent_op) or (Phi^T - I), zero
@@ -1132,10 +1254,15 @@ struct Solver final : pa_ctx {
     void outer_gmres(bool tangent_op, const double* rhs, double rtol, int32_t& its_acc)
     {
         copy(rhs, outer_rhs);
+        int nmv = 0;
+        double t0 = now_ms();
         auto A = [&](const double* v, double* out) {
             if (tangent_op) tangent(v, out);
             else adjoint(v, -1, out, nullptr);
             axpby(-1.0, v, 1.0, out);
+            if (verbose && (++nmv % 10) == 0)
+                fprintf(stderr, "[pa]   %s sweeps %d  %.1f s\n", tangent_op ? "tangent" : "adjoint", nmv,
+                        (now_ms() - t0) / 1e3);
         };
         double rr;
         int its = gmres(A, nullptr, outer_rhs, outer_x, rtol, max_kry, max_kry, Vo, outer_w, outer_z, &rr, false);
@@ -1144,6 +1271,7 @@ struct Solver final : pa_ctx {
         copy(outer_x, wf);
     }
     double *outer_x = nullptr, *outer_w = nullptr, *outer_z = nullptr, *outer_rhs = nullptr, *lam_buf = nullptr;
+    double *nk_delta = nullptr, *nk_save = nullptr;
     double last_outer_rel = 0;
 
     void adjoint_gradient(double rtol, double qoi[2], double dJ[6], pa_adjoint_report* rep) override
@@ -1176,7 +1304,7 @@ struct Solver final : pa_ctx {
         if (qoi) {
             // time-averaged QoIs of the stored trajectory
             std::vector<double> h((size_t)nst * std::max(nwall, 1) * 2);
-            HIPCHK(hipMemcpy(h.data(), qh, sizeof(double) * h.size(), hipMemcpyDeviceToHost));
+            d2h(h.data(), qh, sizeof(double) * h.size());
             double J0 = 0, J1 = 0;
             for (int s = 0; s < nst; ++s) {
                 double f0 = 0, f1 = 0;
@@ -1195,57 +1323,57 @@ struct Solver final : pa_ctx {
     // ---------------------------------------------------------------- host-vector wrappers
     void tangent_sweep_h(const double* v, double* out) override
     {
-        HIPCHK(hipMemcpy(wd, v, sizeof(double) * Nu, hipMemcpyHostToDevice));
+        h2d(wd, v, sizeof(double) * Nu);
         tangent(wd, wf);
-        HIPCHK(hipMemcpy(out, wf, sizeof(double) * Nu, hipMemcpyDeviceToHost));
+        d2h(out, wf, sizeof(double) * Nu);
     }
     void adjoint_sweep_h(const double* lamh, int fq, double* lam0, double* grad) override
     {
-        HIPCHK(hipMemcpy(wd, lamh, sizeof(double) * Nu, hipMemcpyHostToDevice));
+        h2d(wd, lamh, sizeof(double) * Nu);
         adjoint(wd, fq, wf, grad);
-        HIPCHK(hipMemcpy(lam0, wf, sizeof(double) * Nu, hipMemcpyDeviceToHost));
+        d2h(lam0, wf, sizeof(double) * Nu);
     }
 
     // ---------------------------------------------------------------- debug entry points
     void dbg_gbar(int n, int i, double* out, bool deriv) override
     {
         check_stage(n, i);
-        if (deriv) HIPCHK(hipMemcpy(out, dgbs(n, i), sizeof(double) * 3 * nn, hipMemcpyDeviceToHost));
-        else HIPCHK(hipMemcpy(out, gbs(n, i), sizeof(double) * nn, hipMemcpyDeviceToHost));
+        if (deriv) d2h(out, dgbs(n, i), sizeof(double) * 3 * nn);
+        else d2h(out, gbs(n, i), sizeof(double) * nn);
     }
     void dbg_residual(int n, int i, const double* u, double* r, bool dmu) override
     {
         check_stage(n, i);
-        HIPCHK(hipMemcpy(wd, u, sizeof(double) * Nu, hipMemcpyHostToDevice));
+        h2d(wd, u, sizeof(double) * Nu);
         if (dmu) {
             dr_dmu(n, i, wd, drm);
             HIPCHK(hipStreamSynchronize(st));
-            HIPCHK(hipMemcpy(r, drm, sizeof(double) * 3 * Nu, hipMemcpyDeviceToHost));
+            d2h(r, drm, sizeof(double) * 3 * Nu);
         } else {
             residual(n, i, wd, wf);
             HIPCHK(hipStreamSynchronize(st));
-            HIPCHK(hipMemcpy(r, wf, sizeof(double) * Nu, hipMemcpyDeviceToHost));
+            d2h(r, wf, sizeof(double) * Nu);
         }
     }
     void dbg_jacobian(int n, int i, const double* u, double* blk) override
     {
         check_stage(n, i);
-        HIPCHK(hipMemcpy(wd, u, sizeof(double) * Nu, hipMemcpyHostToDevice));
+        h2d(wd, u, sizeof(double) * Nu);
         jacobian(n, i, wd, tJ);
         HIPCHK(hipStreamSynchronize(st));
-        HIPCHK(hipMemcpy(blk, tJ, sizeof(double) * Jsz, hipMemcpyDeviceToHost));
+        d2h(blk, tJ, sizeof(double) * Jsz);
         have_traj = false;
     }
     void dbg_qoi(int n, int i, const double* u, double f[2], double* dfdu, double* dfdmu) override
     {
         check_stage(n, i);
-        HIPCHK(hipMemcpy(wd, u, sizeof(double) * Nu, hipMemcpyHostToDevice));
+        h2d(wd, u, sizeof(double) * Nu);
         double fv[2] = { 0, 0 };
         if (dfdu) {
             for (int q = 0; q < 2; ++q) {
                 qoi_grad(n, i, wd, q, wf, qtmp);
                 HIPCHK(hipStreamSynchronize(st));
-                HIPCHK(hipMemcpy(dfdu + (int64_t)q * Nu, wf, sizeof(double) * Nu, hipMemcpyDeviceToHost));
+                d2h(dfdu + (int64_t)q * Nu, wf, sizeof(double) * Nu);
             }
         }
         double fm[6];
@@ -1255,33 +1383,33 @@ struct Solver final : pa_ctx {
     }
     void dbg_bsr_apply(const double* blk, double alpha, double beta, int tr, const double* x, double* y) override
     {
-        HIPCHK(hipMemcpy(tJ, blk, sizeof(double) * Jsz, hipMemcpyHostToDevice));
-        HIPCHK(hipMemcpy(wd, x, sizeof(double) * Nu, hipMemcpyHostToDevice));
+        h2d(tJ, blk, sizeof(double) * Jsz);
+        h2d(wd, x, sizeof(double) * Nu);
         bsr(tJ, alpha, beta, tr, wd, wf);
         HIPCHK(hipStreamSynchronize(st));
-        HIPCHK(hipMemcpy(y, wf, sizeof(double) * Nu, hipMemcpyDeviceToHost));
+        d2h(y, wf, sizeof(double) * Nu);
         have_traj = false;
     }
     void dbg_blockinv(const double* blk, double adt, double* out) override
     {
-        HIPCHK(hipMemcpy(tJ, blk, sizeof(double) * Jsz, hipMemcpyHostToDevice));
+        h2d(tJ, blk, sizeof(double) * Jsz);
         HIPCHK(hipMemsetAsync(dstatus, 0, sizeof(int), st));
         blockinv(tJ, adt, tAi);
         int stt = 0;
         HIPCHK(hipMemcpyAsync(&stt, dstatus, sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
         if (stt) raise(PA_ENUMERIC, "singular diagonal block");
-        HIPCHK(hipMemcpy(out, tAi, sizeof(double) * Isz, hipMemcpyDeviceToHost));
+        d2h(out, tAi, sizeof(double) * Isz);
         have_traj = false;
     }
     int dbg_stage_solve(const double* blk, double adt, int tr, const double* rhs, double* x) override
     {
-        HIPCHK(hipMemcpy(tJ, blk, sizeof(double) * Jsz, hipMemcpyHostToDevice));
+        h2d(tJ, blk, sizeof(double) * Jsz);
         blockinv(tJ, adt, tAi);
-        HIPCHK(hipMemcpy(wd, rhs, sizeof(double) * Nu, hipMemcpyHostToDevice));
+        h2d(wd, rhs, sizeof(double) * Nu);
         int its = stage_solve(tJ, tAi, adt, tr, wd, wc);
         HIPCHK(hipStreamSynchronize(st));
-        HIPCHK(hipMemcpy(x, wc, sizeof(double) * Nu, hipMemcpyDeviceToHost));
+        d2h(x, wc, sizeof(double) * Nu);
         have_traj = false;
         return its;
     }
@@ -1300,7 +1428,7 @@ struct Solver final : pa_ctx {
             int s = (n - 1) * 3 + (i - 1);
             src = which == 0 ? stU(s) : stK(s);
         }
-        HIPCHK(hipMemcpy(out, src, sizeof(double) * Nu, hipMemcpyDeviceToHost));
+        d2h(out, src, sizeof(double) * Nu);
     }
     double bench_spmv(int reps, int tr) override
     {
@@ -1311,7 +1439,8 @@ struct Solver final : pa_ctx {
         double c = dt * rk.A[0][0];
         bsr(stJ(0), 1.0, -c, tr, u0, wf);
         HIPCHK(hipEventRecord(a, st));
-        for (int r = 0; r < reps; ++r) k_bsr_apply<NP><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, dm.area, dmh, stJ(0), u0, wf, 1.0, -c, tr);
+        for (int r = 0; r < reps; ++r)
+            k_bsr_apply<NP><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, dm.area, dmh, stJ(0), u0, wf, 1.0, -c, tr, nullptr);
         LAUNCHCHK();
         HIPCHK(hipEventRecord(b, st));
         HIPCHK(hipEventSynchronize(b));
@@ -1434,6 +1563,13 @@ pa_status pa_shoot(pa_ctx* c, double tol, double eta, int32_t maxit, pa_shoot_re
     return guard(c, [&] {
         if (!(tol > 0) || !(eta > 0) || maxit < 0) raise(PA_EINVAL, "bad shooting options");
         c->shoot(tol, eta, maxit, rep);
+    });
+}
+pa_status pa_fixed_point(pa_ctx* c, int32_t periods, double* res)
+{
+    return guard(c, [&] {
+        if (periods < 0) raise(PA_EINVAL, "negative period count");
+        c->fixed_point(periods, res);
     });
 }
 pa_status pa_adjoint_gradient(pa_ctx* c, double rtol, double qoi[2], double dJ[6], pa_adjoint_report* rep)

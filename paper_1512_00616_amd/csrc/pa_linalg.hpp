@@ -26,11 +26,12 @@ __global__ void __launch_bounds__(64) k_bsr_apply(int Ne, const int32_t* __restr
                                                   const int8_t* __restrict__ etw, const double* __restrict__ area,
                                                   const double* __restrict__ mh, const double* __restrict__ J,
                                                   const double* __restrict__ x, double* __restrict__ y,
-                                                  double alpha, double beta, int trans)
+                                                  double alpha, double beta, int trans, const int* __restrict__ skip)
 {
     constexpr int B = 4 * NP, BB = B * B;
     __shared__ double sblk[B][B + 1];
     __shared__ double sx[B];
+    if (skip && *skip) return;
     const int K = blockIdx.x, lane = threadIdx.x;
     double acc = 0.0;
     for (int s = 0; s < 4; ++s) {
@@ -156,11 +157,13 @@ __global__ void __launch_bounds__(64) k_blockinv(int Ne, const double* __restric
 // z_K = Ainv_K x_K  (trans: Ainv_K^T x_K)
 template <int NP>
 __global__ void __launch_bounds__(64) k_block_apply(int Ne, const double* __restrict__ Ainv,
-                                                    const double* __restrict__ x, double* __restrict__ z, int trans)
+                                                    const double* __restrict__ x, double* __restrict__ z, int trans,
+                                                    const int* __restrict__ skip)
 {
     constexpr int B = 4 * NP, BB = B * B;
     __shared__ double sblk[B][B + 1];
     __shared__ double sx[B];
+    if (skip && *skip) return;
     const int K = blockIdx.x, lane = threadIdx.x;
     const double2* blk2 = reinterpret_cast<const double2*>(Ainv + (int64_t)K * BB);
     for (int t = lane; t < BB / 2; t += 64) {
@@ -183,40 +186,86 @@ __global__ void __launch_bounds__(64) k_block_apply(int Ne, const double* __rest
 
 // ------------------------------------------------------------------ vector kernels
 constexpr int RED_THREADS = 256;
-constexpr int RED_BLOCKS = 512;
+constexpr int RED_BLOCKS = 256;
 
-// partial[blk][c] = sum over the block's chunk of w . V_c, c < ncols (V_c = V + c*ldv)
-__global__ void __launch_bounds__(RED_THREADS) k_multidot(const double* __restrict__ V, int64_t ldv, int ncols,
-                                                          const double* __restrict__ w, int64_t n,
-                                                          double* __restrict__ partial)
+// Block partials of dot products: partial[blk][c] = sum over the block's
+// chunk of w . X_c for c < nc, where X_c = V + c*ldv for c < ncols and X_c = w
+// for the optional last column.  Columns are processed in groups of DOTG:
+// each thread accumulates the group in registers and the group is reduced
+// in one LDS tree (fixed order, deterministic).
+constexpr int DOTG = 8;
+__device__ __forceinline__ void block_dots(const double* __restrict__ V, int64_t ldv, int ncols, int nc,
+                                           const double* __restrict__ w, int64_t n, double* __restrict__ partial)
 {
-    __shared__ double red[RED_THREADS];
+    __shared__ double red[DOTG][RED_THREADS];
     const int tid = threadIdx.x;
     int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
     int64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
-    for (int c = 0; c < ncols; ++c) {
-        const double* v = V + (int64_t)c * ldv;
-        double s = 0.0;
-        for (int64_t i = lo + tid; i < hi; i += RED_THREADS) s += w[i] * v[i];
-        red[tid] = s;
+    for (int c0 = 0; c0 < nc; c0 += DOTG) {
+        double acc[DOTG];
+#pragma unroll
+        for (int g = 0; g < DOTG; ++g) acc[g] = 0.0;
+        for (int64_t i = lo + tid; i < hi; i += RED_THREADS) {
+            double wi = w[i];
+#pragma unroll
+            for (int g = 0; g < DOTG; ++g) {
+                int c = c0 + g;
+                if (c < nc) acc[g] += wi * (c < ncols ? V[(int64_t)c * ldv + i] : wi);
+            }
+        }
+#pragma unroll
+        for (int g = 0; g < DOTG; ++g) red[g][tid] = acc[g];
         __syncthreads();
-        for (int st = RED_THREADS / 2; st > 0; st >>= 1) {
-            if (tid < st) red[tid] += red[tid + st];
+        for (int stp = RED_THREADS / 2; stp > 0; stp >>= 1) {
+            if (tid < stp) {
+#pragma unroll
+                for (int g = 0; g < DOTG; ++g) red[g][tid] += red[g][tid + stp];
+            }
             __syncthreads();
         }
-        if (tid == 0) partial[(int64_t)blockIdx.x * ncols + c] = red[0];
+        if (tid < DOTG && c0 + tid < nc) partial[(int64_t)blockIdx.x * nc + c0 + tid] = red[tid][0];
         __syncthreads();
     }
 }
 
-// out[c] = sum_blk partial[blk][c] (fixed order)
-__global__ void k_reduce_partials(const double* __restrict__ partial, int nblk, int ncols, double* __restrict__ out)
+__global__ void __launch_bounds__(RED_THREADS) k_multidot(const double* __restrict__ V, int64_t ldv, int ncols,
+                                                          const double* __restrict__ w, int64_t n,
+                                                          double* __restrict__ partial)
 {
-    int c = threadIdx.x;
-    if (c >= ncols) return;
-    double s = 0.0;
-    for (int b = 0; b < nblk; ++b) s += partial[(int64_t)b * ncols + c];
-    out[c] = s;
+    block_dots(V, ldv, ncols, ncols, w, n, partial);
+}
+
+// Column sums of block partials with a 256-lane block, in a fixed order:
+// lane (t, c) with t = tid / 32 sums rows t, t+8, t+16, ... of column c; the
+// 8 slice sums of a column are then added in slice order.  out may be LDS.
+constexpr int PRED_THREADS = 256;
+__device__ __forceinline__ void reduce_partials_block(const double* __restrict__ partial, int nblk, int nc,
+                                                      double* out)
+{
+    __shared__ double sl[8][32];
+    const int tid = threadIdx.x, t = tid >> 5, cl = tid & 31;
+    for (int c0 = 0; c0 < nc; c0 += 32) {
+        int c = c0 + cl;
+        double s = 0.0;
+        if (c < nc)
+            for (int b = t; b < nblk; b += 8) s += partial[(int64_t)b * nc + c];
+        sl[t][cl] = s;
+        __syncthreads();
+        if (t == 0 && c < nc) {
+            double r = 0.0;
+#pragma unroll
+            for (int k = 0; k < 8; ++k) r += sl[k][cl];
+            out[c] = r;
+        }
+        __syncthreads();
+    }
+}
+
+// out[c] = sum_blk partial[blk][c] (fixed order); launch with PRED_THREADS lanes
+__global__ void __launch_bounds__(PRED_THREADS) k_reduce_partials(const double* __restrict__ partial, int nblk, int ncols,
+                                                                  double* __restrict__ out)
+{
+    reduce_partials_block(partial, nblk, ncols, out);
 }
 
 // w += sign * sum_c h[c] V_c
@@ -259,6 +308,164 @@ __global__ void k_stage_residual(int Ne, const double* __restrict__ area, const 
     double s = 0.0;
     for (int b = 0; b < NP; ++b) s += mh[a * NP + b] * kK[b * 4 + m];
     R[i] = 2.0 * area[K] * s - dt * r[i];
+}
+
+}  // namespace pa
+
+namespace pa {
+
+// ------------------------------------------------------------------ device-resident GMRES
+// Arnoldi state of one restart cycle kept in device memory so that the
+// iterations run without host round trips.  Every iteration kernel returns
+// at once when `done` is set; the host polls `done` every few iterations.
+constexpr int GM_MAXM = 64;
+struct GmState {
+    double H[(GM_MAXM + 1) * GM_MAXM];   // Hessenberg (rotated), row-major (m+1) x m
+    double cs[GM_MAXM], sn[GM_MAXM];
+    double g[GM_MAXM + 1];
+    double y[GM_MAXM];
+    double hc[GM_MAXM + 2];              // first Gram-Schmidt pass
+    double h2[GM_MAXM + 2];              // second pass (reorthogonalisation)
+    double inv_hn;                       // 1 / ||w|| after orthogonalisation
+    double tol;                          // absolute residual target
+    double res;                          // current residual estimate
+    int done;                            // 1: converged or happy breakdown
+    int its;                             // columns of the cycle when done
+};
+
+// partials of <V_c, w> (c < ncols) and optionally <w, w> (extra column)
+__global__ void __launch_bounds__(RED_THREADS) k_gm_dot(const double* __restrict__ V, int64_t ldv, int ncols, int with_ww,
+                                                        const double* __restrict__ w, int64_t n,
+                                                        double* __restrict__ partial, const GmState* __restrict__ st)
+{
+    if (st->done) return;
+    block_dots(V, ldv, ncols, ncols + with_ww, w, n, partial);
+}
+
+// first pass: hc[c] = sum_blk partial[blk][c]
+__global__ void __launch_bounds__(PRED_THREADS) k_gm_red1(const double* __restrict__ partial, int nblk, int ncols,
+                                                          GmState* __restrict__ st)
+{
+    if (st->done) return;
+    reduce_partials_block(partial, nblk, ncols, st->hc);
+}
+
+// second pass + Givens: column j of H = hc + h2, ||w|| from <w,w> - |h2|^2,
+// rotations, residual estimate; sets done on convergence or breakdown
+__global__ void __launch_bounds__(PRED_THREADS) k_gm_red2(const double* __restrict__ partial, int nblk, int j, int m,
+                                                          GmState* __restrict__ st)
+{
+    if (st->done) return;
+    __shared__ double s2[GM_MAXM + 2];
+    const int ncols = j + 1, nc = j + 2;
+    reduce_partials_block(partial, nblk, nc, s2);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double corr = 0.0;
+    for (int i = 0; i < ncols; ++i) {
+        st->h2[i] = s2[i];
+        corr += s2[i] * s2[i];
+    }
+    double ww = s2[ncols] - corr;
+    double hn = ww > 0.0 ? sqrt(ww) : 0.0;
+    double* H = st->H;
+    for (int i = 0; i < ncols; ++i) H[i * m + j] = st->hc[i] + st->h2[i];
+    H[(j + 1) * m + j] = hn;
+    for (int i = 0; i < j; ++i) {
+        double a = H[i * m + j], b = H[(i + 1) * m + j];
+        H[i * m + j] = st->cs[i] * a + st->sn[i] * b;
+        H[(i + 1) * m + j] = -st->sn[i] * a + st->cs[i] * b;
+    }
+    double a = H[j * m + j], b = H[(j + 1) * m + j];
+    double rr = sqrt(a * a + b * b);
+    st->cs[j] = a / rr;
+    st->sn[j] = b / rr;
+    H[j * m + j] = rr;
+    H[(j + 1) * m + j] = 0.0;
+    st->g[j + 1] = -st->sn[j] * st->g[j];
+    st->g[j] = st->cs[j] * st->g[j];
+    double res = fabs(st->g[j + 1]);
+    st->res = res;
+    st->inv_hn = hn > 0.0 ? 1.0 / hn : 0.0;
+    if (!(res > st->tol) || hn == 0.0 || !(res == res)) {
+        st->done = 1;
+        st->its = j + 1;
+    }
+}
+
+// w -= sum_c hc[c] V_c   (first Gram-Schmidt pass)
+__global__ void k_gm_upd1(const double* __restrict__ V, int64_t ldv, int ncols, double* __restrict__ w, int64_t n,
+                          const GmState* __restrict__ st)
+{
+    if (st->done) return;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int c = 0; c < ncols; ++c) s += st->hc[c] * V[(int64_t)c * ldv + i];
+    w[i] -= s;
+}
+
+// V_{j+1} = (w - sum_c h2[c] V_c) / ||.||
+__global__ void k_gm_upd2(const double* __restrict__ V, int64_t ldv, int ncols, const double* __restrict__ w,
+                          double* __restrict__ vnext, int64_t n, const GmState* __restrict__ st)
+{
+    if (st->done) return;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int c = 0; c < ncols; ++c) s += st->h2[c] * V[(int64_t)c * ldv + i];
+    vnext[i] = (w[i] - s) * st->inv_hn;
+}
+
+// start of a cycle: V_0 = r / beta, g = beta e_1 (beta = sqrt(<r,r>) from partials)
+__global__ void __launch_bounds__(PRED_THREADS) k_gm_start(const double* __restrict__ partial, int nblk, double tol,
+                                                           GmState* __restrict__ st)
+{
+    __shared__ double tot[1];
+    reduce_partials_block(partial, nblk, 1, tot);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double s = tot[0];
+    double beta = sqrt(s);
+    for (int i = 0; i <= GM_MAXM; ++i) st->g[i] = 0.0;
+    st->g[0] = beta;
+    st->res = beta;
+    st->tol = tol;
+    st->inv_hn = beta > 0.0 ? 1.0 / beta : 0.0;
+    st->done = (beta > tol) ? 0 : 1;
+    st->its = 0;
+}
+
+__global__ void k_gm_scale0(const double* __restrict__ r, double* __restrict__ v0, int64_t n, const GmState* __restrict__ st)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v0[i] = r[i] * st->inv_hn;
+}
+
+// y = R^{-1} g for the first k columns (k = its if done else m)
+__global__ void k_gm_solve(int m, GmState* __restrict__ st)
+{
+    if (threadIdx.x != 0) return;
+    int k = st->done ? st->its : m;
+    const double* H = st->H;
+    for (int i = k - 1; i >= 0; --i) {
+        double s = st->g[i];
+        for (int c = i + 1; c < k; ++c) s -= H[i * m + c] * st->y[c];
+        st->y[i] = s / H[i * m + i];
+    }
+    for (int i = k; i < m; ++i) st->y[i] = 0.0;
+}
+
+// out = sum_{c<m} y[c] V_c   (y is zero beyond the cycle's length)
+__global__ void k_gm_combine(const double* __restrict__ V, int64_t ldv, int m, double* __restrict__ out, int64_t n,
+                             const GmState* __restrict__ st)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int k = st->done ? st->its : m;
+    double s = 0.0;
+    for (int c = 0; c < k; ++c) s += st->y[c] * V[(int64_t)c * ldv + i];
+    out[i] = s;
 }
 
 }  // namespace pa

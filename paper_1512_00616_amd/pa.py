@@ -18,7 +18,7 @@ PA_K_SPMV, PA_K_PRECOND, PA_K_JACOBIAN, PA_K_RESIDUAL, PA_K_BLOCKINV = range(5)
 EXPORTED = [
     "pa_default_config", "pa_create", "pa_destroy", "pa_last_error", "pa_num_dofs", "pa_num_elems",
     "pa_block_size", "pa_device_bytes", "pa_get_mesh", "pa_set_params", "pa_set_state", "pa_set_freestream",
-    "pa_get_state", "pa_primal_period", "pa_shoot", "pa_adjoint_gradient", "pa_tangent_sweep",
+    "pa_get_state", "pa_primal_period", "pa_shoot", "pa_fixed_point", "pa_adjoint_gradient", "pa_tangent_sweep",
     "pa_adjoint_sweep", "pa_dbg_gbar", "pa_dbg_dgbar", "pa_dbg_residual", "pa_dbg_jacobian", "pa_dbg_dr_dmu",
     "pa_dbg_qoi", "pa_dbg_bsr_apply", "pa_dbg_blockinv", "pa_dbg_stage_solve", "pa_dbg_traj", "pa_set_timing",
     "pa_kernel_time", "pa_bench_spmv",
@@ -85,6 +85,7 @@ def lib():
             "pa_get_state": [P, C.c_int32, P, C.c_int64],
             "pa_primal_period": [P, P, P],
             "pa_shoot": [P, C.c_double, C.c_double, C.c_int32, P],
+            "pa_fixed_point": [P, C.c_int32, P],
             "pa_adjoint_gradient": [P, C.c_double, P, P, P],
             "pa_tangent_sweep": [P, P, P],
             "pa_adjoint_sweep": [P, P, C.c_int32, P, P],
@@ -202,6 +203,11 @@ class Solver:
         rep = pa_shoot_report()
         self._chk(lib().pa_shoot(self._c, tol, eta, maxit, C.byref(rep)))
         return rep
+
+    def fixed_point(self, periods):
+        r = np.zeros(1)
+        self._chk(lib().pa_fixed_point(self._c, periods, _ptr(r)))
+        return float(r[0])
 
     def adjoint_gradient(self, rtol=1e-8):
         q = np.zeros(2)
