@@ -180,9 +180,16 @@ enum { PA_K_SPMV = 0, PA_K_PRECOND = 1, PA_K_JACOBIAN = 2, PA_K_RESIDUAL = 3, PA
  * timing was switched on and the sampled mean duration times that count */
 pa_status pa_set_timing(pa_ctx* ctx, int32_t on);
 pa_status pa_kernel_time(pa_ctx* ctx, int32_t kernel, double* total_ms, int64_t* launches);
-/* averaged over reps launches of the stage-operator SpMV y = (M - c J_1) x on
- * the stored first-stage Jacobian (timed with HIP events, library stream) */
+/* averaged over reps launches of the preconditioned stage-operator apply
+ * y = Ahat x (transposed: Ahat^T x) of the stored first stage, Ahat =
+ * (M - dt a_11 J) P^{-1} with P its diagonal blocks (timed with HIP events on
+ * the library stream; needs a stored trajectory) */
 pa_status pa_bench_spmv(pa_ctx* ctx, int32_t reps, int32_t transpose, double* avg_ms);
+/* averaged over reps device-to-device copies of the first stage's stored
+ * operator (*bytes receives the size): a plain copy kernel of known size for
+ * calibrating hardware traffic counters.  Overwrites the second stage's
+ * operator, so the trajectory is invalidated. */
+pa_status pa_bench_copy(pa_ctx* ctx, int32_t reps, double* avg_ms, int64_t* bytes);
 
 #ifdef __cplusplus
 }

@@ -271,6 +271,7 @@ struct pa_ctx {
     virtual void set_timing(bool on) = 0;
     virtual void kernel_time(int k, double* ms, int64_t* cnt) = 0;
     virtual double bench_spmv(int reps, int tr) = 0;
+    virtual double bench_copy(int reps, int64_t* bytes) = 0;
 };
 
 namespace {
@@ -278,6 +279,12 @@ namespace {
 template <int P>
 struct Solver final : pa_ctx {
     static constexpr int NP = Sz<P>::NP, NQ = Sz<P>::NQ, NF = Sz<P>::NF, B = Sz<P>::B, BB = B * B;
+    // stored operators of one stage: Ahat = A P^{-1} (off-diagonal blocks),
+    // P = diagonal blocks of A = M - aii J, and P^{-1}
+    struct StageOps {
+        const double *Ah, *Pd, *Pinv;
+        double aii;   // dt a_ii of the stage
+    };
 
     int Ne = 0, Nt = 0, nst = 0, nwall = 0;
     int64_t Nu = 0, nn = 0, Jsz = 0, Isz = 0;
@@ -306,7 +313,8 @@ struct Solver final : pa_ctx {
 
     double *gb = nullptr, *dgb = nullptr;                          // [(nst+1)][nn], [(nst+1)][3][nn]
     double *tu = nullptr, *tk = nullptr, *tui = nullptr;           // trajectory
-    double *tJ = nullptr, *tAi = nullptr;                          // stage operators
+    double *tAh = nullptr, *tPd = nullptr, *tAi = nullptr;         // stage operators: Ahat, P, P^{-1}
+    double *Jtmp = nullptr;                                        // dr/du of the stage being assembled
     double *qh = nullptr;                                          // [nst][nwall][2]
     double *u0 = nullptr;
     // work vectors
@@ -521,8 +529,12 @@ struct Solver final : pa_ctx {
         tu = dalloc<double>((Nt + 1) * Nu);
         tk = dalloc<double>(nst * Nu);
         tui = dalloc<double>(nst * Nu);
-        tJ = dalloc<double>(nst * Jsz);
+        tAh = dalloc<double>(nst * 3 * Isz);
+        tPd = dalloc<double>(nst * Isz);
         tAi = dalloc<double>(nst * Isz);
+        Jtmp = dalloc<double>(Jsz);
+        gm_b = dalloc<double>(Nu);
+        gm_y = dalloc<double>(Nu);
         qh = dalloc<double>((int64_t)nst * std::max(nwall, 1) * 2);
         u0 = dalloc<double>(Nu);
         wa = dalloc<double>(Nu); wb = dalloc<double>(Nu); wc = dalloc<double>(Nu);
@@ -673,20 +685,20 @@ struct Solver final : pa_ctx {
         LAUNCHCHK();
         tstop(e);
     }
-    void blockinv(const double* J, double c, double* Ai)
-    {
-        hipEvent_t e;
-        tstart(PA_K_BLOCKINV, &e);
-        k_blockinv<NP><<<Ne, 64, 0, st>>>(Ne, dm.area, dmh, J, c, Ai, dstatus);
-        LAUNCHCHK();
-        tstop(e);
-    }
     // y = alpha M x + beta op(J) x
     void bsr(const double* J, double alpha, double beta, int tr, const double* x, double* y, const int* skip = nullptr)
     {
         hipEvent_t e;
         tstart(PA_K_SPMV, &e);
         k_bsr_apply<NP><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, dm.area, dmh, J, x, y, alpha, beta, tr, skip);
+        LAUNCHCHK();
+        tstop(e);
+    }
+    void ahat(const double* Ah, int tr, const double* x, double* y, const int* skip = nullptr)
+    {
+        hipEvent_t e;
+        tstart(PA_K_SPMV, &e);
+        k_ahat_apply<NP><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, Ah, x, y, tr, skip);
         LAUNCHCHK();
         tstop(e);
     }
@@ -834,24 +846,30 @@ struct Solver final : pa_ctx {
 
     // stage solve: (M - c J) x = rhs, or its transpose, with the stored
     // block-Jacobi inverse Ai
-    // Right-preconditioned GMRES(m) with the Arnoldi state on the device:
-    // no host round trip inside an iteration; the host reads the pinned
-    // status every GM_CHECK iterations and then only enqueues early-exiting
-    // launches if the cycle converged in between.
+    // Stage solve with the block-Jacobi factor folded into Ahat = A P^{-1}:
+    //   forward:    Ahat y = rhs,          x = P^{-1} y   (right preconditioning)
+    //   transposed: Ahat^T x = P^{-T} rhs                 (left preconditioning)
+    // GMRES(m) with the Arnoldi state on the device: no host round trip
+    // inside an iteration; the host reads the pinned status every GM_CHECK
+    // iterations and then only enqueues early-exiting launches if the cycle
+    // converged in between.
     static constexpr int GM_CHECK = 5;
-    int stage_solve(const double* J, const double* Ai, double c, int tr, const double* rhs, double* x)
+    int stage_solve(const StageOps& op, int tr, const double* rhs, double* x)
     {
         const int m = restart, maxit = 20 * restart;
         const int* skip = &gms->done;
-        const double bn = norm(rhs);
+        const double* b = rhs;
+        if (tr) { prec(op.Pinv, 1, rhs, gm_b); b = gm_b; }
+        const double bn = norm(b);
         zero(x);
         if (bn == 0.0) return 0;
         const double tol = cfg.lin_rtol * bn;
         double* r = we;
         double* w = we;
-        double* z = wf;
+        double* y = gm_y;
+        zero(y);
         int total = 0;
-        copy(rhs, r);
+        copy(b, r);
         for (;;) {
             k_multidot<<<RED_BLOCKS, RED_THREADS, 0, st>>>(r, 0, 1, r, Nu, part);
             LAUNCHCHK();
@@ -863,14 +881,15 @@ struct Solver final : pa_ctx {
             int jend = m;
             for (int j = 0; j < m; ++j) {
                 double* vj = V + (int64_t)j * Nu;
-                prec(Ai, tr, vj, z, skip);
-                bsr(J, 1.0, -c, tr, z, w, skip);
-                k_gm_dot<<<RED_BLOCKS, RED_THREADS, 0, st>>>(V, Nu, j + 1, 0, w, Nu, part, gms);
-                k_gm_red1<<<1, PRED_THREADS, 0, st>>>(part, RED_BLOCKS, j + 1, gms);
-                k_gm_upd1<<<grid1(Nu), 256, 0, st>>>(V, Nu, j + 1, w, Nu, gms);
+                double* vnext = V + (int64_t)(j + 1) * Nu;
+                ahat(op.Ah, tr, vj, w, skip);
+                // classical Gram-Schmidt, second pass only when flagged on the device
                 k_gm_dot<<<RED_BLOCKS, RED_THREADS, 0, st>>>(V, Nu, j + 1, 1, w, Nu, part, gms);
+                k_gm_red1<<<1, PRED_THREADS, 0, st>>>(part, RED_BLOCKS, j, m, gms);
+                k_gm_upd1<<<grid1(Nu), 256, 0, st>>>(V, Nu, j + 1, w, vnext, Nu, gms);
+                k_gm_dot2<<<RED_BLOCKS, RED_THREADS, 0, st>>>(V, Nu, j + 1, w, Nu, part, gms);
                 k_gm_red2<<<1, PRED_THREADS, 0, st>>>(part, RED_BLOCKS, j, m, gms);
-                k_gm_upd2<<<grid1(Nu), 256, 0, st>>>(V, Nu, j + 1, w, V + (int64_t)(j + 1) * Nu, Nu, gms);
+                k_gm_upd2<<<grid1(Nu), 256, 0, st>>>(V, Nu, j + 1, w, vnext, Nu, gms);
                 LAUNCHCHK();
                 if ((j + 1) % GM_CHECK == 0 || j == m - 1) {
                     HIPCHK(hipMemcpyAsync(hstat, &gms->res, 16, hipMemcpyDeviceToHost, st));
@@ -878,26 +897,45 @@ struct Solver final : pa_ctx {
                     if (hstat->done) { done = true; jend = hstat->its; break; }
                 }
             }
-            // x += P^{-1} V y
+            // y += V ycoef
             k_gm_solve<<<1, 64, 0, st>>>(m, gms);
             k_gm_combine<<<grid1(Nu), 256, 0, st>>>(V, Nu, m, w, Nu, gms);
             LAUNCHCHK();
-            prec(Ai, tr, w, z);
-            axpby(1.0, z, 1.0, x);
+            axpby(1.0, w, 1.0, y);
             total += done ? jend : m;
+            if (done && !std::isfinite(hstat->res)) raise(PA_ENUMERIC, "NaN in stage GMRES");
+            // true residual r = b - Ahat y: accepts a converged cycle (the
+            // Arnoldi estimate can drift when Gram-Schmidt skips its second
+            // pass) or restarts the next one
+            ahat(op.Ah, tr, y, w);
+            lincomb(1.0, b, -1.0, w, r);
             if (done) {
-                if (!std::isfinite(hstat->res)) raise(PA_ENUMERIC, "NaN in stage GMRES");
-                if (hstat->res <= tol) break;
+                double rn = norm(r);
+                if (rn <= 2.0 * tol) break;
             }
             if (total >= maxit)
                 raise(PA_ENOCONV, "stage GMRES did not converge in %d iterations: rel. residual %.3e", total,
                       hstat->res / bn);
-            // restart from the true residual r = b - A x
-            bsr(J, 1.0, -c, tr, x, w);
-            lincomb(1.0, rhs, -1.0, w, r);
         }
+        if (tr) copy(y, x);
+        else prec(op.Pinv, 0, y, x);
         cnt_gmres += total;
         return total;
+    }
+    // out = dt J op(w) of a stage:  c J = M - A,  A = Ahat P,  A^T = P^T Ahat^T
+    void stage_jprod(const StageOps& op, int tr, const double* w, double* out, double* tmp1, double* tmp2)
+    {
+        if (!tr) {
+            prec(op.Pd, 0, w, tmp1);
+            ahat(op.Ah, 0, tmp1, tmp2);
+        } else {
+            ahat(op.Ah, 1, w, tmp1);
+            prec(op.Pd, 1, tmp1, tmp2);
+        }
+        // dt J w = (dt / c)(M w - A w) = (M w - A w) / a_ii
+        const double ia = dt / op.aii;
+        k_mass_axpy<NP><<<grid1(Nu), 256, 0, st>>>(Ne, dm.area, dmh, w, tmp2, ia, -ia, out);
+        LAUNCHCHK();
     }
     struct GmHost { double res; int done; int its; };
     GmState* gms = nullptr;
@@ -1003,8 +1041,27 @@ struct Solver final : pa_ctx {
             }
     }
 
-    double* stJ(int s) { return tJ + (int64_t)s * Jsz; }
-    double* stA(int s) { return tAi + (int64_t)s * Isz; }
+    StageOps ops(int s) const
+    {
+        return { tAh + (int64_t)s * 3 * Isz, tPd + (int64_t)s * Isz, tAi + (int64_t)s * Isz,
+                 dt * rk.A[s % 3][s % 3] };
+    }
+    // dr/du at (n, i, u) -> Jtmp, then P, P^{-1} and Ahat of A = M - c J into stage slot s
+    void assemble(int n, int i, const double* u, double c, int s)
+    {
+        jacobian(n, i, u, Jtmp);
+        prepare_ops(Jtmp, c, s);
+    }
+    void prepare_ops(const double* J, double c, int s)
+    {
+        hipEvent_t e;
+        tstart(PA_K_BLOCKINV, &e);
+        k_blockprep<NP><<<Ne, 64, 0, st>>>(Ne, dm.area, dmh, J, c, tPd + (int64_t)s * Isz, tAi + (int64_t)s * Isz,
+                                          dstatus);
+        k_form_ahat<NP><<<Ne * 3, 64, 0, st>>>(Ne, dm.enb, J, c, tAi + (int64_t)s * Isz, tAh + (int64_t)s * 3 * Isz);
+        LAUNCHCHK();
+        tstop(e);
+    }
     double* stK(int s) { return tk + (int64_t)s * Nu; }
     double* stU(int s) { return tui + (int64_t)s * Nu; }
 
@@ -1056,9 +1113,8 @@ struct Solver final : pa_ctx {
                     if (!std::isfinite(nR)) raise(PA_ENUMERIC, "NaN at stage (%d,%d)", n, i);
                     if (it >= cfg.newton_maxit)
                         raise(PA_ENOCONV, "stage Newton did not converge at (%d,%d): |R| = %.3e", n, i, nR);
-                    jacobian(n, i, ui, stJ(s));
-                    blockinv(stJ(s), c, stA(s));
-                    stage_solve(stJ(s), stA(s), c, 0, R, dk);
+                    assemble(n, i, ui, c, s);
+                    stage_solve(ops(s), 0, R, dk);
                     // backtracking on ||R||: halve until it decreases (NaN counts as no decrease)
                     double lam = 1.0, nT;
                     for (;;) {
@@ -1075,8 +1131,7 @@ struct Solver final : pa_ctx {
                     if (verbose > 1) fprintf(stderr, "[pa] stage (%d,%d) it %d lam %.3g |R| = %.3e\n", n, i, it, lam, nR);
                 }
                 // exact linearisation at the converged stage state
-                jacobian(n, i, ui, stJ(s));
-                blockinv(stJ(s), c, stA(s));
+                assemble(n, i, ui, c, s);
                 qoi_values(n, i, ui, qh + (int64_t)s * std::max(nwall, 1) * 2);
                 done_stages = s + 1 - (i == 3 ? 1 : 0);   // u^(n) is written after the step
             }
@@ -1118,8 +1173,8 @@ struct Solver final : pa_ctx {
                 const int s = (n - 1) * 3 + (i - 1);
                 copy(du, w);
                 for (int j = 1; j < i; ++j) axpby(rk.A[i - 1][j - 1], sk3 + (int64_t)(j - 1) * Nu, 1.0, w);
-                bsr(stJ(s), 0.0, dt, 0, w, rhs);
-                stage_solve(stJ(s), stA(s), dt * rk.A[i - 1][i - 1], 0, rhs, sk3 + (int64_t)(i - 1) * Nu);
+                stage_jprod(ops(s), 0, w, rhs, gm_b, gm_y);
+                stage_solve(ops(s), 0, rhs, sk3 + (int64_t)(i - 1) * Nu);
             }
             for (int i = 0; i < 3; ++i) axpby(rk.b[i], sk3 + (int64_t)i * Nu, 1.0, du);
         }
@@ -1152,8 +1207,8 @@ struct Solver final : pa_ctx {
                 if (fq >= 0)
                     for (int j = i; j <= 3; ++j)
                         axpby(sc * rk.b[j - 1] * rk.A[j - 1][i - 1], fp3 + (int64_t)(j - 1) * Nu, 1.0, rhs);
-                stage_solve(stJ(s), stA(s), dt * rk.A[i - 1][i - 1], 1, rhs, kap);
-                bsr(stJ(s), 0.0, dt, 1, kap, sk3 + (int64_t)(i - 1) * Nu);
+                stage_solve(ops(s), 1, rhs, kap);
+                stage_jprod(ops(s), 1, kap, sk3 + (int64_t)(i - 1) * Nu, gm_b, gm_y);
                 if (fq >= 0) {
                     dr_dmu(n, i, stU(s), drm);
                     double d[3];
@@ -1272,6 +1327,7 @@ struct Solver final : pa_ctx {
     }
     double *outer_x = nullptr, *outer_w = nullptr, *outer_z = nullptr, *outer_rhs = nullptr, *lam_buf = nullptr;
     double *nk_delta = nullptr, *nk_save = nullptr;
+    double *gm_b = nullptr, *gm_y = nullptr;
     double last_outer_rel = 0;
 
     void adjoint_gradient(double rtol, double qoi[2], double dJ[6], pa_adjoint_report* rep) override
@@ -1359,9 +1415,8 @@ struct Solver final : pa_ctx {
     {
         check_stage(n, i);
         h2d(wd, u, sizeof(double) * Nu);
-        jacobian(n, i, wd, tJ);
-        HIPCHK(hipStreamSynchronize(st));
-        d2h(blk, tJ, sizeof(double) * Jsz);
+        jacobian(n, i, wd, Jtmp);
+        d2h(blk, Jtmp, sizeof(double) * Jsz);
         have_traj = false;
     }
     void dbg_qoi(int n, int i, const double* u, double f[2], double* dfdu, double* dfdmu) override
@@ -1383,18 +1438,18 @@ struct Solver final : pa_ctx {
     }
     void dbg_bsr_apply(const double* blk, double alpha, double beta, int tr, const double* x, double* y) override
     {
-        h2d(tJ, blk, sizeof(double) * Jsz);
+        h2d(Jtmp, blk, sizeof(double) * Jsz);
         h2d(wd, x, sizeof(double) * Nu);
-        bsr(tJ, alpha, beta, tr, wd, wf);
+        bsr(Jtmp, alpha, beta, tr, wd, wf);
         HIPCHK(hipStreamSynchronize(st));
         d2h(y, wf, sizeof(double) * Nu);
         have_traj = false;
     }
     void dbg_blockinv(const double* blk, double adt, double* out) override
     {
-        h2d(tJ, blk, sizeof(double) * Jsz);
+        h2d(Jtmp, blk, sizeof(double) * Jsz);
         HIPCHK(hipMemsetAsync(dstatus, 0, sizeof(int), st));
-        blockinv(tJ, adt, tAi);
+        prepare_ops(Jtmp, adt, 0);
         int stt = 0;
         HIPCHK(hipMemcpyAsync(&stt, dstatus, sizeof(int), hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -1404,10 +1459,12 @@ struct Solver final : pa_ctx {
     }
     int dbg_stage_solve(const double* blk, double adt, int tr, const double* rhs, double* x) override
     {
-        h2d(tJ, blk, sizeof(double) * Jsz);
-        blockinv(tJ, adt, tAi);
+        h2d(Jtmp, blk, sizeof(double) * Jsz);
+        prepare_ops(Jtmp, adt, 0);
         h2d(wd, rhs, sizeof(double) * Nu);
-        int its = stage_solve(tJ, tAi, adt, tr, wd, wc);
+        StageOps op = ops(0);
+        op.aii = adt;
+        int its = stage_solve(op, tr, wd, wc);
         HIPCHK(hipStreamSynchronize(st));
         d2h(x, wc, sizeof(double) * Nu);
         have_traj = false;
@@ -1436,11 +1493,10 @@ struct Solver final : pa_ctx {
         hipEvent_t a, b;
         HIPCHK(hipEventCreate(&a));
         HIPCHK(hipEventCreate(&b));
-        double c = dt * rk.A[0][0];
-        bsr(stJ(0), 1.0, -c, tr, u0, wf);
+        const double* Ah = ops(0).Ah;
+        ahat(Ah, tr, u0, wf);
         HIPCHK(hipEventRecord(a, st));
-        for (int r = 0; r < reps; ++r)
-            k_bsr_apply<NP><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, dm.area, dmh, stJ(0), u0, wf, 1.0, -c, tr, nullptr);
+        for (int r = 0; r < reps; ++r) k_ahat_apply<NP><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, Ah, u0, wf, tr, nullptr);
         LAUNCHCHK();
         HIPCHK(hipEventRecord(b, st));
         HIPCHK(hipEventSynchronize(b));
@@ -1448,6 +1504,29 @@ struct Solver final : pa_ctx {
         HIPCHK(hipEventElapsedTime(&ms, a, b));
         (void)hipEventDestroy(a);
         (void)hipEventDestroy(b);
+        return ms / reps;
+    }
+
+    // plain device-to-device copy of the first stage's stored operator
+    // (a copy kernel of known size, used to calibrate traffic counters)
+    double bench_copy(int reps, int64_t* bytes) override
+    {
+        if (nst < 2) raise(PA_EINVAL, "needs at least two stored stages");
+        const size_t nb = sizeof(double) * 3 * (size_t)Isz;
+        hipEvent_t a, b;
+        HIPCHK(hipEventCreate(&a));
+        HIPCHK(hipEventCreate(&b));
+        HIPCHK(hipMemcpyAsync(tAh + 3 * Isz, tAh, nb, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipEventRecord(a, st));
+        for (int r = 0; r < reps; ++r) HIPCHK(hipMemcpyAsync(tAh + 3 * Isz, tAh, nb, hipMemcpyDeviceToDevice, st));
+        HIPCHK(hipEventRecord(b, st));
+        HIPCHK(hipEventSynchronize(b));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, a, b));
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        have_traj = false;
+        if (bytes) *bytes = (int64_t)nb;
         return ms / reps;
     }
 
@@ -1639,6 +1718,13 @@ pa_status pa_set_timing(pa_ctx* c, int32_t on) { return guard(c, [&] { c->set_ti
 pa_status pa_kernel_time(pa_ctx* c, int32_t k, double* ms, int64_t* cnt)
 {
     return guard(c, [&] { c->kernel_time(k, ms, cnt); });
+}
+pa_status pa_bench_copy(pa_ctx* c, int32_t reps, double* avg, int64_t* bytes)
+{
+    return guard(c, [&] {
+        if (reps < 1 || !avg) raise(PA_EINVAL, "bad arguments");
+        *avg = c->bench_copy(reps, bytes);
+    });
 }
 pa_status pa_bench_spmv(pa_ctx* c, int32_t reps, int32_t tr, double* avg)
 {

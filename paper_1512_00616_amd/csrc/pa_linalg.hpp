@@ -11,8 +11,8 @@
 //   J^T is a gather: row K of J^T takes the diagonal block transposed and,
 //   for each neighbour, the neighbour's block that points back at K (its
 //   slot 1 + twin) transposed -- no atomics.
-// * k_blockinv:    block-Jacobi preconditioner: LU with partial pivoting of
-//   every diagonal block of A_i in LDS, then the explicit inverse.
+// * k_blockprep / k_form_ahat / k_ahat_apply (below): the block-Jacobi
+//   factor folded into the stored operator.
 // * GMRES vector kernels with fixed-order (deterministic) reductions.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -76,82 +76,6 @@ __global__ void __launch_bounds__(64) k_bsr_apply(int Ne, const int32_t* __restr
         }
         y[(int64_t)K * B + lane] = alpha * mv + beta * acc;
     }
-}
-
-// inverse of every diagonal block of A = M - c J (partial pivoting, lowest
-// row on ties); Ainv [Ne][B][B] row-major
-template <int NP>
-__global__ void __launch_bounds__(64) k_blockinv(int Ne, const double* __restrict__ area, const double* __restrict__ mh,
-                                                 const double* __restrict__ J, double c, double* __restrict__ Ainv,
-                                                 int* __restrict__ status)
-{
-    constexpr int B = 4 * NP, BB = B * B;
-    __shared__ double a[B][B + 1];
-    __shared__ double inv[B][B + 1];
-    __shared__ int piv[B];
-    __shared__ int sp;
-    const int K = blockIdx.x, lane = threadIdx.x;
-    const double* src = J + (int64_t)K * 4 * BB;
-    const double s2 = 2.0 * area[K];
-    for (int t = lane; t < BB; t += 64) {
-        int i = t / B, j = t % B;
-        double mm = ((i & 3) == (j & 3)) ? s2 * mh[(i >> 2) * NP + (j >> 2)] : 0.0;
-        a[i][j] = mm - c * src[t];
-    }
-    __syncthreads();
-    for (int k = 0; k < B; ++k) {
-        if (lane == 0) {
-            int p = k;
-            double best = fabs(a[k][k]);
-            for (int i = k + 1; i < B; ++i) {
-                double v = fabs(a[i][k]);
-                if (v > best) { best = v; p = i; }
-            }
-            piv[k] = p;
-            sp = p;
-            if (best == 0.0) status[0] = 1;
-        }
-        __syncthreads();
-        int p = sp;
-        if (p != k) {
-            for (int j = lane; j < B; j += 64) {
-                double t = a[k][j];
-                a[k][j] = a[p][j];
-                a[p][j] = t;
-            }
-        }
-        __syncthreads();
-        double d = a[k][k];
-        for (int i = k + 1 + lane; i < B; i += 64) a[i][k] /= d;
-        __syncthreads();
-        for (int t = lane; t < (B - k - 1) * (B - k - 1); t += 64) {
-            int i = k + 1 + t / (B - k - 1), j = k + 1 + t % (B - k - 1);
-            a[i][j] -= a[i][k] * a[k][j];
-        }
-        __syncthreads();
-    }
-    // column c of the inverse solves L U x = P e_c (each lane owns one column of inv)
-    if (lane < B) {
-        const int col = lane;
-        for (int i = 0; i < B; ++i) inv[i][col] = (i == col) ? 1.0 : 0.0;
-        for (int k = 0; k < B; ++k) {
-            int p = piv[k];
-            if (p != k) { double t = inv[k][col]; inv[k][col] = inv[p][col]; inv[p][col] = t; }
-        }
-        for (int i = 0; i < B; ++i) {
-            double s = inv[i][col];
-            for (int j = 0; j < i; ++j) s -= a[i][j] * inv[j][col];
-            inv[i][col] = s;
-        }
-        for (int i = B - 1; i >= 0; --i) {
-            double s = inv[i][col];
-            for (int j = i + 1; j < B; ++j) s -= a[i][j] * inv[j][col];
-            inv[i][col] = s / a[i][i];
-        }
-    }
-    __syncthreads();
-    double* dst = Ainv + (int64_t)K * BB;
-    for (int t = lane; t < BB; t += 64) dst[t] = inv[t / B][t % B];
 }
 
 // z_K = Ainv_K x_K  (trans: Ainv_K^T x_K)
@@ -248,7 +172,8 @@ __device__ __forceinline__ void reduce_partials_block(const double* __restrict__
         int c = c0 + cl;
         double s = 0.0;
         if (c < nc)
-            for (int b = t; b < nblk; b += 8) s += partial[(int64_t)b * nc + c];
+    #pragma unroll 4
+        for (int b = t; b < nblk; b += 8) s += partial[(int64_t)b * nc + c];
         sl[t][cl] = s;
         __syncthreads();
         if (t == 0 && c < nc) {
@@ -328,6 +253,7 @@ struct GmState {
     double h2[GM_MAXM + 2];              // second pass (reorthogonalisation)
     double inv_hn;                       // 1 / ||w|| after orthogonalisation
     double tol;                          // absolute residual target
+    int reorth;                          // 1: this column needs the second Gram-Schmidt pass
     double res;                          // current residual estimate
     int done;                            // 1: converged or happy breakdown
     int its;                             // columns of the cycle when done
@@ -342,34 +268,11 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_dot(const double* __restrict
     block_dots(V, ldv, ncols, ncols + with_ww, w, n, partial);
 }
 
-// first pass: hc[c] = sum_blk partial[blk][c]
-__global__ void __launch_bounds__(PRED_THREADS) k_gm_red1(const double* __restrict__ partial, int nblk, int ncols,
-                                                          GmState* __restrict__ st)
+// Givens update of column j of H (entries already in H[0..j][j] and the
+// subdiagonal norm hn): rotations, residual estimate, convergence flag
+__device__ __forceinline__ void gm_givens(GmState* st, int j, int m, double hn)
 {
-    if (st->done) return;
-    reduce_partials_block(partial, nblk, ncols, st->hc);
-}
-
-// second pass + Givens: column j of H = hc + h2, ||w|| from <w,w> - |h2|^2,
-// rotations, residual estimate; sets done on convergence or breakdown
-__global__ void __launch_bounds__(PRED_THREADS) k_gm_red2(const double* __restrict__ partial, int nblk, int j, int m,
-                                                          GmState* __restrict__ st)
-{
-    if (st->done) return;
-    __shared__ double s2[GM_MAXM + 2];
-    const int ncols = j + 1, nc = j + 2;
-    reduce_partials_block(partial, nblk, nc, s2);
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    double corr = 0.0;
-    for (int i = 0; i < ncols; ++i) {
-        st->h2[i] = s2[i];
-        corr += s2[i] * s2[i];
-    }
-    double ww = s2[ncols] - corr;
-    double hn = ww > 0.0 ? sqrt(ww) : 0.0;
     double* H = st->H;
-    for (int i = 0; i < ncols; ++i) H[i * m + j] = st->hc[i] + st->h2[i];
     H[(j + 1) * m + j] = hn;
     for (int i = 0; i < j; ++i) {
         double a = H[i * m + j], b = H[(i + 1) * m + j];
@@ -393,28 +296,91 @@ __global__ void __launch_bounds__(PRED_THREADS) k_gm_red2(const double* __restri
     }
 }
 
-// w -= sum_c hc[c] V_c   (first Gram-Schmidt pass)
-__global__ void k_gm_upd1(const double* __restrict__ V, int64_t ldv, int ncols, double* __restrict__ w, int64_t n,
-                          const GmState* __restrict__ st)
+// first pass: hc[c] = <V_c, w> (c <= j) and <w, w> from the partials.  With
+// orthonormal V, ||w - V hc||^2 = <w,w> - |hc|^2.  Classical Gram-Schmidt
+// loses orthogonality in proportion to ||w|| / ||w - V hc||; while that ratio
+// stays below 100 (orthogonality error ~1e-14, norm from the difference of
+// squares good to ~1e-12) the column is finished here, otherwise the second
+// pass is flagged.
+__global__ void __launch_bounds__(PRED_THREADS) k_gm_red1(const double* __restrict__ partial, int nblk, int j, int m,
+                                                          GmState* __restrict__ st)
 {
     if (st->done) return;
+    __shared__ double s1[GM_MAXM + 2];
+    const int ncols = j + 1, nc = j + 2;
+    reduce_partials_block(partial, nblk, nc, s1);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double proj = 0.0;
+    for (int i = 0; i < ncols; ++i) {
+        st->hc[i] = s1[i];
+        proj += s1[i] * s1[i];
+    }
+    double ww = s1[ncols];
+    double rem = ww - proj;
+    if (rem > 1e-4 * ww) {
+        st->reorth = 0;
+        for (int i = 0; i < ncols; ++i) st->H[i * m + j] = st->hc[i];
+        gm_givens(st, j, m, sqrt(rem));
+    } else {
+        st->reorth = 1;
+    }
+}
+
+// second pass (only when flagged): h2 = <V_c, w'>, ||w' - V h2|| from
+// <w',w'> - |h2|^2, column j = hc + h2, Givens
+__global__ void __launch_bounds__(PRED_THREADS) k_gm_red2(const double* __restrict__ partial, int nblk, int j, int m,
+                                                          GmState* __restrict__ st)
+{
+    if (st->done || !st->reorth) return;
+    __shared__ double s2[GM_MAXM + 2];
+    const int ncols = j + 1, nc = j + 2;
+    reduce_partials_block(partial, nblk, nc, s2);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    double corr = 0.0;
+    for (int i = 0; i < ncols; ++i) {
+        st->h2[i] = s2[i];
+        corr += s2[i] * s2[i];
+    }
+    double ww = s2[ncols] - corr;
+    for (int i = 0; i < ncols; ++i) st->H[i * m + j] = st->hc[i] + st->h2[i];
+    gm_givens(st, j, m, ww > 0.0 ? sqrt(ww) : 0.0);
+}
+
+// after the first pass: without reorthogonalisation V_{j+1} = (w - V hc)/||.||
+// directly; with it, w <- w - V hc for the second pass
+__global__ void k_gm_upd1(const double* __restrict__ V, int64_t ldv, int ncols, double* __restrict__ w,
+                          double* __restrict__ vnext, int64_t n, const GmState* __restrict__ st)
+{
+    if (st->done) return;   // converged: the cycle needs no further basis vector
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double s = 0.0;
     for (int c = 0; c < ncols; ++c) s += st->hc[c] * V[(int64_t)c * ldv + i];
-    w[i] -= s;
+    if (st->reorth) w[i] -= s;
+    else vnext[i] = (w[i] - s) * st->inv_hn;
 }
 
-// V_{j+1} = (w - sum_c h2[c] V_c) / ||.||
+// second pass: V_{j+1} = (w - sum_c h2[c] V_c) / ||.||
 __global__ void k_gm_upd2(const double* __restrict__ V, int64_t ldv, int ncols, const double* __restrict__ w,
                           double* __restrict__ vnext, int64_t n, const GmState* __restrict__ st)
 {
-    if (st->done) return;
+    if (st->done || !st->reorth) return;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double s = 0.0;
     for (int c = 0; c < ncols; ++c) s += st->h2[c] * V[(int64_t)c * ldv + i];
     vnext[i] = (w[i] - s) * st->inv_hn;
+}
+
+// second-pass dot products, only when reorthogonalisation is flagged
+__global__ void __launch_bounds__(RED_THREADS) k_gm_dot2(const double* __restrict__ V, int64_t ldv, int ncols,
+                                                         const double* __restrict__ w, int64_t n,
+                                                         double* __restrict__ partial, const GmState* __restrict__ st)
+{
+    if (st->done || !st->reorth) return;
+    block_dots(V, ldv, ncols, ncols + 1, w, n, partial);
 }
 
 // start of a cycle: V_0 = r / beta, g = beta e_1 (beta = sqrt(<r,r>) from partials)
@@ -434,6 +400,7 @@ __global__ void __launch_bounds__(PRED_THREADS) k_gm_start(const double* __restr
     st->inv_hn = beta > 0.0 ? 1.0 / beta : 0.0;
     st->done = (beta > tol) ? 0 : 1;
     st->its = 0;
+    st->reorth = 0;
 }
 
 __global__ void k_gm_scale0(const double* __restrict__ r, double* __restrict__ v0, int64_t n, const GmState* __restrict__ st)
@@ -466,6 +433,212 @@ __global__ void k_gm_combine(const double* __restrict__ V, int64_t ldv, int m, d
     double s = 0.0;
     for (int c = 0; c < k; ++c) s += st->y[c] * V[(int64_t)c * ldv + i];
     out[i] = s;
+}
+
+}  // namespace pa
+
+namespace pa {
+
+// ------------------------------------------------------------------ preconditioned stage operator
+// A = M - c J with the block-Jacobi factor P = blockdiag(A) folded in:
+//   Ahat = A P^{-1}:  Ahat_KK = I,  Ahat_{K,nb} = -c J_{K,nb} P_nb^{-1}.
+// Forward solves (right preconditioning):   Ahat y = b,  x = P^{-1} y.
+// Transposed solves (left preconditioning): Ahat^T x = P^{-T} b.
+// Only the three off-diagonal blocks of a row are streamed per iteration.
+
+// P (diagonal blocks of A) and P^{-1}: LU with partial pivoting (lowest row
+// on ties) of each diagonal block in LDS, then the explicit inverse.
+template <int NP>
+__global__ void __launch_bounds__(64) k_blockprep(int Ne, const double* __restrict__ area, const double* __restrict__ mh,
+                                                  const double* __restrict__ J, double c, double* __restrict__ Pd,
+                                                  double* __restrict__ Pinv, int* __restrict__ status)
+{
+    constexpr int B = 4 * NP, BB = B * B;
+    __shared__ double a[B][B + 1];
+    __shared__ double inv[B][B + 1];
+    __shared__ int piv[B];
+    __shared__ int sp;
+    const int K = blockIdx.x, lane = threadIdx.x;
+    const double* src = J + (int64_t)K * 4 * BB;
+    const double s2 = 2.0 * area[K];
+    double* pd = Pd + (int64_t)K * BB;
+    for (int t = lane; t < BB; t += 64) {
+        int i = t / B, j = t % B;
+        double mm = ((i & 3) == (j & 3)) ? s2 * mh[(i >> 2) * NP + (j >> 2)] : 0.0;
+        double v = mm - c * src[t];
+        a[i][j] = v;
+        pd[t] = v;
+    }
+    __syncthreads();
+    for (int k = 0; k < B; ++k) {
+        if (lane == 0) {
+            int p = k;
+            double best = fabs(a[k][k]);
+            for (int i = k + 1; i < B; ++i) {
+                double v = fabs(a[i][k]);
+                if (v > best) { best = v; p = i; }
+            }
+            piv[k] = p;
+            sp = p;
+            if (best == 0.0) status[0] = 1;
+        }
+        __syncthreads();
+        int p = sp;
+        if (p != k)
+            for (int j = lane; j < B; j += 64) {
+                double t = a[k][j];
+                a[k][j] = a[p][j];
+                a[p][j] = t;
+            }
+        __syncthreads();
+        double d = a[k][k];
+        for (int i = k + 1 + lane; i < B; i += 64) a[i][k] /= d;
+        __syncthreads();
+        for (int t = lane; t < (B - k - 1) * (B - k - 1); t += 64) {
+            int i = k + 1 + t / (B - k - 1), j = k + 1 + t % (B - k - 1);
+            a[i][j] -= a[i][k] * a[k][j];
+        }
+        __syncthreads();
+    }
+    if (lane < B) {
+        const int col = lane;
+        for (int i = 0; i < B; ++i) inv[i][col] = (i == col) ? 1.0 : 0.0;
+        for (int k = 0; k < B; ++k) {
+            int p = piv[k];
+            if (p != k) { double t = inv[k][col]; inv[k][col] = inv[p][col]; inv[p][col] = t; }
+        }
+        for (int i = 0; i < B; ++i) {
+            double s = inv[i][col];
+            for (int j = 0; j < i; ++j) s -= a[i][j] * inv[j][col];
+            inv[i][col] = s;
+        }
+        for (int i = B - 1; i >= 0; --i) {
+            double s = inv[i][col];
+            for (int j = i + 1; j < B; ++j) s -= a[i][j] * inv[j][col];
+            inv[i][col] = s / a[i][i];
+        }
+    }
+    __syncthreads();
+    double* dst = Pinv + (int64_t)K * BB;
+    for (int t = lane; t < BB; t += 64) dst[t] = inv[t / B][t % B];
+}
+
+// Ahat_{K,f} = -c J_{K,1+f} Pinv_nb (zero block when face f is on the boundary);
+// one workgroup per (element, face)
+template <int NP>
+__global__ void __launch_bounds__(64) k_form_ahat(int Ne, const int32_t* __restrict__ enb, const double* __restrict__ J,
+                                                  double c, const double* __restrict__ Pinv, double* __restrict__ Ah)
+{
+    constexpr int B = 4 * NP, BB = B * B;
+    __shared__ double sj[B][B + 1];
+    __shared__ double sp[B][B + 1];
+    const int K = blockIdx.x / 3, f = blockIdx.x % 3, lane = threadIdx.x;
+    const int nb = enb[3 * K + f];
+    double* dst = Ah + ((int64_t)K * 3 + f) * BB;
+    if (nb < 0) {
+        for (int t = lane; t < BB; t += 64) dst[t] = 0.0;
+        return;
+    }
+    const double* js = J + ((int64_t)K * 4 + 1 + f) * BB;
+    const double* ps = Pinv + (int64_t)nb * BB;
+    for (int t = lane; t < BB; t += 64) {
+        sj[t / B][t % B] = -c * js[t];
+        sp[t / B][t % B] = ps[t];
+    }
+    __syncthreads();
+    for (int t = lane; t < BB; t += 64) {
+        int i = t / B, j = t % B;
+        double s = 0.0;
+#pragma unroll 8
+        for (int k = 0; k < B; ++k) s += sj[i][k] * sp[k][j];
+        dst[t] = s;
+    }
+}
+
+// y = x + Ahat x (forward) or y = x + Ahat^T x (transposed gather: row K of
+// Ahat^T takes, for each neighbour, the neighbour's block that points back at
+// K, transposed).  One wave per block row; the three blocks of the row are
+// loaded with 16-byte coalesced loads before any arithmetic (more bytes in
+// flight per wave) and reduced from LDS.
+template <int NP>
+__global__ void __launch_bounds__(64) k_ahat_apply(int Ne, const int32_t* __restrict__ enb, const int8_t* __restrict__ etw,
+                                                   const double* __restrict__ Ah, const double* __restrict__ x,
+                                                   double* __restrict__ y, int trans, const int* __restrict__ skip)
+{
+    constexpr int B = 4 * NP, BB = B * B, H = BB / 2;
+    constexpr int PER = (H + 63) / 64;   // 16-byte loads per lane per block
+    __shared__ double sblk[3][B][B + 1];
+    __shared__ double sx[3][B];
+    if (skip && *skip) return;
+    const int K = blockIdx.x, lane = threadIdx.x;
+    int nbs[3];
+    const double2* src[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        int nb = enb[3 * K + f];
+        nbs[f] = nb;
+        src[f] = nullptr;
+        if (nb >= 0) {
+            int64_t blk = trans ? (int64_t)nb * 3 + etw[3 * K + f] : (int64_t)K * 3 + f;
+            src[f] = reinterpret_cast<const double2*>(Ah + blk * BB);
+        }
+    }
+    double2 v[3][PER];
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            int t = lane + 64 * r;
+            if (src[f] && t < H) v[f][r] = src[f][t];
+        }
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+        if (nbs[f] >= 0 && lane < B) sx[f][lane] = x[(int64_t)nbs[f] * B + lane];
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            int t = lane + 64 * r;
+            if (src[f] && t < H) {
+                int e = 2 * t;
+                sblk[f][e / B][e % B] = v[f][r].x;
+                sblk[f][(e + 1) / B][(e + 1) % B] = v[f][r].y;
+            }
+        }
+    __syncthreads();
+    if (lane < B) {
+        double acc = x[(int64_t)K * B + lane];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            if (nbs[f] < 0) continue;
+            double a = 0.0;
+            if (!trans) {
+#pragma unroll 8
+                for (int j = 0; j < B; ++j) a += sblk[f][lane][j] * sx[f][j];
+            } else {
+#pragma unroll 8
+                for (int i = 0; i < B; ++i) a += sblk[f][i][lane] * sx[f][i];
+            }
+            acc += a;
+        }
+        y[(int64_t)K * B + lane] = acc;
+    }
+}
+
+// out = alpha M x + beta y  (M applied block-wise)
+template <int NP>
+__global__ void k_mass_axpy(int Ne, const double* __restrict__ area, const double* __restrict__ mh,
+                            const double* __restrict__ x, const double* __restrict__ y, double alpha, double beta,
+                            double* __restrict__ out)
+{
+    constexpr int B = 4 * NP;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)Ne * B) return;
+    int K = (int)(i / B), l = (int)(i % B), a = l >> 2, m = l & 3;
+    const double* xK = x + (int64_t)K * B;
+    double s = 0.0;
+    for (int b = 0; b < NP; ++b) s += mh[a * NP + b] * xK[b * 4 + m];
+    out[i] = alpha * 2.0 * area[K] * s + beta * y[i];
 }
 
 }  // namespace pa

@@ -21,7 +21,7 @@ EXPORTED = [
     "pa_get_state", "pa_primal_period", "pa_shoot", "pa_fixed_point", "pa_adjoint_gradient", "pa_tangent_sweep",
     "pa_adjoint_sweep", "pa_dbg_gbar", "pa_dbg_dgbar", "pa_dbg_residual", "pa_dbg_jacobian", "pa_dbg_dr_dmu",
     "pa_dbg_qoi", "pa_dbg_bsr_apply", "pa_dbg_blockinv", "pa_dbg_stage_solve", "pa_dbg_traj", "pa_set_timing",
-    "pa_kernel_time", "pa_bench_spmv",
+    "pa_kernel_time", "pa_bench_spmv", "pa_bench_copy",
 ]
 
 
@@ -102,6 +102,7 @@ def lib():
             "pa_set_timing": [P, C.c_int32],
             "pa_kernel_time": [P, C.c_int32, P, P],
             "pa_bench_spmv": [P, C.c_int32, C.c_int32, P],
+            "pa_bench_copy": [P, C.c_int32, P, P],
         }
         for fn, args in sig.items():
             f = getattr(L, fn)
@@ -199,9 +200,14 @@ class Solver:
         self._chk(lib().pa_primal_period(self._c, _ptr(q), _ptr(r)))
         return q, float(r[0])
 
-    def shoot(self, tol=1e-8, eta=1e-3, maxit=30):
+    def shoot(self, tol=1e-8, eta=1e-3, maxit=30, allow_unconverged=False):
+        """Newton-Krylov shooting; with allow_unconverged the report of a run
+        that stopped at maxit Newton steps is returned instead of raising."""
         rep = pa_shoot_report()
-        self._chk(lib().pa_shoot(self._c, tol, eta, maxit, C.byref(rep)))
+        rc = lib().pa_shoot(self._c, tol, eta, maxit, C.byref(rep))
+        if rc == PA_ENOCONV and allow_unconverged and rep.primal_sweeps > 0:
+            return rep
+        self._chk(rc)
         return rep
 
     def fixed_point(self, periods):
@@ -297,6 +303,12 @@ class Solver:
         cnt = C.c_int64()
         self._chk(lib().pa_kernel_time(self._c, k, C.byref(ms), C.byref(cnt)))
         return ms.value, cnt.value
+
+    def bench_copy(self, reps=20):
+        ms = C.c_double()
+        nb = C.c_int64()
+        self._chk(lib().pa_bench_copy(self._c, reps, C.byref(ms), C.byref(nb)))
+        return ms.value, nb.value
 
     def bench_spmv(self, reps=50, transpose=False):
         ms = C.c_double()
