@@ -883,13 +883,10 @@ struct Solver final : pa_ctx {
                 double* vj = V + (int64_t)j * Nu;
                 double* vnext = V + (int64_t)(j + 1) * Nu;
                 ahat(op.Ah, tr, vj, w, skip);
-                // classical Gram-Schmidt, second pass only when flagged on the device
+                // one classical Gram-Schmidt pass; the cycle closes on cancellation
                 k_gm_dot<<<RED_BLOCKS, RED_THREADS, 0, st>>>(V, Nu, j + 1, 1, w, Nu, part, gms);
                 k_gm_red1<<<1, PRED_THREADS, 0, st>>>(part, RED_BLOCKS, j, m, gms);
                 k_gm_upd1<<<grid1(Nu), 256, 0, st>>>(V, Nu, j + 1, w, vnext, Nu, gms);
-                k_gm_dot2<<<RED_BLOCKS, RED_THREADS, 0, st>>>(V, Nu, j + 1, w, Nu, part, gms);
-                k_gm_red2<<<1, PRED_THREADS, 0, st>>>(part, RED_BLOCKS, j, m, gms);
-                k_gm_upd2<<<grid1(Nu), 256, 0, st>>>(V, Nu, j + 1, w, vnext, Nu, gms);
                 LAUNCHCHK();
                 if ((j + 1) % GM_CHECK == 0 || j == m - 1) {
                     HIPCHK(hipMemcpyAsync(hstat, &gms->res, 16, hipMemcpyDeviceToHost, st));
@@ -898,7 +895,7 @@ struct Solver final : pa_ctx {
                 }
             }
             // y += V ycoef
-            k_gm_solve<<<1, 64, 0, st>>>(m, gms);
+            k_gm_solve<<<1, 256, 0, st>>>(m, gms);
             k_gm_combine<<<grid1(Nu), 256, 0, st>>>(V, Nu, m, w, Nu, gms);
             LAUNCHCHK();
             axpby(1.0, w, 1.0, y);

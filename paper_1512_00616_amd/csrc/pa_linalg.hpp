@@ -117,7 +117,7 @@ constexpr int RED_BLOCKS = 256;
 // for the optional last column.  Columns are processed in groups of DOTG:
 // each thread accumulates the group in registers and the group is reduced
 // in one LDS tree (fixed order, deterministic).
-constexpr int DOTG = 8;
+constexpr int DOTG = 16;
 __device__ __forceinline__ void block_dots(const double* __restrict__ V, int64_t ldv, int ncols, int nc,
                                            const double* __restrict__ w, int64_t n, double* __restrict__ partial)
 {
@@ -129,6 +129,7 @@ __device__ __forceinline__ void block_dots(const double* __restrict__ V, int64_t
         double acc[DOTG];
 #pragma unroll
         for (int g = 0; g < DOTG; ++g) acc[g] = 0.0;
+#pragma unroll 2
         for (int64_t i = lo + tid; i < hi; i += RED_THREADS) {
             double wi = w[i];
 #pragma unroll
@@ -249,11 +250,9 @@ struct GmState {
     double cs[GM_MAXM], sn[GM_MAXM];
     double g[GM_MAXM + 1];
     double y[GM_MAXM];
-    double hc[GM_MAXM + 2];              // first Gram-Schmidt pass
-    double h2[GM_MAXM + 2];              // second pass (reorthogonalisation)
+    double hc[GM_MAXM + 2];              // Gram-Schmidt coefficients of the current column
     double inv_hn;                       // 1 / ||w|| after orthogonalisation
     double tol;                          // absolute residual target
-    int reorth;                          // 1: this column needs the second Gram-Schmidt pass
     double res;                          // current residual estimate
     int done;                            // 1: converged or happy breakdown
     int its;                             // columns of the cycle when done
@@ -268,119 +267,80 @@ __global__ void __launch_bounds__(RED_THREADS) k_gm_dot(const double* __restrict
     block_dots(V, ldv, ncols, ncols + with_ww, w, n, partial);
 }
 
-// Givens update of column j of H (entries already in H[0..j][j] and the
-// subdiagonal norm hn): rotations, residual estimate, convergence flag
-__device__ __forceinline__ void gm_givens(GmState* st, int j, int m, double hn)
-{
-    double* H = st->H;
-    H[(j + 1) * m + j] = hn;
-    for (int i = 0; i < j; ++i) {
-        double a = H[i * m + j], b = H[(i + 1) * m + j];
-        H[i * m + j] = st->cs[i] * a + st->sn[i] * b;
-        H[(i + 1) * m + j] = -st->sn[i] * a + st->cs[i] * b;
-    }
-    double a = H[j * m + j], b = H[(j + 1) * m + j];
-    double rr = sqrt(a * a + b * b);
-    st->cs[j] = a / rr;
-    st->sn[j] = b / rr;
-    H[j * m + j] = rr;
-    H[(j + 1) * m + j] = 0.0;
-    st->g[j + 1] = -st->sn[j] * st->g[j];
-    st->g[j] = st->cs[j] * st->g[j];
-    double res = fabs(st->g[j + 1]);
-    st->res = res;
-    st->inv_hn = hn > 0.0 ? 1.0 / hn : 0.0;
-    if (!(res > st->tol) || hn == 0.0 || !(res == res)) {
-        st->done = 1;
-        st->its = j + 1;
-    }
-}
-
-// first pass: hc[c] = <V_c, w> (c <= j) and <w, w> from the partials.  With
-// orthonormal V, ||w - V hc||^2 = <w,w> - |hc|^2.  Classical Gram-Schmidt
-// loses orthogonality in proportion to ||w|| / ||w - V hc||; while that ratio
-// stays below 100 (orthogonality error ~1e-14, norm from the difference of
-// squares good to ~1e-12) the column is finished here, otherwise the second
-// pass is flagged.
+// first pass of classical Gram-Schmidt: hc[c] = <V_c, w> (c <= j) and
+// <w, w> from the partials; with orthonormal V, ||w - V hc||^2 = <w,w> -
+// |hc|^2.  Column j of H is rotated by the previous Givens rotations (staged
+// in LDS by all lanes; one lane applies them) and a new rotation zeroes the
+// subdiagonal; the residual estimate is |g[j+1]|.  When the projection
+// cancels more than 99% of ||w|| (where a single Gram-Schmidt pass would
+// lose orthogonality) the cycle is closed at this column and the caller's
+// true-residual check decides whether to restart.
 __global__ void __launch_bounds__(PRED_THREADS) k_gm_red1(const double* __restrict__ partial, int nblk, int j, int m,
                                                           GmState* __restrict__ st)
 {
     if (st->done) return;
     __shared__ double s1[GM_MAXM + 2];
+    __shared__ double scs[GM_MAXM], ssn[GM_MAXM];
+    __shared__ double col[GM_MAXM + 2];
+    __shared__ double rot[4];
     const int ncols = j + 1, nc = j + 2;
     reduce_partials_block(partial, nblk, nc, s1);
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    double proj = 0.0;
-    for (int i = 0; i < ncols; ++i) {
-        st->hc[i] = s1[i];
-        proj += s1[i] * s1[i];
+    for (int i = threadIdx.x; i < j; i += blockDim.x) {
+        scs[i] = st->cs[i];
+        ssn[i] = st->sn[i];
     }
-    double ww = s1[ncols];
-    double rem = ww - proj;
-    if (rem > 1e-4 * ww) {
-        st->reorth = 0;
-        for (int i = 0; i < ncols; ++i) st->H[i * m + j] = st->hc[i];
-        gm_givens(st, j, m, sqrt(rem));
-    } else {
-        st->reorth = 1;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double proj = 0.0;
+        for (int i = 0; i < ncols; ++i) { col[i] = s1[i]; proj += s1[i] * s1[i]; }
+        double ww = s1[ncols], rem = ww - proj;
+        bool close = !(rem > 1e-4 * ww);
+        double hn = rem > 0.0 ? sqrt(rem) : 0.0;
+        col[j + 1] = hn;
+        for (int i = 0; i < j; ++i) {
+            double a = col[i], b = col[i + 1];
+            col[i] = scs[i] * a + ssn[i] * b;
+            col[i + 1] = -ssn[i] * a + scs[i] * b;
+        }
+        double a = col[j], b = col[j + 1];
+        double rr = sqrt(a * a + b * b);
+        double c = a / rr, sgn = b / rr;
+        col[j] = rr;
+        col[j + 1] = 0.0;
+        double gj = st->g[j];
+        double gj1 = -sgn * gj;
+        rot[0] = c; rot[1] = sgn; rot[2] = c * gj; rot[3] = gj1;
+        double res = fabs(gj1);
+        st->res = res;
+        st->inv_hn = hn > 0.0 ? 1.0 / hn : 0.0;
+        if (!(res > st->tol) || hn == 0.0 || close || !(res == res)) {
+            st->done = 1;
+            st->its = j + 1;
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) {
+        st->H[i * m + j] = col[i];
+        if (i <= j) st->hc[i] = s1[i];
+    }
+    if (threadIdx.x == 0) {
+        st->cs[j] = rot[0];
+        st->sn[j] = rot[1];
+        st->g[j] = rot[2];
+        st->g[j + 1] = rot[3];
     }
 }
 
-// second pass (only when flagged): h2 = <V_c, w'>, ||w' - V h2|| from
-// <w',w'> - |h2|^2, column j = hc + h2, Givens
-__global__ void __launch_bounds__(PRED_THREADS) k_gm_red2(const double* __restrict__ partial, int nblk, int j, int m,
-                                                          GmState* __restrict__ st)
-{
-    if (st->done || !st->reorth) return;
-    __shared__ double s2[GM_MAXM + 2];
-    const int ncols = j + 1, nc = j + 2;
-    reduce_partials_block(partial, nblk, nc, s2);
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    double corr = 0.0;
-    for (int i = 0; i < ncols; ++i) {
-        st->h2[i] = s2[i];
-        corr += s2[i] * s2[i];
-    }
-    double ww = s2[ncols] - corr;
-    for (int i = 0; i < ncols; ++i) st->H[i * m + j] = st->hc[i] + st->h2[i];
-    gm_givens(st, j, m, ww > 0.0 ? sqrt(ww) : 0.0);
-}
-
-// after the first pass: without reorthogonalisation V_{j+1} = (w - V hc)/||.||
-// directly; with it, w <- w - V hc for the second pass
-__global__ void k_gm_upd1(const double* __restrict__ V, int64_t ldv, int ncols, double* __restrict__ w,
+// V_{j+1} = (w - V hc) / ||w - V hc||
+__global__ void k_gm_upd1(const double* __restrict__ V, int64_t ldv, int ncols, const double* __restrict__ w,
                           double* __restrict__ vnext, int64_t n, const GmState* __restrict__ st)
 {
-    if (st->done) return;   // converged: the cycle needs no further basis vector
+    if (st->done) return;   // the cycle needs no further basis vector
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     double s = 0.0;
     for (int c = 0; c < ncols; ++c) s += st->hc[c] * V[(int64_t)c * ldv + i];
-    if (st->reorth) w[i] -= s;
-    else vnext[i] = (w[i] - s) * st->inv_hn;
-}
-
-// second pass: V_{j+1} = (w - sum_c h2[c] V_c) / ||.||
-__global__ void k_gm_upd2(const double* __restrict__ V, int64_t ldv, int ncols, const double* __restrict__ w,
-                          double* __restrict__ vnext, int64_t n, const GmState* __restrict__ st)
-{
-    if (st->done || !st->reorth) return;
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double s = 0.0;
-    for (int c = 0; c < ncols; ++c) s += st->h2[c] * V[(int64_t)c * ldv + i];
     vnext[i] = (w[i] - s) * st->inv_hn;
-}
-
-// second-pass dot products, only when reorthogonalisation is flagged
-__global__ void __launch_bounds__(RED_THREADS) k_gm_dot2(const double* __restrict__ V, int64_t ldv, int ncols,
-                                                         const double* __restrict__ w, int64_t n,
-                                                         double* __restrict__ partial, const GmState* __restrict__ st)
-{
-    if (st->done || !st->reorth) return;
-    block_dots(V, ldv, ncols, ncols + 1, w, n, partial);
 }
 
 // start of a cycle: V_0 = r / beta, g = beta e_1 (beta = sqrt(<r,r>) from partials)
@@ -400,7 +360,6 @@ __global__ void __launch_bounds__(PRED_THREADS) k_gm_start(const double* __restr
     st->inv_hn = beta > 0.0 ? 1.0 / beta : 0.0;
     st->done = (beta > tol) ? 0 : 1;
     st->its = 0;
-    st->reorth = 0;
 }
 
 __global__ void k_gm_scale0(const double* __restrict__ r, double* __restrict__ v0, int64_t n, const GmState* __restrict__ st)
@@ -409,18 +368,24 @@ __global__ void k_gm_scale0(const double* __restrict__ r, double* __restrict__ v
     if (i < n) v0[i] = r[i] * st->inv_hn;
 }
 
-// y = R^{-1} g for the first k columns (k = its if done else m)
-__global__ void k_gm_solve(int m, GmState* __restrict__ st)
+// y = R^{-1} g for the first k columns (k = its if done else m); R is
+// staged in LDS by all lanes, one lane back-substitutes
+__global__ void __launch_bounds__(256) k_gm_solve(int m, GmState* __restrict__ st)
 {
-    if (threadIdx.x != 0) return;
-    int k = st->done ? st->its : m;
-    const double* H = st->H;
-    for (int i = k - 1; i >= 0; --i) {
-        double s = st->g[i];
-        for (int c = i + 1; c < k; ++c) s -= H[i * m + c] * st->y[c];
-        st->y[i] = s / H[i * m + i];
-    }
-    for (int i = k; i < m; ++i) st->y[i] = 0.0;
+    __shared__ double R[GM_MAXM * GM_MAXM];
+    __shared__ double yy[GM_MAXM];
+    const int k = st->done ? st->its : m;
+    for (int t = threadIdx.x; t < k * k; t += blockDim.x) R[t] = st->H[(t / k) * m + (t % k)];
+    for (int t = threadIdx.x; t < k; t += blockDim.x) yy[t] = st->g[t];
+    __syncthreads();
+    if (threadIdx.x == 0)
+        for (int i = k - 1; i >= 0; --i) {
+            double s = yy[i];
+            for (int c = i + 1; c < k; ++c) s -= R[i * k + c] * yy[c];
+            yy[i] = s / R[i * k + i];
+        }
+    __syncthreads();
+    for (int t = threadIdx.x; t < m; t += blockDim.x) st->y[t] = t < k ? yy[t] : 0.0;
 }
 
 // out = sum_{c<m} y[c] V_c   (y is zero beyond the cycle's length)
