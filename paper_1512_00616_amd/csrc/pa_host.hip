@@ -323,7 +323,7 @@ struct Solver final : pa_ctx {
     double *fp3 = nullptr;                                         // 3 * Nu (QoI derivatives)
     double *drm = nullptr;                                         // 3 * Nu (dr/dmu)
     double *V = nullptr, *Vo = nullptr;                            // stage / outer Krylov bases
-    double *part = nullptr, *hdev = nullptr;
+    double *part = nullptr, *hdev = nullptr;                       // multi-dot partials / results
     double *qtmp = nullptr, *qdu = nullptr, *qdmu = nullptr;
     double *rg4 = nullptr, *kg4 = nullptr;                         // GCL work [3][4][nn]
     int64_t cnt_newton = 0, cnt_gmres = 0;
@@ -381,6 +381,8 @@ struct Solver final : pa_ctx {
         for (auto& e : evpool) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
         for (void* p : allocs) (void)hipFree(p);
         if (hstat) (void)hipHostFree(hstat);
+        for (auto& e : gm_ev)
+            if (e) (void)hipEventDestroy(e);
         if (st) (void)hipStreamDestroy(st);
     }
 
@@ -544,7 +546,7 @@ struct Solver final : pa_ctx {
         drm = dalloc<double>(3 * Nu);
         V = dalloc<double>((int64_t)(restart + 1) * Nu);
         Vo = dalloc<double>((int64_t)(max_kry + 1) * Nu);
-        part = dalloc<double>((int64_t)RED_BLOCKS * (std::max(restart, max_kry) + 2));
+        part = dalloc<double>(mdot_blocks(Nu) * (std::max(restart, max_kry) + 2));
         hdev = dalloc<double>(std::max(restart, max_kry) + 2);
         qtmp = dalloc<double>((int64_t)std::max(nwall, 1) * 2);
         qdu = dalloc<double>((int64_t)std::max(nwall, 1) * 2 * B);
@@ -559,7 +561,8 @@ struct Solver final : pa_ctx {
         nk_delta = dalloc<double>(Nu);
         nk_save = dalloc<double>(Nu);
         gms = dalloc<GmState>(1);
-        HIPCHK(hipHostMalloc((void**)&hstat, sizeof(GmHost), hipHostMallocDefault));
+        HIPCHK(hipHostMalloc((void**)&hstat, 3 * sizeof(GmHost), hipHostMallocDefault));
+        for (auto& e : gm_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         set_jacobian_smem();
     }
 
@@ -731,9 +734,9 @@ struct Solver final : pa_ctx {
     // host h[c] = <V_c, w>, c < ncols (V_c = V + c*ldv); one synchronisation
     void dots(const double* Vb, int64_t ldv, int ncols, const double* w, double* h)
     {
-        k_multidot<<<RED_BLOCKS, RED_THREADS, 0, st>>>(Vb, ldv, ncols, w, Nu, part);
-        LAUNCHCHK();
-        k_reduce_partials<<<1, PRED_THREADS, 0, st>>>(part, RED_BLOCKS, ncols, hdev);
+        const int nb = (int)mdot_blocks(Nu);
+        k_mdot_part<<<nb, MD_THREADS, 0, st>>>(Vb, ldv, ncols, 0, w, Nu, part, nullptr);
+        k_mdot_fin<<<1, MD_THREADS, 0, st>>>(part, nb, ncols, hdev);
         LAUNCHCHK();
         HIPCHK(hipMemcpyAsync(h, hdev, sizeof(double) * ncols, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -793,13 +796,9 @@ struct Solver final : pa_ctx {
                 vupdate(Vb, Nu, j + 1, h.data(), -1.0, wk);
                 // second pass; the last column returns |w|^2 for the norm
                 {
-                    k_multidot<<<RED_BLOCKS, RED_THREADS, 0, st>>>(Vb, Nu, j + 1, wk, Nu, part);
-                    LAUNCHCHK();
-                    k_multidot<<<RED_BLOCKS, RED_THREADS, 0, st>>>(wk, 0, 1, wk, Nu, part + RED_BLOCKS * (j + 1));
-                    LAUNCHCHK();
-                    k_reduce_partials<<<1, PRED_THREADS, 0, st>>>(part, RED_BLOCKS, j + 1, hdev);
-                    LAUNCHCHK();
-                    k_reduce_partials<<<1, PRED_THREADS, 0, st>>>(part + RED_BLOCKS * (j + 1), RED_BLOCKS, 1, hdev + j + 1);
+                    const int nb = (int)mdot_blocks(Nu);
+                    k_mdot_part<<<nb, MD_THREADS, 0, st>>>(Vb, Nu, j + 1, 1, wk, Nu, part, nullptr);
+                    k_mdot_fin<<<1, MD_THREADS, 0, st>>>(part, nb, j + 2, hdev);
                     LAUNCHCHK();
                     HIPCHK(hipMemcpyAsync(h2.data(), hdev, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, st));
                     HIPCHK(hipStreamSynchronize(st));
@@ -850,14 +849,16 @@ struct Solver final : pa_ctx {
     //   forward:    Ahat y = rhs,          x = P^{-1} y   (right preconditioning)
     //   transposed: Ahat^T x = P^{-T} rhs                 (left preconditioning)
     // GMRES(m) with the Arnoldi state on the device: no host round trip
-    // inside an iteration; the host reads the pinned status every GM_CHECK
-    // iterations and then only enqueues early-exiting launches if the cycle
-    // converged in between.
+    // inside an iteration.  Every GM_CHECK iterations the status is copied
+    // to pinned memory behind an event; the host waits for the previous
+    // copy only, so GM_CHECK iterations stay queued on the device while it
+    // looks.  Iterations enqueued after convergence exit at once.
     static constexpr int GM_CHECK = 5;
     int stage_solve(const StageOps& op, int tr, const double* rhs, double* x)
     {
         const int m = restart, maxit = 20 * restart;
         const int* skip = &gms->done;
+        const int nb = (int)mdot_blocks(Nu);
         const double* b = rhs;
         if (tr) { prec(op.Pinv, 1, rhs, gm_b); b = gm_b; }
         const double bn = norm(b);
@@ -871,48 +872,49 @@ struct Solver final : pa_ctx {
         int total = 0;
         copy(b, r);
         for (;;) {
-            k_multidot<<<RED_BLOCKS, RED_THREADS, 0, st>>>(r, 0, 1, r, Nu, part);
+            k_mdot_part<<<nb, MD_THREADS, 0, st>>>(r, 0, 1, 0, r, Nu, part, nullptr);
+            k_gm_begin<<<nb, MD_THREADS, 0, st>>>(r, V, Nu, part, nb, tol, gms);
             LAUNCHCHK();
-            k_gm_start<<<1, PRED_THREADS, 0, st>>>(part, RED_BLOCKS, tol, gms);
-            LAUNCHCHK();
-            k_gm_scale0<<<grid1(Nu), 256, 0, st>>>(r, V, Nu, gms);
-            LAUNCHCHK();
-            bool done = false;
-            int jend = m;
+            int pending = -1, slot = 0;
             for (int j = 0; j < m; ++j) {
                 double* vj = V + (int64_t)j * Nu;
                 double* vnext = V + (int64_t)(j + 1) * Nu;
                 ahat(op.Ah, tr, vj, w, skip);
                 // one classical Gram-Schmidt pass; the cycle closes on cancellation
-                k_gm_dot<<<RED_BLOCKS, RED_THREADS, 0, st>>>(V, Nu, j + 1, 1, w, Nu, part, gms);
-                k_gm_red1<<<1, PRED_THREADS, 0, st>>>(part, RED_BLOCKS, j, m, gms);
-                k_gm_upd1<<<grid1(Nu), 256, 0, st>>>(V, Nu, j + 1, w, vnext, Nu, gms);
+                k_mdot_part<<<nb, MD_THREADS, 0, st>>>(V, Nu, j + 1, 1, w, Nu, part, skip);
+                k_gm_upd<<<nb, MD_THREADS, 0, st>>>(V, Nu, j, m, w, vnext, Nu, part, nb, gms);
                 LAUNCHCHK();
-                if ((j + 1) % GM_CHECK == 0 || j == m - 1) {
-                    HIPCHK(hipMemcpyAsync(hstat, &gms->res, 16, hipMemcpyDeviceToHost, st));
-                    HIPCHK(hipStreamSynchronize(st));
-                    if (hstat->done) { done = true; jend = hstat->its; break; }
+                if ((j + 1) % GM_CHECK == 0 && j < m - 1) {
+                    if (pending >= 0) {
+                        HIPCHK(hipEventSynchronize(gm_ev[pending]));
+                        if (hstat[pending].done) break;
+                    }
+                    HIPCHK(hipMemcpyAsync(&hstat[slot], &gms->res, sizeof(GmHost), hipMemcpyDeviceToHost, st));
+                    HIPCHK(hipEventRecord(gm_ev[slot], st));
+                    pending = slot;
+                    slot ^= 1;
                 }
             }
+            HIPCHK(hipMemcpyAsync(&hstat[2], &gms->res, sizeof(GmHost), hipMemcpyDeviceToHost, st));
             // y += V ycoef
             k_gm_solve<<<1, 256, 0, st>>>(m, gms);
             k_gm_combine<<<grid1(Nu), 256, 0, st>>>(V, Nu, m, w, Nu, gms);
             LAUNCHCHK();
             axpby(1.0, w, 1.0, y);
-            total += done ? jend : m;
-            if (done && !std::isfinite(hstat->res)) raise(PA_ENUMERIC, "NaN in stage GMRES");
             // true residual r = b - Ahat y: accepts a converged cycle (the
             // Arnoldi estimate can drift when Gram-Schmidt skips its second
             // pass) or restarts the next one
             ahat(op.Ah, tr, y, w);
             lincomb(1.0, b, -1.0, w, r);
-            if (done) {
-                double rn = norm(r);
-                if (rn <= 2.0 * tol) break;
-            }
+            const double rn = norm(r);   // synchronises: hstat[2] is valid below
+            const bool done = hstat[2].done != 0;
+            total += done ? hstat[2].its : m;
+            if (done && !std::isfinite(hstat[2].res)) raise(PA_ENUMERIC, "NaN in stage GMRES");
+            if (!std::isfinite(rn)) raise(PA_ENUMERIC, "NaN in stage GMRES");
+            if (done && rn <= 2.0 * tol) break;
             if (total >= maxit)
                 raise(PA_ENOCONV, "stage GMRES did not converge in %d iterations: rel. residual %.3e", total,
-                      hstat->res / bn);
+                      rn / bn);
         }
         if (tr) copy(y, x);
         else prec(op.Pinv, 0, y, x);
@@ -936,7 +938,8 @@ struct Solver final : pa_ctx {
     }
     struct GmHost { double res; int done; int its; };
     GmState* gms = nullptr;
-    GmHost* hstat = nullptr;
+    GmHost* hstat = nullptr;       // pinned: two check slots and the end-of-cycle status
+    hipEvent_t gm_ev[2] = {nullptr, nullptr};
 
     // ---------------------------------------------------------------- setup
     void set_params(const double m[3]) override

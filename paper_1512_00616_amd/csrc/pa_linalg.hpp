@@ -109,89 +109,154 @@ __global__ void __launch_bounds__(64) k_block_apply(int Ne, const double* __rest
 }
 
 // ------------------------------------------------------------------ vector kernels
-constexpr int RED_THREADS = 256;
-constexpr int RED_BLOCKS = 256;
+// Multi-column dot products  s_c = <X_c, w>,  X_c = V + c*ldv (c < ncols),
+// optionally followed by <w, w>, in one launch and in a fixed summation
+// order (bitwise reproducible, no floating-point atomics):
+//   1. block b covers MD_TILE consecutive entries; each thread holds two
+//      double2 of w and, eight columns at a time, issues all sixteen
+//      16-byte loads of those columns before using any of them;
+//   2. the 32 per-thread products of a column group are summed over the
+//      wave by a halving exchange (32 shuffles for 32 columns instead of
+//      6 per column), then over the four waves through LDS;
+//   3. the block's row of partials goes to `partial[b][nc]`; the last block
+//      to finish (integer counter, reset by that block) sums the rows in
+//      block order and finishes the step (plain sums, or the Givens update
+//      of GMRES).
+constexpr int MD_THREADS = 256;
+constexpr int MD_TILE = 4 * MD_THREADS;   // doubles per block
+constexpr int MD_GROUP = 32;              // columns per reduction group
+constexpr int MD_MAXC = 256;              // column limit of a launch
+inline int64_t mdot_blocks(int64_t n) { return (n + MD_TILE - 1) / MD_TILE; }
 
-// Block partials of dot products: partial[blk][c] = sum over the block's
-// chunk of w . X_c for c < nc, where X_c = V + c*ldv for c < ncols and X_c = w
-// for the optional last column.  Columns are processed in groups of DOTG:
-// each thread accumulates the group in registers and the group is reduced
-// in one LDS tree (fixed order, deterministic).
-constexpr int DOTG = 16;
-__device__ __forceinline__ void block_dots(const double* __restrict__ V, int64_t ldv, int ncols, int nc,
-                                           const double* __restrict__ w, int64_t n, double* __restrict__ partial)
+__device__ __forceinline__ double2 ld2(const double* p) { return *reinterpret_cast<const double2*>(p); }
+
+// Column sums over a wave: on entry every lane holds p[0..31]; on exit p[0]
+// of lane l holds the wave total of column l >> 1.  Each halving exchange
+// (offset o = 2K, K columns kept) sends the half of the columns the partner
+// keeps; the lane with bit o set keeps the upper half.
+template <int K>
+__device__ __forceinline__ void colsum_halve(double (&p)[MD_GROUP], int lane)
 {
-    __shared__ double red[DOTG][RED_THREADS];
+    constexpr int o = 2 * K;
+    const bool up = (lane & o) != 0;
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+        const double keep = up ? p[c + K] : p[c];
+        const double send = up ? p[c] : p[c + K];
+        p[c] = keep + __shfl_xor(send, o, 64);
+    }
+    if constexpr (K > 1) colsum_halve<K / 2>(p, lane);
+}
+__device__ __forceinline__ void wave_colsum32(double (&p)[MD_GROUP])
+{
+    const int lane = threadIdx.x & 63;
+    colsum_halve<MD_GROUP / 2>(p, lane);
+    p[0] += __shfl_xor(p[0], 1, 64);
+}
+
+// Block total of the wave column sums: result for column u is valid in
+// thread u (u < 32) after the call.
+__device__ __forceinline__ double block_colsum32(double (&p)[MD_GROUP], double (*sred)[MD_GROUP])
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    wave_colsum32(p);
+    if ((lane & 1) == 0) sred[wv][lane >> 1] = p[0];
+    __syncthreads();
+    double s = 0.0;
+    if (tid < MD_GROUP)
+#pragma unroll
+        for (int k = 0; k < MD_THREADS / 64; ++k) s += sred[k][tid];
+    __syncthreads();
+    return s;
+}
+
+// Phase 1: this block's partial sums, written to partial[blockIdx.x][nc]
+// with nc = ncols + with_ww.  Requires n even and 16-byte aligned columns.
+__device__ __forceinline__ void mdot_partials(const double* __restrict__ V, int64_t ldv, int ncols, int with_ww,
+                                              const double* __restrict__ w, int64_t n, double* __restrict__ partial)
+{
+    __shared__ double sred[MD_THREADS / 64][MD_GROUP];
     const int tid = threadIdx.x;
-    int64_t chunk = (n + gridDim.x - 1) / gridDim.x;
-    int64_t lo = blockIdx.x * chunk, hi = lo + chunk < n ? lo + chunk : n;
-    for (int c0 = 0; c0 < nc; c0 += DOTG) {
-        double acc[DOTG];
+    const int nc = ncols + with_ww;
+    const int64_t i0 = (int64_t)blockIdx.x * MD_TILE + 2 * tid, i1 = i0 + 2 * MD_THREADS;
+    const bool in0 = i0 < n, in1 = i1 < n;
+    const int64_t a0 = in0 ? i0 : 0, a1 = in1 ? i1 : 0;   // clamped (valid) addresses
+    double2 w0 = make_double2(0.0, 0.0), w1 = make_double2(0.0, 0.0);
+    if (in0) w0 = ld2(w + i0);
+    if (in1) w1 = ld2(w + i1);
+    const double ww = w0.x * w0.x + w0.y * w0.y + w1.x * w1.x + w1.y * w1.y;
+    for (int g0 = 0; g0 < nc; g0 += MD_GROUP) {
+        double p[MD_GROUP];
 #pragma unroll
-        for (int g = 0; g < DOTG; ++g) acc[g] = 0.0;
-#pragma unroll 2
-        for (int64_t i = lo + tid; i < hi; i += RED_THREADS) {
-            double wi = w[i];
+        for (int q = 0; q < MD_GROUP / 8; ++q) {
+            const int cb = g0 + 8 * q;
+            if (cb < nc) {
+                double2 a[8], b[8];
 #pragma unroll
-            for (int g = 0; g < DOTG; ++g) {
-                int c = c0 + g;
-                if (c < nc) acc[g] += wi * (c < ncols ? V[(int64_t)c * ldv + i] : wi);
+                for (int u = 0; u < 8; ++u) {
+                    const int c = cb + u;
+                    const double* vc = V + (int64_t)(c < ncols ? c : ncols - 1) * ldv;
+                    a[u] = ld2(vc + a0);
+                    b[u] = ld2(vc + a1);
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int c = cb + u;
+                    const double s = a[u].x * w0.x + a[u].y * w0.y + b[u].x * w1.x + b[u].y * w1.y;
+                    p[8 * q + u] = c < ncols ? s : (c == ncols && with_ww ? ww : 0.0);
+                }
+            } else {
+#pragma unroll
+                for (int u = 0; u < 8; ++u) p[8 * q + u] = 0.0;
             }
         }
-#pragma unroll
-        for (int g = 0; g < DOTG; ++g) red[g][tid] = acc[g];
-        __syncthreads();
-        for (int stp = RED_THREADS / 2; stp > 0; stp >>= 1) {
-            if (tid < stp) {
-#pragma unroll
-                for (int g = 0; g < DOTG; ++g) red[g][tid] += red[g][tid + stp];
-            }
-            __syncthreads();
-        }
-        if (tid < DOTG && c0 + tid < nc) partial[(int64_t)blockIdx.x * nc + c0 + tid] = red[tid][0];
-        __syncthreads();
+        const double s = block_colsum32(p, sred);
+        if (tid < MD_GROUP && g0 + tid < nc) partial[(int64_t)blockIdx.x * nc + g0 + tid] = s;
     }
 }
 
-__global__ void __launch_bounds__(RED_THREADS) k_multidot(const double* __restrict__ V, int64_t ldv, int ncols,
-                                                          const double* __restrict__ w, int64_t n,
-                                                          double* __restrict__ partial)
+// Phase 2: out[c] = sum over blocks (block order within each thread's row
+// set, then the fixed exchange tree) of partial[b][c], c < nc; out in LDS.
+// Every block that calls it gets the same bits.
+__device__ __forceinline__ void mdot_finish(const double* __restrict__ partial, int nblk, int nc, double* out)
 {
-    block_dots(V, ldv, ncols, ncols, w, n, partial);
-}
-
-// Column sums of block partials with a 256-lane block, in a fixed order:
-// lane (t, c) with t = tid / 32 sums rows t, t+8, t+16, ... of column c; the
-// 8 slice sums of a column are then added in slice order.  out may be LDS.
-constexpr int PRED_THREADS = 256;
-__device__ __forceinline__ void reduce_partials_block(const double* __restrict__ partial, int nblk, int nc,
-                                                      double* out)
-{
-    __shared__ double sl[8][32];
-    const int tid = threadIdx.x, t = tid >> 5, cl = tid & 31;
-    for (int c0 = 0; c0 < nc; c0 += 32) {
-        int c = c0 + cl;
-        double s = 0.0;
-        if (c < nc)
-    #pragma unroll 4
-        for (int b = t; b < nblk; b += 8) s += partial[(int64_t)b * nc + c];
-        sl[t][cl] = s;
-        __syncthreads();
-        if (t == 0 && c < nc) {
-            double r = 0.0;
+    __shared__ double sred[MD_THREADS / 64][MD_GROUP];
+    const int tid = threadIdx.x;
+    for (int g0 = 0; g0 < nc; g0 += MD_GROUP) {
+        double p[MD_GROUP];
 #pragma unroll
-            for (int k = 0; k < 8; ++k) r += sl[k][cl];
-            out[c] = r;
+        for (int u = 0; u < MD_GROUP; ++u) p[u] = 0.0;
+        for (int b = tid; b < nblk; b += MD_THREADS) {
+            const double* row = partial + (int64_t)b * nc;
+            double v[MD_GROUP];
+#pragma unroll
+            for (int u = 0; u < MD_GROUP; ++u) v[u] = row[g0 + u < nc ? g0 + u : nc - 1];
+#pragma unroll
+            for (int u = 0; u < MD_GROUP; ++u) p[u] += g0 + u < nc ? v[u] : 0.0;
         }
-        __syncthreads();
+        const double s = block_colsum32(p, sred);
+        if (tid < MD_GROUP && g0 + tid < nc) out[g0 + tid] = s;
     }
+    __syncthreads();
 }
 
-// out[c] = sum_blk partial[blk][c] (fixed order); launch with PRED_THREADS lanes
-__global__ void __launch_bounds__(PRED_THREADS) k_reduce_partials(const double* __restrict__ partial, int nblk, int ncols,
-                                                                  double* __restrict__ out)
+// partial[b][c] of <X_c, w> (c < ncols) and <w, w> (if with_ww); skipped
+// when the GMRES state `st` (optional) is done
+__global__ void __launch_bounds__(MD_THREADS) k_mdot_part(const double* __restrict__ V, int64_t ldv, int ncols,
+                                                          int with_ww, const double* __restrict__ w, int64_t n,
+                                                          double* __restrict__ partial, const int* __restrict__ skip)
 {
-    reduce_partials_block(partial, nblk, ncols, out);
+    if (skip && *skip) return;
+    mdot_partials(V, ldv, ncols, with_ww, w, n, partial);
+}
+
+// out[c] = sum_b partial[b][c]; one block
+__global__ void __launch_bounds__(MD_THREADS) k_mdot_fin(const double* __restrict__ partial, int nblk, int nc,
+                                                         double* __restrict__ out)
+{
+    __shared__ double tot[MD_MAXC];
+    mdot_finish(partial, nblk, nc, tot);
+    for (int c = threadIdx.x; c < nc; c += MD_THREADS) out[c] = tot[c];
 }
 
 // w += sign * sum_c h[c] V_c
@@ -251,51 +316,58 @@ struct GmState {
     double g[GM_MAXM + 1];
     double y[GM_MAXM];
     double hc[GM_MAXM + 2];              // Gram-Schmidt coefficients of the current column
-    double inv_hn;                       // 1 / ||w|| after orthogonalisation
     double tol;                          // absolute residual target
     double res;                          // current residual estimate
     int done;                            // 1: converged or happy breakdown
     int its;                             // columns of the cycle when done
 };
 
-// partials of <V_c, w> (c < ncols) and optionally <w, w> (extra column)
-__global__ void __launch_bounds__(RED_THREADS) k_gm_dot(const double* __restrict__ V, int64_t ldv, int ncols, int with_ww,
-                                                        const double* __restrict__ w, int64_t n,
-                                                        double* __restrict__ partial, const GmState* __restrict__ st)
+// relaxed read of the done flag (block 0 of k_gm_upd may set it while
+// other blocks of the same launch read it; either value is correct there)
+__device__ __forceinline__ int gm_done(const GmState* st)
 {
-    if (st->done) return;
-    block_dots(V, ldv, ncols, ncols + with_ww, w, n, partial);
+    return __hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// first pass of classical Gram-Schmidt: hc[c] = <V_c, w> (c <= j) and
-// <w, w> from the partials; with orthonormal V, ||w - V hc||^2 = <w,w> -
-// |hc|^2.  Column j of H is rotated by the previous Givens rotations (staged
-// in LDS by all lanes; one lane applies them) and a new rotation zeroes the
-// subdiagonal; the residual estimate is |g[j+1]|.  When the projection
-// cancels more than 99% of ||w|| (where a single Gram-Schmidt pass would
-// lose orthogonality) the cycle is closed at this column and the caller's
-// true-residual check decides whether to restart.
-__global__ void __launch_bounds__(PRED_THREADS) k_gm_red1(const double* __restrict__ partial, int nblk, int j, int m,
-                                                          GmState* __restrict__ st)
+// One Arnoldi step after w = A v_j and the partials of <V_c, w> (c <= j)
+// and <w, w> (k_mdot_part), with one classical Gram-Schmidt pass.  Every
+// block sums the partials in the same fixed order (hc[c] = <V_c, w>, and
+// with orthonormal V ||w - V hc||^2 = <w,w> - |hc|^2) and writes its part of
+//   V_{j+1} = (w - V hc) / ||w - V hc||.
+// Block 0 also rotates column j of H by the previous Givens rotations,
+// makes the rotation that zeroes the subdiagonal and updates the residual
+// estimate |g[j+1]|.  When the projection cancels more than 99% of ||w||
+// (where one pass would lose orthogonality) the cycle is closed at this
+// column and the caller's true-residual check decides whether to restart.
+// V_{j+1} is written even when the cycle ends here; it is then unused.
+// Blocks cover the same MD_TILE ranges as k_mdot_part; each thread owns two
+// double2 and the loads of eight basis columns are issued together
+// (columns past j re-read column j with weight zero).
+__global__ void __launch_bounds__(MD_THREADS) k_gm_upd(const double* __restrict__ V, int64_t ldv, int j, int m,
+                                                       const double* __restrict__ w, double* __restrict__ vnext,
+                                                       int64_t n, const double* __restrict__ partial, int nblk,
+                                                       GmState* __restrict__ st)
 {
-    if (st->done) return;
+    if (gm_done(st)) return;
     __shared__ double s1[GM_MAXM + 2];
     __shared__ double scs[GM_MAXM], ssn[GM_MAXM];
     __shared__ double col[GM_MAXM + 2];
-    __shared__ double rot[4];
     const int ncols = j + 1, nc = j + 2;
-    reduce_partials_block(partial, nblk, nc, s1);
-    for (int i = threadIdx.x; i < j; i += blockDim.x) {
-        scs[i] = st->cs[i];
-        ssn[i] = st->sn[i];
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        double proj = 0.0;
-        for (int i = 0; i < ncols; ++i) { col[i] = s1[i]; proj += s1[i] * s1[i]; }
-        double ww = s1[ncols], rem = ww - proj;
-        bool close = !(rem > 1e-4 * ww);
-        double hn = rem > 0.0 ? sqrt(rem) : 0.0;
+    const bool lead = blockIdx.x == 0;
+    if (lead)
+        for (int i = threadIdx.x; i < j; i += blockDim.x) {
+            scs[i] = st->cs[i];
+            ssn[i] = st->sn[i];
+        }
+    mdot_finish(partial, nblk, nc, s1);
+    double proj = 0.0;
+    for (int i = 0; i < ncols; ++i) proj += s1[i] * s1[i];
+    const double ww = s1[ncols], rem = ww - proj;
+    const double hn = rem > 0.0 ? sqrt(rem) : 0.0;
+    const double ih = hn > 0.0 ? 1.0 / hn : 0.0;
+    if (lead && threadIdx.x == 0) {
+        const bool close = !(rem > 1e-4 * ww);
+        for (int i = 0; i < ncols; ++i) col[i] = s1[i];
         col[j + 1] = hn;
         for (int i = 0; i < j; ++i) {
             double a = col[i], b = col[i + 1];
@@ -309,63 +381,85 @@ __global__ void __launch_bounds__(PRED_THREADS) k_gm_red1(const double* __restri
         col[j + 1] = 0.0;
         double gj = st->g[j];
         double gj1 = -sgn * gj;
-        rot[0] = c; rot[1] = sgn; rot[2] = c * gj; rot[3] = gj1;
+        st->cs[j] = c;
+        st->sn[j] = sgn;
+        st->g[j] = c * gj;
+        st->g[j + 1] = gj1;
         double res = fabs(gj1);
         st->res = res;
-        st->inv_hn = hn > 0.0 ? 1.0 / hn : 0.0;
         if (!(res > st->tol) || hn == 0.0 || close || !(res == res)) {
-            st->done = 1;
             st->its = j + 1;
+            __hip_atomic_store(&st->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
     }
-    __syncthreads();
-    for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) {
-        st->H[i * m + j] = col[i];
-        if (i <= j) st->hc[i] = s1[i];
+    if (lead) {
+        __syncthreads();
+        for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) {
+            st->H[i * m + j] = col[i];
+            if (i <= j) st->hc[i] = s1[i];
+        }
     }
-    if (threadIdx.x == 0) {
-        st->cs[j] = rot[0];
-        st->sn[j] = rot[1];
-        st->g[j] = rot[2];
-        st->g[j + 1] = rot[3];
+    // V_{j+1}
+    const int64_t i0 = (int64_t)blockIdx.x * MD_TILE + 2 * threadIdx.x, i1 = i0 + 2 * MD_THREADS;
+    const bool in0 = i0 < n, in1 = i1 < n;
+    const int64_t a0 = in0 ? i0 : 0, a1 = in1 ? i1 : 0;   // clamped (valid) addresses
+    double2 s0 = make_double2(0.0, 0.0), s1v = make_double2(0.0, 0.0);
+    for (int cb = 0; cb < ncols; cb += 8) {
+        double2 a[8], b[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double* vc = V + (int64_t)(cb + u < ncols ? cb + u : ncols - 1) * ldv;
+            a[u] = ld2(vc + a0);
+            b[u] = ld2(vc + a1);
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double h = cb + u < ncols ? s1[cb + u] : 0.0;
+            s0.x += h * a[u].x;
+            s0.y += h * a[u].y;
+            s1v.x += h * b[u].x;
+            s1v.y += h * b[u].y;
+        }
+    }
+    if (in0) {
+        const double2 wi = ld2(w + i0);
+        *reinterpret_cast<double2*>(vnext + i0) = make_double2((wi.x - s0.x) * ih, (wi.y - s0.y) * ih);
+    }
+    if (in1) {
+        const double2 wi = ld2(w + i1);
+        *reinterpret_cast<double2*>(vnext + i1) = make_double2((wi.x - s1v.x) * ih, (wi.y - s1v.y) * ih);
     }
 }
 
-// V_{j+1} = (w - V hc) / ||w - V hc||
-__global__ void k_gm_upd1(const double* __restrict__ V, int64_t ldv, int ncols, const double* __restrict__ w,
-                          double* __restrict__ vnext, int64_t n, const GmState* __restrict__ st)
-{
-    if (st->done) return;   // the cycle needs no further basis vector
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    double s = 0.0;
-    for (int c = 0; c < ncols; ++c) s += st->hc[c] * V[(int64_t)c * ldv + i];
-    vnext[i] = (w[i] - s) * st->inv_hn;
-}
-
-// start of a cycle: V_0 = r / beta, g = beta e_1 (beta = sqrt(<r,r>) from partials)
-__global__ void __launch_bounds__(PRED_THREADS) k_gm_start(const double* __restrict__ partial, int nblk, double tol,
-                                                           GmState* __restrict__ st)
+// start of a cycle from the partials of <r, r>: beta = ||r||, g = beta e_1,
+// V_0 = r / beta (every block sums the partials in the same order; block 0
+// writes the state)
+__global__ void __launch_bounds__(MD_THREADS) k_gm_begin(const double* __restrict__ r, double* __restrict__ v0,
+                                                         int64_t n, const double* __restrict__ partial, int nblk,
+                                                         double tol, GmState* __restrict__ st)
 {
     __shared__ double tot[1];
-    reduce_partials_block(partial, nblk, 1, tot);
-    __syncthreads();
-    if (threadIdx.x != 0) return;
-    double s = tot[0];
-    double beta = sqrt(s);
-    for (int i = 0; i <= GM_MAXM; ++i) st->g[i] = 0.0;
-    st->g[0] = beta;
-    st->res = beta;
-    st->tol = tol;
-    st->inv_hn = beta > 0.0 ? 1.0 / beta : 0.0;
-    st->done = (beta > tol) ? 0 : 1;
-    st->its = 0;
-}
-
-__global__ void k_gm_scale0(const double* __restrict__ r, double* __restrict__ v0, int64_t n, const GmState* __restrict__ st)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) v0[i] = r[i] * st->inv_hn;
+    mdot_finish(partial, nblk, 1, tot);
+    const double beta = sqrt(tot[0]);
+    const double ib = beta > 0.0 ? 1.0 / beta : 0.0;
+    if (blockIdx.x == 0) {
+        for (int i = threadIdx.x; i <= GM_MAXM; i += blockDim.x) st->g[i] = i == 0 ? beta : 0.0;
+        if (threadIdx.x == 0) {
+            st->res = beta;
+            st->tol = tol;
+            st->its = 0;
+            st->done = (beta > tol) ? 0 : 1;
+        }
+    }
+    const int64_t i0 = (int64_t)blockIdx.x * MD_TILE + 2 * threadIdx.x, i1 = i0 + 2 * MD_THREADS;
+    if (i0 < n) {
+        const double2 ri = ld2(r + i0);
+        *reinterpret_cast<double2*>(v0 + i0) = make_double2(ri.x * ib, ri.y * ib);
+    }
+    if (i1 < n) {
+        const double2 ri = ld2(r + i1);
+        *reinterpret_cast<double2*>(v0 + i1) = make_double2(ri.x * ib, ri.y * ib);
+    }
 }
 
 // y = R^{-1} g for the first k columns (k = its if done else m); R is
