@@ -63,11 +63,24 @@ typedef struct pa_config {
     int32_t newton_maxit;
     int32_t max_krylov;         /* outer Krylov basis size (shooting, periodic adjoint) */
     int32_t device;             /* HIP device ordinal */
+    int32_t precision;          /* stage solves: PA_PREC_FP64, PA_PREC_FP32 or PA_PREC_BF16 */
 } pa_config;
+
+/* Precision of the stage linear solves (Sec. 2.2 eq. dirk, each stage's
+ * (M - dt a_ii dr/du) or its transpose):
+ *   PA_PREC_FP64: GMRES in FP64 on the FP64 operator;
+ *   PA_PREC_FP32 / PA_PREC_BF16: iterative refinement -- the residual
+ *     b - A y, the update of y, the stopping test (lin_rtol) and everything
+ *     outside the linear solves stay FP64; each correction is one GMRES
+ *     cycle in FP32 arithmetic on a copy of the block-Jacobi-scaled stage
+ *     operator stored in FP32 or BF16.  Converged results agree with the
+ *     FP64 mode to the solve tolerance; the copy costs 4 (FP32) or 2 (BF16)
+ *     bytes per off-diagonal block entry per stage. */
+enum { PA_PREC_FP64 = 0, PA_PREC_FP32 = 1, PA_PREC_BF16 = 2 };
 
 /* defaults: 8x24 O-grid, p = 1, Nt = 20, r_far 10, stretch 1.3, M 0.2,
  * Re 1000, gamma 1.4, Pr 0.72, T 1, blend 2..8, GMRES(30) 1e-10,
- * Newton 1e-10 / 20, outer basis 100 */
+ * Newton 1e-10 / 20, outer basis 100, FP64 stage solves */
 void pa_default_config(pa_config* cfg);
 
 /* Builds the mesh, the reference tables and every device buffer the method
@@ -174,7 +187,15 @@ pa_status pa_dbg_traj(pa_ctx* ctx, int32_t which, int32_t n, int32_t i, double* 
 
 /* ---- measurement ---- */
 /* kernel ids for pa_kernel_time */
-enum { PA_K_SPMV = 0, PA_K_PRECOND = 1, PA_K_JACOBIAN = 2, PA_K_RESIDUAL = 3, PA_K_BLOCKINV = 4, PA_K_COUNT = 5 };
+enum {
+    PA_K_SPMV = 0,      /* FP64 stage-operator apply */
+    PA_K_PRECOND = 1,   /* block-diagonal apply */
+    PA_K_JACOBIAN = 2,
+    PA_K_RESIDUAL = 3,
+    PA_K_BLOCKINV = 4,  /* diagonal-block LU/inverse and operator formation */
+    PA_K_SPMV_LO = 5,   /* low-precision stage-operator apply (mixed-precision modes) */
+    PA_K_COUNT = 6
+};
 /* when on, every 8th launch of each listed kernel is bracketed by HIP events
  * on the library's stream; pa_kernel_time returns the launch count since
  * timing was switched on and the sampled mean duration times that count */
@@ -185,6 +206,9 @@ pa_status pa_kernel_time(pa_ctx* ctx, int32_t kernel, double* total_ms, int64_t*
  * (M - dt a_11 J) P^{-1} with P its diagonal blocks (timed with HIP events on
  * the library stream; needs a stored trajectory) */
 pa_status pa_bench_spmv(pa_ctx* ctx, int32_t reps, int32_t transpose, double* avg_ms);
+/* as pa_bench_spmv for the FP32/BF16 copy of the operator with FP32 vectors;
+ * PA_ESTATE unless the context was created with precision FP32 or BF16 */
+pa_status pa_bench_spmv_lo(pa_ctx* ctx, int32_t reps, int32_t transpose, double* avg_ms);
 /* averaged over reps device-to-device copies of the first stage's stored
  * operator (*bytes receives the size): a plain copy kernel of known size for
  * calibrating hardware traffic counters.  Overwrites the second stage's

@@ -271,6 +271,7 @@ struct pa_ctx {
     virtual void set_timing(bool on) = 0;
     virtual void kernel_time(int k, double* ms, int64_t* cnt) = 0;
     virtual double bench_spmv(int reps, int tr) = 0;
+    virtual double bench_spmv_lo(int reps, int tr) = 0;
     virtual double bench_copy(int reps, int64_t* bytes) = 0;
 };
 
@@ -283,7 +284,8 @@ struct Solver final : pa_ctx {
     // P = diagonal blocks of A = M - aii J, and P^{-1}
     struct StageOps {
         const double *Ah, *Pd, *Pinv;
-        double aii;   // dt a_ii of the stage
+        double aii;        // dt a_ii of the stage
+        const void* Al;    // low-precision copy of Ah (mixed-precision modes)
     };
 
     int Ne = 0, Nt = 0, nst = 0, nwall = 0;
@@ -294,6 +296,9 @@ struct Solver final : pa_ctx {
     double mu[3] = { 0, 0, 0 };
     bool have_params = false, have_traj = false;
     int restart = 30, max_kry = 100;
+    int pmode = PA_PREC_FP64;                                      // stage-solve precision
+    void* tAl = nullptr;                                           // low-precision Ahat copies [nst][Ne][3][B][B]
+    float *V32 = nullptr, *w32 = nullptr, *r32 = nullptr;          // FP32 inner Krylov basis and vectors
     int verbose = 0;   // PA_VERBOSE=1: solver progress on stderr, 2: also per-stage Newton history
     int64_t bytes = 0;
 
@@ -360,6 +365,7 @@ struct Solver final : pa_ctx {
         nst = 3 * Nt;
         dt = c.T / c.Nt;
         restart = c.gmres_restart;
+        pmode = c.precision;
         max_kry = c.max_krylov;
         ph.gam = c.gamma;
         ph.muv = 1.0 / c.re;
@@ -545,6 +551,14 @@ struct Solver final : pa_ctx {
         fp3 = dalloc<double>(3 * Nu);
         drm = dalloc<double>(3 * Nu);
         V = dalloc<double>((int64_t)(restart + 1) * Nu);
+        if (pmode != PA_PREC_FP64) {
+            const int64_t n = (int64_t)nst * 3 * Isz;
+            if (pmode == PA_PREC_FP32) tAl = dalloc<float>(n);
+            else tAl = dalloc<bf16_t>(n);
+            V32 = dalloc<float>((int64_t)(restart + 1) * Nu);
+            w32 = dalloc<float>(Nu);
+            r32 = dalloc<float>(Nu);
+        }
         Vo = dalloc<double>((int64_t)(max_kry + 1) * Nu);
         part = dalloc<double>(mdot_blocks(Nu) * (std::max(restart, max_kry) + 2));
         hdev = dalloc<double>(std::max(restart, max_kry) + 2);
@@ -705,6 +719,17 @@ struct Solver final : pa_ctx {
         LAUNCHCHK();
         tstop(e);
     }
+    void ahat_lo(const void* Al, int tr, const float* x, float* y, const int* skip = nullptr)
+    {
+        hipEvent_t e;
+        tstart(PA_K_SPMV_LO, &e);
+        if (pmode == PA_PREC_FP32)
+            k_ahat_apply_lo<NP, float><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, (const float*)Al, x, y, tr, skip);
+        else
+            k_ahat_apply_lo<NP, bf16_t><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, (const bf16_t*)Al, x, y, tr, skip);
+        LAUNCHCHK();
+        tstop(e);
+    }
     void prec(const double* Ai, int tr, const double* x, double* z, const int* skip = nullptr)
     {
         hipEvent_t e;
@@ -856,6 +881,7 @@ struct Solver final : pa_ctx {
     static constexpr int GM_CHECK = 5;
     int stage_solve(const StageOps& op, int tr, const double* rhs, double* x)
     {
+        if (pmode != PA_PREC_FP64) return stage_solve_ir(op, tr, rhs, x);
         const int m = restart, maxit = 20 * restart;
         const int* skip = &gms->done;
         const int nb = (int)mdot_blocks(Nu);
@@ -915,6 +941,76 @@ struct Solver final : pa_ctx {
             if (total >= maxit)
                 raise(PA_ENOCONV, "stage GMRES did not converge in %d iterations: rel. residual %.3e", total,
                       rn / bn);
+        }
+        if (tr) copy(y, x);
+        else prec(op.Pinv, 0, y, x);
+        cnt_gmres += total;
+        return total;
+    }
+    // Mixed-precision stage solve by iterative refinement on the same
+    // preconditioned system as stage_solve (forward: Ahat y = b, x = P^{-1} y;
+    // transposed: Ahat^T x = P^{-T} b).  The residual r = b - Ahat y, the
+    // update y += |r| d and the stopping test |r| <= lin_rtol |b| are FP64;
+    // each correction d is one GMRES cycle in FP32 on Ahat_lo d = r / |r|,
+    // stopped at the relative reduction the stored precision can still
+    // deliver (FP32 1e-6, BF16 1e-2) or at the tolerance, whichever is larger.
+    int stage_solve_ir(const StageOps& op, int tr, const double* rhs, double* x)
+    {
+        const int m = restart, maxit = 20 * restart;
+        const int* skip = &gms->done;
+        const int nb = (int)mdot_blocks(Nu);
+        const double floor_red = pmode == PA_PREC_FP32 ? 1e-6 : 1e-2;
+        const double* b = rhs;
+        if (tr) { prec(op.Pinv, 1, rhs, gm_b); b = gm_b; }
+        const double bn = norm(b);
+        zero(x);
+        if (bn == 0.0) return 0;
+        const double tol = cfg.lin_rtol * bn;
+        double* r = we;
+        double* y = gm_y;
+        zero(y);
+        copy(b, r);
+        double rn = bn;
+        int total = 0;
+        for (;;) {
+            k_scale_to_f32<<<grid1(Nu), 256, 0, st>>>(1.0 / rn, r, r32, Nu);
+            k_mdot_part<<<nb, MD_THREADS, 0, st>>>(r32, 0, 1, 0, r32, Nu, part, nullptr);
+            k_gm_begin<<<nb, MD_THREADS, 0, st>>>(r32, V32, Nu, part, nb, std::max(tol / rn, floor_red), gms);
+            LAUNCHCHK();
+            int pending = -1, slot = 0;
+            for (int j = 0; j < m; ++j) {
+                float* vj = V32 + (int64_t)j * Nu;
+                float* vnext = V32 + (int64_t)(j + 1) * Nu;
+                ahat_lo(op.Al, tr, vj, w32, skip);
+                k_mdot_part<<<nb, MD_THREADS, 0, st>>>((const float*)V32, Nu, j + 1, 1, (const float*)w32, Nu, part, skip);
+                k_gm_upd<<<nb, MD_THREADS, 0, st>>>((const float*)V32, Nu, j, m, (const float*)w32, vnext, Nu, part, nb, gms);
+                LAUNCHCHK();
+                if ((j + 1) % GM_CHECK == 0 && j < m - 1) {
+                    if (pending >= 0) {
+                        HIPCHK(hipEventSynchronize(gm_ev[pending]));
+                        if (hstat[pending].done) break;
+                    }
+                    HIPCHK(hipMemcpyAsync(&hstat[slot], &gms->res, sizeof(GmHost), hipMemcpyDeviceToHost, st));
+                    HIPCHK(hipEventRecord(gm_ev[slot], st));
+                    pending = slot;
+                    slot ^= 1;
+                }
+            }
+            HIPCHK(hipMemcpyAsync(&hstat[2], &gms->res, sizeof(GmHost), hipMemcpyDeviceToHost, st));
+            k_gm_solve<<<1, 256, 0, st>>>(m, gms);
+            k_gm_combine<<<grid1(Nu), 256, 0, st>>>((const float*)V32, Nu, m, r, Nu, gms);
+            LAUNCHCHK();
+            axpby(rn, r, 1.0, y);
+            // FP64 refinement residual
+            ahat(op.Ah, tr, y, r);
+            lincomb(1.0, b, -1.0, r, r);
+            rn = norm(r);   // synchronises: hstat[2] is valid below
+            total += hstat[2].done ? hstat[2].its : m;
+            if (!std::isfinite(rn) || !std::isfinite(hstat[2].res)) raise(PA_ENUMERIC, "NaN in stage GMRES");
+            if (rn <= tol) break;
+            if (total >= maxit)
+                raise(PA_ENOCONV, "stage GMRES (mixed precision) did not converge in %d iterations: rel. residual %.3e",
+                      total, rn / bn);
         }
         if (tr) copy(y, x);
         else prec(op.Pinv, 0, y, x);
@@ -1043,8 +1139,11 @@ struct Solver final : pa_ctx {
 
     StageOps ops(int s) const
     {
+        const void* al = nullptr;
+        if (pmode == PA_PREC_FP32) al = (const float*)tAl + (int64_t)s * 3 * Isz;
+        else if (pmode == PA_PREC_BF16) al = (const bf16_t*)tAl + (int64_t)s * 3 * Isz;
         return { tAh + (int64_t)s * 3 * Isz, tPd + (int64_t)s * Isz, tAi + (int64_t)s * Isz,
-                 dt * rk.A[s % 3][s % 3] };
+                 dt * rk.A[s % 3][s % 3], al };
     }
     // dr/du at (n, i, u) -> Jtmp, then P, P^{-1} and Ahat of A = M - c J into stage slot s
     void assemble(int n, int i, const double* u, double c, int s)
@@ -1059,6 +1158,12 @@ struct Solver final : pa_ctx {
         k_blockprep<NP><<<Ne, 64, 0, st>>>(Ne, dm.area, dmh, J, c, tPd + (int64_t)s * Isz, tAi + (int64_t)s * Isz,
                                           dstatus);
         k_form_ahat<NP><<<Ne * 3, 64, 0, st>>>(Ne, dm.enb, J, c, tAi + (int64_t)s * Isz, tAh + (int64_t)s * 3 * Isz);
+        LAUNCHCHK();
+        const int64_t n3 = 3 * Isz;
+        if (pmode == PA_PREC_FP32)
+            k_to_lo<float><<<grid1(n3), 256, 0, st>>>(tAh + s * n3, (float*)tAl + s * n3, n3);
+        else if (pmode == PA_PREC_BF16)
+            k_to_lo<bf16_t><<<grid1(n3), 256, 0, st>>>(tAh + s * n3, (bf16_t*)tAl + s * n3, n3);
         LAUNCHCHK();
         tstop(e);
     }
@@ -1507,6 +1612,33 @@ struct Solver final : pa_ctx {
         return ms / reps;
     }
 
+    double bench_spmv_lo(int reps, int tr) override
+    {
+        if (!have_traj) raise(PA_ESTATE, "no trajectory");
+        if (pmode == PA_PREC_FP64) raise(PA_ESTATE, "context has no low-precision operator (precision FP64)");
+        hipEvent_t a, b;
+        HIPCHK(hipEventCreate(&a));
+        HIPCHK(hipEventCreate(&b));
+        const void* Al = ops(0).Al;
+        k_scale_to_f32<<<grid1(Nu), 256, 0, st>>>(1.0, u0, r32, Nu);
+        ahat_lo(Al, tr, r32, w32);
+        HIPCHK(hipEventRecord(a, st));
+        for (int r = 0; r < reps; ++r) {
+            if (pmode == PA_PREC_FP32)
+                k_ahat_apply_lo<NP, float><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, (const float*)Al, r32, w32, tr, nullptr);
+            else
+                k_ahat_apply_lo<NP, bf16_t><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, (const bf16_t*)Al, r32, w32, tr, nullptr);
+        }
+        LAUNCHCHK();
+        HIPCHK(hipEventRecord(b, st));
+        HIPCHK(hipEventSynchronize(b));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, a, b));
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        return ms / reps;
+    }
+
     // plain device-to-device copy of the first stage's stored operator
     // (a copy kernel of known size, used to calibrate traffic counters)
     double bench_copy(int reps, int64_t* bytes) override
@@ -1574,6 +1706,7 @@ void pa_default_config(pa_config* c)
     c->gmres_restart = 30; c->lin_rtol = 1e-10;
     c->newton_atol = 1e-10; c->newton_maxit = 20;
     c->max_krylov = 100;
+    c->precision = PA_PREC_FP64;
     c->device = 0;
 }
 
@@ -1585,7 +1718,7 @@ pa_status pa_create(const pa_config* cfg, pa_ctx** out)
     *out = nullptr;
     if (!cfg || cfg->Nr < 1 || cfg->Nth < 3 || cfg->p < 1 || cfg->p > 3 || cfg->Nt < 1 || cfg->gmres_restart < 1 ||
         cfg->gmres_restart > 64 || cfg->max_krylov < 1 || cfg->max_krylov > 126 || !(cfg->r_far > 1.0) ||
-        !(cfg->stretch > 0.0) || !(cfg->T > 0.0)) {
+        !(cfg->stretch > 0.0) || !(cfg->T > 0.0) || cfg->precision < PA_PREC_FP64 || cfg->precision > PA_PREC_BF16) {
         g_create_err = "invalid configuration";
         return PA_EINVAL;
     }
@@ -1726,6 +1859,14 @@ pa_status pa_bench_copy(pa_ctx* c, int32_t reps, double* avg, int64_t* bytes)
         *avg = c->bench_copy(reps, bytes);
     });
 }
+pa_status pa_bench_spmv_lo(pa_ctx* c, int32_t reps, int32_t tr, double* avg)
+{
+    return guard(c, [&] {
+        if (!avg || reps < 1) raise(PA_EINVAL, "bad arguments");
+        *avg = c->bench_spmv_lo(reps, tr);
+    });
+}
+
 pa_status pa_bench_spmv(pa_ctx* c, int32_t reps, int32_t tr, double* avg)
 {
     return guard(c, [&] {

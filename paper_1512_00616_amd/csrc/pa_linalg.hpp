@@ -128,7 +128,18 @@ constexpr int MD_GROUP = 32;              // columns per reduction group
 constexpr int MD_MAXC = 256;              // column limit of a launch
 inline int64_t mdot_blocks(int64_t n) { return (n + MD_TILE - 1) / MD_TILE; }
 
+// two consecutive entries (16- or 8-byte aligned) widened to double
 __device__ __forceinline__ double2 ld2(const double* p) { return *reinterpret_cast<const double2*>(p); }
+__device__ __forceinline__ double2 ld2(const float* p)
+{
+    const float2 f = *reinterpret_cast<const float2*>(p);
+    return make_double2(f.x, f.y);
+}
+__device__ __forceinline__ void st2(double* p, double2 v) { *reinterpret_cast<double2*>(p) = v; }
+__device__ __forceinline__ void st2(float* p, double2 v)
+{
+    *reinterpret_cast<float2*>(p) = make_float2((float)v.x, (float)v.y);
+}
 
 // Column sums over a wave: on entry every lane holds p[0..31]; on exit p[0]
 // of lane l holds the wave total of column l >> 1.  Each halving exchange
@@ -172,8 +183,9 @@ __device__ __forceinline__ double block_colsum32(double (&p)[MD_GROUP], double (
 
 // Phase 1: this block's partial sums, written to partial[blockIdx.x][nc]
 // with nc = ncols + with_ww.  Requires n even and 16-byte aligned columns.
-__device__ __forceinline__ void mdot_partials(const double* __restrict__ V, int64_t ldv, int ncols, int with_ww,
-                                              const double* __restrict__ w, int64_t n, double* __restrict__ partial)
+template <class T>
+__device__ __forceinline__ void mdot_partials(const T* __restrict__ V, int64_t ldv, int ncols, int with_ww,
+                                              const T* __restrict__ w, int64_t n, double* __restrict__ partial)
 {
     __shared__ double sred[MD_THREADS / 64][MD_GROUP];
     const int tid = threadIdx.x;
@@ -195,7 +207,7 @@ __device__ __forceinline__ void mdot_partials(const double* __restrict__ V, int6
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const int c = cb + u;
-                    const double* vc = V + (int64_t)(c < ncols ? c : ncols - 1) * ldv;
+                    const T* vc = V + (int64_t)(c < ncols ? c : ncols - 1) * ldv;
                     a[u] = ld2(vc + a0);
                     b[u] = ld2(vc + a1);
                 }
@@ -242,8 +254,9 @@ __device__ __forceinline__ void mdot_finish(const double* __restrict__ partial, 
 
 // partial[b][c] of <X_c, w> (c < ncols) and <w, w> (if with_ww); skipped
 // when the GMRES state `st` (optional) is done
-__global__ void __launch_bounds__(MD_THREADS) k_mdot_part(const double* __restrict__ V, int64_t ldv, int ncols,
-                                                          int with_ww, const double* __restrict__ w, int64_t n,
+template <class T>
+__global__ void __launch_bounds__(MD_THREADS) k_mdot_part(const T* __restrict__ V, int64_t ldv, int ncols,
+                                                          int with_ww, const T* __restrict__ w, int64_t n,
                                                           double* __restrict__ partial, const int* __restrict__ skip)
 {
     if (skip && *skip) return;
@@ -343,8 +356,9 @@ __device__ __forceinline__ int gm_done(const GmState* st)
 // Blocks cover the same MD_TILE ranges as k_mdot_part; each thread owns two
 // double2 and the loads of eight basis columns are issued together
 // (columns past j re-read column j with weight zero).
-__global__ void __launch_bounds__(MD_THREADS) k_gm_upd(const double* __restrict__ V, int64_t ldv, int j, int m,
-                                                       const double* __restrict__ w, double* __restrict__ vnext,
+template <class T>
+__global__ void __launch_bounds__(MD_THREADS) k_gm_upd(const T* __restrict__ V, int64_t ldv, int j, int m,
+                                                       const T* __restrict__ w, T* __restrict__ vnext,
                                                        int64_t n, const double* __restrict__ partial, int nblk,
                                                        GmState* __restrict__ st)
 {
@@ -408,7 +422,7 @@ __global__ void __launch_bounds__(MD_THREADS) k_gm_upd(const double* __restrict_
         double2 a[8], b[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
-            const double* vc = V + (int64_t)(cb + u < ncols ? cb + u : ncols - 1) * ldv;
+            const T* vc = V + (int64_t)(cb + u < ncols ? cb + u : ncols - 1) * ldv;
             a[u] = ld2(vc + a0);
             b[u] = ld2(vc + a1);
         }
@@ -423,18 +437,19 @@ __global__ void __launch_bounds__(MD_THREADS) k_gm_upd(const double* __restrict_
     }
     if (in0) {
         const double2 wi = ld2(w + i0);
-        *reinterpret_cast<double2*>(vnext + i0) = make_double2((wi.x - s0.x) * ih, (wi.y - s0.y) * ih);
+        st2(vnext + i0, make_double2((wi.x - s0.x) * ih, (wi.y - s0.y) * ih));
     }
     if (in1) {
         const double2 wi = ld2(w + i1);
-        *reinterpret_cast<double2*>(vnext + i1) = make_double2((wi.x - s1v.x) * ih, (wi.y - s1v.y) * ih);
+        st2(vnext + i1, make_double2((wi.x - s1v.x) * ih, (wi.y - s1v.y) * ih));
     }
 }
 
 // start of a cycle from the partials of <r, r>: beta = ||r||, g = beta e_1,
 // V_0 = r / beta (every block sums the partials in the same order; block 0
 // writes the state)
-__global__ void __launch_bounds__(MD_THREADS) k_gm_begin(const double* __restrict__ r, double* __restrict__ v0,
+template <class T>
+__global__ void __launch_bounds__(MD_THREADS) k_gm_begin(const T* __restrict__ r, T* __restrict__ v0,
                                                          int64_t n, const double* __restrict__ partial, int nblk,
                                                          double tol, GmState* __restrict__ st)
 {
@@ -454,11 +469,11 @@ __global__ void __launch_bounds__(MD_THREADS) k_gm_begin(const double* __restric
     const int64_t i0 = (int64_t)blockIdx.x * MD_TILE + 2 * threadIdx.x, i1 = i0 + 2 * MD_THREADS;
     if (i0 < n) {
         const double2 ri = ld2(r + i0);
-        *reinterpret_cast<double2*>(v0 + i0) = make_double2(ri.x * ib, ri.y * ib);
+        st2(v0 + i0, make_double2(ri.x * ib, ri.y * ib));
     }
     if (i1 < n) {
         const double2 ri = ld2(r + i1);
-        *reinterpret_cast<double2*>(v0 + i1) = make_double2(ri.x * ib, ri.y * ib);
+        st2(v0 + i1, make_double2(ri.x * ib, ri.y * ib));
     }
 }
 
@@ -483,7 +498,8 @@ __global__ void __launch_bounds__(256) k_gm_solve(int m, GmState* __restrict__ s
 }
 
 // out = sum_{c<m} y[c] V_c   (y is zero beyond the cycle's length)
-__global__ void k_gm_combine(const double* __restrict__ V, int64_t ldv, int m, double* __restrict__ out, int64_t n,
+template <class T>
+__global__ void k_gm_combine(const T* __restrict__ V, int64_t ldv, int m, double* __restrict__ out, int64_t n,
                              const GmState* __restrict__ st)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -682,6 +698,112 @@ __global__ void __launch_bounds__(64) k_ahat_apply(int Ne, const int32_t* __rest
         }
         y[(int64_t)K * B + lane] = acc;
     }
+}
+
+// ------------------------------------------------------------------ low-precision stage operator
+// Storage formats of the inner operator of the mixed-precision solve: FP32,
+// or BF16 (the upper 16 bits of an FP32, rounded to nearest even through
+// FP32).  Arithmetic and accumulation are FP32 in both.
+struct bf16_t { uint16_t b; };
+__device__ __forceinline__ float lo_to_f(float v) { return v; }
+__device__ __forceinline__ float lo_to_f(bf16_t v) { return __uint_as_float((uint32_t)v.b << 16); }
+__device__ __forceinline__ void f_to_lo(double v, float& o) { o = (float)v; }
+__device__ __forceinline__ void f_to_lo(double v, bf16_t& o)
+{
+    const uint32_t u = __float_as_uint((float)v);
+    if ((u & 0x7f800000u) == 0x7f800000u) {           // Inf / NaN: keep class, quiet NaN
+        o.b = (uint16_t)((u >> 16) | ((u & 0x007fffffu) ? 0x40u : 0u));
+        return;
+    }
+    o.b = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+}
+
+// dst = lo(src), n entries
+template <class TM>
+__global__ void k_to_lo(const double* __restrict__ src, TM* __restrict__ dst, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) f_to_lo(src[i], dst[i]);
+}
+
+// y = x + Ahat_lo x or y = x + Ahat_lo^T x in FP32 (as k_ahat_apply, with
+// 16-byte loads of 4 FP32 or 8 BF16 entries)
+template <int NP, class TM>
+__global__ void __launch_bounds__(64) k_ahat_apply_lo(int Ne, const int32_t* __restrict__ enb,
+                                                      const int8_t* __restrict__ etw, const TM* __restrict__ Ah,
+                                                      const float* __restrict__ x, float* __restrict__ y, int trans,
+                                                      const int* __restrict__ skip)
+{
+    constexpr int B = 4 * NP, BB = B * B;
+    constexpr int EPL = 16 / sizeof(TM);              // entries per 16-byte load
+    constexpr int H = BB / EPL;                       // loads per block
+    constexpr int PER = (H + 63) / 64;
+    __shared__ float sblk[3][B][B + 1];
+    __shared__ float sx[3][B];
+    if (skip && *skip) return;
+    const int K = blockIdx.x, lane = threadIdx.x;
+    int nbs[3];
+    const uint4* src[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        int nb = enb[3 * K + f];
+        nbs[f] = nb;
+        src[f] = nullptr;
+        if (nb >= 0) {
+            int64_t blk = trans ? (int64_t)nb * 3 + etw[3 * K + f] : (int64_t)K * 3 + f;
+            src[f] = reinterpret_cast<const uint4*>(Ah + blk * BB);
+        }
+    }
+    uint4 v[3][PER];
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            int t = lane + 64 * r;
+            if (src[f] && t < H) v[f][r] = src[f][t];
+        }
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+        if (nbs[f] >= 0 && lane < B) sx[f][lane] = x[(int64_t)nbs[f] * B + lane];
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            int t = lane + 64 * r;
+            if (src[f] && t < H) {
+                const TM* e8 = reinterpret_cast<const TM*>(&v[f][r]);
+#pragma unroll
+                for (int q = 0; q < EPL; ++q) {
+                    int e = EPL * t + q;
+                    sblk[f][e / B][e % B] = lo_to_f(e8[q]);
+                }
+            }
+        }
+    __syncthreads();
+    if (lane < B) {
+        float acc = x[(int64_t)K * B + lane];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            if (nbs[f] < 0) continue;
+            float a = 0.0f;
+            if (!trans) {
+#pragma unroll 8
+                for (int j = 0; j < B; ++j) a += sblk[f][lane][j] * sx[f][j];
+            } else {
+#pragma unroll 8
+                for (int i = 0; i < B; ++i) a += sblk[f][i][lane] * sx[f][i];
+            }
+            acc += a;
+        }
+        y[(int64_t)K * B + lane] = acc;
+    }
+}
+
+// z = a * x (FP64 -> FP32), y += a * x (FP32 -> FP64)
+__global__ void k_scale_to_f32(double a, const double* __restrict__ x, float* __restrict__ z, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) z[i] = (float)(a * x[i]);
 }
 
 // out = alpha M x + beta y  (M applied block-wise)

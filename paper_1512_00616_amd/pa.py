@@ -13,7 +13,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpa.so")
 
 PA_OK, PA_EINVAL, PA_ENOMEM, PA_EDEVICE, PA_ENOCONV, PA_ENUMERIC, PA_ESTATE = 0, -1, -2, -3, -4, -5, -6
-PA_K_SPMV, PA_K_PRECOND, PA_K_JACOBIAN, PA_K_RESIDUAL, PA_K_BLOCKINV = range(5)
+PA_K_SPMV, PA_K_PRECOND, PA_K_JACOBIAN, PA_K_RESIDUAL, PA_K_BLOCKINV, PA_K_SPMV_LO = range(6)
 
 EXPORTED = [
     "pa_default_config", "pa_create", "pa_destroy", "pa_last_error", "pa_num_dofs", "pa_num_elems",
@@ -21,7 +21,7 @@ EXPORTED = [
     "pa_get_state", "pa_primal_period", "pa_shoot", "pa_fixed_point", "pa_adjoint_gradient", "pa_tangent_sweep",
     "pa_adjoint_sweep", "pa_dbg_gbar", "pa_dbg_dgbar", "pa_dbg_residual", "pa_dbg_jacobian", "pa_dbg_dr_dmu",
     "pa_dbg_qoi", "pa_dbg_bsr_apply", "pa_dbg_blockinv", "pa_dbg_stage_solve", "pa_dbg_traj", "pa_set_timing",
-    "pa_kernel_time", "pa_bench_spmv", "pa_bench_copy",
+    "pa_kernel_time", "pa_bench_spmv", "pa_bench_spmv_lo", "pa_bench_copy",
 ]
 
 
@@ -33,8 +33,11 @@ class pa_config(C.Structure):
         ("T", C.c_double), ("r_blend0", C.c_double), ("r_blend1", C.c_double),
         ("wall_is_farfield", C.c_int32), ("gmres_restart", C.c_int32), ("lin_rtol", C.c_double),
         ("newton_atol", C.c_double), ("newton_maxit", C.c_int32), ("max_krylov", C.c_int32),
-        ("device", C.c_int32),
+        ("device", C.c_int32), ("precision", C.c_int32),
     ]
+
+
+PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 
 
 class pa_shoot_report(C.Structure):
@@ -102,6 +105,7 @@ def lib():
             "pa_set_timing": [P, C.c_int32],
             "pa_kernel_time": [P, C.c_int32, P, P],
             "pa_bench_spmv": [P, C.c_int32, C.c_int32, P],
+            "pa_bench_spmv_lo": [P, C.c_int32, C.c_int32, P],
             "pa_bench_copy": [P, C.c_int32, P, P],
         }
         for fn, args in sig.items():
@@ -313,4 +317,9 @@ class Solver:
     def bench_spmv(self, reps=50, transpose=False):
         ms = C.c_double()
         self._chk(lib().pa_bench_spmv(self._c, reps, int(transpose), C.byref(ms)))
+        return ms.value
+
+    def bench_spmv_lo(self, reps=50, transpose=False):
+        ms = C.c_double()
+        self._chk(lib().pa_bench_spmv_lo(self._c, reps, int(transpose), C.byref(ms)))
         return ms.value
