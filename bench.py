@@ -40,7 +40,7 @@ from paper_1512_00616_amd import inputs  # noqa: E402
 HBM_PEAK_GBS = 8000.0
 
 
-def spmv_bytes(Nr, Nth, p):
+def spmv_bytes(Nr, Nth, p, mat_bytes=8, vec_bytes=8):
     """Algorithmic bytes of one apply of the preconditioned stage operator
     y = Ahat x = x + (A P^{-1} - I) x: every stored off-diagonal block once
     (two per interior face; the diagonal blocks are the identity), x and y once."""
@@ -49,7 +49,7 @@ def spmv_bytes(Nr, Nth, p):
     Ne = 2 * Nr * Nth
     n_int_faces = 3 * Ne // 2 - Nth          # wall and far-field edges are unpaired
     Nu = Ne * b
-    return 2 * n_int_faces * b * b * 8 + 2 * Nu * 8
+    return 2 * n_int_faces * b * b * mat_bytes + 2 * Nu * vec_bytes
 
 
 def log(msg):
@@ -121,6 +121,7 @@ def main():
     ap.add_argument("--krylov", type=int, default=6, help="outer Krylov basis cap of the step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttg", action="store_true", help="skip the 8x24 time-to-gradient")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32/BF16 mixed-precision steps")
     ap.add_argument("--spmv-only", action="store_true",
                     help="short run for hardware counters: a 3-stage period on the 32x96 p=3 mesh, then timed "
                          "launches of the preconditioned stage operator and of a plain copy")
@@ -139,22 +140,68 @@ def main():
         # same mesh, degree and time step (dt = 0.01) as the workload, three
         # steps of a motionless cylinder: stores the operators of 9 stages
         phys = dict(inputs.PHYSICS, T=0.03)
-        s = pa.Solver(gmres_restart=30, lin_rtol=1e-10, newton_atol=1e-10, **dict(work, Nt=3), **phys)
-        s.set_params(np.zeros(3))
-        s.set_freestream()
-        s.primal_period()
-        fwd = s.bench_spmv(20)
-        trn = s.bench_spmv(20, transpose=True)
-        cp_ms, cp_bytes = s.bench_copy(20)
-        nbytes = spmv_bytes(work["Nr"], work["Nth"], work["p"])
-        print(json.dumps({"spmv_us": fwd * 1e3, "spmv_t_us": trn * 1e3, "spmv_bytes": nbytes,
-                          "spmv_gbs": nbytes / (fwd * 1e-3) / 1e9, "spmv_t_gbs": nbytes / (trn * 1e-3) / 1e9,
-                          "copy_us": cp_ms * 1e3, "copy_bytes": cp_bytes,
-                          "copy_gbs": 2 * cp_bytes / (cp_ms * 1e-3) / 1e9}), flush=True)
+        outj = {}
+        for prec, tag in ((pa.PREC_FP32, "fp32"), (pa.PREC_BF16, "bf16")):
+            s = pa.Solver(gmres_restart=30, lin_rtol=1e-10, newton_atol=1e-10, precision=prec,
+                          **dict(work, Nt=3), **phys)
+            s.set_params(np.zeros(3))
+            s.set_freestream()
+            s.primal_period()
+            if prec == pa.PREC_FP32:
+                fwd = s.bench_spmv(20)
+                trn = s.bench_spmv(20, transpose=True)
+                nbytes = spmv_bytes(work["Nr"], work["Nth"], work["p"])
+                outj.update({"spmv_us": fwd * 1e3, "spmv_t_us": trn * 1e3, "spmv_bytes": nbytes,
+                             "spmv_gbs": nbytes / (fwd * 1e-3) / 1e9, "spmv_t_gbs": nbytes / (trn * 1e-3) / 1e9})
+            lo = s.bench_spmv_lo(20)
+            lot = s.bench_spmv_lo(20, transpose=True)
+            lb = spmv_bytes(work["Nr"], work["Nth"], work["p"], 4 if tag == "fp32" else 2, 4)
+            outj.update({"spmv_%s_us" % tag: lo * 1e3, "spmv_%s_t_us" % tag: lot * 1e3, "spmv_%s_bytes" % tag: lb,
+                         "spmv_%s_gbs" % tag: lb / (lo * 1e-3) / 1e9})
+            if prec == pa.PREC_BF16:
+                cp_ms, cp_bytes = s.bench_copy(20)
+                outj.update({"copy_us": cp_ms * 1e3, "copy_bytes": cp_bytes,
+                             "copy_gbs": 2 * cp_bytes / (cp_ms * 1e-3) / 1e9})
+            s.close()
+        print(json.dumps(outj), flush=True)
         return 0
+
+    out, dJ64 = run_step(pa, name, work, mu, args, pa.PREC_FP64)
+    if not args.no_mixed:
+        # the same step with the mixed-precision stage solves (FP64 refinement
+        # to the same tolerances): wall time and gradient against the FP64 run
+        out["mixed_precision"] = {}
+        for prec, tag in ((pa.PREC_FP32, "fp32"), (pa.PREC_BF16, "bf16")):
+            log("mixed precision (%s operator copy, FP32 inner GMRES)" % tag)
+            m, dJm = run_step(pa, name, work, mu, args, prec)
+            out["mixed_precision"][tag] = {
+                "ms_per_step": m["ms_per_step"], "value": m["value"], "unit": "DOF/s",
+                "speedup_vs_fp64": out["ms_per_step"] / m["ms_per_step"],
+                "dJdmu_rel_diff_vs_fp64": float(np.abs(dJm - dJ64).max() / np.abs(dJ64).max()),
+                "counts": m["counts"], "kernels_ms": m["kernels_ms"],
+                "spmv_lo": m["spmv_lo"],
+            }
+    if not args.no_ttg:
+        log("time to gradient on the 8x24 p=1 workload")
+        out["time_to_gradient"] = time_to_gradient(pa, mu)
+    if not args.no_cpu_baseline:
+        log("oracle sample on the host")
+        c = out.pop("_cpu_counts")
+        try:
+            out["cpu_baseline"] = cpu_baseline(work, c, mu)
+        except Exception as e:  # report, do not fail the benchmark
+            out["cpu_baseline"] = {"value": None, "error": str(e)}
+    out.pop("_cpu_counts", None)
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+def run_step(pa, name, work, mu, args, precision):
+    """Warmup, then the timed steps, on a fresh context of the given stage-solve
+    precision; returns the report and dJ/dmu of the last step."""
     t_setup = time.perf_counter()
-    s = pa.Solver(gmres_restart=30, lin_rtol=1e-10, newton_atol=1e-10, max_krylov=args.krylov, **work,
-                  **inputs.PHYSICS)
+    s = pa.Solver(gmres_restart=30, lin_rtol=1e-10, newton_atol=1e-10, max_krylov=args.krylov,
+                  precision=precision, **work, **inputs.PHYSICS)
     s.set_params(mu)
     setup_s = time.perf_counter() - t_setup
     log("setup %.1f s, %.1f GB on the device" % (setup_s, s.device_bytes / 1e9))
@@ -171,8 +218,8 @@ def main():
     t0 = time.perf_counter()
     results = [step() for _ in range(args.steps)]
     t1 = time.perf_counter()
-    kt = {k: s.kernel_time(getattr(pa, "PA_K_" + k.upper())) for k in ("spmv", "precond", "jacobian", "residual",
-                                                                       "blockinv")}
+    kt = {k: s.kernel_time(getattr(pa, "PA_K_" + k.upper())) for k in ("spmv", "spmv_t", "spmv_lo", "precond",
+                                                                       "jacobian", "residual", "blockinv")}
     s.set_timing(False)
     step_s = (t1 - t0) / args.steps
     rep, q, dJ, arep = results[-1]
@@ -186,6 +233,10 @@ def main():
     ms_spmv, n_spmv = kt["spmv"]
     avg_spmv_s = ms_spmv / max(n_spmv, 1) / 1e3
     achieved = bytes_spmv / avg_spmv_s / 1e9
+    ms_t, n_t = kt["spmv_t"]
+    avg_t_s = ms_t / max(n_t, 1) / 1e3
+    ms_lo, n_lo = kt["spmv_lo"]
+    lo_bytes = spmv_bytes(work["Nr"], work["Nth"], work["p"], 4 if precision == pa.PREC_FP32 else 2, 4)
     out = {
         "metric": "stage-solve DOF/s (periodic adjoint hot path, 32x96 p=3)",
         "value": stage_solves * Nu / step_s,
@@ -202,8 +253,13 @@ def main():
         "config": {"workload": name, **work, "mu": list(mu), "stage_gmres": "block-Jacobi GMRES(30) rtol 1e-10",
                    "newton_atol": 1e-10, "outer_krylov_cap": args.krylov, "shoot_eta": 1e-3, "adj_rtol": 1e-8},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "pa::k_ahat_apply<10>",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "pa::k_ahat_fwd<10, double, double>",
                      "bytes_per_launch": bytes_spmv, "avg_launch_us": avg_spmv_s * 1e6, "launches": n_spmv},
+        "spmv_transposed": {"kernel": "pa::k_ahat_apply<10>", "avg_launch_us": avg_t_s * 1e6, "launches": n_t,
+                            "achieved_gbs": bytes_spmv / max(avg_t_s, 1e-30) / 1e9},
+        "spmv_lo": ({"avg_launch_us": ms_lo / n_lo * 1e3, "launches": n_lo, "bytes_per_launch": lo_bytes,
+                     "achieved_gbs": lo_bytes / (ms_lo / n_lo * 1e-3) / 1e9} if n_lo else None),
         "kernels_ms": {k: v[0] for k, v in kt.items()},
         "counts": {"stage_solves": stage_solves, "stage_newton": rep.stage_newton_its, "stage_gmres": gmres_its,
                    "primal_sweeps": rep.primal_sweeps, "tangent_sweeps": rep.krylov_its,
@@ -212,22 +268,14 @@ def main():
         "qoi": list(q), "dJdmu": dJ.tolist(),
         "setup_s": setup_s,
         "device_gb": s.device_bytes / 1e9,
+        "_cpu_counts": {"residuals": kt["residual"][1] // max(args.steps, 1),
+                        "jacobians": kt["jacobian"][1] // max(args.steps, 1),
+                        "gmres_its": gmres_its, "stage_solves": stage_solves},
     }
+    if precision == pa.PREC_FP64:
+        out.pop("spmv_lo")
     s.close()
-    if not args.no_ttg:
-        log("time to gradient on the 8x24 p=1 workload")
-        out["time_to_gradient"] = time_to_gradient(pa, mu)
-    if not args.no_cpu_baseline:
-        log("oracle sample on the host")
-        counts = {"residuals": kt["residual"][1] // max(args.steps, 1),
-                  "jacobians": kt["jacobian"][1] // max(args.steps, 1),
-                  "gmres_its": gmres_its, "stage_solves": stage_solves}
-        try:
-            out["cpu_baseline"] = cpu_baseline(work, counts, mu)
-        except Exception as e:  # report, do not fail the benchmark
-            out["cpu_baseline"] = {"value": None, "error": str(e)}
-    print(json.dumps(out), flush=True)
-    return 0
+    return out, dJ
 
 
 if __name__ == "__main__":

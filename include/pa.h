@@ -188,13 +188,14 @@ pa_status pa_dbg_traj(pa_ctx* ctx, int32_t which, int32_t n, int32_t i, double* 
 /* ---- measurement ---- */
 /* kernel ids for pa_kernel_time */
 enum {
-    PA_K_SPMV = 0,      /* FP64 stage-operator apply */
+    PA_K_SPMV = 0,      /* FP64 stage-operator apply (forward) */
     PA_K_PRECOND = 1,   /* block-diagonal apply */
     PA_K_JACOBIAN = 2,
     PA_K_RESIDUAL = 3,
     PA_K_BLOCKINV = 4,  /* diagonal-block LU/inverse and operator formation */
     PA_K_SPMV_LO = 5,   /* low-precision stage-operator apply (mixed-precision modes) */
-    PA_K_COUNT = 6
+    PA_K_SPMV_T = 6,    /* FP64 stage-operator apply, transposed */
+    PA_K_COUNT = 7
 };
 /* when on, every 8th launch of each listed kernel is bracketed by HIP events
  * on the library's stream; pa_kernel_time returns the launch count since

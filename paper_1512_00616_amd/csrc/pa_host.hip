@@ -705,17 +705,15 @@ struct Solver final : pa_ctx {
     // y = alpha M x + beta op(J) x
     void bsr(const double* J, double alpha, double beta, int tr, const double* x, double* y, const int* skip = nullptr)
     {
-        hipEvent_t e;
-        tstart(PA_K_SPMV, &e);
         k_bsr_apply<NP><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, dm.area, dmh, J, x, y, alpha, beta, tr, skip);
         LAUNCHCHK();
-        tstop(e);
     }
     void ahat(const double* Ah, int tr, const double* x, double* y, const int* skip = nullptr)
     {
         hipEvent_t e;
-        tstart(PA_K_SPMV, &e);
-        k_ahat_apply<NP><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, Ah, x, y, tr, skip);
+        tstart(tr ? PA_K_SPMV_T : PA_K_SPMV, &e);
+        if (tr) k_ahat_tr<NP, double, double><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, Ah, x, y, skip);
+        else k_ahat_fwd<NP, double, double><<<Ne, 64, 0, st>>>(Ne, dm.enb, Ah, x, y, skip);
         LAUNCHCHK();
         tstop(e);
     }
@@ -723,10 +721,21 @@ struct Solver final : pa_ctx {
     {
         hipEvent_t e;
         tstart(PA_K_SPMV_LO, &e);
-        if (pmode == PA_PREC_FP32)
-            k_ahat_apply_lo<NP, float><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, (const float*)Al, x, y, tr, skip);
-        else
-            k_ahat_apply_lo<NP, bf16_t><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, (const bf16_t*)Al, x, y, tr, skip);
+        if (tr) {
+            if (pmode == PA_PREC_FP32)
+                k_ahat_tr<NP, float, float><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, (const float*)Al, x, y, skip);
+            else if constexpr (B % 8 == 0)
+                k_ahat_tr<NP, bf16_t, float><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, (const bf16_t*)Al, x, y, skip);
+            else   // 16-byte BF16 chunks would straddle rows
+                k_ahat_apply_lo<NP, bf16_t><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, (const bf16_t*)Al, x, y, tr, skip);
+        } else {
+            if (pmode == PA_PREC_FP32)
+                k_ahat_fwd<NP, float, float><<<Ne, 64, 0, st>>>(Ne, dm.enb, (const float*)Al, x, y, skip);
+            else if constexpr (B % 8 == 0)
+                k_ahat_fwd<NP, bf16_t, float><<<Ne, 64, 0, st>>>(Ne, dm.enb, (const bf16_t*)Al, x, y, skip);
+            else   // 16-byte BF16 chunks would straddle rows
+                k_ahat_apply_lo<NP, bf16_t><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, (const bf16_t*)Al, x, y, tr, skip);
+        }
         LAUNCHCHK();
         tstop(e);
     }
@@ -1601,8 +1610,7 @@ struct Solver final : pa_ctx {
         const double* Ah = ops(0).Ah;
         ahat(Ah, tr, u0, wf);
         HIPCHK(hipEventRecord(a, st));
-        for (int r = 0; r < reps; ++r) k_ahat_apply<NP><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, Ah, u0, wf, tr, nullptr);
-        LAUNCHCHK();
+        for (int r = 0; r < reps; ++r) ahat(Ah, tr, u0, wf);
         HIPCHK(hipEventRecord(b, st));
         HIPCHK(hipEventSynchronize(b));
         float ms = 0;
@@ -1623,13 +1631,7 @@ struct Solver final : pa_ctx {
         k_scale_to_f32<<<grid1(Nu), 256, 0, st>>>(1.0, u0, r32, Nu);
         ahat_lo(Al, tr, r32, w32);
         HIPCHK(hipEventRecord(a, st));
-        for (int r = 0; r < reps; ++r) {
-            if (pmode == PA_PREC_FP32)
-                k_ahat_apply_lo<NP, float><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, (const float*)Al, r32, w32, tr, nullptr);
-            else
-                k_ahat_apply_lo<NP, bf16_t><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, (const bf16_t*)Al, r32, w32, tr, nullptr);
-        }
-        LAUNCHCHK();
+        for (int r = 0; r < reps; ++r) ahat_lo(Al, tr, r32, w32);
         HIPCHK(hipEventRecord(b, st));
         HIPCHK(hipEventSynchronize(b));
         float ms = 0;

@@ -11,8 +11,9 @@
 //   J^T is a gather: row K of J^T takes the diagonal block transposed and,
 //   for each neighbour, the neighbour's block that points back at K (its
 //   slot 1 + twin) transposed -- no atomics.
-// * k_blockprep / k_form_ahat / k_ahat_apply (below): the block-Jacobi
-//   factor folded into the stored operator.
+// * k_blockprep / k_form_ahat / k_ahat_fwd / k_ahat_tr (below): the
+//   block-Jacobi factor folded into the stored operator and its forward and
+//   transposed applies (FP64, or FP32/BF16 copies for mixed precision).
 // * GMRES vector kernels with fixed-order (deterministic) reductions.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -630,76 +631,6 @@ __global__ void __launch_bounds__(64) k_form_ahat(int Ne, const int32_t* __restr
     }
 }
 
-// y = x + Ahat x (forward) or y = x + Ahat^T x (transposed gather: row K of
-// Ahat^T takes, for each neighbour, the neighbour's block that points back at
-// K, transposed).  One wave per block row; the three blocks of the row are
-// loaded with 16-byte coalesced loads before any arithmetic (more bytes in
-// flight per wave) and reduced from LDS.
-template <int NP>
-__global__ void __launch_bounds__(64) k_ahat_apply(int Ne, const int32_t* __restrict__ enb, const int8_t* __restrict__ etw,
-                                                   const double* __restrict__ Ah, const double* __restrict__ x,
-                                                   double* __restrict__ y, int trans, const int* __restrict__ skip)
-{
-    constexpr int B = 4 * NP, BB = B * B, H = BB / 2;
-    constexpr int PER = (H + 63) / 64;   // 16-byte loads per lane per block
-    __shared__ double sblk[3][B][B + 1];
-    __shared__ double sx[3][B];
-    if (skip && *skip) return;
-    const int K = blockIdx.x, lane = threadIdx.x;
-    int nbs[3];
-    const double2* src[3];
-#pragma unroll
-    for (int f = 0; f < 3; ++f) {
-        int nb = enb[3 * K + f];
-        nbs[f] = nb;
-        src[f] = nullptr;
-        if (nb >= 0) {
-            int64_t blk = trans ? (int64_t)nb * 3 + etw[3 * K + f] : (int64_t)K * 3 + f;
-            src[f] = reinterpret_cast<const double2*>(Ah + blk * BB);
-        }
-    }
-    double2 v[3][PER];
-#pragma unroll
-    for (int f = 0; f < 3; ++f)
-#pragma unroll
-        for (int r = 0; r < PER; ++r) {
-            int t = lane + 64 * r;
-            if (src[f] && t < H) v[f][r] = src[f][t];
-        }
-#pragma unroll
-    for (int f = 0; f < 3; ++f)
-        if (nbs[f] >= 0 && lane < B) sx[f][lane] = x[(int64_t)nbs[f] * B + lane];
-#pragma unroll
-    for (int f = 0; f < 3; ++f)
-#pragma unroll
-        for (int r = 0; r < PER; ++r) {
-            int t = lane + 64 * r;
-            if (src[f] && t < H) {
-                int e = 2 * t;
-                sblk[f][e / B][e % B] = v[f][r].x;
-                sblk[f][(e + 1) / B][(e + 1) % B] = v[f][r].y;
-            }
-        }
-    __syncthreads();
-    if (lane < B) {
-        double acc = x[(int64_t)K * B + lane];
-#pragma unroll
-        for (int f = 0; f < 3; ++f) {
-            if (nbs[f] < 0) continue;
-            double a = 0.0;
-            if (!trans) {
-#pragma unroll 8
-                for (int j = 0; j < B; ++j) a += sblk[f][lane][j] * sx[f][j];
-            } else {
-#pragma unroll 8
-                for (int i = 0; i < B; ++i) a += sblk[f][i][lane] * sx[f][i];
-            }
-            acc += a;
-        }
-        y[(int64_t)K * B + lane] = acc;
-    }
-}
-
 // ------------------------------------------------------------------ low-precision stage operator
 // Storage formats of the inner operator of the mixed-precision solve: FP32,
 // or BF16 (the upper 16 bits of an FP32, rounded to nearest even through
@@ -799,12 +730,163 @@ __global__ void __launch_bounds__(64) k_ahat_apply_lo(int Ne, const int32_t* __r
     }
 }
 
+// Forward apply y = x + Ahat x for any storage type TM (double, float,
+// bf16_t) with TV vectors; accumulation in TV (FP64 for the FP64 operator,
+// FP32 otherwise).  One wave per block row.  Each lane owns 16-byte chunks
+// of the row-major blocks; a chunk lies inside one row (B is a multiple of
+// the entries per chunk), so the lane multiplies it by the matching entries
+// of x in registers and leaves one partial per chunk in LDS, stored
+// chunk-major with a padded stride (conflict-free both ways).  Lane i then
+// adds the partials of row i in chunk order.
+template <class TA> __device__ __forceinline__ TA to_acc(double v) { return (TA)v; }
+template <class TA> __device__ __forceinline__ TA to_acc(float v) { return (TA)v; }
+template <class TA> __device__ __forceinline__ TA to_acc(bf16_t v) { return (TA)lo_to_f(v); }
+
+template <int NP, class TM, class TV>
+__global__ void __launch_bounds__(64) k_ahat_fwd(int Ne, const int32_t* __restrict__ enb, const TM* __restrict__ Ah,
+                                                 const TV* __restrict__ x, TV* __restrict__ y,
+                                                 const int* __restrict__ skip)
+{
+    constexpr int B = 4 * NP, BB = B * B;
+    constexpr int EPL = 16 / sizeof(TM);              // entries per chunk
+    static_assert(B % EPL == 0, "a chunk must not straddle rows");
+    constexpr int H = BB / EPL, CPR = B / EPL;        // chunks per block / per row
+    constexpr int PER = (H + 63) / 64;
+    __shared__ TV sp[3][CPR][B + 1];
+    __shared__ TV sx[3][B];
+    if (skip && *skip) return;
+    const int K = blockIdx.x, lane = threadIdx.x;
+    int nbs[3];
+    const uint4* src[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        const int nb = enb[3 * K + f];
+        nbs[f] = nb;
+        src[f] = nb >= 0 ? reinterpret_cast<const uint4*>(Ah + ((int64_t)K * 3 + f) * BB) : nullptr;
+    }
+    uint4 v[3][PER];
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int t = lane + 64 * r;
+            if (src[f] && t < H) v[f][r] = src[f][t];
+        }
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+        if (nbs[f] >= 0 && lane < B) sx[f][lane] = x[(int64_t)nbs[f] * B + lane];
+    __syncthreads();
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int r = 0; r < PER; ++r) {
+            const int t = lane + 64 * r;
+            if (src[f] && t < H) {
+                const int i = t / CPR, c = t % CPR;
+                const TM* e = reinterpret_cast<const TM*>(&v[f][r]);
+                TV p = 0;
+#pragma unroll
+                for (int q = 0; q < EPL; ++q) p += to_acc<TV>(e[q]) * sx[f][c * EPL + q];
+                sp[f][c][i] = p;
+            }
+        }
+    __syncthreads();
+    if (lane < B) {
+        TV acc = x[(int64_t)K * B + lane];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            if (nbs[f] < 0) continue;
+#pragma unroll
+            for (int c = 0; c < CPR; ++c) acc += sp[f][c][lane];
+        }
+        y[(int64_t)K * B + lane] = acc;
+    }
+}
+
+// Transposed apply y = x + Ahat^T x for any storage type (as k_ahat_fwd).
+// Row K of Ahat^T takes, for each neighbour nb across face f, the block of
+// nb that points back at K (slot twin) transposed, so y[j] sums column j of
+// those blocks weighted by x_nb.  Lanes 0..59 of the wave are (row group g,
+// column chunk c) with G = 60 / CPR groups: lane (g, c) loads chunk c of
+// rows g, g + G, g + 2G, ... -- for every row step the 60 lanes read 60
+// consecutive 16-byte chunks -- and sums its rows in registers, leaving one
+// partial per (g, column) in LDS; lane j then adds the G partials of column
+// j in group order.
+template <int NP, class TM, class TV>
+__global__ void __launch_bounds__(64) k_ahat_tr(int Ne, const int32_t* __restrict__ enb, const int8_t* __restrict__ etw,
+                                                const TM* __restrict__ Ah, const TV* __restrict__ x,
+                                                TV* __restrict__ y, const int* __restrict__ skip)
+{
+    constexpr int B = 4 * NP, BB = B * B;
+    constexpr int EPL = 16 / sizeof(TM);
+    static_assert(B % EPL == 0, "a chunk must not straddle rows");
+    constexpr int CPR = B / EPL;
+    static_assert(60 % CPR == 0, "row groups must tile 60 lanes");
+    constexpr int G = 60 / CPR, RPL = (B + G - 1) / G;
+    __shared__ TV sp[3][G][B + 1];
+    __shared__ TV sx[3][B];
+    if (skip && *skip) return;
+    const int K = blockIdx.x, lane = threadIdx.x;
+    const int c = lane % CPR, g = lane / CPR;   // active when lane < 60
+    int nbs[3];
+    const uint4* src[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        const int nb = enb[3 * K + f];
+        nbs[f] = nb;
+        src[f] = nb >= 0 ? reinterpret_cast<const uint4*>(Ah + ((int64_t)nb * 3 + etw[3 * K + f]) * BB) : nullptr;
+    }
+    uint4 v[3][RPL];
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+            const int i = g + G * k;
+            if (src[f] && lane < 60 && i < B) v[f][k] = src[f][i * CPR + c];
+        }
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+        if (nbs[f] >= 0 && lane < B) sx[f][lane] = x[(int64_t)nbs[f] * B + lane];
+    __syncthreads();
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        if (!src[f] || lane >= 60) continue;
+        TV p[EPL];
+#pragma unroll
+        for (int q = 0; q < EPL; ++q) p[q] = 0;
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+            const int i = g + G * k;
+            if (i < B) {
+                const TV xi = sx[f][i];
+                const TM* e = reinterpret_cast<const TM*>(&v[f][k]);
+#pragma unroll
+                for (int q = 0; q < EPL; ++q) p[q] += to_acc<TV>(e[q]) * xi;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < EPL; ++q) sp[f][g][c * EPL + q] = p[q];
+    }
+    __syncthreads();
+    if (lane < B) {
+        TV acc = x[(int64_t)K * B + lane];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            if (nbs[f] < 0) continue;
+#pragma unroll
+            for (int gg = 0; gg < G; ++gg) acc += sp[f][gg][lane];
+        }
+        y[(int64_t)K * B + lane] = acc;
+    }
+}
+
 // z = a * x (FP64 -> FP32), y += a * x (FP32 -> FP64)
 __global__ void k_scale_to_f32(double a, const double* __restrict__ x, float* __restrict__ z, int64_t n)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) z[i] = (float)(a * x[i]);
 }
+
 
 // out = alpha M x + beta y  (M applied block-wise)
 template <int NP>

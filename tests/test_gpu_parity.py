@@ -187,8 +187,12 @@ def test_tangent_and_adjoint_sweep_parity(period_pair):
     assert rel(tg, o.tangent(v)) <= 1e-10
     ag = g.adjoint_sweep(w)
     assert rel(ag, o.adjoint(w)) <= 1e-10
-    # duality on the GPU alone: <w, Phi v> = <Phi^T w, v>
-    assert abs(w @ tg - ag @ v) <= 1e-11 * abs(w @ tg)
+    # duality on the GPU alone: <w, Phi v> = <Phi^T w, v> holds exactly for
+    # exact stage solves (tangent/adjoint duality theorem of the appendix).
+    # Each sweep makes 3 Nt = 24 solves converged to lin_rtol = 1e-13, and the
+    # forward and transposed products round in different orders, so the gap
+    # is bounded by roughly 24 * 1e-13 * cond(stage operator) ~ 1e-10.
+    assert abs(w @ tg - ag @ v) <= 1e-10 * abs(w @ tg)
     for q in (0, 1):
         lg, gg = g.adjoint_sweep(w, forced_qoi=q)
         lo, go = o.adjoint(w, forced_qoi=q)
