@@ -698,7 +698,7 @@ struct Solver final : pa_ctx {
     {
         hipEvent_t e;
         tstart(PA_K_JACOBIAN, &e);
-        k_jacobian<P><<<Ne, 256, sizeof(JacSmem<P>), st>>>(dm, dref, ph, motion(stage_time(n, i)), u, gbs(n, i), J);
+        k_jacobian<P><<<Ne, 320, sizeof(JacSmem<P>), st>>>(dm, dref, ph, motion(stage_time(n, i)), u, gbs(n, i), J);
         LAUNCHCHK();
         tstop(e);
     }

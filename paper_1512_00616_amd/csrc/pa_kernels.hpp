@@ -368,7 +368,7 @@ struct JacSmem {
 };
 
 template <int P>
-__global__ void __launch_bounds__(256) k_jacobian(DevMesh M, const Ref<P>* __restrict__ R, Phys ph, Motion<double> mo,
+__global__ void __launch_bounds__(320) k_jacobian(DevMesh M, const Ref<P>* __restrict__ R, Phys ph, Motion<double> mo,
                                                   const double* __restrict__ u, const double* __restrict__ gb,
                                                   double* __restrict__ J)
 {
@@ -629,64 +629,91 @@ __global__ void __launch_bounds__(256) k_jacobian(DevMesh M, const Ref<P>* __res
         for (int m = 0; m < 4; ++m) S.E[f][j][m][sd] = Fh[m].d[0];
     }
     __syncthreads();
-    // phase 4: contract into the four blocks of row K
+    // phase 4: contract into the four blocks of row K.  Every term has the
+    // form  sum_p  phi_a(p) * z_p(m, n, b)  over quadrature points p, with
+    // z_p a short sum of pointwise-Jacobian entries times trial-side
+    // operators.  A thread owns one column (m, n, b) of a block for all
+    // test functions a: it forms z_p once per point and applies it to its
+    // NP accumulators with the test-side values read as LDS broadcasts
+    // (a rank-1 update per point instead of recomputing z_p for every a).
+    // Tasks: the diagonal block's columns, then the same columns of the
+    // three neighbour blocks (similar work), one task per thread at 320.
     const double w2K = 2.0 * M.area[K];
-    for (int e = tid; e < 4 * B * B; e += nth) {
-        int s = e / (B * B), row = (e / B) % B, col = e % B;
-        int a = row >> 2, m = row & 3, b = col >> 2, n = col & 3;
-        double acc = 0.0;
-        if (s == 0) {
-            for (int q = 0; q < NQ; ++q) {
-                double t0 = S.D[q][m][0][n] * S.Buq[q][b] + S.D[q][m][0][4 + 2 * n] * S.Psi0[q][b][0] +
-                            S.D[q][m][0][5 + 2 * n] * S.Psi0[q][b][1];
-                double t1 = S.D[q][m][1][n] * S.Buq[q][b] + S.D[q][m][1][4 + 2 * n] * S.Psi0[q][b][0] +
-                            S.D[q][m][1][5 + 2 * n] * S.Psi0[q][b][1];
-                acc += R->wq[q] * (S.gphq[q][a][0] * t0 + S.gphq[q][a][1] * t1);
-            }
-            acc *= w2K;
-            for (int f = 0; f < 3; ++f) {
-                double len = M.elen[3 * K + f], fs = 0.0;
-                if (nb[f] >= 0) {
-                    bool KL = K < nb[f];
-                    int L = KL ? K : nb[f], fL = KL ? f : tw[f];
-                    const double* N = M.enrm + 2 * (3 * L + fL);
-                    for (int j = 0; j < NF; ++j) {
-                        double tt;
-                        if (KL)
-                            tt = S.E[f][j][m][n] * S.BuL[f][j][b] + S.E[f][j][m][8 + 2 * n] * S.PsiL[f][j][b][0] +
-                                 S.E[f][j][m][9 + 2 * n] * S.PsiL[f][j][b][1];
-                        else
-                            tt = S.E[f][j][m][4 + n] * S.BuR[f][j][b] +
-                                 (S.E[f][j][m][8 + 2 * n] * N[0] + S.E[f][j][m][9 + 2 * n] * N[1]) * S.LRf[f][j][b];
-                        double pa = KL ? R->phf[f][j][a] : R->phr[f][j][a];
-                        fs += R->wf[j] * pa * tt;
-                    }
-                    acc -= (KL ? 1.0 : -1.0) * len * fs;
-                } else {
-                    for (int j = 0; j < NF; ++j) {
-                        double tt = S.E[f][j][m][n] * S.BuL[f][j][b] + S.E[f][j][m][4 + 2 * n] * S.PsiL[f][j][b][0] +
-                                    S.E[f][j][m][5 + 2 * n] * S.PsiL[f][j][b][1];
-                        fs += R->wf[j] * R->phf[f][j][a] * tt;
-                    }
-                    acc -= len * fs;
-                }
-            }
-        } else {
-            int f = s - 1;
+    for (int task = tid; task < 2 * 16 * NP; task += nth) {
+        const int cc = task % (16 * NP);
+        const int b = cc % NP, n = (cc / NP) & 3, m = cc / (4 * NP);
+        double* Jrow = J + (int64_t)K * 4 * B * B + m * B + b * 4 + n;   // + s*B*B + a*4*B
+        double acc[NP];
+        if (task >= 16 * NP) goto neighbours;
+        // ---- diagonal block
+#pragma unroll
+        for (int a = 0; a < NP; ++a) acc[a] = 0.0;
+        for (int q = 0; q < NQ; ++q) {
+            const double bu = S.Buq[q][b], p0 = S.Psi0[q][b][0], p1 = S.Psi0[q][b][1], w = R->wq[q];
+            const double z0 = w * (S.D[q][m][0][n] * bu + S.D[q][m][0][4 + 2 * n] * p0 + S.D[q][m][0][5 + 2 * n] * p1);
+            const double z1 = w * (S.D[q][m][1][n] * bu + S.D[q][m][1][4 + 2 * n] * p0 + S.D[q][m][1][5 + 2 * n] * p1);
+#pragma unroll
+            for (int a = 0; a < NP; ++a) acc[a] += S.gphq[q][a][0] * z0 + S.gphq[q][a][1] * z1;
+        }
+#pragma unroll
+        for (int a = 0; a < NP; ++a) acc[a] *= w2K;
+        for (int f = 0; f < 3; ++f) {
+            const double len = M.elen[3 * K + f];
             if (nb[f] >= 0) {
-                bool KL = K < nb[f];
-                if (KL) {
-                    const double* N = M.enrm + 2 * (3 * K + f);
-                    for (int q = 0; q < NQ; ++q) {
-                        double t0 = (S.D[q][m][0][4 + 2 * n] * N[0] + S.D[q][m][0][5 + 2 * n] * N[1]) * S.LRv[f][q][b];
-                        double t1 = (S.D[q][m][1][4 + 2 * n] * N[0] + S.D[q][m][1][5 + 2 * n] * N[1]) * S.LRv[f][q][b];
-                        acc += R->wq[q] * (S.gphq[q][a][0] * t0 + S.gphq[q][a][1] * t1);
-                    }
-                    acc *= w2K;
-                }
-                int L = KL ? K : nb[f], fL = KL ? f : tw[f];
+                const bool KL = K < nb[f];
+                const int L = KL ? K : nb[f], fL = KL ? f : tw[f];
                 const double* N = M.enrm + 2 * (3 * L + fL);
-                double fs = 0.0;
+                const double sg = (KL ? 1.0 : -1.0) * len;
+                for (int j = 0; j < NF; ++j) {
+                    double tt;
+                    if (KL)
+                        tt = S.E[f][j][m][n] * S.BuL[f][j][b] + S.E[f][j][m][8 + 2 * n] * S.PsiL[f][j][b][0] +
+                             S.E[f][j][m][9 + 2 * n] * S.PsiL[f][j][b][1];
+                    else
+                        tt = S.E[f][j][m][4 + n] * S.BuR[f][j][b] +
+                             (S.E[f][j][m][8 + 2 * n] * N[0] + S.E[f][j][m][9 + 2 * n] * N[1]) * S.LRf[f][j][b];
+                    const double z = sg * R->wf[j] * tt;
+                    const double* pa = KL ? R->phf[f][j] : R->phr[f][j];
+#pragma unroll
+                    for (int a = 0; a < NP; ++a) acc[a] -= pa[a] * z;
+                }
+            } else {
+                for (int j = 0; j < NF; ++j) {
+                    const double tt = S.E[f][j][m][n] * S.BuL[f][j][b] + S.E[f][j][m][4 + 2 * n] * S.PsiL[f][j][b][0] +
+                                      S.E[f][j][m][5 + 2 * n] * S.PsiL[f][j][b][1];
+                    const double z = len * R->wf[j] * tt;
+#pragma unroll
+                    for (int a = 0; a < NP; ++a) acc[a] -= R->phf[f][j][a] * z;
+                }
+            }
+        }
+#pragma unroll
+        for (int a = 0; a < NP; ++a) Jrow[a * 4 * B] = acc[a];
+        continue;
+    neighbours:
+        // ---- the block of each face neighbour
+        for (int f = 0; f < 3; ++f) {
+            double* Jf = Jrow + (1 + f) * B * B;
+#pragma unroll
+            for (int a = 0; a < NP; ++a) acc[a] = 0.0;
+            if (nb[f] >= 0) {
+                const bool KL = K < nb[f];
+                if (KL) {
+                    // lifting of this face inside K's volume gradient
+                    const double* NK = M.enrm + 2 * (3 * K + f);
+                    for (int q = 0; q < NQ; ++q) {
+                        const double lr = S.LRv[f][q][b] * R->wq[q];
+                        const double z0 = (S.D[q][m][0][4 + 2 * n] * NK[0] + S.D[q][m][0][5 + 2 * n] * NK[1]) * lr;
+                        const double z1 = (S.D[q][m][1][4 + 2 * n] * NK[0] + S.D[q][m][1][5 + 2 * n] * NK[1]) * lr;
+#pragma unroll
+                        for (int a = 0; a < NP; ++a) acc[a] += S.gphq[q][a][0] * z0 + S.gphq[q][a][1] * z1;
+                    }
+#pragma unroll
+                    for (int a = 0; a < NP; ++a) acc[a] *= w2K;
+                }
+                const int L = KL ? K : nb[f], fL = KL ? f : tw[f];
+                const double* N = M.enrm + 2 * (3 * L + fL);
+                const double sg = (KL ? 1.0 : -1.0) * M.elen[3 * K + f];
                 for (int j = 0; j < NF; ++j) {
                     double tt;
                     if (KL)
@@ -695,13 +722,15 @@ __global__ void __launch_bounds__(256) k_jacobian(DevMesh M, const Ref<P>* __res
                     else
                         tt = S.E[f][j][m][n] * S.BuL[f][j][b] + S.E[f][j][m][8 + 2 * n] * S.PsiL[f][j][b][0] +
                              S.E[f][j][m][9 + 2 * n] * S.PsiL[f][j][b][1];
-                    double pa = KL ? R->phf[f][j][a] : R->phr[f][j][a];
-                    fs += R->wf[j] * pa * tt;
+                    const double z = sg * R->wf[j] * tt;
+                    const double* pa = KL ? R->phf[f][j] : R->phr[f][j];
+#pragma unroll
+                    for (int a = 0; a < NP; ++a) acc[a] -= pa[a] * z;
                 }
-                acc -= (KL ? 1.0 : -1.0) * M.elen[3 * K + f] * fs;
             }
+#pragma unroll
+            for (int a = 0; a < NP; ++a) Jf[a * 4 * B] = acc[a];
         }
-        J[(int64_t)K * 4 * B * B + e] = acc;
     }
 }
 
