@@ -146,7 +146,8 @@ pa_status pa_fixed_point(pa_ctx* ctx, int32_t periods, double* res);
 
 typedef struct pa_adjoint_report {
     int32_t krylov_its[2];      /* outer GMRES iterations per QoI */
-    int32_t sweeps;             /* backward sweeps in total */
+    int32_t sweeps;             /* backward sweeps in total (the two QoIs ride together) */
+    int32_t rhs_sweeps;         /* right-hand sides carried, summed over the sweeps */
     int64_t stage_gmres_its;
     double  rel_res[2];
     double  ms;

@@ -287,6 +287,7 @@ struct Solver final : pa_ctx {
         double aii;        // dt a_ii of the stage
         const void* Al;    // low-precision copy of Ah (mixed-precision modes)
     };
+    struct GmHost { double res; int done; int its; };   // mirrors GmState::res, done, its
 
     int Ne = 0, Nt = 0, nst = 0, nwall = 0;
     int64_t Nu = 0, nn = 0, Jsz = 0, Isz = 0;
@@ -387,6 +388,7 @@ struct Solver final : pa_ctx {
         for (auto& e : evpool) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
         for (void* p : allocs) (void)hipFree(p);
         if (hstat) (void)hipHostFree(hstat);
+        if (hstm) (void)hipHostFree(hstm);
         for (auto& e : gm_ev)
             if (e) (void)hipEventDestroy(e);
         if (st) (void)hipStreamDestroy(st);
@@ -908,16 +910,15 @@ struct Solver final : pa_ctx {
         copy(b, r);
         for (;;) {
             k_mdot_part<<<nb, MD_THREADS, 0, st>>>(r, 0, 1, 0, r, Nu, part, nullptr);
-            k_gm_begin<<<nb, MD_THREADS, 0, st>>>(r, V, Nu, part, nb, tol, gms);
+            k_gm_begin<<<nb, MD_THREADS, 0, st>>>(r, V, Nu, part, nb, GmTol{ { tol } }, gms);
             LAUNCHCHK();
             int pending = -1, slot = 0;
             for (int j = 0; j < m; ++j) {
                 double* vj = V + (int64_t)j * Nu;
-                double* vnext = V + (int64_t)(j + 1) * Nu;
                 ahat(op.Ah, tr, vj, w, skip);
                 // one classical Gram-Schmidt pass; the cycle closes on cancellation
-                k_mdot_part<<<nb, MD_THREADS, 0, st>>>(V, Nu, j + 1, 1, w, Nu, part, skip);
-                k_gm_upd<<<nb, MD_THREADS, 0, st>>>(V, Nu, j, m, w, vnext, Nu, part, nb, gms);
+                k_mdot_part<<<nb, MD_THREADS, 0, st>>>(V, Nu, j + 1, 1, w, Nu, part, gms);
+                k_gm_upd<<<nb, MD_THREADS, 0, st>>>(V, Nu, j, m, w, Nu, part, nb, gms);
                 LAUNCHCHK();
                 if ((j + 1) % GM_CHECK == 0 && j < m - 1) {
                     if (pending >= 0) {
@@ -984,15 +985,16 @@ struct Solver final : pa_ctx {
         for (;;) {
             k_scale_to_f32<<<grid1(Nu), 256, 0, st>>>(1.0 / rn, r, r32, Nu);
             k_mdot_part<<<nb, MD_THREADS, 0, st>>>(r32, 0, 1, 0, r32, Nu, part, nullptr);
-            k_gm_begin<<<nb, MD_THREADS, 0, st>>>(r32, V32, Nu, part, nb, std::max(tol / rn, floor_red), gms);
+            k_gm_begin<<<nb, MD_THREADS, 0, st>>>(r32, V32, Nu, part, nb, GmTol{ { std::max(tol / rn, floor_red) } },
+                                                  gms);
             LAUNCHCHK();
             int pending = -1, slot = 0;
             for (int j = 0; j < m; ++j) {
                 float* vj = V32 + (int64_t)j * Nu;
-                float* vnext = V32 + (int64_t)(j + 1) * Nu;
                 ahat_lo(op.Al, tr, vj, w32, skip);
-                k_mdot_part<<<nb, MD_THREADS, 0, st>>>((const float*)V32, Nu, j + 1, 1, (const float*)w32, Nu, part, skip);
-                k_gm_upd<<<nb, MD_THREADS, 0, st>>>((const float*)V32, Nu, j, m, (const float*)w32, vnext, Nu, part, nb, gms);
+                k_mdot_part<<<nb, MD_THREADS, 0, st>>>((const float*)V32, Nu, j + 1, 1, (const float*)w32, Nu, part,
+                                                       gms);
+                k_gm_upd<<<nb, MD_THREADS, 0, st>>>((const float*)V32, Nu, j, m, (const float*)w32, Nu, part, nb, gms);
                 LAUNCHCHK();
                 if ((j + 1) % GM_CHECK == 0 && j < m - 1) {
                     if (pending >= 0) {
@@ -1026,6 +1028,208 @@ struct Solver final : pa_ctx {
         cnt_gmres += total;
         return total;
     }
+    // ---------------------------------------------------------------- several right-hand sides
+    // R <= GM_RMAX systems with the same stage operator solved in lockstep:
+    // one apply per iteration reads the stored blocks once for all R basis
+    // vectors; the Arnoldi kernels run with one grid row per system; each
+    // system has its own device GMRES state and stops on its own tolerance.
+    int RM = 0;
+    double *Vm = nullptr, *wm = nullptr, *ym = nullptr, *bm = nullptr, *rm = nullptr, *partm = nullptr;
+    double *t1m = nullptr, *t2m = nullptr;                     // jprod temporaries
+    double *lamm = nullptr, *rhsm = nullptr, *kapm = nullptr, *skm = nullptr, *fpm = nullptr, *drmm = nullptr;
+    GmState* gmsm = nullptr;
+    GmHost* hstm = nullptr;                                    // pinned [GM_RMAX]
+    void ensure_multi()
+    {
+        if (RM) return;
+        const int R = GM_RMAX;
+        Vm = dalloc<double>((int64_t)R * (restart + 1) * Nu);
+        wm = dalloc<double>(R * Nu); ym = dalloc<double>(R * Nu); bm = dalloc<double>(R * Nu);
+        rm = dalloc<double>(R * Nu); t1m = dalloc<double>(R * Nu); t2m = dalloc<double>(R * Nu);
+        lamm = dalloc<double>(R * Nu); rhsm = dalloc<double>(R * Nu); kapm = dalloc<double>(R * Nu);
+        skm = dalloc<double>(3 * R * Nu); fpm = dalloc<double>(3 * R * Nu); drmm = dalloc<double>(3 * Nu);
+        partm = dalloc<double>((int64_t)R * mdot_blocks(Nu) * (restart + 2));
+        stgX = dalloc<double>(R * Nu); stgY = dalloc<double>(R * Nu); outm = dalloc<double>(R * Nu);
+        brhs = dalloc<double>(R * Nu);
+        gmsm = dalloc<GmState>(R);
+        HIPCHK(hipHostMalloc((void**)&hstm, R * sizeof(GmHost), hipHostMallocDefault));
+        RM = R;
+    }
+    void ahat_m(const double* Ah, int tr, int R, const double* x, int64_t sx, double* y, int64_t sy,
+                const GmState* skip = nullptr)
+    {
+        hipEvent_t e;
+        tstart(tr ? PA_K_SPMV_T : PA_K_SPMV, &e);
+        if (tr) k_ahat_tr_m<NP><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, Ah, R, x, sx, y, sy, skip);
+        else k_ahat_fwd_m<NP><<<Ne, 64, 0, st>>>(Ne, dm.enb, Ah, R, x, sx, y, sy, skip);
+        LAUNCHCHK();
+        tstop(e);
+    }
+    void poll_multi(int R)
+    {
+        for (int r = 0; r < R; ++r)
+            HIPCHK(hipMemcpyAsync(&hstm[r], &gmsm[r].res, sizeof(GmHost), hipMemcpyDeviceToHost, st));
+    }
+    // x_r solves op(A) x_r = rhs_r, r < R; rhs and x hold R vectors at stride Nu
+    int stage_solve_multi(const StageOps& op, int tr, int R, const double* rhs, double* x)
+    {
+        if (R == 1 || pmode != PA_PREC_FP64) {
+            int tot = 0;
+            for (int r = 0; r < R; ++r) tot += stage_solve(op, tr, rhs + r * Nu, x + r * Nu);
+            return tot;
+        }
+        if (R > GM_RMAX) raise(PA_EINVAL, "at most %d right-hand sides", GM_RMAX);
+        ensure_multi();
+        const int m = restart, maxit = 20 * restart;
+        const int nb = (int)mdot_blocks(Nu);
+        const int64_t sV = (int64_t)(m + 1) * Nu, sP = (int64_t)nb * (m + 2);
+        const double* b = rhs;
+        if (tr) {
+            for (int r = 0; r < R; ++r) prec(op.Pinv, 1, rhs + r * Nu, bm + r * Nu);
+            b = bm;
+        }
+        double bn[GM_RMAX], tol[GM_RMAX];
+        bool acc[GM_RMAX];
+        GmTol tl{};
+        for (int r = 0; r < R; ++r) {
+            bn[r] = norm(b + r * Nu);
+            tol[r] = cfg.lin_rtol * bn[r];
+            acc[r] = bn[r] == 0.0;
+            tl.t[r] = acc[r] ? 1e300 : tol[r];
+        }
+        zero(ym, R * Nu);
+        HIPCHK(hipMemcpyAsync(rm, b, sizeof(double) * R * Nu, hipMemcpyDeviceToDevice, st));
+        int total = 0;
+        bool all = true;
+        for (int r = 0; r < R; ++r) all = all && acc[r];
+        while (!all) {
+            const dim3 g2(nb, R);
+            k_mdot_part<<<g2, MD_THREADS, 0, st>>>(rm, 0, 1, 0, rm, Nu, partm, nullptr, Nu, Nu, sP);
+            k_gm_begin<<<g2, MD_THREADS, 0, st>>>(rm, Vm, Nu, partm, nb, tl, gmsm, Nu, sV, sP);
+            LAUNCHCHK();
+            int pending = -1, jlast = 0;
+            hipEvent_t ev_p = nullptr;
+            for (int j = 0; j < m; ++j) {
+                jlast = j;
+                ahat_m(op.Ah, tr, R, Vm + (int64_t)j * Nu, sV, wm, Nu, gmsm);
+                k_mdot_part<<<g2, MD_THREADS, 0, st>>>(Vm, Nu, j + 1, 1, wm, Nu, partm, gmsm, sV, Nu, sP);
+                k_gm_upd<<<g2, MD_THREADS, 0, st>>>(Vm, Nu, j, m, wm, Nu, partm, nb, gmsm, sV, Nu, sP);
+                LAUNCHCHK();
+                if ((j + 1) % GM_CHECK == 0 && j < m - 1) {
+                    if (pending >= 0) {
+                        HIPCHK(hipEventSynchronize(ev_p));
+                        bool alldone = true;
+                        for (int r = 0; r < R; ++r) alldone = alldone && hstm[r].done;
+                        if (alldone) break;
+                    }
+                    poll_multi(R);
+                    HIPCHK(hipEventRecord(gm_ev[0], st));
+                    ev_p = gm_ev[0];
+                    pending = 0;
+                }
+            }
+            (void)jlast;
+            k_gm_solve<<<R, 256, 0, st>>>(m, gmsm);
+            k_gm_combine<<<dim3(grid1(Nu), R), 256, 0, st>>>(Vm, Nu, m, wm, Nu, gmsm, sV, Nu);
+            LAUNCHCHK();
+            poll_multi(R);
+            for (int r = 0; r < R; ++r)
+                if (!acc[r]) axpby(1.0, wm + r * Nu, 1.0, ym + r * Nu);
+            ahat_m(op.Ah, tr, R, ym, Nu, wm, Nu);
+            for (int r = 0; r < R; ++r) lincomb(1.0, b + r * Nu, -1.0, wm + r * Nu, rm + r * Nu);
+            all = true;
+            int cyc = 0;
+            for (int r = 0; r < R; ++r) {
+                const double rn = norm(rm + r * Nu);   // synchronises: hstm valid
+                if (!acc[r]) {
+                    cyc = std::max(cyc, hstm[r].done ? hstm[r].its : m);
+                    if (!std::isfinite(rn) || !std::isfinite(hstm[r].res)) raise(PA_ENUMERIC, "NaN in stage GMRES");
+                    if (hstm[r].done && rn <= 2.0 * tol[r]) { acc[r] = true; tl.t[r] = 1e300; }
+                }
+                all = all && acc[r];
+            }
+            total += cyc;
+            if (!all && total >= maxit) raise(PA_ENOCONV, "stage GMRES (%d systems) did not converge in %d iterations", R, total);
+        }
+        for (int r = 0; r < R; ++r) {
+            if (tr) copy(ym + r * Nu, x + r * Nu);
+            else prec(op.Pinv, 0, ym + r * Nu, x + r * Nu);
+        }
+        cnt_gmres += (int64_t)total * R;
+        return total;
+    }
+    // out_r = dt J^T w_r (transposed stage Jacobian products, R systems)
+    void stage_jprod_tr_multi(const StageOps& op, int R, const double* w, double* out)
+    {
+        ahat_m(op.Ah, 1, R, w, Nu, t1m, Nu);
+        const double ia = dt / op.aii;
+        for (int r = 0; r < R; ++r) {
+            prec(op.Pd, 1, t1m + r * Nu, t2m + r * Nu);
+            k_mass_axpy<NP><<<grid1(Nu), 256, 0, st>>>(Ne, dm.area, dmh, w + r * Nu, t2m + r * Nu, ia, -ia, out + r * Nu);
+        }
+        LAUNCHCHK();
+    }
+    // backward sweeps of R systems together (as adjoint()): lamNt, lam0 hold R
+    // vectors; system r is forced by QoI fq[r] >= 0 (then grad[3 r + k])
+    void adjoint_multi(int R, const double* lamNt, const int* fq, double* lam0, double* grad)
+    {
+        if (!have_traj) raise(PA_ESTATE, "no trajectory");
+        if (R == 1) { adjoint(lamNt, fq[0], lam0, grad); return; }
+        ensure_multi();
+        if (R > GM_RMAX) raise(PA_EINVAL, "at most %d right-hand sides", GM_RMAX);
+        double* lam = lamm;
+        double* rhs = rhsm;
+        double* kap = kapm;
+        auto SK = [&](int i, int r) { return skm + ((int64_t)i * R + r) * Nu; };
+        auto FP = [&](int i, int r) { return fpm + ((int64_t)i * R + r) * Nu; };
+        HIPCHK(hipMemcpyAsync(lam, lamNt, sizeof(double) * R * Nu, hipMemcpyDeviceToDevice, st));
+        std::vector<double> g(3 * R, 0.0);
+        bool anyf = false;
+        for (int r = 0; r < R; ++r) anyf = anyf || fq[r] >= 0;
+        const double sc = dt / cfg.T;
+        for (int n = Nt; n >= 1; --n) {
+            for (int r = 0; r < R; ++r) {
+                if (fq[r] < 0) continue;
+                for (int i = 1; i <= 3; ++i) {
+                    const int s = (n - 1) * 3 + (i - 1);
+                    qoi_grad(n, i, stU(s), fq[r], FP(i - 1, r), qtmp);
+                    double fm[6];
+                    qoi_dmu(n, i, stU(s), fm, nullptr);
+                    for (int k = 0; k < 3; ++k) g[3 * r + k] += sc * rk.b[i - 1] * fm[3 * fq[r] + k];
+                }
+            }
+            for (int i = 3; i >= 1; --i) {
+                const int s = (n - 1) * 3 + (i - 1);
+                for (int r = 0; r < R; ++r) {
+                    double* rr = rhs + r * Nu;
+                    lincomb(rk.b[i - 1], lam + r * Nu, 0.0, lam + r * Nu, rr);
+                    for (int j = i + 1; j <= 3; ++j) axpby(rk.A[j - 1][i - 1], SK(j - 1, r), 1.0, rr);
+                    if (fq[r] >= 0)
+                        for (int j = i; j <= 3; ++j) axpby(sc * rk.b[j - 1] * rk.A[j - 1][i - 1], FP(j - 1, r), 1.0, rr);
+                }
+                stage_solve_multi(ops(s), 1, R, rhs, kap);
+                // dt J^T kap_r into the stage slots (contiguous per stage)
+                stage_jprod_tr_multi(ops(s), R, kap, SK(i - 1, 0));
+                if (anyf) {
+                    dr_dmu(n, i, stU(s), drmm);
+                    for (int r = 0; r < R; ++r) {
+                        if (fq[r] < 0) continue;
+                        double d[3];
+                        dots(drmm, Nu, 3, kap + r * Nu, d);
+                        for (int k = 0; k < 3; ++k) g[3 * r + k] += dt * d[k];
+                    }
+                }
+            }
+            for (int r = 0; r < R; ++r) {
+                for (int i = 0; i < 3; ++i) axpby(1.0, SK(i, r), 1.0, lam + r * Nu);
+                if (fq[r] >= 0)
+                    for (int i = 0; i < 3; ++i) axpby(sc * rk.b[i], FP(i, r), 1.0, lam + r * Nu);
+            }
+        }
+        HIPCHK(hipMemcpyAsync(lam0, lam, sizeof(double) * R * Nu, hipMemcpyDeviceToDevice, st));
+        if (grad) for (int k = 0; k < 3 * R; ++k) grad[k] = g[k];
+    }
+
     // out = dt J op(w) of a stage:  c J = M - A,  A = Ahat P,  A^T = P^T Ahat^T
     void stage_jprod(const StageOps& op, int tr, const double* w, double* out, double* tmp1, double* tmp2)
     {
@@ -1041,7 +1245,6 @@ struct Solver final : pa_ctx {
         k_mass_axpy<NP><<<grid1(Nu), 256, 0, st>>>(Ne, dm.area, dmh, w, tmp2, ia, -ia, out);
         LAUNCHCHK();
     }
-    struct GmHost { double res; int done; int its; };
     GmState* gms = nullptr;
     GmHost* hstat = nullptr;       // pinned: two check slots and the end-of-cycle status
     hipEvent_t gm_ev[2] = {nullptr, nullptr};
@@ -1444,33 +1647,140 @@ struct Solver final : pa_ctx {
     double *gm_b = nullptr, *gm_y = nullptr;
     double last_outer_rel = 0;
 
+    // Outer matrix-free GMRES on (Phi^T - I) for R right-hand sides in
+    // lockstep (no restart, zero initial guess): every iteration applies one
+    // backward sweep carrying the current basis vector of each unconverged
+    // system; Gram-Schmidt (two passes) and Givens rotations per system as in
+    // gmres().  Solutions to outm (R vectors at stride Nu).
+    double *VoM = nullptr, *stgX = nullptr, *stgY = nullptr, *outm = nullptr, *brhs = nullptr;
+    void outer_adjoint_multi(int R, const double* rhs, double rtol, int32_t* its, double* rel)
+    {
+        ensure_multi();
+        if (!VoM) VoM = dalloc<double>((int64_t)GM_RMAX * (max_kry + 1) * Nu);
+        const int m = max_kry;
+        struct Sys {
+            std::vector<double> H, cs, sn, g, h, h2;
+            double bn = 0, res = 0;
+            int j = 0;
+            bool active = true;
+        };
+        std::vector<Sys> S(R);
+        auto Vb = [&](int r) { return VoM + (int64_t)r * (m + 1) * Nu; };
+        for (int r = 0; r < R; ++r) {
+            Sys& y = S[r];
+            y.H.assign((m + 1) * m, 0.0); y.cs.assign(m, 0.0); y.sn.assign(m, 0.0); y.g.assign(m + 1, 0.0);
+            y.h.assign(m + 2, 0.0); y.h2.assign(m + 2, 0.0);
+            y.bn = norm(rhs + r * Nu);
+            y.res = y.bn;
+            y.g[0] = y.bn;
+            y.active = y.bn > 0.0;
+            its[r] = 0;
+            if (y.active) lincomb(1.0 / y.bn, rhs + r * Nu, 0.0, rhs + r * Nu, Vb(r));
+        }
+        double t0 = now_ms();
+        int nmv = 0;
+        const int fq[GM_RMAX] = { -1, -1, -1, -1, -1, -1, -1, -1 };
+        for (;;) {
+            int act[GM_RMAX], na = 0;
+            for (int r = 0; r < R; ++r)
+                if (S[r].active) act[na++] = r;
+            if (na == 0) break;
+            for (int a = 0; a < na; ++a) copy(Vb(act[a]) + (int64_t)S[act[a]].j * Nu, stgX + a * Nu);
+            adjoint_multi(na, stgX, fq, stgY, nullptr);
+            ++nmv;
+            if (verbose && nmv % 10 == 0)
+                fprintf(stderr, "[pa]   adjoint sweeps %d (%d systems)  %.1f s\n", nmv, na, (now_ms() - t0) / 1e3);
+            for (int a = 0; a < na; ++a) {
+                const int r = act[a];
+                Sys& y = S[r];
+                const int j = y.j;
+                double* wk = stgY + a * Nu;
+                axpby(-1.0, stgX + a * Nu, 1.0, wk);   // (Phi^T - I) v
+                ++its[r];
+                dots(Vb(r), Nu, j + 1, wk, y.h.data());
+                vupdate(Vb(r), Nu, j + 1, y.h.data(), -1.0, wk);
+                const int nb = (int)mdot_blocks(Nu);
+                k_mdot_part<<<nb, MD_THREADS, 0, st>>>(Vb(r), Nu, j + 1, 1, wk, Nu, part, nullptr);
+                k_mdot_fin<<<1, MD_THREADS, 0, st>>>(part, nb, j + 2, hdev);
+                LAUNCHCHK();
+                HIPCHK(hipMemcpyAsync(y.h2.data(), hdev, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, st));
+                HIPCHK(hipStreamSynchronize(st));
+                double ww = y.h2[j + 1], corr = 0.0;
+                for (int i = 0; i <= j; ++i) corr += y.h2[i] * y.h2[i];
+                vupdate(Vb(r), Nu, j + 1, y.h2.data(), -1.0, wk);
+                for (int i = 0; i <= j; ++i) y.H[i * m + j] = y.h[i] + y.h2[i];
+                double hn = std::sqrt(std::max(ww - corr, 0.0));
+                if (!std::isfinite(hn)) raise(PA_ENUMERIC, "NaN in GMRES");
+                y.H[(j + 1) * m + j] = hn;
+                for (int i = 0; i < j; ++i) {
+                    double p = y.H[i * m + j], q = y.H[(i + 1) * m + j];
+                    y.H[i * m + j] = y.cs[i] * p + y.sn[i] * q;
+                    y.H[(i + 1) * m + j] = -y.sn[i] * p + y.cs[i] * q;
+                }
+                double p = y.H[j * m + j], q = y.H[(j + 1) * m + j];
+                double rr = std::sqrt(p * p + q * q);
+                y.cs[j] = p / rr;
+                y.sn[j] = q / rr;
+                y.H[j * m + j] = rr;
+                y.H[(j + 1) * m + j] = 0.0;
+                y.g[j + 1] = -y.sn[j] * y.g[j];
+                y.g[j] = y.cs[j] * y.g[j];
+                y.res = std::fabs(y.g[j + 1]);
+                y.j = j + 1;
+                const bool stop = y.res <= rtol * y.bn || hn == 0.0 || y.j >= m;
+                if (!stop) lincomb(1.0 / hn, wk, 0.0, wk, Vb(r) + (int64_t)(j + 1) * Nu);
+                else y.active = false;
+            }
+        }
+        for (int r = 0; r < R; ++r) {
+            Sys& y = S[r];
+            const int k = y.j;
+            std::vector<double> c(std::max(k, 1), 0.0);
+            for (int i = k - 1; i >= 0; --i) {
+                double t = y.g[i];
+                for (int q = i + 1; q < k; ++q) t -= y.H[i * m + q] * c[q];
+                c[i] = t / y.H[i * m + i];
+            }
+            zero(outm + r * Nu);
+            if (k > 0) vupdate(Vb(r), Nu, k, c.data(), 1.0, outm + r * Nu);
+            rel[r] = y.bn > 0.0 ? y.res / y.bn : 0.0;
+        }
+    }
+
     void adjoint_gradient(double rtol, double qoi[2], double dJ[6], pa_adjoint_report* rep) override
     {
         if (!have_traj) raise(PA_ESTATE, "no trajectory (run pa_primal_period or pa_shoot first)");
         double t0 = now_ms();
         int64_t g0 = cnt_gmres;
         pa_adjoint_report r{};
-        double* lamN = lam_buf;
+        // both QoIs in lockstep: every backward sweep carries one right-hand
+        // side per QoI (g_F sweeps, the Krylov sweeps, the final sweeps)
+        ensure_multi();
+        const int fq[2] = { 0, 1 };
+        double grad[6];
+        zero(stgX, 2 * Nu);
+        adjoint_multi(2, stgX, fq, brhs, grad);          // g_F of both QoIs from zero
+        r.sweeps += 1;
+        r.rhs_sweeps += 2;
+        axpby(-1.0, brhs, 0.0, brhs);                    // b = -g_F  (dF/du^(Nt) = 0)
+        axpby(-1.0, brhs + Nu, 0.0, brhs + Nu);
+        int32_t its[2];
+        double rel[2];
+        outer_adjoint_multi(2, brhs, rtol, its, rel);
         for (int q = 0; q < 2; ++q) {
-            double grad[3];
-            // g_F: forced sweep from zero
-            zero(lamN);
-            adjoint(lamN, q, wd, grad);
-            ++r.sweeps;
-            axpby(-1.0, wd, 0.0, wd);   // b = -g_F  (dF/du^(Nt) = 0)
-            int its = 0;
-            outer_gmres(false, wd, rtol, its);
-            r.krylov_its[q] = its;
-            r.rel_res[q] = last_outer_rel;
-            if (verbose)
-                fprintf(stderr, "[pa] adjoint qoi %d: %d krylov its, rel res %.2e, %.1f s\n", q, its, last_outer_rel,
-                        (now_ms() - t0) / 1e3);
-            r.sweeps += its + 1;
-            copy(wf, lamN);
-            adjoint(lamN, q, wd, grad);
-            ++r.sweeps;
-            for (int k = 0; k < 3; ++k) dJ[3 * q + k] = grad[k];
+            r.krylov_its[q] = its[q];
+            r.rel_res[q] = rel[q];
         }
+        r.sweeps += std::max(its[0], its[1]);
+        r.rhs_sweeps += its[0] + its[1];
+        if (verbose)
+            fprintf(stderr, "[pa] adjoint (2 QoIs in lockstep): %d / %d krylov its, rel res %.2e / %.2e, %.1f s\n",
+                    its[0], its[1], rel[0], rel[1], (now_ms() - t0) / 1e3);
+        HIPCHK(hipMemcpyAsync(stgX, outm, sizeof(double) * 2 * Nu, hipMemcpyDeviceToDevice, st));
+        adjoint_multi(2, stgX, fq, stgY, grad);
+        r.sweeps += 1;
+        r.rhs_sweeps += 2;
+        for (int k = 0; k < 6; ++k) dJ[k] = grad[k];
         if (qoi) {
             // time-averaged QoIs of the stored trajectory
             std::vector<double> h((size_t)nst * std::max(nwall, 1) * 2);

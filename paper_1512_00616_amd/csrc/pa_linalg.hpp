@@ -109,6 +109,22 @@ __global__ void __launch_bounds__(64) k_block_apply(int Ne, const double* __rest
     }
 }
 
+// Arnoldi state of one restart cycle kept in device memory so that the
+// iterations run without host round trips.  Every iteration kernel returns
+// at once when `done` is set; the host polls `done` every few iterations.
+constexpr int GM_MAXM = 64;
+struct GmState {
+    double H[(GM_MAXM + 1) * GM_MAXM];   // Hessenberg (rotated), row-major (m+1) x m
+    double cs[GM_MAXM], sn[GM_MAXM];
+    double g[GM_MAXM + 1];
+    double y[GM_MAXM];
+    double hc[GM_MAXM + 2];              // Gram-Schmidt coefficients of the current column
+    double tol;                          // absolute residual target
+    double res;                          // current residual estimate
+    int done;                            // 1: converged or happy breakdown
+    int its;                             // columns of the cycle when done
+};
+
 // ------------------------------------------------------------------ vector kernels
 // Multi-column dot products  s_c = <X_c, w>,  X_c = V + c*ldv (c < ncols),
 // optionally followed by <w, w>, in one launch and in a fixed summation
@@ -253,15 +269,19 @@ __device__ __forceinline__ void mdot_finish(const double* __restrict__ partial, 
     __syncthreads();
 }
 
-// partial[b][c] of <X_c, w> (c < ncols) and <w, w> (if with_ww); skipped
-// when the GMRES state `st` (optional) is done
+// partial[b][c] of <X_c, w> (c < ncols) and <w, w> (if with_ww).  Several
+// independent systems r = blockIdx.y (right-hand sides sharing an operator)
+// are addressed by the strides sV, sw, sP; system r is skipped when its GMRES
+// state st[r] (optional) is done.
 template <class T>
 __global__ void __launch_bounds__(MD_THREADS) k_mdot_part(const T* __restrict__ V, int64_t ldv, int ncols,
                                                           int with_ww, const T* __restrict__ w, int64_t n,
-                                                          double* __restrict__ partial, const int* __restrict__ skip)
+                                                          double* __restrict__ partial, const GmState* __restrict__ st,
+                                                          int64_t sV = 0, int64_t sw = 0, int64_t sP = 0)
 {
-    if (skip && *skip) return;
-    mdot_partials(V, ldv, ncols, with_ww, w, n, partial);
+    const int r = blockIdx.y;
+    if (st && st[r].done) return;
+    mdot_partials(V + r * sV, ldv, ncols, with_ww, w + r * sw, n, partial + r * sP);
 }
 
 // out[c] = sum_b partial[b][c]; one block
@@ -320,21 +340,7 @@ __global__ void k_stage_residual(int Ne, const double* __restrict__ area, const 
 namespace pa {
 
 // ------------------------------------------------------------------ device-resident GMRES
-// Arnoldi state of one restart cycle kept in device memory so that the
-// iterations run without host round trips.  Every iteration kernel returns
-// at once when `done` is set; the host polls `done` every few iterations.
-constexpr int GM_MAXM = 64;
-struct GmState {
-    double H[(GM_MAXM + 1) * GM_MAXM];   // Hessenberg (rotated), row-major (m+1) x m
-    double cs[GM_MAXM], sn[GM_MAXM];
-    double g[GM_MAXM + 1];
-    double y[GM_MAXM];
-    double hc[GM_MAXM + 2];              // Gram-Schmidt coefficients of the current column
-    double tol;                          // absolute residual target
-    double res;                          // current residual estimate
-    int done;                            // 1: converged or happy breakdown
-    int its;                             // columns of the cycle when done
-};
+
 
 // relaxed read of the done flag (block 0 of k_gm_upd may set it while
 // other blocks of the same launch read it; either value is correct there)
@@ -359,10 +365,19 @@ __device__ __forceinline__ int gm_done(const GmState* st)
 // (columns past j re-read column j with weight zero).
 template <class T>
 __global__ void __launch_bounds__(MD_THREADS) k_gm_upd(const T* __restrict__ V, int64_t ldv, int j, int m,
-                                                       const T* __restrict__ w, T* __restrict__ vnext,
-                                                       int64_t n, const double* __restrict__ partial, int nblk,
-                                                       GmState* __restrict__ st)
+                                                       const T* __restrict__ w, int64_t n,
+                                                       const double* __restrict__ partial, int nblk,
+                                                       GmState* __restrict__ st, int64_t sV = 0, int64_t sw = 0,
+                                                       int64_t sP = 0)
 {
+    {   // system r = blockIdx.y
+        const int r = blockIdx.y;
+        V += r * sV;
+        w += r * sw;
+        partial += r * sP;
+        st += r;
+    }
+    T* __restrict__ vnext = const_cast<T*>(V) + (int64_t)(j + 1) * ldv;
     if (gm_done(st)) return;
     __shared__ double s1[GM_MAXM + 2];
     __shared__ double scs[GM_MAXM], ssn[GM_MAXM];
@@ -449,11 +464,20 @@ __global__ void __launch_bounds__(MD_THREADS) k_gm_upd(const T* __restrict__ V, 
 // start of a cycle from the partials of <r, r>: beta = ||r||, g = beta e_1,
 // V_0 = r / beta (every block sums the partials in the same order; block 0
 // writes the state)
+constexpr int GM_RMAX = 8;   // systems per launch
+struct GmTol { double t[GM_RMAX]; };
 template <class T>
 __global__ void __launch_bounds__(MD_THREADS) k_gm_begin(const T* __restrict__ r, T* __restrict__ v0,
                                                          int64_t n, const double* __restrict__ partial, int nblk,
-                                                         double tol, GmState* __restrict__ st)
+                                                         GmTol tols, GmState* __restrict__ st, int64_t sr = 0,
+                                                         int64_t sV = 0, int64_t sP = 0)
 {
+    const int sys = blockIdx.y;
+    r += sys * sr;
+    v0 += sys * sV;
+    partial += sys * sP;
+    st += sys;
+    const double tol = tols.t[sys];
     __shared__ double tot[1];
     mdot_finish(partial, nblk, 1, tot);
     const double beta = sqrt(tot[0]);
@@ -482,6 +506,7 @@ __global__ void __launch_bounds__(MD_THREADS) k_gm_begin(const T* __restrict__ r
 // staged in LDS by all lanes, one lane back-substitutes
 __global__ void __launch_bounds__(256) k_gm_solve(int m, GmState* __restrict__ st)
 {
+    st += blockIdx.x;   // one block per system
     __shared__ double R[GM_MAXM * GM_MAXM];
     __shared__ double yy[GM_MAXM];
     const int k = st->done ? st->its : m;
@@ -501,8 +526,11 @@ __global__ void __launch_bounds__(256) k_gm_solve(int m, GmState* __restrict__ s
 // out = sum_{c<m} y[c] V_c   (y is zero beyond the cycle's length)
 template <class T>
 __global__ void k_gm_combine(const T* __restrict__ V, int64_t ldv, int m, double* __restrict__ out, int64_t n,
-                             const GmState* __restrict__ st)
+                             const GmState* __restrict__ st, int64_t sV = 0, int64_t sOut = 0)
 {
+    V += blockIdx.y * sV;
+    out += blockIdx.y * sOut;
+    st += blockIdx.y;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     int k = st->done ? st->its : m;
@@ -878,6 +906,148 @@ __global__ void __launch_bounds__(64) k_ahat_tr(int Ne, const int32_t* __restric
         }
         y[(int64_t)K * B + lane] = acc;
     }
+}
+
+// ------------------------------------------------------------------ several right-hand sides
+// y_r = x_r + Ahat x_r (forward) for R systems sharing the stored operator
+// (x_r = x + r sx, y_r = y + r sy): the three blocks of the row are read
+// from HBM once into registers and applied to every x_r (same per-chunk
+// partials as k_ahat_fwd, one LDS pass per system).  The launch returns at
+// once when every system's GMRES state (optional) is done.
+template <int NP>
+__global__ void __launch_bounds__(64) k_ahat_fwd_m(int Ne, const int32_t* __restrict__ enb, const double* __restrict__ Ah,
+                                                   int R, const double* __restrict__ x, int64_t sx,
+                                                   double* __restrict__ y, int64_t sy, const GmState* __restrict__ st)
+{
+    constexpr int B = 4 * NP, BB = B * B, EPL = 2;
+    constexpr int H = BB / EPL, CPR = B / EPL, PER = (H + 63) / 64;
+    __shared__ double sp[3][CPR][B + 1];
+    __shared__ double sxr[GM_RMAX][3][B];
+    if (st) {
+        bool all = true;
+        for (int r = 0; r < R; ++r) all = all && st[r].done;
+        if (all) return;
+    }
+    const int K = blockIdx.x, lane = threadIdx.x;
+    int nbs[3];
+    const uint4* src[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        const int nb = enb[3 * K + f];
+        nbs[f] = nb;
+        src[f] = nb >= 0 ? reinterpret_cast<const uint4*>(Ah + ((int64_t)K * 3 + f) * BB) : nullptr;
+    }
+    uint4 v[3][PER];
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int rr = 0; rr < PER; ++rr) {
+            const int t = lane + 64 * rr;
+            if (src[f] && t < H) v[f][rr] = src[f][t];
+        }
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+            if (nbs[f] >= 0 && lane < B) sxr[r][f][lane] = x[r * sx + (int64_t)nbs[f] * B + lane];
+    __syncthreads();
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+#pragma unroll
+            for (int rr = 0; rr < PER; ++rr) {
+                const int t = lane + 64 * rr;
+                if (src[f] && t < H) {
+                    const int i = t / CPR, c = t % CPR;
+                    const double* e = reinterpret_cast<const double*>(&v[f][rr]);
+                    sp[f][c][i] = e[0] * sxr[r][f][c * EPL] + e[1] * sxr[r][f][c * EPL + 1];
+                }
+            }
+        __syncthreads();
+        if (lane < B) {
+            double acc = x[r * sx + (int64_t)K * B + lane];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                if (nbs[f] < 0) continue;
+#pragma unroll
+                for (int c = 0; c < CPR; ++c) acc += sp[f][c][lane];
+            }
+            y[r * sy + (int64_t)K * B + lane] = acc;
+        }
+        __syncthreads();
+    }
+}
+
+// transposed counterpart of k_ahat_fwd_m (layout of k_ahat_tr)
+template <int NP>
+__global__ void __launch_bounds__(64) k_ahat_tr_m(int Ne, const int32_t* __restrict__ enb, const int8_t* __restrict__ etw,
+                                                  const double* __restrict__ Ah, int R, const double* __restrict__ x,
+                                                  int64_t sx, double* __restrict__ y, int64_t sy,
+                                                  const GmState* __restrict__ st)
+{
+    constexpr int B = 4 * NP, BB = B * B, EPL = 2;
+    constexpr int CPR = B / EPL;
+    static_assert(60 % CPR == 0, "row groups must tile 60 lanes");
+    constexpr int G = 60 / CPR, RPL = (B + G - 1) / G;
+    __shared__ double sp[GM_RMAX][3][G][B + 1];
+    __shared__ double sxr[GM_RMAX][3][B];
+    if (st) {
+        bool all = true;
+        for (int r = 0; r < R; ++r) all = all && st[r].done;
+        if (all) return;
+    }
+    const int K = blockIdx.x, lane = threadIdx.x;
+    const int c = lane % CPR, g = lane / CPR;
+    int nbs[3];
+    const uint4* src[3];
+#pragma unroll
+    for (int f = 0; f < 3; ++f) {
+        const int nb = enb[3 * K + f];
+        nbs[f] = nb;
+        src[f] = nb >= 0 ? reinterpret_cast<const uint4*>(Ah + ((int64_t)nb * 3 + etw[3 * K + f]) * BB) : nullptr;
+    }
+    uint4 v[3][RPL];
+#pragma unroll
+    for (int f = 0; f < 3; ++f)
+#pragma unroll
+        for (int k = 0; k < RPL; ++k) {
+            const int i = g + G * k;
+            if (src[f] && lane < 60 && i < B) v[f][k] = src[f][i * CPR + c];
+        }
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int f = 0; f < 3; ++f)
+            if (nbs[f] >= 0 && lane < B) sxr[r][f][lane] = x[r * sx + (int64_t)nbs[f] * B + lane];
+    __syncthreads();
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            if (!src[f] || lane >= 60) continue;
+            double p0 = 0.0, p1 = 0.0;
+#pragma unroll
+            for (int k = 0; k < RPL; ++k) {
+                const int i = g + G * k;
+                if (i < B) {
+                    const double xi = sxr[r][f][i];
+                    const double* e = reinterpret_cast<const double*>(&v[f][k]);
+                    p0 += e[0] * xi;
+                    p1 += e[1] * xi;
+                }
+            }
+            sp[r][f][g][c * EPL] = p0;
+            sp[r][f][g][c * EPL + 1] = p1;
+        }
+    __syncthreads();
+    if (lane < B)
+        for (int r = 0; r < R; ++r) {
+            double acc = x[r * sx + (int64_t)K * B + lane];
+#pragma unroll
+            for (int f = 0; f < 3; ++f) {
+                if (nbs[f] < 0) continue;
+#pragma unroll
+                for (int gg = 0; gg < G; ++gg) acc += sp[r][f][gg][lane];
+            }
+            y[r * sy + (int64_t)K * B + lane] = acc;
+        }
 }
 
 // z = a * x (FP64 -> FP32), y += a * x (FP32 -> FP64)

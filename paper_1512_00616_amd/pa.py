@@ -47,7 +47,8 @@ class pa_shoot_report(C.Structure):
 
 
 class pa_adjoint_report(C.Structure):
-    _fields_ = [("krylov_its", C.c_int32 * 2), ("sweeps", C.c_int32), ("stage_gmres_its", C.c_int64),
+    _fields_ = [("krylov_its", C.c_int32 * 2), ("sweeps", C.c_int32), ("rhs_sweeps", C.c_int32),
+                ("stage_gmres_its", C.c_int64),
                 ("rel_res", C.c_double * 2), ("ms", C.c_double)]
 
 
