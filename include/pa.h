@@ -158,6 +158,15 @@ typedef struct pa_adjoint_report {
  * qoi[2] (may be NULL), dJdmu[2*3] (QoI-major). */
 pa_status pa_adjoint_gradient(pa_ctx* ctx, double rtol, double qoi[2], double dJdmu[6], pa_adjoint_report* rep);
 
+/* Direct (tangent) gradient about the stored periodic trajectory, the
+ * dual of pa_adjoint_gradient (Sec. 2.3: eq. dirk-sens-mvp with the
+ * parameter forcing dt dr/dmu_k at every stage; the periodic tangent solves
+ * (Phi - I) du0_k = -s_k with s_k the forced sweep from zero).  The three
+ * parameter tangents ride in the same sweeps.  dJdmu[2*3] (QoI-major),
+ * krylov_its[3] (may be NULL) per parameter; rtol is the outer GMRES
+ * relative tolerance. */
+pa_status pa_tangent_gradient(pa_ctx* ctx, double rtol, double dJdmu[6], int32_t krylov_its[3]);
+
 /* Sweeps about the stored trajectory (host vectors of length Nu):
  * tangent: out = Phi v (eq. dirk-sens-mvp);
  * adjoint: lam0 = lambda^(0) from lambda^(Nt) = lamNt (eq.

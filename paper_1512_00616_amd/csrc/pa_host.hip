@@ -258,6 +258,7 @@ struct pa_ctx {
     virtual void shoot(double tol, double eta, int maxit, pa_shoot_report* rep) = 0;
     virtual void fixed_point(int periods, double* res) = 0;
     virtual void adjoint_gradient(double rtol, double qoi[2], double dJ[6], pa_adjoint_report* rep) = 0;
+    virtual void tangent_gradient(double rtol, double dJ[6], int32_t its[3]) = 0;
     virtual void tangent_sweep_h(const double* v, double* out) = 0;
     virtual void adjoint_sweep_h(const double* lam, int fq, double* lam0, double* grad) = 0;
     virtual void dbg_gbar(int n, int i, double* out, bool deriv) = 0;
@@ -1169,6 +1170,75 @@ struct Solver final : pa_ctx {
         }
         LAUNCHCHK();
     }
+    // forward stage Jacobian products out_r = dt J w_r for R systems
+    void stage_jprod_fwd_multi(const StageOps& op, int R, const double* w, double* out)
+    {
+        for (int r = 0; r < R; ++r) prec(op.Pd, 0, w + r * Nu, t1m + r * Nu);
+        ahat_m(op.Ah, 0, R, t1m, Nu, t2m, Nu);
+        const double ia = dt / op.aii;
+        for (int r = 0; r < R; ++r)
+            k_mass_axpy<NP><<<grid1(Nu), 256, 0, st>>>(Ne, dm.area, dmh, w + r * Nu, t2m + r * Nu, ia, -ia, out + r * Nu);
+        LAUNCHCHK();
+    }
+    // tangent sweeps of R systems together: out_r = Phi v_r, plus (mu_dir[r]
+    // >= 0) the forcing dt dr/dmu_k of a parameter tangent (Sec. 2.3 eq.
+    // dirk-sens-mvp with the parameter term), and (dq != NULL) the tangent of
+    // both time-averaged QoIs: dq[2 r + q] = sum_n sum_i dt b_i / T
+    // (df_q/du(u_i) du_i + df_q/dmu_k), du_i = w_i + a_ii dk_i
+    void tangent_multi(int R, const double* v, const int* mu_dir, double* out, double* dq)
+    {
+        if (!have_traj) raise(PA_ESTATE, "no trajectory");
+        if (R > GM_RMAX) raise(PA_EINVAL, "at most %d right-hand sides", GM_RMAX);
+        ensure_multi();
+        double* du = lamm;
+        double* w = rhsm;
+        double* rhs = kapm;
+        auto DK = [&](int i, int r) { return skm + ((int64_t)i * R + r) * Nu; };
+        HIPCHK(hipMemcpyAsync(du, v, sizeof(double) * R * Nu, hipMemcpyDeviceToDevice, st));
+        bool forced = false;
+        for (int r = 0; r < R; ++r) forced = forced || mu_dir[r] >= 0;
+        std::vector<double> acc(2 * R, 0.0);
+        double* qg = fpm;            // df_q/du, q = 0, 1 (two vectors)
+        double* dui = fpm + 2 * Nu;  // du_i of one system
+        const double sc = dt / cfg.T;
+        for (int n = 1; n <= Nt; ++n) {
+            for (int i = 1; i <= 3; ++i) {
+                const int s = (n - 1) * 3 + (i - 1);
+                for (int r = 0; r < R; ++r) {
+                    copy(du + r * Nu, w + r * Nu);
+                    for (int j = 1; j < i; ++j) axpby(rk.A[i - 1][j - 1], DK(j - 1, r), 1.0, w + r * Nu);
+                }
+                stage_jprod_fwd_multi(ops(s), R, w, rhs);
+                if (forced) {
+                    dr_dmu(n, i, stU(s), drmm);
+                    for (int r = 0; r < R; ++r)
+                        if (mu_dir[r] >= 0) axpby(dt, drmm + (int64_t)mu_dir[r] * Nu, 1.0, rhs + r * Nu);
+                }
+                stage_solve_multi(ops(s), 0, R, rhs, DK(i - 1, 0));
+                if (dq) {
+                    qoi_grad(n, i, stU(s), 0, qg, qtmp);
+                    qoi_grad(n, i, stU(s), 1, qg + Nu, qtmp);
+                    double fm[6] = { 0, 0, 0, 0, 0, 0 };
+                    if (forced) qoi_dmu(n, i, stU(s), fm, nullptr);
+                    for (int r = 0; r < R; ++r) {
+                        lincomb(1.0, w + r * Nu, rk.A[i - 1][i - 1], DK(i - 1, r), dui);
+                        double d[2];
+                        dots(qg, Nu, 2, dui, d);
+                        for (int q = 0; q < 2; ++q) {
+                            double t = d[q];
+                            if (mu_dir[r] >= 0) t += fm[3 * q + mu_dir[r]];
+                            acc[2 * r + q] += sc * rk.b[i - 1] * t;
+                        }
+                    }
+                }
+            }
+            for (int r = 0; r < R; ++r)
+                for (int i = 0; i < 3; ++i) axpby(rk.b[i], DK(i, r), 1.0, du + r * Nu);
+        }
+        HIPCHK(hipMemcpyAsync(out, du, sizeof(double) * R * Nu, hipMemcpyDeviceToDevice, st));
+        if (dq) for (int k = 0; k < 2 * R; ++k) dq[k] = acc[k];
+    }
+
     // backward sweeps of R systems together (as adjoint()): lamNt, lam0 hold R
     // vectors; system r is forced by QoI fq[r] >= 0 (then grad[3 r + k])
     void adjoint_multi(int R, const double* lamNt, const int* fq, double* lam0, double* grad)
@@ -1655,6 +1725,11 @@ struct Solver final : pa_ctx {
     double *VoM = nullptr, *stgX = nullptr, *stgY = nullptr, *outm = nullptr, *brhs = nullptr;
     void outer_adjoint_multi(int R, const double* rhs, double rtol, int32_t* its, double* rel)
     {
+        outer_multi(false, R, rhs, rtol, its, rel);
+    }
+    // as above on (Phi - I) with tangent sweeps (tangent_op) or (Phi^T - I)
+    void outer_multi(bool tangent_op, int R, const double* rhs, double rtol, int32_t* its, double* rel)
+    {
         ensure_multi();
         if (!VoM) VoM = dalloc<double>((int64_t)GM_RMAX * (max_kry + 1) * Nu);
         const int m = max_kry;
@@ -1686,16 +1761,18 @@ struct Solver final : pa_ctx {
                 if (S[r].active) act[na++] = r;
             if (na == 0) break;
             for (int a = 0; a < na; ++a) copy(Vb(act[a]) + (int64_t)S[act[a]].j * Nu, stgX + a * Nu);
-            adjoint_multi(na, stgX, fq, stgY, nullptr);
+            if (tangent_op) tangent_multi(na, stgX, fq, stgY, nullptr);
+            else adjoint_multi(na, stgX, fq, stgY, nullptr);
             ++nmv;
             if (verbose && nmv % 10 == 0)
-                fprintf(stderr, "[pa]   adjoint sweeps %d (%d systems)  %.1f s\n", nmv, na, (now_ms() - t0) / 1e3);
+                fprintf(stderr, "[pa]   %s sweeps %d (%d systems)  %.1f s\n", tangent_op ? "tangent" : "adjoint", nmv,
+                        na, (now_ms() - t0) / 1e3);
             for (int a = 0; a < na; ++a) {
                 const int r = act[a];
                 Sys& y = S[r];
                 const int j = y.j;
                 double* wk = stgY + a * Nu;
-                axpby(-1.0, stgX + a * Nu, 1.0, wk);   // (Phi^T - I) v
+                axpby(-1.0, stgX + a * Nu, 1.0, wk);   // (Phi - I) v or (Phi^T - I) v
                 ++its[r];
                 dots(Vb(r), Nu, j + 1, wk, y.h.data());
                 vupdate(Vb(r), Nu, j + 1, y.h.data(), -1.0, wk);
@@ -1745,6 +1822,34 @@ struct Solver final : pa_ctx {
             if (k > 0) vupdate(Vb(r), Nu, k, c.data(), 1.0, outm + r * Nu);
             rel[r] = y.bn > 0.0 ? y.res / y.bn : 0.0;
         }
+    }
+
+    // Direct (tangent) gradient, Sec. 2.3 with the parameter forcing: for the
+    // three parameters together, the forced tangent sweeps from zero give
+    // s_k, the periodic tangents solve (Phi - I) du0_k = -s_k, and one forced
+    // sweep from du0_k accumulates dJ_q/dmu_k.  Independent of the adjoint.
+    void tangent_gradient(double rtol, double dJ[6], int32_t its_out[3]) override
+    {
+        if (!have_traj) raise(PA_ESTATE, "no trajectory (run pa_primal_period or pa_shoot first)");
+        ensure_multi();
+        const int dirs[3] = { 0, 1, 2 };
+        zero(stgX, 3 * Nu);
+        tangent_multi(3, stgX, dirs, brhs, nullptr);
+        for (int k = 0; k < 3; ++k) axpby(-1.0, brhs + k * Nu, 0.0, brhs + k * Nu);
+        int32_t its[3];
+        double rel[3];
+        outer_multi(true, 3, brhs, rtol, its, rel);
+        HIPCHK(hipMemcpyAsync(stgX, outm, sizeof(double) * 3 * Nu, hipMemcpyDeviceToDevice, st));
+        double dq[6];
+        tangent_multi(3, stgX, dirs, stgY, dq);
+        for (int k = 0; k < 3; ++k) {
+            dJ[k] = dq[2 * k];
+            dJ[3 + k] = dq[2 * k + 1];
+            if (its_out) its_out[k] = its[k];
+        }
+        if (verbose)
+            fprintf(stderr, "[pa] tangent gradient: %d / %d / %d krylov its, rel res %.1e / %.1e / %.1e\n", its[0],
+                    its[1], its[2], rel[0], rel[1], rel[2]);
     }
 
     void adjoint_gradient(double rtol, double qoi[2], double dJ[6], pa_adjoint_report* rep) override
@@ -2103,6 +2208,14 @@ pa_status pa_adjoint_gradient(pa_ctx* c, double rtol, double qoi[2], double dJ[6
         c->adjoint_gradient(rtol, qoi, dJ, rep);
     });
 }
+pa_status pa_tangent_gradient(pa_ctx* c, double rtol, double dJ[6], int32_t its[3])
+{
+    return guard(c, [&] {
+        if (!dJ || !(rtol > 0.0)) raise(PA_EINVAL, "bad arguments");
+        c->tangent_gradient(rtol, dJ, its);
+    });
+}
+
 pa_status pa_tangent_sweep(pa_ctx* c, const double* v, double* out)
 {
     return guard(c, [&] { if (!v || !out) raise(PA_EINVAL, "null vector"); c->tangent_sweep_h(v, out); });

@@ -18,7 +18,7 @@ PA_K_SPMV, PA_K_PRECOND, PA_K_JACOBIAN, PA_K_RESIDUAL, PA_K_BLOCKINV, PA_K_SPMV_
 EXPORTED = [
     "pa_default_config", "pa_create", "pa_destroy", "pa_last_error", "pa_num_dofs", "pa_num_elems",
     "pa_block_size", "pa_device_bytes", "pa_get_mesh", "pa_set_params", "pa_set_state", "pa_set_freestream",
-    "pa_get_state", "pa_primal_period", "pa_shoot", "pa_fixed_point", "pa_adjoint_gradient", "pa_tangent_sweep",
+    "pa_get_state", "pa_primal_period", "pa_shoot", "pa_fixed_point", "pa_adjoint_gradient", "pa_tangent_gradient", "pa_tangent_sweep",
     "pa_adjoint_sweep", "pa_dbg_gbar", "pa_dbg_dgbar", "pa_dbg_residual", "pa_dbg_jacobian", "pa_dbg_dr_dmu",
     "pa_dbg_qoi", "pa_dbg_bsr_apply", "pa_dbg_blockinv", "pa_dbg_stage_solve", "pa_dbg_traj", "pa_set_timing",
     "pa_kernel_time", "pa_bench_spmv", "pa_bench_spmv_lo", "pa_bench_copy",
@@ -91,6 +91,7 @@ def lib():
             "pa_shoot": [P, C.c_double, C.c_double, C.c_int32, P],
             "pa_fixed_point": [P, C.c_int32, P],
             "pa_adjoint_gradient": [P, C.c_double, P, P, P],
+            "pa_tangent_gradient": [P, C.c_double, P, P],
             "pa_tangent_sweep": [P, P, P],
             "pa_adjoint_sweep": [P, P, C.c_int32, P, P],
             "pa_dbg_gbar": [P, C.c_int32, C.c_int32, P],
@@ -226,6 +227,13 @@ class Solver:
         rep = pa_adjoint_report()
         self._chk(lib().pa_adjoint_gradient(self._c, rtol, _ptr(q), _ptr(g), C.byref(rep)))
         return q, g.reshape(2, 3), rep
+
+    def tangent_gradient(self, rtol=1e-8):
+        """Direct-method dJ/dmu (2 x 3) and the outer Krylov counts per parameter."""
+        g = np.zeros(6)
+        its = np.zeros(3, dtype=np.int32)
+        self._chk(lib().pa_tangent_gradient(self._c, rtol, _ptr(g), _ptr(its)))
+        return g.reshape(2, 3), its
 
     def tangent_sweep(self, v):
         v = self._vec(v)

@@ -213,4 +213,10 @@ def test_shoot_and_periodic_gradient_parity(libs):
     go = np.stack([o.periodic_adjoint(q, rtol=1e-13)[0] for q in (0, 1)])
     assert rel(dJ, go) <= 1e-8
     # and against the oracle's independent direct (tangent) gradient
-    assert rel(dJ, o.tangent_gradient(rtol=1e-13)) <= 1e-8
+    to = o.tangent_gradient(rtol=1e-13)
+    assert rel(dJ, to) <= 1e-8
+    # the GPU direct method (three parameter tangents in the same sweeps)
+    tg, its = g.tangent_gradient(rtol=1e-12)
+    assert all(its > 0)
+    assert rel(tg, to) <= 1e-8
+    assert rel(tg, dJ) <= 1e-8
