@@ -113,6 +113,30 @@ def time_to_gradient(pa, mu):
             "qoi": list(q), "dJdmu": dJ.tolist()}
 
 
+def batched(pa, args):
+    """Many kinematic instances (seeded h0 ~ U[0.1,0.5], theta0 ~ U[0,30 deg],
+    phi ~ U[0,pi]) on the 16x48 p=2, 60-step workload: the same bounded
+    per-instance step as the main benchmark (one Newton-Krylov shooting step
+    with a 6-vector basis, then both QoIs' periodic adjoints and dJ/dmu), run
+    one after another on one context and by concurrent contexts inside the
+    library (pa_batch_gradients); instances per second of each."""
+    name = "circle-16x48-p2-nt60"
+    work = dict(inputs.WORKLOADS[name], **inputs.PHYSICS)
+    mu = inputs.batch_params(args.batch, seed=4)
+    kw = dict(shoot_maxit=1, allow_unconverged=True, max_krylov=args.krylov, **work)
+    t0 = time.perf_counter()
+    q1, g1, _ = pa.batch_gradients(mu, workers=1, **kw)
+    t_seq = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    qb, gb, _ = pa.batch_gradients(mu, workers=args.batch_workers, **kw)
+    t_bat = time.perf_counter() - t0
+    return {"workload": name, "instances": args.batch, "workers": args.batch_workers,
+            "step": "1 NK shooting step (basis %d) + periodic adjoint gradient of both QoIs" % args.krylov,
+            "sequential_s": t_seq, "batched_s": t_bat,
+            "instances_per_s": args.batch / t_bat, "sequential_instances_per_s": args.batch / t_seq,
+            "speedup": t_seq / t_bat, "bitwise_equal": bool(np.array_equal(g1, gb) and np.array_equal(q1, qb))}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +146,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-ttg", action="store_true", help="skip the 8x24 time-to-gradient")
     ap.add_argument("--no-mixed", action="store_true", help="skip the FP32/BF16 mixed-precision steps")
+    ap.add_argument("--batch", type=int, default=8,
+                    help="instances of the 16x48 p=2 batched comparison (0 skips it)")
+    ap.add_argument("--batch-workers", type=int, default=4)
     ap.add_argument("--spmv-only", action="store_true",
                     help="short run for hardware counters: a 3-stage period on the 32x96 p=3 mesh, then timed "
                          "launches of the preconditioned stage operator and of a plain copy")
@@ -181,6 +208,9 @@ def main():
                 "counts": m["counts"], "kernels_ms": m["kernels_ms"],
                 "spmv_lo": m["spmv_lo"],
             }
+    if args.batch > 0:
+        log("batched instances on the 16x48 p=2 workload")
+        out["batched"] = batched(pa, args)
     if not args.no_ttg:
         log("time to gradient on the 8x24 p=1 workload")
         out["time_to_gradient"] = time_to_gradient(pa, mu)

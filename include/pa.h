@@ -195,6 +195,29 @@ pa_status pa_dbg_stage_solve(pa_ctx* ctx, const double* blk, double a_dt, int32_
 /* trajectory: which = 0 stage state u_i^(n), 1 stage k_i^(n), 2 step state u^(n) */
 pa_status pa_dbg_traj(pa_ctx* ctx, int32_t which, int32_t n, int32_t i, double* out);
 
+/* ---- many parameter instances ---- */
+typedef struct pa_batch_opts {
+    int32_t workers;            /* contexts run concurrently, each with its own host thread and stream */
+    int32_t shoot_maxit;        /* Newton-Krylov steps per instance (0: one primal period, no shooting) */
+    double  shoot_tol, shoot_eta;
+    int32_t allow_unconverged;  /* 1: shooting that stops at shoot_maxit still yields the gradient */
+    double  adj_rtol;           /* periodic adjoint relative tolerance */
+} pa_batch_opts;
+
+/* The whole method (Alg. 4) for n independent kinematic parameter vectors
+ * mu[n][3] on one mesh/configuration: per instance, free stream start,
+ * shooting (Alg. 2), then QoIs and dJ/dmu by the periodic adjoint (Alg. 3).
+ * Instances are taken in index order by `workers` contexts that run side by
+ * side on the device (one host thread and one stream each), which fills the
+ * GPU when one instance's kernels alone do not.  Each context holds the full
+ * per-instance trajectory storage (pa_device_bytes of one context).
+ * Outputs (host, caller-owned): qoi[n][2], dJdmu[n][6], periodicity[n]
+ * (||u^(Nt) - u0||_2 after shooting); any may be NULL.  Results are the
+ * same bits as the same instances run one after another on one context.
+ * On failure the first error is returned and pa_last_error(NULL) reports it. */
+pa_status pa_batch_gradients(const pa_config* cfg, int32_t n, const double* mu, const pa_batch_opts* opts,
+                             double* qoi, double* dJdmu, double* periodicity);
+
 /* ---- measurement ---- */
 /* kernel ids for pa_kernel_time */
 enum {

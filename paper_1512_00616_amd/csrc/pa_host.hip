@@ -29,6 +29,9 @@
 #include <functional>
 #include <string>
 #include <vector>
+#include <thread>
+#include <atomic>
+#include <mutex>
 
 using namespace pa;
 
@@ -2187,6 +2190,62 @@ pa_status pa_primal_period(pa_ctx* c, double qoi[2], double* res)
 {
     return guard(c, [&] { c->primal_period(qoi, res); });
 }
+pa_status pa_batch_gradients(const pa_config* cfg, int32_t n, const double* mu, const pa_batch_opts* o,
+                             double* qoi, double* dJ, double* per)
+{
+    if (!cfg || !mu || !o || n < 0 || o->workers < 1 || o->shoot_maxit < 0) {
+        g_create_err = "bad batch arguments";
+        return PA_EINVAL;
+    }
+    std::atomic<int> next{ 0 };
+    std::mutex mtx;
+    pa_status first = PA_OK;
+    std::string first_msg;
+    auto fail = [&](pa_status rc, const std::string& msg) {
+        std::lock_guard<std::mutex> lk(mtx);
+        if (first == PA_OK) { first = rc; first_msg = msg; }
+        next.store(n);   // stop handing out instances
+    };
+    auto worker = [&]() {
+        pa_ctx* c = nullptr;
+        pa_status rc = pa_create(cfg, &c);
+        if (rc != PA_OK) { fail(rc, pa_last_error(nullptr)); return; }
+        for (;;) {
+            const int i = next.fetch_add(1);
+            if (i >= n) break;
+            double q[2], g[6], res = 0.0;
+            rc = pa_set_params(c, mu + 3 * (int64_t)i);
+            if (rc == PA_OK) rc = pa_set_freestream(c, nullptr);
+            if (rc == PA_OK) {
+                if (o->shoot_maxit > 0) {
+                    pa_shoot_report rep{};
+                    rc = pa_shoot(c, o->shoot_tol, o->shoot_eta, o->shoot_maxit, &rep);
+                    if (rc == PA_ENOCONV && o->allow_unconverged && rep.newton_its >= o->shoot_maxit) rc = PA_OK;
+                    res = rep.res;
+                } else {
+                    double qq[2];
+                    rc = pa_primal_period(c, qq, &res);
+                }
+            }
+            if (rc == PA_OK) rc = pa_adjoint_gradient(c, o->adj_rtol, q, g, nullptr);
+            if (rc != PA_OK) {
+                fail(rc, std::string("instance ") + std::to_string(i) + ": " + pa_last_error(c));
+                break;
+            }
+            if (qoi) { qoi[2 * (int64_t)i] = q[0]; qoi[2 * (int64_t)i + 1] = q[1]; }
+            if (dJ) for (int k = 0; k < 6; ++k) dJ[6 * (int64_t)i + k] = g[k];
+            if (per) per[i] = res;
+        }
+        pa_destroy(c);
+    };
+    std::vector<std::thread> pool;
+    const int nw = std::min<int>(o->workers, std::max(n, 1));
+    for (int w = 0; w < nw; ++w) pool.emplace_back(worker);
+    for (auto& t : pool) t.join();
+    if (first != PA_OK) g_create_err = first_msg;
+    return first;
+}
+
 pa_status pa_shoot(pa_ctx* c, double tol, double eta, int32_t maxit, pa_shoot_report* rep)
 {
     return guard(c, [&] {

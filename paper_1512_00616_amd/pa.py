@@ -18,7 +18,7 @@ PA_K_SPMV, PA_K_PRECOND, PA_K_JACOBIAN, PA_K_RESIDUAL, PA_K_BLOCKINV, PA_K_SPMV_
 EXPORTED = [
     "pa_default_config", "pa_create", "pa_destroy", "pa_last_error", "pa_num_dofs", "pa_num_elems",
     "pa_block_size", "pa_device_bytes", "pa_get_mesh", "pa_set_params", "pa_set_state", "pa_set_freestream",
-    "pa_get_state", "pa_primal_period", "pa_shoot", "pa_fixed_point", "pa_adjoint_gradient", "pa_tangent_gradient", "pa_tangent_sweep",
+    "pa_get_state", "pa_primal_period", "pa_shoot", "pa_fixed_point", "pa_adjoint_gradient", "pa_tangent_gradient", "pa_batch_gradients", "pa_tangent_sweep",
     "pa_adjoint_sweep", "pa_dbg_gbar", "pa_dbg_dgbar", "pa_dbg_residual", "pa_dbg_jacobian", "pa_dbg_dr_dmu",
     "pa_dbg_qoi", "pa_dbg_bsr_apply", "pa_dbg_blockinv", "pa_dbg_stage_solve", "pa_dbg_traj", "pa_set_timing",
     "pa_kernel_time", "pa_bench_spmv", "pa_bench_spmv_lo", "pa_bench_copy",
@@ -50,6 +50,11 @@ class pa_adjoint_report(C.Structure):
     _fields_ = [("krylov_its", C.c_int32 * 2), ("sweeps", C.c_int32), ("rhs_sweeps", C.c_int32),
                 ("stage_gmres_its", C.c_int64),
                 ("rel_res", C.c_double * 2), ("ms", C.c_double)]
+
+
+class pa_batch_opts(C.Structure):
+    _fields_ = [("workers", C.c_int32), ("shoot_maxit", C.c_int32), ("shoot_tol", C.c_double),
+                ("shoot_eta", C.c_double), ("allow_unconverged", C.c_int32), ("adj_rtol", C.c_double)]
 
 
 class PaError(RuntimeError):
@@ -89,6 +94,7 @@ def lib():
             "pa_get_state": [P, C.c_int32, P, C.c_int64],
             "pa_primal_period": [P, P, P],
             "pa_shoot": [P, C.c_double, C.c_double, C.c_int32, P],
+            "pa_batch_gradients": [P, C.c_int32, P, P, P, P, P],
             "pa_fixed_point": [P, C.c_int32, P],
             "pa_adjoint_gradient": [P, C.c_double, P, P, P],
             "pa_tangent_gradient": [P, C.c_double, P, P],
@@ -134,6 +140,24 @@ def default_config(**kw):
             raise KeyError(k)
         setattr(cfg, k, v)
     return cfg
+
+
+def batch_gradients(mu, workers=4, shoot_maxit=30, shoot_tol=1e-8, shoot_eta=1e-3, allow_unconverged=False,
+                    adj_rtol=1e-8, **cfg_kw):
+    """Alg. 4 for every row of mu (n x 3) on one configuration, run by
+    `workers` concurrent contexts inside the library; returns qoi (n x 2),
+    dJ/dmu (n x 2 x 3) and the final periodicity residuals (n)."""
+    mu = np.ascontiguousarray(np.asarray(mu, dtype=np.float64).reshape(-1, 3))
+    n = mu.shape[0]
+    cfg = default_config(**cfg_kw)
+    o = pa_batch_opts(workers, shoot_maxit, shoot_tol, shoot_eta, int(allow_unconverged), adj_rtol)
+    q = np.zeros((n, 2))
+    g = np.zeros((n, 6))
+    per = np.zeros(n)
+    rc = lib().pa_batch_gradients(C.byref(cfg), n, _ptr(mu), C.byref(o), _ptr(q), _ptr(g), _ptr(per))
+    if rc != PA_OK:
+        raise PaError(rc, lib().pa_last_error(None).decode())
+    return q, g.reshape(n, 2, 3), per
 
 
 class Solver:
