@@ -113,6 +113,57 @@ def time_to_gradient(pa, mu):
             "qoi": list(q), "dJdmu": dJ.tolist()}
 
 
+def learned(pa, args):
+    """Learned warm start on the 8x24 p=1, 20-step workload: periodic orbits
+    for seeded training parameters (seed 5) by concurrent contexts, POD + MLP
+    trained on the device, then time to gradient (shooting to 1e-8 and both
+    QoIs' periodic adjoint gradients at 1e-8) on held-out draws (seed 55)
+    from the free stream and from the predicted state (with the free-stream
+    fallback rule)."""
+    name = "circle-8x24-p1-nt20"
+    work = dict(inputs.WORKLOADS[name], **inputs.PHYSICS)
+    mu_tr = inputs.warmstart_params(args.learned_train, seed=5)
+    t0 = time.perf_counter()
+    _, _, per, states = pa.batch_gradients(mu_tr, workers=8, shoot_maxit=30, shoot_tol=1e-8, shoot_eta=1e-3,
+                                           return_states=True, keep_going=True, **work)
+    t_gen = time.perf_counter() - t0
+    ok = np.isfinite(per)
+    s = pa.Solver(**work)
+    t0 = time.perf_counter()
+    loss = s.ws_train(mu_tr[ok], states[ok], modes=16, width=256, epochs=3000, lr=1e-3, seed=5)
+    t_train = time.perf_counter() - t0
+    tests = []
+    for mu in inputs.warmstart_params(args.learned_test, seed=55):
+        row = {"mu": [float(x) for x in mu]}
+        for mode in ("free_stream", "warm"):
+            s.set_params(mu)
+            t0 = time.perf_counter()
+            try:
+                if mode == "warm":
+                    rep, fb = s.ws_shoot(tol=1e-8, eta=1e-3, maxit=30)
+                    row["fell_back"] = fb
+                else:
+                    s.set_freestream()
+                    rep = s.shoot(tol=1e-8, eta=1e-3, maxit=30)
+                _, dJ, _ = s.adjoint_gradient(rtol=1e-8)
+                row[mode] = {"seconds": time.perf_counter() - t0, "newton": rep.newton_its,
+                             "tangent_sweeps": rep.krylov_its, "periodicity": rep.res}
+                row[mode + "_dJ"] = dJ
+            except pa.PaError as e:
+                row[mode] = {"failed": str(e), "seconds": time.perf_counter() - t0}
+        if "free_stream_dJ" in row and "warm_dJ" in row:
+            a, b = row.pop("warm_dJ"), row.pop("free_stream_dJ")
+            row["dJdmu_rel_diff"] = float(np.abs(a - b).max() / np.abs(b).max())
+        row.pop("warm_dJ", None)
+        row.pop("free_stream_dJ", None)
+        tests.append(row)
+    s.close()
+    return {"workload": name, "training_orbits": int(ok.sum()), "training_draws": args.learned_train,
+            "generation_s": t_gen, "train_s": t_train, "final_loss": loss,
+            "model": "POD 16 modes + MLP 3-256-256-256-16 (tanh, FP32, Adam 3000 full-batch steps)",
+            "held_out": tests}
+
+
 def batched(pa, args):
     """Many kinematic instances (seeded h0 ~ U[0.1,0.5], theta0 ~ U[0,30 deg],
     phi ~ U[0,pi]) on the 16x48 p=2, 60-step workload: the same bounded
@@ -149,6 +200,9 @@ def main():
     ap.add_argument("--batch", type=int, default=8,
                     help="instances of the 16x48 p=2 batched comparison (0 skips it)")
     ap.add_argument("--batch-workers", type=int, default=4)
+    ap.add_argument("--learned-train", type=int, default=16,
+                    help="periodic orbits that train the warm start on the 8x24 p=1 workload (0 skips it)")
+    ap.add_argument("--learned-test", type=int, default=2, help="held-out parameter draws of the warm-start test")
     ap.add_argument("--spmv-only", action="store_true",
                     help="short run for hardware counters: a 3-stage period on the 32x96 p=3 mesh, then timed "
                          "launches of the preconditioned stage operator and of a plain copy")
@@ -211,6 +265,9 @@ def main():
     if args.batch > 0:
         log("batched instances on the 16x48 p=2 workload")
         out["batched"] = batched(pa, args)
+    if args.learned_train > 0:
+        log("learned warm start on the 8x24 p=1 workload")
+        out["learned_warm_start"] = learned(pa, args)
     if not args.no_ttg:
         log("time to gradient on the 8x24 p=1 workload")
         out["time_to_gradient"] = time_to_gradient(pa, mu)

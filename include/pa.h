@@ -192,6 +192,13 @@ pa_status pa_dbg_blockinv(pa_ctx* ctx, const double* blk, double a_dt, double* o
  * block-Jacobi GMRES; *iters receives the iteration count */
 pa_status pa_dbg_stage_solve(pa_ctx* ctx, const double* blk, double a_dt, int32_t transpose, const double* rhs,
                              double* x, int32_t* iters);
+/* one forward and backward pass of the warm-start perceptron
+ * in -> width -> width -> width -> out (tanh hidden, linear output) on the
+ * device with no context: params flat [W1 b1 W2 b2 W3 b3 W4 b4], W_l
+ * row-major [out_l][in_l]; X[in][batch], T[out][batch] column-major batches;
+ * *loss = mean squared error, grads laid out as params */
+pa_status pa_dbg_mlp(int32_t in, int32_t width, int32_t out, int32_t batch, const float* params, const float* X,
+                     const float* T, float* loss, float* grads);
 /* trajectory: which = 0 stage state u_i^(n), 1 stage k_i^(n), 2 step state u^(n) */
 pa_status pa_dbg_traj(pa_ctx* ctx, int32_t which, int32_t n, int32_t i, double* out);
 
@@ -202,6 +209,8 @@ typedef struct pa_batch_opts {
     double  shoot_tol, shoot_eta;
     int32_t allow_unconverged;  /* 1: shooting that stops at shoot_maxit still yields the gradient */
     double  adj_rtol;           /* periodic adjoint relative tolerance */
+    int32_t keep_going;         /* 1: an instance whose shooting or adjoint fails gets NaN outputs and the
+                                   others go on (device errors still stop the batch) */
 } pa_batch_opts;
 
 /* The whole method (Alg. 4) for n independent kinematic parameter vectors
@@ -212,11 +221,42 @@ typedef struct pa_batch_opts {
  * GPU when one instance's kernels alone do not.  Each context holds the full
  * per-instance trajectory storage (pa_device_bytes of one context).
  * Outputs (host, caller-owned): qoi[n][2], dJdmu[n][6], periodicity[n]
- * (||u^(Nt) - u0||_2 after shooting); any may be NULL.  Results are the
- * same bits as the same instances run one after another on one context.
- * On failure the first error is returned and pa_last_error(NULL) reports it. */
+ * (||u^(Nt) - u0||_2 after shooting), states[n][N_u] (the initial state u0
+ * after shooting, canonical order); any may be NULL.  Results are the same
+ * bits as the same instances run one after another on one context.  On
+ * failure the first error is returned and pa_last_error(NULL) reports it. */
 pa_status pa_batch_gradients(const pa_config* cfg, int32_t n, const double* mu, const pa_batch_opts* opts,
-                             double* qoi, double* dJdmu, double* periodicity);
+                             double* qoi, double* dJdmu, double* periodicity, double* states);
+
+/* ---- learned warm start ---- */
+typedef struct pa_ws_opts {
+    int32_t  modes;    /* POD modes kept (at most training states - 1, at most 128) */
+    int32_t  width;    /* hidden width of the 3 -> w -> w -> w -> modes perceptron (tanh) */
+    int32_t  epochs;   /* full-batch Adam steps */
+    float    lr;       /* Adam learning rate */
+    uint64_t seed;     /* initial weights (splitmix64, Glorot-uniform) */
+} pa_ws_opts;
+
+/* Learned warm start for shooting (a start closer to the periodic orbit cuts
+ * Newton-Krylov steps, Sec. 2.3).  Training data: S method-generated periodic
+ * initial states (e.g. from pa_batch_gradients) and their parameters,
+ * params[S][3], states[S][N_u] (host).  Builds the POD of the centred states
+ * on the device (method of snapshots) and trains, on the device with FP32
+ * kernels, a perceptron from normalised parameters to normalised POD
+ * coefficients by full-batch Adam on the mean squared error; *final_loss
+ * (may be NULL) receives the last training loss.  Replaces any previous model. */
+pa_status pa_ws_train(pa_ctx* ctx, const double* params, const double* states, int32_t S, const pa_ws_opts* opts,
+                      double* final_loss);
+/* u0 = mean + POD modes x predicted coefficients for mu[3]; invalidates the
+ * trajectory.  PA_ESTATE without a model. */
+pa_status pa_ws_predict(pa_ctx* ctx, const double mu[3]);
+/* pa_shoot from the predicted state for the current parameters; when the
+ * first Newton step fails or does not lower ||u^(Nt) - u0||, shooting starts
+ * again from the free stream (*fell_back = 1).  The report sums both runs. */
+pa_status pa_ws_shoot(pa_ctx* ctx, double tol, double eta, int32_t maxit, pa_shoot_report* rep, int32_t* fell_back);
+/* model file (binary, this library's layout); load checks N_u */
+pa_status pa_ws_save(pa_ctx* ctx, const char* path);
+pa_status pa_ws_load(pa_ctx* ctx, const char* path);
 
 /* ---- measurement ---- */
 /* kernel ids for pa_kernel_time */

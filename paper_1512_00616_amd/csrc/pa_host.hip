@@ -16,6 +16,7 @@
 #include "../../include/pa.h"
 #include "pa_kernels.hpp"
 #include "pa_linalg.hpp"
+#include "pa_learn.hpp"
 
 #include <hip/hip_runtime.h>
 
@@ -241,6 +242,187 @@ struct Dirk3 {
 
 inline int grid1(int64_t n, int bs = 256) { return (int)((n + bs - 1) / bs); }
 
+// Multilayer perceptron on the device (FP32): widths dims[0] -> ... -> dims[L],
+// tanh on hidden layers, linear output, parameters flat [W_1 b_1 W_2 b_2 ...]
+// with W_l [dims[l]][dims[l-1]] row-major; batches column-major [feature][sample].
+struct Mlp {
+    std::vector<int> dims;
+    std::vector<int64_t> woff, boff;
+    int64_t nparam = 0;
+    int cap = 0, maxw = 0;
+    float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+    float *X = nullptr, *T = nullptr, *dA = nullptr, *dB = nullptr, *loss = nullptr;
+    std::vector<float*> H;
+    hipStream_t st = nullptr;
+    int step = 0;
+    static void fr(float*& q) { if (q) (void)hipFree(q); q = nullptr; }
+    static float* al(int64_t n)
+    {
+        float* q = nullptr;
+        hipError_t e = hipMalloc((void**)&q, sizeof(float) * (size_t)std::max<int64_t>(n, 1));
+        if (e != hipSuccess) raise(PA_ENOMEM, "hipMalloc failed: %s", hipGetErrorString(e));
+        return q;
+    }
+    void release()
+    {
+        fr(p); fr(g); fr(m); fr(v); fr(X); fr(T); fr(dA); fr(dB); fr(loss);
+        for (auto& h : H) fr(h);
+        H.clear();
+        cap = 0;
+    }
+    ~Mlp() { release(); }
+    void init(const std::vector<int>& d, hipStream_t s)
+    {
+        release();
+        dims = d;
+        st = s;
+        step = 0;
+        const int L = (int)d.size() - 1;
+        woff.assign(L, 0);
+        boff.assign(L, 0);
+        nparam = 0;
+        maxw = 0;
+        for (int l = 0; l < L; ++l) {
+            woff[l] = nparam;
+            nparam += (int64_t)d[l + 1] * d[l];
+            boff[l] = nparam;
+            nparam += d[l + 1];
+            maxw = std::max(maxw, std::max(d[l], d[l + 1]));
+        }
+        p = al(nparam); g = al(nparam); m = al(nparam); v = al(nparam);
+        HIPCHK(hipMemsetAsync(m, 0, sizeof(float) * nparam, st));
+        HIPCHK(hipMemsetAsync(v, 0, sizeof(float) * nparam, st));
+        loss = al(1);
+    }
+    void reserve(int batch)
+    {
+        if (batch <= cap) return;
+        for (auto& h : H) fr(h);
+        fr(X); fr(T); fr(dA); fr(dB);
+        const int L = (int)dims.size() - 1;
+        H.assign(L, nullptr);
+        for (int l = 0; l < L; ++l) H[l] = al((int64_t)dims[l + 1] * batch);
+        X = al((int64_t)dims[0] * batch);
+        T = al((int64_t)dims[L] * batch);
+        dA = al((int64_t)maxw * batch);
+        dB = al((int64_t)maxw * batch);
+        cap = batch;
+    }
+    void gemm(int M, int N, int K, const float* A, int tA, const float* B, int tB, float* C)
+    {
+        dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
+        k_gemm_f32<<<grid, GT * GT, 0, st>>>(M, N, K, 1.0f, A, tA, B, tB, 0.0f, C);
+        LAUNCHCHK();
+    }
+    const float* out() const { return H.back(); }
+    void forward(int S)
+    {
+        const int L = (int)dims.size() - 1;
+        const float* in = X;
+        for (int l = 0; l < L; ++l) {
+            gemm(dims[l + 1], S, dims[l], p + woff[l], 0, in, 0, H[l]);
+            k_bias_act<<<grid1((int64_t)dims[l + 1] * S), 256, 0, st>>>(H[l], p + boff[l], dims[l + 1], S, l < L - 1);
+            LAUNCHCHK();
+            in = H[l];
+        }
+    }
+    // loss and dY = d loss / d output into dA
+    void mse(int S)
+    {
+        const int L = (int)dims.size() - 1;
+        k_mse<<<1, 256, 0, st>>>(H[L - 1], T, dA, (int64_t)dims[L] * S, loss);
+        LAUNCHCHK();
+    }
+    // gradients into g from dY in dA (after forward and mse)
+    void backward(int S)
+    {
+        const int L = (int)dims.size() - 1;
+        float* cur = dA;
+        for (int l = L - 1; l >= 0; --l) {
+            const float* in = l == 0 ? X : H[l - 1];
+            gemm(dims[l + 1], dims[l], S, cur, 0, in, 1, g + woff[l]);
+            k_row_sum<<<grid1(dims[l + 1]), 256, 0, st>>>(cur, g + boff[l], dims[l + 1], S);
+            LAUNCHCHK();
+            if (l > 0) {
+                float* nxt = cur == dA ? dB : dA;
+                gemm(dims[l], S, dims[l + 1], p + woff[l], 1, cur, 0, nxt);
+                k_tanh_back<<<grid1((int64_t)dims[l] * S), 256, 0, st>>>(nxt, H[l - 1], (int64_t)dims[l] * S);
+                LAUNCHCHK();
+                cur = nxt;
+            }
+        }
+    }
+    void adam(float lr)
+    {
+        ++step;
+        const float b1 = 0.9f, b2 = 0.999f;
+        const float c1 = 1.0f - std::pow(b1, (float)step), c2 = 1.0f - std::pow(b2, (float)step);
+        k_adam<<<grid1(nparam), 256, 0, st>>>(p, g, m, v, nparam, lr, b1, b2, 1e-8f, c1, c2);
+        LAUNCHCHK();
+    }
+};
+
+// splitmix64: seeded initial weights
+inline uint64_t splitmix64(uint64_t& x)
+{
+    uint64_t z = (x += 0x9E3779B97F4A7C15ull);
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+// eigenpairs of a symmetric n x n matrix (row-major, destroyed) by cyclic
+// Jacobi rotations; eigenvalues descending in w, eigenvectors as columns of V
+inline void sym_eig(std::vector<double>& A, int n, std::vector<double>& w, std::vector<double>& V)
+{
+    V.assign((size_t)n * n, 0.0);
+    for (int i = 0; i < n; ++i) V[(size_t)i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                const double a = A[(size_t)i * n + j] * A[(size_t)i * n + j];
+                tot += a;
+                if (i != j) off += a;
+            }
+        if (off <= 1e-30 * tot) break;
+        for (int p = 0; p < n - 1; ++p)
+            for (int q = p + 1; q < n; ++q) {
+                const double apq = A[(size_t)p * n + q];
+                if (std::fabs(apq) < 1e-300) continue;
+                const double app = A[(size_t)p * n + p], aqq = A[(size_t)q * n + q];
+                const double th = (aqq - app) / (2.0 * apq);
+                const double t = (th >= 0 ? 1.0 : -1.0) / (std::fabs(th) + std::sqrt(th * th + 1.0));
+                const double c = 1.0 / std::sqrt(t * t + 1.0), s = t * c;
+                for (int k = 0; k < n; ++k) {   // columns p, q
+                    const double akp = A[(size_t)k * n + p], akq = A[(size_t)k * n + q];
+                    A[(size_t)k * n + p] = c * akp - s * akq;
+                    A[(size_t)k * n + q] = s * akp + c * akq;
+                }
+                for (int k = 0; k < n; ++k) {   // rows p, q
+                    const double apk = A[(size_t)p * n + k], aqk = A[(size_t)q * n + k];
+                    A[(size_t)p * n + k] = c * apk - s * aqk;
+                    A[(size_t)q * n + k] = s * apk + c * aqk;
+                }
+                for (int k = 0; k < n; ++k) {
+                    const double vkp = V[(size_t)k * n + p], vkq = V[(size_t)k * n + q];
+                    V[(size_t)k * n + p] = c * vkp - s * vkq;
+                    V[(size_t)k * n + q] = s * vkp + c * vkq;
+                }
+            }
+    }
+    std::vector<int> idx(n);
+    for (int i = 0; i < n; ++i) idx[i] = i;
+    std::sort(idx.begin(), idx.end(), [&](int a, int b) { return A[(size_t)a * n + a] > A[(size_t)b * n + b]; });
+    std::vector<double> V2((size_t)n * n);
+    w.assign(n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        w[j] = A[(size_t)idx[j] * n + idx[j]];
+        for (int k = 0; k < n; ++k) V2[(size_t)k * n + j] = V[(size_t)k * n + idx[j]];
+    }
+    V.swap(V2);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ context
@@ -262,6 +444,11 @@ struct pa_ctx {
     virtual void fixed_point(int periods, double* res) = 0;
     virtual void adjoint_gradient(double rtol, double qoi[2], double dJ[6], pa_adjoint_report* rep) = 0;
     virtual void tangent_gradient(double rtol, double dJ[6], int32_t its[3]) = 0;
+    virtual void ws_train(const double* params, const double* states, int S, const pa_ws_opts& o, double* loss) = 0;
+    virtual void ws_predict(const double m[3]) = 0;
+    virtual void ws_shoot(double tol, double eta, int maxit, pa_shoot_report* rep, int32_t* fell_back) = 0;
+    virtual void ws_save(const char* path) = 0;
+    virtual void ws_load(const char* path) = 0;
     virtual void tangent_sweep_h(const double* v, double* out) = 0;
     virtual void adjoint_sweep_h(const double* lam, int fq, double* lam0, double* grad) = 0;
     virtual void dbg_gbar(int n, int i, double* out, bool deriv) = 0;
@@ -1032,6 +1219,211 @@ struct Solver final : pa_ctx {
         cnt_gmres += total;
         return total;
     }
+    // ---------------------------------------------------------------- learned warm start
+    // POD of method-generated periodic initial states (snapshot method: the
+    // Gram matrix of the centred states on the device, its eigenpairs on
+    // the host, the modes formed on the device) and an MLP from normalised
+    // parameters to normalised POD coefficients, trained with Adam.
+    Mlp mlp;
+    int ws_k = 0;
+    double *ws_mean = nullptr, *ws_psi = nullptr;
+    float* ws_cs = nullptr;                   // device coefficient scales [ws_k]
+    std::vector<float> ws_cs_h;
+    float ws_xm[3] = { 0, 0, 0 }, ws_xs[3] = { 1, 1, 1 };
+    static constexpr int WS_MAXK = 128;
+    void ws_alloc()
+    {
+        if (ws_mean) return;
+        ws_mean = dalloc<double>(Nu);
+        ws_psi = dalloc<double>((int64_t)WS_MAXK * Nu);
+        ws_cs = dalloc<float>(WS_MAXK);
+    }
+    void ws_train(const double* params, const double* states, int S, const pa_ws_opts& o, double* final_loss) override
+    {
+        if (S < 2 || !params || !states) raise(PA_EINVAL, "need at least two training states");
+        if (o.modes < 1 || o.width < 1 || o.epochs < 0 || !(o.lr > 0)) raise(PA_EINVAL, "bad warm-start options");
+        ws_alloc();
+        double* D = nullptr;
+        if (hipMalloc((void**)&D, sizeof(double) * (size_t)S * Nu) != hipSuccess) raise(PA_ENOMEM, "snapshot storage");
+        struct Free { double* q; ~Free() { (void)hipFree(q); } } fd{ D };
+        h2d(D, states, sizeof(double) * (size_t)S * Nu);
+        // mean and centred snapshots
+        zero(ws_mean);
+        for (int i = 0; i < S; ++i) axpby(1.0 / S, D + (int64_t)i * Nu, 1.0, ws_mean);
+        for (int i = 0; i < S; ++i) axpby(-1.0, ws_mean, 1.0, D + (int64_t)i * Nu);
+        std::vector<double> G((size_t)S * S), row(S);
+        for (int i = 0; i < S; ++i) {
+            dots(D, Nu, i + 1, D + (int64_t)i * Nu, row.data());
+            for (int j = 0; j <= i; ++j) G[(size_t)i * S + j] = G[(size_t)j * S + i] = row[j];
+        }
+        std::vector<double> lam, Vg;
+        sym_eig(G, S, lam, Vg);
+        int k = std::min({ o.modes, S - 1, WS_MAXK });
+        while (k > 1 && !(lam[k - 1] > 1e-13 * lam[0])) --k;
+        if (!(lam[0] > 0.0)) raise(PA_EINVAL, "training states are all equal");
+        ws_k = k;
+        ws_cs_h.assign(k, 0.0f);
+        std::vector<double> coef(S);
+        std::vector<float> Th((size_t)k * S);
+        for (int j = 0; j < k; ++j) {
+            const double sl = std::sqrt(lam[j]);
+            for (int i = 0; i < S; ++i) coef[i] = Vg[(size_t)i * S + j] / sl;
+            zero(ws_psi + (int64_t)j * Nu);
+            vupdate(D, Nu, S, coef.data(), 1.0, ws_psi + (int64_t)j * Nu);
+            // coefficients of the training states: c_j,i = sqrt(lam_j) V[i][j];
+            // scaled by their RMS sqrt(lam_j / S)
+            ws_cs_h[j] = (float)std::sqrt(lam[j] / S);
+            for (int i = 0; i < S; ++i) Th[(size_t)j * S + i] = (float)(std::sqrt((double)S) * Vg[(size_t)i * S + j]);
+        }
+        h2d(ws_cs, ws_cs_h.data(), sizeof(float) * k);
+        // normalised inputs
+        std::vector<float> Xh((size_t)3 * S);
+        for (int c = 0; c < 3; ++c) {
+            double mean = 0, var = 0;
+            for (int i = 0; i < S; ++i) mean += params[3 * i + c];
+            mean /= S;
+            for (int i = 0; i < S; ++i) var += (params[3 * i + c] - mean) * (params[3 * i + c] - mean);
+            const double sd = std::sqrt(var / S);
+            ws_xm[c] = (float)mean;
+            ws_xs[c] = (float)(sd > 1e-12 ? sd : 1.0);
+            for (int i = 0; i < S; ++i) Xh[(size_t)c * S + i] = (float)((params[3 * i + c] - mean) / ws_xs[c]);
+        }
+        mlp.init({ 3, o.width, o.width, o.width, k }, st);
+        std::vector<float> P0(mlp.nparam, 0.0f);
+        uint64_t sd = o.seed;
+        for (size_t l = 0; l + 1 < mlp.dims.size(); ++l) {
+            const int fi = mlp.dims[l], fo = mlp.dims[l + 1];
+            const double a = std::sqrt(6.0 / (fi + fo));
+            for (int64_t q = 0; q < (int64_t)fi * fo; ++q) {
+                const double u = (double)(splitmix64(sd) >> 11) * (1.0 / 9007199254740992.0);
+                P0[mlp.woff[l] + q] = (float)((2.0 * u - 1.0) * a);
+            }
+        }
+        h2d(mlp.p, P0.data(), sizeof(float) * mlp.nparam);
+        mlp.reserve(S);
+        h2d(mlp.X, Xh.data(), sizeof(float) * Xh.size());
+        h2d(mlp.T, Th.data(), sizeof(float) * Th.size());
+        for (int e = 0; e < o.epochs; ++e) {
+            mlp.forward(S);
+            mlp.mse(S);
+            mlp.backward(S);
+            mlp.adam(o.lr);
+        }
+        mlp.forward(S);
+        mlp.mse(S);
+        float L = 0;
+        d2h(&L, mlp.loss, sizeof(float));
+        if (final_loss) *final_loss = L;
+        if (verbose) fprintf(stderr, "[pa] warm start: %d states, %d modes, %d epochs, loss %.3e\n", S, k, o.epochs, L);
+    }
+    void ws_predict(const double m[3]) override
+    {
+        if (!ws_k) raise(PA_ESTATE, "no trained warm-start model");
+        float x[3];
+        for (int c = 0; c < 3; ++c) x[c] = (float)((m[c] - ws_xm[c]) / ws_xs[c]);
+        mlp.reserve(1);
+        // a single column: X [3][1]
+        h2d(mlp.X, x, sizeof x);
+        mlp.forward(1);
+        k_pod_expand<<<grid1(Nu), 256, 0, st>>>(ws_mean, ws_psi, ws_k, Nu, mlp.out(), ws_cs, u0, Nu);
+        LAUNCHCHK();
+        HIPCHK(hipStreamSynchronize(st));
+        have_traj = false;
+    }
+    // shooting from the predicted state; if the first Newton step does not
+    // lower ||R|| (or fails), start again from the free stream
+    void ws_shoot(double tol, double eta, int maxit, pa_shoot_report* rep, int32_t* fell_back) override
+    {
+        if (!have_params) raise(PA_ESTATE, "set the parameters first");
+        ws_predict(mu);
+        pa_shoot_report r1{}, r2{};
+        bool progressed = false, converged = false;
+        try {
+            shoot(tol, eta, 1, &r1);
+            converged = true;
+        } catch (const PaError& e) {
+            if (e.code != PA_ENOCONV && e.code != PA_ENUMERIC) throw;
+            progressed = r1.newton_its >= 1 && r1.res < r1.res0;
+        }
+        if (fell_back) *fell_back = 0;
+        if (!converged) {
+            if (progressed) {
+                shoot(tol, eta, std::max(maxit - 1, 0), &r2);
+            } else {
+                if (fell_back) *fell_back = 1;
+                set_freestream(nullptr);
+                shoot(tol, eta, maxit, &r2);
+            }
+        }
+        if (rep) {
+            pa_shoot_report r = converged ? r1 : r2;
+            if (!converged) {
+                r.newton_its += r1.newton_its;
+                r.krylov_its += r1.krylov_its;
+                r.primal_sweeps += r1.primal_sweeps;
+                r.stage_newton_its += r1.stage_newton_its;
+                r.stage_gmres_its += r1.stage_gmres_its;
+                r.res0 = r1.res0;
+                r.ms += r1.ms;
+            }
+            *rep = r;
+        }
+    }
+    void ws_save(const char* path) override
+    {
+        if (!ws_k) raise(PA_ESTATE, "no trained warm-start model");
+        FILE* f = std::fopen(path, "wb");
+        if (!f) raise(PA_EINVAL, "cannot write %s", path);
+        std::vector<double> mean(Nu), psi((size_t)ws_k * Nu);
+        std::vector<float> W(mlp.nparam);
+        d2h(mean.data(), ws_mean, sizeof(double) * Nu);
+        d2h(psi.data(), ws_psi, sizeof(double) * psi.size());
+        d2h(W.data(), mlp.p, sizeof(float) * W.size());
+        const char magic[8] = { 'P', 'A', 'W', 'S', '1', 0, 0, 0 };
+        const int64_t hdr[3] = { Nu, ws_k, mlp.dims[1] };
+        bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(hdr, sizeof hdr, 1, f) == 1 &&
+                  std::fwrite(ws_xm, sizeof ws_xm, 1, f) == 1 && std::fwrite(ws_xs, sizeof ws_xs, 1, f) == 1 &&
+                  std::fwrite(ws_cs_h.data(), sizeof(float), ws_k, f) == (size_t)ws_k &&
+                  std::fwrite(mean.data(), sizeof(double), Nu, f) == (size_t)Nu &&
+                  std::fwrite(psi.data(), sizeof(double), psi.size(), f) == psi.size() &&
+                  std::fwrite(W.data(), sizeof(float), W.size(), f) == W.size();
+        std::fclose(f);
+        if (!ok) raise(PA_EINVAL, "short write to %s", path);
+    }
+    void ws_load(const char* path) override
+    {
+        FILE* f = std::fopen(path, "rb");
+        if (!f) raise(PA_EINVAL, "cannot read %s", path);
+        struct Close { FILE* f; ~Close() { std::fclose(f); } } cl{ f };
+        char magic[8];
+        int64_t hdr[3];
+        if (std::fread(magic, 1, 8, f) != 8 || std::memcmp(magic, "PAWS1", 5) != 0) raise(PA_EINVAL, "not a warm-start file");
+        if (std::fread(hdr, sizeof hdr, 1, f) != 1 || hdr[0] != Nu || hdr[1] < 1 || hdr[1] > WS_MAXK || hdr[2] < 1 ||
+            hdr[2] > 4096)
+            raise(PA_EINVAL, "warm-start file does not match this discretisation");
+        const int k = (int)hdr[1], width = (int)hdr[2];
+        std::vector<float> cs(k);
+        std::vector<double> mean(Nu), psi((size_t)k * Nu);
+        float xm[3], xs[3];
+        if (std::fread(xm, sizeof xm, 1, f) != 1 || std::fread(xs, sizeof xs, 1, f) != 1 ||
+            std::fread(cs.data(), sizeof(float), k, f) != (size_t)k ||
+            std::fread(mean.data(), sizeof(double), Nu, f) != (size_t)Nu ||
+            std::fread(psi.data(), sizeof(double), psi.size(), f) != psi.size())
+            raise(PA_EINVAL, "truncated warm-start file");
+        ws_alloc();
+        mlp.init({ 3, width, width, width, k }, st);
+        std::vector<float> W(mlp.nparam);
+        if (std::fread(W.data(), sizeof(float), W.size(), f) != W.size()) raise(PA_EINVAL, "truncated warm-start file");
+        h2d(mlp.p, W.data(), sizeof(float) * W.size());
+        h2d(ws_mean, mean.data(), sizeof(double) * Nu);
+        h2d(ws_psi, psi.data(), sizeof(double) * psi.size());
+        h2d(ws_cs, cs.data(), sizeof(float) * k);
+        ws_cs_h = cs;
+        std::memcpy(ws_xm, xm, sizeof xm);
+        std::memcpy(ws_xs, xs, sizeof xs);
+        ws_k = k;
+    }
+
     // ---------------------------------------------------------------- several right-hand sides
     // R <= GM_RMAX systems with the same stage operator solved in lockstep:
     // one apply per iteration reads the stored blocks once for all R basis
@@ -2190,8 +2582,78 @@ pa_status pa_primal_period(pa_ctx* c, double qoi[2], double* res)
 {
     return guard(c, [&] { c->primal_period(qoi, res); });
 }
+pa_status pa_ws_train(pa_ctx* c, const double* params, const double* states, int32_t S, const pa_ws_opts* o,
+                      double* loss)
+{
+    return guard(c, [&] {
+        if (!o) raise(PA_EINVAL, "no options");
+        c->ws_train(params, states, S, *o, loss);
+    });
+}
+pa_status pa_ws_predict(pa_ctx* c, const double mu[3])
+{
+    return guard(c, [&] {
+        if (!mu) raise(PA_EINVAL, "no parameters");
+        c->ws_predict(mu);
+    });
+}
+pa_status pa_ws_shoot(pa_ctx* c, double tol, double eta, int32_t maxit, pa_shoot_report* rep, int32_t* fell_back)
+{
+    return guard(c, [&] {
+        if (!(tol > 0) || !(eta > 0) || maxit < 1) raise(PA_EINVAL, "bad shooting options");
+        c->ws_shoot(tol, eta, maxit, rep, fell_back);
+    });
+}
+pa_status pa_ws_save(pa_ctx* c, const char* path)
+{
+    return guard(c, [&] {
+        if (!path) raise(PA_EINVAL, "no path");
+        c->ws_save(path);
+    });
+}
+pa_status pa_ws_load(pa_ctx* c, const char* path)
+{
+    return guard(c, [&] {
+        if (!path) raise(PA_EINVAL, "no path");
+        c->ws_load(path);
+    });
+}
+
+pa_status pa_dbg_mlp(int32_t in, int32_t width, int32_t out, int32_t batch, const float* params, const float* X,
+                     const float* T, float* loss, float* grads)
+{
+    if (in < 1 || width < 1 || out < 1 || batch < 1 || !params || !X || !T || !loss || !grads) {
+        g_create_err = "bad arguments";
+        return PA_EINVAL;
+    }
+    hipStream_t st = nullptr;
+    try {
+        HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        {
+            Mlp m;
+            m.init({ in, width, width, width, out }, st);
+            m.reserve(batch);
+            HIPCHK(hipMemcpyAsync(m.p, params, sizeof(float) * m.nparam, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(m.X, X, sizeof(float) * (size_t)in * batch, hipMemcpyHostToDevice, st));
+            HIPCHK(hipMemcpyAsync(m.T, T, sizeof(float) * (size_t)out * batch, hipMemcpyHostToDevice, st));
+            m.forward(batch);
+            m.mse(batch);
+            m.backward(batch);
+            HIPCHK(hipMemcpyAsync(loss, m.loss, sizeof(float), hipMemcpyDeviceToHost, st));
+            HIPCHK(hipMemcpyAsync(grads, m.g, sizeof(float) * m.nparam, hipMemcpyDeviceToHost, st));
+            HIPCHK(hipStreamSynchronize(st));
+        }
+        (void)hipStreamDestroy(st);
+        return PA_OK;
+    } catch (const PaError& e) {
+        if (st) (void)hipStreamDestroy(st);
+        g_create_err = e.msg;
+        return e.code;
+    }
+}
+
 pa_status pa_batch_gradients(const pa_config* cfg, int32_t n, const double* mu, const pa_batch_opts* o,
-                             double* qoi, double* dJ, double* per)
+                             double* qoi, double* dJ, double* per, double* states)
 {
     if (!cfg || !mu || !o || n < 0 || o->workers < 1 || o->shoot_maxit < 0) {
         g_create_err = "bad batch arguments";
@@ -2227,7 +2689,16 @@ pa_status pa_batch_gradients(const pa_config* cfg, int32_t n, const double* mu, 
                     rc = pa_primal_period(c, qq, &res);
                 }
             }
+            if (rc == PA_OK && states)
+                rc = pa_get_state(c, 0, states + (int64_t)i * pa_num_dofs(c), pa_num_dofs(c));
             if (rc == PA_OK) rc = pa_adjoint_gradient(c, o->adj_rtol, q, g, nullptr);
+            if (rc != PA_OK && o->keep_going && rc != PA_EDEVICE && rc != PA_ENOMEM) {
+                const double nan = std::nan("");
+                if (qoi) qoi[2 * (int64_t)i] = qoi[2 * (int64_t)i + 1] = nan;
+                if (dJ) for (int k = 0; k < 6; ++k) dJ[6 * (int64_t)i + k] = nan;
+                if (per) per[i] = nan;
+                continue;
+            }
             if (rc != PA_OK) {
                 fail(rc, std::string("instance ") + std::to_string(i) + ": " + pa_last_error(c));
                 break;

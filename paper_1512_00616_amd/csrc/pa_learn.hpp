@@ -1,0 +1,130 @@
+// Kernels of the learned warm start: a small multilayer perceptron (FP32)
+// mapping kinematic parameters to POD coefficients of the periodic initial
+// state, trained and evaluated on the device.
+//
+// Layout: activations are column-major batches, X[feature][sample] with the
+// sample index fastest (ld = batch).  A dense layer computes
+//   Z = W X + b 1^T,  W [out][in] row-major,
+// hidden layers H = tanh(Z), the last layer is linear.  Training minimises
+// the mean squared error over all outputs and samples with Adam.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pa {
+
+constexpr int GT = 16;   // GEMM tile edge
+
+// C[M][N] = alpha * op(A)[M][K] op(B)[K][N] + beta * C, row-major storage;
+// op(A) = A (A is M x K, lda = K) or A^T (A is K x M, lda = M), likewise B.
+// 16 x 16 output tile per 256-thread block, K staged through LDS in tiles of
+// 16; accumulation in FP32 in a fixed order.
+__global__ void __launch_bounds__(GT * GT) k_gemm_f32(int M, int N, int K, float alpha, const float* __restrict__ A,
+                                                      int transA, const float* __restrict__ B, int transB,
+                                                      float beta, float* __restrict__ C)
+{
+    __shared__ float sa[GT][GT + 1], sb[GT][GT + 1];
+    const int tx = threadIdx.x % GT, ty = threadIdx.x / GT;
+    const int row = blockIdx.y * GT + ty, col = blockIdx.x * GT + tx;
+    float acc = 0.0f;
+    for (int k0 = 0; k0 < K; k0 += GT) {
+        // sa[ty][tx] = op(A)[blockIdx.y*GT + ty][k0 + tx]
+        {
+            const int r = blockIdx.y * GT + ty, k = k0 + tx;
+            float v = 0.0f;
+            if (r < M && k < K) v = transA ? A[(int64_t)k * M + r] : A[(int64_t)r * K + k];
+            sa[ty][tx] = v;
+        }
+        // sb[ty][tx] = op(B)[k0 + ty][blockIdx.x*GT + tx]
+        {
+            const int k = k0 + ty, c = blockIdx.x * GT + tx;
+            float v = 0.0f;
+            if (k < K && c < N) v = transB ? B[(int64_t)c * K + k] : B[(int64_t)k * N + c];
+            sb[ty][tx] = v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < GT; ++k) acc += sa[ty][k] * sb[k][tx];
+        __syncthreads();
+    }
+    if (row < M && col < N) {
+        float* c = C + (int64_t)row * N + col;
+        *c = alpha * acc + (beta == 0.0f ? 0.0f : beta * *c);
+    }
+}
+
+// H = act(Z + b 1^T) in place on Z [rows][cols]; act = tanh when hidden != 0
+__global__ void k_bias_act(float* __restrict__ Z, const float* __restrict__ b, int rows, int cols, int hidden)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= (int64_t)rows * cols) return;
+    const float v = Z[i] + b[i / cols];
+    Z[i] = hidden ? tanhf(v) : v;
+}
+
+// dZ = dH * (1 - H^2) (tanh derivative), in place on dH
+__global__ void k_tanh_back(float* __restrict__ dH, const float* __restrict__ H, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dH[i] *= 1.0f - H[i] * H[i];
+}
+
+// db[r] = sum_c dZ[r][c] (fixed order), one thread per row
+__global__ void k_row_sum(const float* __restrict__ dZ, float* __restrict__ db, int rows, int cols)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= rows) return;
+    float s = 0.0f;
+    for (int c = 0; c < cols; ++c) s += dZ[(int64_t)r * cols + c];
+    db[r] = s;
+}
+
+// dY = 2 (Y - T) / n and loss = sum (Y - T)^2 / n, n = rows * cols; one
+// block of 256 threads, fixed-order reduction
+__global__ void __launch_bounds__(256) k_mse(const float* __restrict__ Y, const float* __restrict__ T,
+                                             float* __restrict__ dY, int64_t n, float* __restrict__ loss)
+{
+    __shared__ float red[256];
+    float s = 0.0f;
+    const float inv = 1.0f / (float)n;
+    for (int64_t i = threadIdx.x; i < n; i += 256) {
+        const float d = Y[i] - T[i];
+        dY[i] = 2.0f * d * inv;
+        s += d * d;
+    }
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = 128; st > 0; st >>= 1) {
+        if ((int)threadIdx.x < st) red[threadIdx.x] += red[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *loss = red[0] * inv;
+}
+
+// Adam step (bias-corrected), t >= 1
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float* __restrict__ m, float* __restrict__ v,
+                       int64_t n, float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = g[i];
+    const float mi = b1 * m[i] + (1.0f - b1) * gi;
+    const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// out = base + sum_k c[k] Psi_k (FP64), c on the device
+__global__ void k_pod_expand(const double* __restrict__ base, const double* __restrict__ Psi, int k, int64_t ld,
+                             const float* __restrict__ c, const float* __restrict__ cscale, double* __restrict__ out,
+                             int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = base[i];
+    for (int j = 0; j < k; ++j) s += (double)c[j] * (double)cscale[j] * Psi[(int64_t)j * ld + i];
+    out[i] = s;
+}
+
+}  // namespace pa

@@ -41,6 +41,12 @@ def random_vectors(n, k=2, seed=7):
     return [g.standard_normal(n) for _ in range(k)]
 
 
+def warmstart_params(count, seed):
+    """Kinematics for the learned warm start: training draws (seed 5) and
+    held-out draws (seed 55), same ranges as batch_params."""
+    return batch_params(count, seed=seed)
+
+
 def batch_params(count, seed=4):
     """(h0, theta0 [rad], phi) with h0 ~ U[0.1, 0.5], theta0 ~ U[0, 30 deg], phi ~ U[0, pi]."""
     g = rng(seed)

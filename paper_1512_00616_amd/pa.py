@@ -18,7 +18,8 @@ PA_K_SPMV, PA_K_PRECOND, PA_K_JACOBIAN, PA_K_RESIDUAL, PA_K_BLOCKINV, PA_K_SPMV_
 EXPORTED = [
     "pa_default_config", "pa_create", "pa_destroy", "pa_last_error", "pa_num_dofs", "pa_num_elems",
     "pa_block_size", "pa_device_bytes", "pa_get_mesh", "pa_set_params", "pa_set_state", "pa_set_freestream",
-    "pa_get_state", "pa_primal_period", "pa_shoot", "pa_fixed_point", "pa_adjoint_gradient", "pa_tangent_gradient", "pa_batch_gradients", "pa_tangent_sweep",
+    "pa_get_state", "pa_primal_period", "pa_shoot", "pa_fixed_point", "pa_adjoint_gradient", "pa_tangent_gradient", "pa_batch_gradients",
+    "pa_ws_train", "pa_ws_predict", "pa_ws_shoot", "pa_ws_save", "pa_ws_load", "pa_dbg_mlp", "pa_tangent_sweep",
     "pa_adjoint_sweep", "pa_dbg_gbar", "pa_dbg_dgbar", "pa_dbg_residual", "pa_dbg_jacobian", "pa_dbg_dr_dmu",
     "pa_dbg_qoi", "pa_dbg_bsr_apply", "pa_dbg_blockinv", "pa_dbg_stage_solve", "pa_dbg_traj", "pa_set_timing",
     "pa_kernel_time", "pa_bench_spmv", "pa_bench_spmv_lo", "pa_bench_copy",
@@ -54,7 +55,13 @@ class pa_adjoint_report(C.Structure):
 
 class pa_batch_opts(C.Structure):
     _fields_ = [("workers", C.c_int32), ("shoot_maxit", C.c_int32), ("shoot_tol", C.c_double),
-                ("shoot_eta", C.c_double), ("allow_unconverged", C.c_int32), ("adj_rtol", C.c_double)]
+                ("shoot_eta", C.c_double), ("allow_unconverged", C.c_int32), ("adj_rtol", C.c_double),
+                ("keep_going", C.c_int32)]
+
+
+class pa_ws_opts(C.Structure):
+    _fields_ = [("modes", C.c_int32), ("width", C.c_int32), ("epochs", C.c_int32), ("lr", C.c_float),
+                ("seed", C.c_uint64)]
 
 
 class PaError(RuntimeError):
@@ -94,7 +101,13 @@ def lib():
             "pa_get_state": [P, C.c_int32, P, C.c_int64],
             "pa_primal_period": [P, P, P],
             "pa_shoot": [P, C.c_double, C.c_double, C.c_int32, P],
-            "pa_batch_gradients": [P, C.c_int32, P, P, P, P, P],
+            "pa_batch_gradients": [P, C.c_int32, P, P, P, P, P, P],
+            "pa_ws_train": [P, P, P, C.c_int32, P, P],
+            "pa_ws_predict": [P, P],
+            "pa_ws_shoot": [P, C.c_double, C.c_double, C.c_int32, P, P],
+            "pa_ws_save": [P, C.c_char_p],
+            "pa_ws_load": [P, C.c_char_p],
+            "pa_dbg_mlp": [C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P],
             "pa_fixed_point": [P, C.c_int32, P],
             "pa_adjoint_gradient": [P, C.c_double, P, P, P],
             "pa_tangent_gradient": [P, C.c_double, P, P],
@@ -143,21 +156,43 @@ def default_config(**kw):
 
 
 def batch_gradients(mu, workers=4, shoot_maxit=30, shoot_tol=1e-8, shoot_eta=1e-3, allow_unconverged=False,
-                    adj_rtol=1e-8, **cfg_kw):
+                    adj_rtol=1e-8, return_states=False, keep_going=False, **cfg_kw):
     """Alg. 4 for every row of mu (n x 3) on one configuration, run by
     `workers` concurrent contexts inside the library; returns qoi (n x 2),
-    dJ/dmu (n x 2 x 3) and the final periodicity residuals (n)."""
+    dJ/dmu (n x 2 x 3), the final periodicity residuals (n) and, with
+    return_states, the periodic initial states (n x N_u)."""
     mu = np.ascontiguousarray(np.asarray(mu, dtype=np.float64).reshape(-1, 3))
     n = mu.shape[0]
     cfg = default_config(**cfg_kw)
-    o = pa_batch_opts(workers, shoot_maxit, shoot_tol, shoot_eta, int(allow_unconverged), adj_rtol)
+    o = pa_batch_opts(workers, shoot_maxit, shoot_tol, shoot_eta, int(allow_unconverged), adj_rtol, int(keep_going))
     q = np.zeros((n, 2))
     g = np.zeros((n, 6))
     per = np.zeros(n)
-    rc = lib().pa_batch_gradients(C.byref(cfg), n, _ptr(mu), C.byref(o), _ptr(q), _ptr(g), _ptr(per))
+    states = None
+    if return_states:
+        np_ = (cfg.p + 1) * (cfg.p + 2) // 2
+        states = np.zeros((n, 2 * cfg.Nr * cfg.Nth * 4 * np_))
+    rc = lib().pa_batch_gradients(C.byref(cfg), n, _ptr(mu), C.byref(o), _ptr(q), _ptr(g), _ptr(per), _ptr(states))
     if rc != PA_OK:
         raise PaError(rc, lib().pa_last_error(None).decode())
+    if return_states:
+        return q, g.reshape(n, 2, 3), per, states
     return q, g.reshape(n, 2, 3), per
+
+
+def dbg_mlp(params, X, T, width):
+    """One device forward/backward pass of the warm-start perceptron
+    (X [in][batch], T [out][batch]); returns (loss, grads)."""
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    X = np.ascontiguousarray(X, dtype=np.float32)
+    T = np.ascontiguousarray(T, dtype=np.float32)
+    grads = np.zeros_like(params)
+    loss = np.zeros(1, dtype=np.float32)
+    rc = lib().pa_dbg_mlp(X.shape[0], width, T.shape[0], X.shape[1], _ptr(params), _ptr(X), _ptr(T), _ptr(loss),
+                          _ptr(grads))
+    if rc != PA_OK:
+        raise PaError(rc, lib().pa_last_error(None).decode())
+    return float(loss[0]), grads
 
 
 class Solver:
@@ -251,6 +286,31 @@ class Solver:
         rep = pa_adjoint_report()
         self._chk(lib().pa_adjoint_gradient(self._c, rtol, _ptr(q), _ptr(g), C.byref(rep)))
         return q, g.reshape(2, 3), rep
+
+    # learned warm start
+    def ws_train(self, params, states, modes=16, width=256, epochs=2000, lr=1e-3, seed=5):
+        params = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(-1, 3))
+        states = np.ascontiguousarray(np.asarray(states, dtype=np.float64).reshape(params.shape[0], self.Nu))
+        o = pa_ws_opts(modes, width, epochs, lr, seed)
+        loss = np.zeros(1)
+        self._chk(lib().pa_ws_train(self._c, _ptr(params), _ptr(states), params.shape[0], C.byref(o), _ptr(loss)))
+        return float(loss[0])
+
+    def ws_predict(self, mu):
+        mu = np.ascontiguousarray(mu, dtype=np.float64)
+        self._chk(lib().pa_ws_predict(self._c, _ptr(mu)))
+
+    def ws_shoot(self, tol=1e-8, eta=1e-3, maxit=30):
+        rep = pa_shoot_report()
+        fb = np.zeros(1, dtype=np.int32)
+        self._chk(lib().pa_ws_shoot(self._c, tol, eta, maxit, C.byref(rep), _ptr(fb)))
+        return rep, bool(fb[0])
+
+    def ws_save(self, path):
+        self._chk(lib().pa_ws_save(self._c, str(path).encode()))
+
+    def ws_load(self, path):
+        self._chk(lib().pa_ws_load(self._c, str(path).encode()))
 
     def tangent_gradient(self, rtol=1e-8):
         """Direct-method dJ/dmu (2 x 3) and the outer Krylov counts per parameter."""
