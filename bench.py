@@ -38,6 +38,11 @@ os.environ.setdefault("PA_VERBOSE", "1")   # progress lines from the library (st
 from paper_1512_00616_amd import inputs  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
+# hardware-counter traffic per launch of the forward FP64 stage-operator apply
+# on the 32x96 p=3 workload (FETCH_SIZE and WRITE_SIZE calibrated against a
+# plain copy; profiles/k_ahat_fwd_32x96_p3.md); valid for that kernel as
+# measured, to be re-taken when it changes
+TRAFFIC_BYTES = {"pa::k_ahat_fwd<10, double, double>": 243.0e6}
 
 
 def spmv_bytes(Nr, Nth, p, mat_bytes=8, vec_bytes=8):
@@ -341,7 +346,9 @@ def run_step(pa, name, work, mu, args, precision):
         "config": {"workload": name, **work, "mu": list(mu), "stage_gmres": "block-Jacobi GMRES(30) rtol 1e-10",
                    "newton_atol": 1e-10, "outer_krylov_cap": args.krylov, "shoot_eta": 1e-3, "adj_rtol": 1e-8},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": TRAFFIC_BYTES.get("pa::k_ahat_fwd<10, double, double>")
+                     if (work["Nr"], work["Nth"], work["p"]) == (32, 96, 3) else None,
                      "kernel": "pa::k_ahat_fwd<10, double, double>",
                      "bytes_per_launch": bytes_spmv, "avg_launch_us": avg_spmv_s * 1e6, "launches": n_spmv},
         # transposed applies: k_ahat_tr<10, double, double> for one right-hand
