@@ -112,10 +112,14 @@ def time_to_gradient(pa, mu):
     rep = s.shoot(tol=1e-8, eta=1e-3, maxit=30)
     q, dJ, arep = s.adjoint_gradient(rtol=1e-8)
     t = time.perf_counter() - t0
+    # after the timed region: leading Floquet multipliers of the orbit
+    # (Arnoldi with 40 tangent sweeps)
+    ritz, _ = s.floquet(k=40, seed=13)
     s.close()
     return {"workload": "circle-8x24-p1-nt20", "seconds": t, "newton": rep.newton_its,
             "tangent_sweeps": rep.krylov_its, "periodicity": rep.res, "adjoint_krylov": list(arep.krylov_its),
-            "qoi": list(q), "dJdmu": dJ.tolist()}
+            "qoi": list(q), "dJdmu": dJ.tolist(),
+            "floquet_leading": [[float(z.real), float(z.imag)] for z in ritz[:4]]}
 
 
 def learned(pa, args):

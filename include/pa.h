@@ -144,6 +144,16 @@ pa_status pa_shoot(pa_ctx* ctx, double tol, double eta, int32_t maxit, pa_shoot_
  * the last period.  The stored trajectory is invalidated. */
 pa_status pa_fixed_point(pa_ctx* ctx, int32_t periods, double* res);
 
+/* Floquet multipliers (eigenvalues of the flow-map Jacobian Phi of Sec. 2.3)
+ * about the stored trajectory, e.g. a periodic one after pa_shoot: k steps
+ * of Arnoldi with tangent sweeps from a seeded random start (splitmix64),
+ * then the eigenvalues of the k x k Hessenberg matrix.  re[k], im[k]
+ * (host) receive the Ritz values by decreasing modulus; *nritz the number
+ * computed (less than k if an invariant subspace was found); *hsub (may be
+ * NULL) the last subdiagonal entry.  1 <= k <= max_krylov.  The orbit is
+ * linearly stable when every multiplier lies inside the unit circle. */
+pa_status pa_floquet(pa_ctx* ctx, int32_t k, uint64_t seed, double* re, double* im, int32_t* nritz, double* hsub);
+
 typedef struct pa_adjoint_report {
     int32_t krylov_its[2];      /* outer GMRES iterations per QoI */
     int32_t sweeps;             /* backward sweeps in total (the two QoIs ride together) */

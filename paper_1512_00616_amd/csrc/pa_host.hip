@@ -23,6 +23,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <complex>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -362,6 +363,61 @@ struct Mlp {
     }
 };
 
+// eigenvalues of an upper Hessenberg matrix (n x n, row-major) by the
+// shifted QR algorithm in complex arithmetic (Wilkinson shift, deflation of
+// negligible subdiagonals); the matrix is overwritten
+inline void hess_eig(std::vector<std::complex<double>>& H, int n, std::vector<std::complex<double>>& ev)
+{
+    using cd = std::complex<double>;
+    ev.assign(n, cd(0, 0));
+    auto at = [&](int i, int j) -> cd& { return H[(size_t)i * n + j]; };
+    int hi = n - 1, iter = 0;
+    while (hi >= 0) {
+        if (hi == 0) { ev[0] = at(0, 0); break; }
+        // find the active block [lo, hi]
+        int lo = hi;
+        while (lo > 0) {
+            const double sub = std::abs(at(lo, lo - 1));
+            const double dia = std::abs(at(lo, lo)) + std::abs(at(lo - 1, lo - 1));
+            if (sub <= 1e-15 * (dia > 0 ? dia : 1.0)) { at(lo, lo - 1) = 0; break; }
+            --lo;
+        }
+        if (lo == hi) { ev[hi] = at(hi, hi); --hi; iter = 0; continue; }
+        if (++iter > 100 * n) raise(PA_ENOCONV, "Hessenberg QR did not converge");
+        // Wilkinson shift from the trailing 2 x 2 block (exceptional shift now and then)
+        const cd a = at(hi - 1, hi - 1), b = at(hi - 1, hi), c = at(hi, hi - 1), d = at(hi, hi);
+        const cd tr = a + d, det = a * d - b * c;
+        const cd disc = std::sqrt(tr * tr - 4.0 * det);
+        const cd l1 = 0.5 * (tr + disc), l2 = 0.5 * (tr - disc);
+        cd mu = std::abs(l1 - d) < std::abs(l2 - d) ? l1 : l2;
+        if (iter % 11 == 0) mu += cd(std::abs(at(hi, hi - 1)), 0.0);
+        // QR step on the block by Givens rotations: H - mu I = Q R, H <- R Q + mu I
+        std::vector<cd> cs(hi - lo), sn(hi - lo);
+        for (int k = lo; k <= hi; ++k) at(k, k) -= mu;
+        for (int k = lo; k < hi; ++k) {
+            const cd x = at(k, k), y = at(k + 1, k);
+            const double r = std::sqrt(std::norm(x) + std::norm(y));
+            const cd cc = r > 0 ? x / r : cd(1, 0), ss = r > 0 ? y / r : cd(0, 0);
+            cs[k - lo] = cc;
+            sn[k - lo] = ss;
+            for (int j = k; j < n; ++j) {   // rows k, k+1 <- G^H rows
+                const cd u = at(k, j), v = at(k + 1, j);
+                at(k, j) = std::conj(cc) * u + std::conj(ss) * v;
+                at(k + 1, j) = -ss * u + cc * v;
+            }
+        }
+        for (int k = lo; k < hi; ++k) {     // columns k, k+1 <- columns G
+            const cd cc = cs[k - lo], ss = sn[k - lo];
+            for (int i = 0; i <= std::min(k + 1, hi); ++i) {
+                const cd u = at(i, k), v = at(i, k + 1);
+                at(i, k) = u * cc + v * ss;
+                at(i, k + 1) = -u * std::conj(ss) + v * std::conj(cc);
+            }
+        }
+        for (int k = lo; k <= hi; ++k) at(k, k) += mu;
+    }
+}
+
 // splitmix64: seeded initial weights
 inline uint64_t splitmix64(uint64_t& x)
 {
@@ -442,6 +498,7 @@ struct pa_ctx {
     virtual void primal_period(double qoi[2], double* res) = 0;
     virtual void shoot(double tol, double eta, int maxit, pa_shoot_report* rep) = 0;
     virtual void fixed_point(int periods, double* res) = 0;
+    virtual int floquet(int k, uint64_t seed, double* re, double* im, double* hsub) = 0;
     virtual void adjoint_gradient(double rtol, double qoi[2], double dJ[6], pa_adjoint_report* rep) = 0;
     virtual void tangent_gradient(double rtol, double dJ[6], int32_t its[3]) = 0;
     virtual void ws_train(const double* params, const double* states, int S, const pa_ws_opts& o, double* loss) = 0;
@@ -2072,6 +2129,53 @@ struct Solver final : pa_ctx {
         finish();
     }
 
+    // Floquet multipliers of the stored trajectory (Sec. 2.3 discusses the
+    // spectrum of Phi): k steps of Arnoldi on Phi with tangent sweeps from a
+    // seeded random start (two Gram-Schmidt passes), then the eigenvalues of
+    // the k x k Hessenberg matrix (Ritz values), sorted by modulus, largest
+    // first.  Returns the basis size reached (smaller on an invariant
+    // subspace); *hsub receives the last subdiagonal entry h_{k+1,k}.
+    int floquet(int k, uint64_t seed, double* re, double* im, double* hsub) override
+    {
+        if (!have_traj) raise(PA_ESTATE, "no trajectory (run pa_primal_period or pa_shoot first)");
+        if (k < 1 || k > max_kry) raise(PA_EINVAL, "basis size must be 1..max_krylov (%d)", max_kry);
+        const int m = k;
+        std::vector<double> H((size_t)(m + 1) * m, 0.0), h(m + 2), h2(m + 2);
+        std::vector<double> v0(Nu);
+        for (int64_t i = 0; i < Nu; ++i) v0[i] = (double)(splitmix64(seed) >> 11) * (1.0 / 9007199254740992.0) - 0.5;
+        h2d(outer_w, v0.data(), sizeof(double) * Nu);
+        const double n0 = norm(outer_w);
+        lincomb(1.0 / n0, outer_w, 0.0, outer_w, Vo);
+        int j = 0;
+        double last = 0.0;
+        for (; j < m; ++j) {
+            double* wk = outer_w;
+            tangent(Vo + (int64_t)j * Nu, wk);
+            dots(Vo, Nu, j + 1, wk, h.data());
+            vupdate(Vo, Nu, j + 1, h.data(), -1.0, wk);
+            dots(Vo, Nu, j + 1, wk, h2.data());
+            vupdate(Vo, Nu, j + 1, h2.data(), -1.0, wk);
+            for (int i = 0; i <= j; ++i) H[(size_t)i * m + j] = h[i] + h2[i];
+            const double hn = norm(wk);
+            last = hn;
+            if (j + 1 < m) H[(size_t)(j + 1) * m + j] = hn;
+            if (!(hn > 1e-14 * std::fabs(H[(size_t)j * m + j]) + 1e-300)) { ++j; break; }
+            if (j + 1 < m) lincomb(1.0 / hn, wk, 0.0, wk, Vo + (int64_t)(j + 1) * Nu);
+            if (verbose && (j + 1) % 10 == 0) fprintf(stderr, "[pa] floquet arnoldi %d/%d\n", j + 1, m);
+        }
+        const int kk = std::min(j, m);
+        std::vector<std::complex<double>> Hc((size_t)kk * kk), ev;
+        for (int r = 0; r < kk; ++r)
+            for (int c = 0; c < kk; ++c) Hc[(size_t)r * kk + c] = H[(size_t)r * m + c];
+        hess_eig(Hc, kk, ev);
+        std::sort(ev.begin(), ev.end(), [](const std::complex<double>& a, const std::complex<double>& b) {
+            return std::abs(a) > std::abs(b);
+        });
+        for (int i = 0; i < kk; ++i) { re[i] = ev[i].real(); im[i] = ev[i].imag(); }
+        if (hsub) *hsub = last;
+        return kk;
+    }
+
     // Alg. 1: m fixed-point periods u0 <- u^(Nt)(u0)
     void fixed_point(int periods, double* res_out) override
     {
@@ -2722,6 +2826,14 @@ pa_status pa_shoot(pa_ctx* c, double tol, double eta, int32_t maxit, pa_shoot_re
     return guard(c, [&] {
         if (!(tol > 0) || !(eta > 0) || maxit < 0) raise(PA_EINVAL, "bad shooting options");
         c->shoot(tol, eta, maxit, rep);
+    });
+}
+pa_status pa_floquet(pa_ctx* c, int32_t k, uint64_t seed, double* re, double* im, int32_t* nritz, double* hsub)
+{
+    return guard(c, [&] {
+        if (!re || !im) raise(PA_EINVAL, "no output");
+        const int n = c->floquet(k, seed, re, im, hsub);
+        if (nritz) *nritz = n;
     });
 }
 pa_status pa_fixed_point(pa_ctx* c, int32_t periods, double* res)

@@ -18,7 +18,7 @@ PA_K_SPMV, PA_K_PRECOND, PA_K_JACOBIAN, PA_K_RESIDUAL, PA_K_BLOCKINV, PA_K_SPMV_
 EXPORTED = [
     "pa_default_config", "pa_create", "pa_destroy", "pa_last_error", "pa_num_dofs", "pa_num_elems",
     "pa_block_size", "pa_device_bytes", "pa_get_mesh", "pa_set_params", "pa_set_state", "pa_set_freestream",
-    "pa_get_state", "pa_primal_period", "pa_shoot", "pa_fixed_point", "pa_adjoint_gradient", "pa_tangent_gradient", "pa_batch_gradients",
+    "pa_get_state", "pa_primal_period", "pa_shoot", "pa_fixed_point", "pa_floquet", "pa_adjoint_gradient", "pa_tangent_gradient", "pa_batch_gradients",
     "pa_ws_train", "pa_ws_predict", "pa_ws_shoot", "pa_ws_save", "pa_ws_load", "pa_dbg_mlp", "pa_tangent_sweep",
     "pa_adjoint_sweep", "pa_dbg_gbar", "pa_dbg_dgbar", "pa_dbg_residual", "pa_dbg_jacobian", "pa_dbg_dr_dmu",
     "pa_dbg_qoi", "pa_dbg_bsr_apply", "pa_dbg_blockinv", "pa_dbg_stage_solve", "pa_dbg_traj", "pa_set_timing",
@@ -102,6 +102,7 @@ def lib():
             "pa_primal_period": [P, P, P],
             "pa_shoot": [P, C.c_double, C.c_double, C.c_int32, P],
             "pa_batch_gradients": [P, C.c_int32, P, P, P, P, P, P],
+            "pa_floquet": [P, C.c_int32, C.c_uint64, P, P, P, P],
             "pa_ws_train": [P, P, P, C.c_int32, P, P],
             "pa_ws_predict": [P, P],
             "pa_ws_shoot": [P, C.c_double, C.c_double, C.c_int32, P, P],
@@ -274,6 +275,16 @@ class Solver:
             return rep
         self._chk(rc)
         return rep
+
+    def floquet(self, k=40, seed=13):
+        """Ritz values of Phi (complex, by decreasing modulus) and the last
+        Arnoldi subdiagonal entry."""
+        re = np.zeros(k)
+        im = np.zeros(k)
+        n = np.zeros(1, dtype=np.int32)
+        h = np.zeros(1)
+        self._chk(lib().pa_floquet(self._c, k, seed, _ptr(re), _ptr(im), _ptr(n), _ptr(h)))
+        return (re + 1j * im)[: n[0]], float(h[0])
 
     def fixed_point(self, periods):
         r = np.zeros(1)
