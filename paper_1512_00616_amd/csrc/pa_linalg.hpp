@@ -760,15 +760,23 @@ __global__ void __launch_bounds__(64) k_ahat_apply_lo(int Ne, const int32_t* __r
 
 // Forward apply y = x + Ahat x for any storage type TM (double, float,
 // bf16_t) with TV vectors; accumulation in TV (FP64 for the FP64 operator,
-// FP32 otherwise).  One wave per block row.  Each lane owns 16-byte chunks
-// of the row-major blocks; a chunk lies inside one row (B is a multiple of
-// the entries per chunk), so the lane multiplies it by the matching entries
-// of x in registers and leaves one partial per chunk in LDS, stored
-// chunk-major with a padded stride (conflict-free both ways).  Lane i then
-// adds the partials of row i in chunk order.
+// FP32 otherwise).  One wave per block row.  A task is Q consecutive 16-byte
+// chunks of one row of a row-major block (Q chosen so that a task never
+// straddles rows and holds at most 8 entries): the lane loads them with Q
+// coalesced 16-byte loads (all tasks of the three blocks before any
+// arithmetic), multiplies them by the matching entries of x in registers and
+// leaves one partial per task in LDS, stored task-major with a padded stride
+// (conflict-free both ways).  Lane i then adds the partials of row i in task
+// order (B / (Q EPL) per block, 5 at p = 3 for every storage type).
 template <class TA> __device__ __forceinline__ TA to_acc(double v) { return (TA)v; }
 template <class TA> __device__ __forceinline__ TA to_acc(float v) { return (TA)v; }
 template <class TA> __device__ __forceinline__ TA to_acc(bf16_t v) { return (TA)lo_to_f(v); }
+
+template <int B, int EPL>
+constexpr int fwd_chunks_per_task()
+{
+    return (8 % EPL == 0 && B % 8 == 0) ? 8 / EPL : (B % (2 * EPL) == 0 && 2 * EPL <= 8 ? 2 : 1);
+}
 
 template <int NP, class TM, class TV>
 __global__ void __launch_bounds__(64) k_ahat_fwd(int Ne, const int32_t* __restrict__ enb, const TM* __restrict__ Ah,
@@ -776,11 +784,14 @@ __global__ void __launch_bounds__(64) k_ahat_fwd(int Ne, const int32_t* __restri
                                                  const int* __restrict__ skip)
 {
     constexpr int B = 4 * NP, BB = B * B;
-    constexpr int EPL = 16 / sizeof(TM);              // entries per chunk
+    constexpr int EPL = 16 / sizeof(TM);              // entries per 16-byte chunk
     static_assert(B % EPL == 0, "a chunk must not straddle rows");
-    constexpr int H = BB / EPL, CPR = B / EPL;        // chunks per block / per row
+    constexpr int Q = fwd_chunks_per_task<B, EPL>();  // chunks per task
+    constexpr int EPT = Q * EPL;                      // entries per task
+    static_assert(B % EPT == 0, "a task must not straddle rows");
+    constexpr int H = BB / EPT, TPR = B / EPT;        // tasks per block / per row
     constexpr int PER = (H + 63) / 64;
-    __shared__ TV sp[3][CPR][B + 1];
+    __shared__ TV sp[3][TPR][B + 1];
     __shared__ TV sx[3][B];
     if (skip && *skip) return;
     const int K = blockIdx.x, lane = threadIdx.x;
@@ -792,13 +803,15 @@ __global__ void __launch_bounds__(64) k_ahat_fwd(int Ne, const int32_t* __restri
         nbs[f] = nb;
         src[f] = nb >= 0 ? reinterpret_cast<const uint4*>(Ah + ((int64_t)K * 3 + f) * BB) : nullptr;
     }
-    uint4 v[3][PER];
+    uint4 v[3][PER][Q];
 #pragma unroll
     for (int f = 0; f < 3; ++f)
 #pragma unroll
         for (int r = 0; r < PER; ++r) {
             const int t = lane + 64 * r;
-            if (src[f] && t < H) v[f][r] = src[f][t];
+            if (src[f] && t < H)
+#pragma unroll
+                for (int q = 0; q < Q; ++q) v[f][r][q] = src[f][t * Q + q];
         }
 #pragma unroll
     for (int f = 0; f < 3; ++f)
@@ -810,11 +823,14 @@ __global__ void __launch_bounds__(64) k_ahat_fwd(int Ne, const int32_t* __restri
         for (int r = 0; r < PER; ++r) {
             const int t = lane + 64 * r;
             if (src[f] && t < H) {
-                const int i = t / CPR, c = t % CPR;
-                const TM* e = reinterpret_cast<const TM*>(&v[f][r]);
+                const int i = t / TPR, c = t % TPR;
                 TV p = 0;
 #pragma unroll
-                for (int q = 0; q < EPL; ++q) p += to_acc<TV>(e[q]) * sx[f][c * EPL + q];
+                for (int q = 0; q < Q; ++q) {
+                    const TM* e = reinterpret_cast<const TM*>(&v[f][r][q]);
+#pragma unroll
+                    for (int u = 0; u < EPL; ++u) p += to_acc<TV>(e[u]) * sx[f][c * EPT + q * EPL + u];
+                }
                 sp[f][c][i] = p;
             }
         }
@@ -825,7 +841,7 @@ __global__ void __launch_bounds__(64) k_ahat_fwd(int Ne, const int32_t* __restri
         for (int f = 0; f < 3; ++f) {
             if (nbs[f] < 0) continue;
 #pragma unroll
-            for (int c = 0; c < CPR; ++c) acc += sp[f][c][lane];
+            for (int c = 0; c < TPR; ++c) acc += sp[f][c][lane];
         }
         y[(int64_t)K * B + lane] = acc;
     }
@@ -911,7 +927,7 @@ __global__ void __launch_bounds__(64) k_ahat_tr(int Ne, const int32_t* __restric
 // ------------------------------------------------------------------ several right-hand sides
 // y_r = x_r + Ahat x_r (forward) for R systems sharing the stored operator
 // (x_r = x + r sx, y_r = y + r sy): the three blocks of the row are read
-// from HBM once into registers and applied to every x_r (same per-chunk
+// from HBM once into registers and applied to every x_r (same per-task
 // partials as k_ahat_fwd, one LDS pass per system).  The launch returns at
 // once when every system's GMRES state (optional) is done.
 template <int NP>
@@ -920,8 +936,9 @@ __global__ void __launch_bounds__(64) k_ahat_fwd_m(int Ne, const int32_t* __rest
                                                    double* __restrict__ y, int64_t sy, const GmState* __restrict__ st)
 {
     constexpr int B = 4 * NP, BB = B * B, EPL = 2;
-    constexpr int H = BB / EPL, CPR = B / EPL, PER = (H + 63) / 64;
-    __shared__ double sp[3][CPR][B + 1];
+    constexpr int Q = fwd_chunks_per_task<B, EPL>(), EPT = Q * EPL;   // tasks as in k_ahat_fwd
+    constexpr int H = BB / EPT, TPR = B / EPT, PER = (H + 63) / 64;
+    __shared__ double sp[3][TPR][B + 1];
     __shared__ double sxr[GM_RMAX][3][B];
     if (st) {
         bool all = true;
@@ -937,13 +954,15 @@ __global__ void __launch_bounds__(64) k_ahat_fwd_m(int Ne, const int32_t* __rest
         nbs[f] = nb;
         src[f] = nb >= 0 ? reinterpret_cast<const uint4*>(Ah + ((int64_t)K * 3 + f) * BB) : nullptr;
     }
-    uint4 v[3][PER];
+    uint4 v[3][PER][Q];
 #pragma unroll
     for (int f = 0; f < 3; ++f)
 #pragma unroll
         for (int rr = 0; rr < PER; ++rr) {
             const int t = lane + 64 * rr;
-            if (src[f] && t < H) v[f][rr] = src[f][t];
+            if (src[f] && t < H)
+#pragma unroll
+                for (int q = 0; q < Q; ++q) v[f][rr][q] = src[f][t * Q + q];
         }
     for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -957,9 +976,14 @@ __global__ void __launch_bounds__(64) k_ahat_fwd_m(int Ne, const int32_t* __rest
             for (int rr = 0; rr < PER; ++rr) {
                 const int t = lane + 64 * rr;
                 if (src[f] && t < H) {
-                    const int i = t / CPR, c = t % CPR;
-                    const double* e = reinterpret_cast<const double*>(&v[f][rr]);
-                    sp[f][c][i] = e[0] * sxr[r][f][c * EPL] + e[1] * sxr[r][f][c * EPL + 1];
+                    const int i = t / TPR, c = t % TPR;
+                    double p = 0.0;
+#pragma unroll
+                    for (int q = 0; q < Q; ++q) {
+                        const double* e = reinterpret_cast<const double*>(&v[f][rr][q]);
+                        p += e[0] * sxr[r][f][c * EPT + q * EPL] + e[1] * sxr[r][f][c * EPT + q * EPL + 1];
+                    }
+                    sp[f][c][i] = p;
                 }
             }
         __syncthreads();
@@ -969,7 +993,7 @@ __global__ void __launch_bounds__(64) k_ahat_fwd_m(int Ne, const int32_t* __rest
             for (int f = 0; f < 3; ++f) {
                 if (nbs[f] < 0) continue;
 #pragma unroll
-                for (int c = 0; c < CPR; ++c) acc += sp[f][c][lane];
+                for (int c = 0; c < TPR; ++c) acc += sp[f][c][lane];
             }
             y[r * sy + (int64_t)K * B + lane] = acc;
         }
