@@ -1513,7 +1513,7 @@ struct Solver final : pa_ctx {
     {
         hipEvent_t e;
         tstart(tr ? PA_K_SPMV_T : PA_K_SPMV, &e);
-        if (tr) k_ahat_tr_m<NP><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, Ah, R, x, sx, y, sy, skip);
+        if (tr) k_ahat_tr_m<NP><<<Ne, 64, ahat_tr_m_smem<NP>(R), st>>>(Ne, dm.enb, dm.etw, Ah, R, x, sx, y, sy, skip);
         else k_ahat_fwd_m<NP><<<Ne, 64, 0, st>>>(Ne, dm.enb, Ah, R, x, sx, y, sy, skip);
         LAUNCHCHK();
         tstop(e);

@@ -384,6 +384,19 @@ __global__ void __launch_bounds__(MD_THREADS) k_gm_upd(const T* __restrict__ V, 
     __shared__ double col[GM_MAXM + 2];
     const int ncols = j + 1, nc = j + 2;
     const bool lead = blockIdx.x == 0;
+    // this thread's entries of w and of the first eight basis columns are
+    // loaded before the partials are summed, so both latencies overlap
+    const int64_t i0 = (int64_t)blockIdx.x * MD_TILE + 2 * threadIdx.x, i1 = i0 + 2 * MD_THREADS;
+    const bool in0 = i0 < n, in1 = i1 < n;
+    const int64_t a0 = in0 ? i0 : 0, a1 = in1 ? i1 : 0;   // clamped (valid) addresses
+    double2 pa[8], pb[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const T* vc = V + (int64_t)(u < ncols ? u : ncols - 1) * ldv;
+        pa[u] = ld2(vc + a0);
+        pb[u] = ld2(vc + a1);
+    }
+    const double2 wa = ld2(w + a0), wb = ld2(w + a1);
     if (lead)
         for (int i = threadIdx.x; i < j; i += blockDim.x) {
             scs[i] = st->cs[i];
@@ -430,11 +443,16 @@ __global__ void __launch_bounds__(MD_THREADS) k_gm_upd(const T* __restrict__ V, 
         }
     }
     // V_{j+1}
-    const int64_t i0 = (int64_t)blockIdx.x * MD_TILE + 2 * threadIdx.x, i1 = i0 + 2 * MD_THREADS;
-    const bool in0 = i0 < n, in1 = i1 < n;
-    const int64_t a0 = in0 ? i0 : 0, a1 = in1 ? i1 : 0;   // clamped (valid) addresses
     double2 s0 = make_double2(0.0, 0.0), s1v = make_double2(0.0, 0.0);
-    for (int cb = 0; cb < ncols; cb += 8) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const double h = u < ncols ? s1[u] : 0.0;
+        s0.x += h * pa[u].x;
+        s0.y += h * pa[u].y;
+        s1v.x += h * pb[u].x;
+        s1v.y += h * pb[u].y;
+    }
+    for (int cb = 8; cb < ncols; cb += 8) {
         double2 a[8], b[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -451,14 +469,8 @@ __global__ void __launch_bounds__(MD_THREADS) k_gm_upd(const T* __restrict__ V, 
             s1v.y += h * b[u].y;
         }
     }
-    if (in0) {
-        const double2 wi = ld2(w + i0);
-        st2(vnext + i0, make_double2((wi.x - s0.x) * ih, (wi.y - s0.y) * ih));
-    }
-    if (in1) {
-        const double2 wi = ld2(w + i1);
-        st2(vnext + i1, make_double2((wi.x - s1v.x) * ih, (wi.y - s1v.y) * ih));
-    }
+    if (in0) st2(vnext + i0, make_double2((wa.x - s0.x) * ih, (wa.y - s0.y) * ih));
+    if (in1) st2(vnext + i1, make_double2((wb.x - s1v.x) * ih, (wb.y - s1v.y) * ih));
 }
 
 // start of a cycle from the partials of <r, r>: beta = ||r||, g = beta e_1,
@@ -1001,7 +1013,18 @@ __global__ void __launch_bounds__(64) k_ahat_fwd_m(int Ne, const int32_t* __rest
     }
 }
 
-// transposed counterpart of k_ahat_fwd_m (layout of k_ahat_tr)
+// transposed counterpart of k_ahat_fwd_m (layout of k_ahat_tr); dynamic LDS
+// of ahat_tr_m_smem<NP>(R) bytes, sized for the R systems of the launch
+template <int NP>
+constexpr size_t ahat_tr_m_row_doubles()
+{
+    return (size_t)3 * (60 / (4 * NP / 2)) * (4 * NP + 1) + 3 * (4 * NP);
+}
+template <int NP>
+inline size_t ahat_tr_m_smem(int R)
+{
+    return sizeof(double) * (size_t)R * ahat_tr_m_row_doubles<NP>();
+}
 template <int NP>
 __global__ void __launch_bounds__(64) k_ahat_tr_m(int Ne, const int32_t* __restrict__ enb, const int8_t* __restrict__ etw,
                                                   const double* __restrict__ Ah, int R, const double* __restrict__ x,
@@ -1012,8 +1035,12 @@ __global__ void __launch_bounds__(64) k_ahat_tr_m(int Ne, const int32_t* __restr
     constexpr int CPR = B / EPL;
     static_assert(60 % CPR == 0, "row groups must tile 60 lanes");
     constexpr int G = 60 / CPR, RPL = (B + G - 1) / G;
-    __shared__ double sp[GM_RMAX][3][G][B + 1];
-    __shared__ double sxr[GM_RMAX][3][B];
+    extern __shared__ double dsm[];
+    // sp[r][f][g][col] and sxr[r][f][i], R systems
+    double* sp = dsm;
+    double* sxr = dsm + (size_t)R * 3 * G * (B + 1);
+    auto SP = [&](int r, int f, int g_, int col) -> double& { return sp[(((size_t)r * 3 + f) * G + g_) * (B + 1) + col]; };
+    auto SX = [&](int r, int f, int i) -> double& { return sxr[((size_t)r * 3 + f) * B + i]; };
     if (st) {
         bool all = true;
         for (int r = 0; r < R; ++r) all = all && st[r].done;
@@ -1040,7 +1067,7 @@ __global__ void __launch_bounds__(64) k_ahat_tr_m(int Ne, const int32_t* __restr
     for (int r = 0; r < R; ++r)
 #pragma unroll
         for (int f = 0; f < 3; ++f)
-            if (nbs[f] >= 0 && lane < B) sxr[r][f][lane] = x[r * sx + (int64_t)nbs[f] * B + lane];
+            if (nbs[f] >= 0 && lane < B) SX(r, f, lane) = x[r * sx + (int64_t)nbs[f] * B + lane];
     __syncthreads();
     for (int r = 0; r < R; ++r)
 #pragma unroll
@@ -1051,14 +1078,14 @@ __global__ void __launch_bounds__(64) k_ahat_tr_m(int Ne, const int32_t* __restr
             for (int k = 0; k < RPL; ++k) {
                 const int i = g + G * k;
                 if (i < B) {
-                    const double xi = sxr[r][f][i];
+                    const double xi = SX(r, f, i);
                     const double* e = reinterpret_cast<const double*>(&v[f][k]);
                     p0 += e[0] * xi;
                     p1 += e[1] * xi;
                 }
             }
-            sp[r][f][g][c * EPL] = p0;
-            sp[r][f][g][c * EPL + 1] = p1;
+            SP(r, f, g, c * EPL) = p0;
+            SP(r, f, g, c * EPL + 1) = p1;
         }
     __syncthreads();
     if (lane < B)
@@ -1068,7 +1095,7 @@ __global__ void __launch_bounds__(64) k_ahat_tr_m(int Ne, const int32_t* __restr
             for (int f = 0; f < 3; ++f) {
                 if (nbs[f] < 0) continue;
 #pragma unroll
-                for (int gg = 0; gg < G; ++gg) acc += sp[r][f][gg][lane];
+                for (int gg = 0; gg < G; ++gg) acc += SP(r, f, gg, lane);
             }
             y[r * sy + (int64_t)K * B + lane] = acc;
         }
