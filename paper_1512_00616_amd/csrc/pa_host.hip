@@ -1891,7 +1891,7 @@ struct Solver final : pa_ctx {
         tstart(PA_K_BLOCKINV, &e);
         k_blockprep<NP><<<Ne, 64, 0, st>>>(Ne, dm.area, dmh, J, c, tPd + (int64_t)s * Isz, tAi + (int64_t)s * Isz,
                                           dstatus);
-        k_form_ahat<NP><<<Ne * 3, 64, 0, st>>>(Ne, dm.enb, J, c, tAi + (int64_t)s * Isz, tAh + (int64_t)s * 3 * Isz);
+        k_form_ahat_mfma<NP><<<Ne * 3, 64, 0, st>>>(Ne, dm.enb, J, c, tAi + (int64_t)s * Isz, tAh + (int64_t)s * 3 * Isz);
         LAUNCHCHK();
         const int64_t n3 = 3 * Isz;
         if (pmode == PA_PREC_FP32)

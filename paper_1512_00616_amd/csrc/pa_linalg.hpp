@@ -641,6 +641,58 @@ __global__ void __launch_bounds__(64) k_blockprep(int Ne, const double* __restri
 
 // Ahat_{K,f} = -c J_{K,1+f} Pinv_nb (zero block when face f is on the boundary);
 // one workgroup per (element, face)
+// Ahat_{K,f} = -c J_{K,nb} P_nb^{-1} on the matrix cores (FP64 MFMA
+// 16x16x4): one wave per product; both factors staged in LDS (J scaled by
+// -c), the 40 x 40 output as 3 x 3 tiles of 16 x 16 (rows and columns past B
+// padded with zeros), B / 4 steps of k each.  Lane layout of the builtin
+// (checked on the device): A[i][k] from lane i + 16 k, B[k][j] from lane
+// j + 16 k, result element (lane / 16 + 4 r, lane % 16) in register r.
+typedef double mf_d4 __attribute__((ext_vector_type(4)));
+template <int NP>
+__global__ void __launch_bounds__(64) k_form_ahat_mfma(int Ne, const int32_t* __restrict__ enb,
+                                                       const double* __restrict__ J, double c,
+                                                       const double* __restrict__ Pinv, double* __restrict__ Ah)
+{
+    constexpr int B = 4 * NP, BB = B * B, T = (B + 15) / 16, KS = B / 4;
+    __shared__ double sj[B][B + 1];
+    __shared__ double sp[B][B + 1];
+    const int K = blockIdx.x / 3, f = blockIdx.x % 3, lane = threadIdx.x;
+    const int nb = enb[3 * K + f];
+    double* dst = Ah + ((int64_t)K * 3 + f) * BB;
+    if (nb < 0) {
+        for (int t = lane; t < BB; t += 64) dst[t] = 0.0;
+        return;
+    }
+    const double* js = J + ((int64_t)K * 4 + 1 + f) * BB;
+    const double* ps = Pinv + (int64_t)nb * BB;
+    for (int t = lane; t < BB; t += 64) {
+        sj[t / B][t % B] = -c * js[t];
+        sp[t / B][t % B] = ps[t];
+    }
+    __syncthreads();
+    const int li = lane % 16, lk = lane / 16;
+    for (int ti = 0; ti < T; ++ti) {
+        const int row = ti * 16 + li;
+        for (int tj = 0; tj < T; ++tj) {
+            const int colb = tj * 16 + li;
+            mf_d4 acc = { 0.0, 0.0, 0.0, 0.0 };
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                const int kk = ks * 4 + lk;
+                const double a = row < B ? sj[row][kk] : 0.0;
+                const double b = colb < B ? sp[kk][colb] : 0.0;
+                acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+            }
+            const int col = tj * 16 + li;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int i = ti * 16 + lk + 4 * r;
+                if (i < B && col < B) dst[i * B + col] = acc[r];
+            }
+        }
+    }
+}
+
 template <int NP>
 __global__ void __launch_bounds__(64) k_form_ahat(int Ne, const int32_t* __restrict__ enb, const double* __restrict__ J,
                                                   double c, const double* __restrict__ Pinv, double* __restrict__ Ah)
