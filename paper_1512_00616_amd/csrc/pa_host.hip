@@ -1019,7 +1019,7 @@ struct Solver final : pa_ctx {
     void dots(const double* Vb, int64_t ldv, int ncols, const double* w, double* h)
     {
         const int nb = (int)mdot_blocks(Nu);
-        k_mdot_part<<<nb, MD_THREADS, 0, st>>>(Vb, ldv, ncols, 0, w, Nu, part, nullptr);
+        k_mdot_part<<<dim3(nb, mdot_chunks(ncols)), MD_THREADS, 0, st>>>(Vb, ldv, ncols, 0, w, Nu, part, nullptr);
         k_mdot_fin<<<1, MD_THREADS, 0, st>>>(part, nb, ncols, hdev);
         LAUNCHCHK();
         HIPCHK(hipMemcpyAsync(h, hdev, sizeof(double) * ncols, hipMemcpyDeviceToHost, st));
@@ -1081,7 +1081,7 @@ struct Solver final : pa_ctx {
                 // second pass; the last column returns |w|^2 for the norm
                 {
                     const int nb = (int)mdot_blocks(Nu);
-                    k_mdot_part<<<nb, MD_THREADS, 0, st>>>(Vb, Nu, j + 1, 1, wk, Nu, part, nullptr);
+                    k_mdot_part<<<dim3(nb, mdot_chunks(j + 2)), MD_THREADS, 0, st>>>(Vb, Nu, j + 1, 1, wk, Nu, part, nullptr);
                     k_mdot_fin<<<1, MD_THREADS, 0, st>>>(part, nb, j + 2, hdev);
                     LAUNCHCHK();
                     HIPCHK(hipMemcpyAsync(h2.data(), hdev, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, st));
@@ -1165,7 +1165,7 @@ struct Solver final : pa_ctx {
                 double* vj = V + (int64_t)j * Nu;
                 ahat(op.Ah, tr, vj, w, skip);
                 // one classical Gram-Schmidt pass; the cycle closes on cancellation
-                k_mdot_part<<<nb, MD_THREADS, 0, st>>>(V, Nu, j + 1, 1, w, Nu, part, gms);
+                k_mdot_part<<<dim3(nb, mdot_chunks(j + 2)), MD_THREADS, 0, st>>>(V, Nu, j + 1, 1, w, Nu, part, gms);
                 k_gm_upd<<<nb, MD_THREADS, 0, st>>>(V, Nu, j, m, w, Nu, part, nb, gms);
                 LAUNCHCHK();
                 if ((j + 1) % GM_CHECK == 0 && j < m - 1) {
@@ -1240,7 +1240,8 @@ struct Solver final : pa_ctx {
             for (int j = 0; j < m; ++j) {
                 float* vj = V32 + (int64_t)j * Nu;
                 ahat_lo(op.Al, tr, vj, w32, skip);
-                k_mdot_part<<<nb, MD_THREADS, 0, st>>>((const float*)V32, Nu, j + 1, 1, (const float*)w32, Nu, part,
+                k_mdot_part<<<dim3(nb, mdot_chunks(j + 2)), MD_THREADS, 0, st>>>((const float*)V32, Nu, j + 1, 1,
+                                                                                  (const float*)w32, Nu, part,
                                                        gms);
                 k_gm_upd<<<nb, MD_THREADS, 0, st>>>((const float*)V32, Nu, j, m, (const float*)w32, Nu, part, nb, gms);
                 LAUNCHCHK();
@@ -1565,7 +1566,8 @@ struct Solver final : pa_ctx {
             for (int j = 0; j < m; ++j) {
                 jlast = j;
                 ahat_m(op.Ah, tr, R, Vm + (int64_t)j * Nu, sV, wm, Nu, gmsm);
-                k_mdot_part<<<g2, MD_THREADS, 0, st>>>(Vm, Nu, j + 1, 1, wm, Nu, partm, gmsm, sV, Nu, sP);
+                k_mdot_part<<<dim3(nb, mdot_chunks(j + 2) * R), MD_THREADS, 0, st>>>(Vm, Nu, j + 1, 1, wm, Nu, partm, gmsm,
+                                                                                     sV, Nu, sP);
                 k_gm_upd<<<g2, MD_THREADS, 0, st>>>(Vm, Nu, j, m, wm, Nu, partm, nb, gmsm, sV, Nu, sP);
                 LAUNCHCHK();
                 if ((j + 1) % GM_CHECK == 0 && j < m - 1) {
@@ -2276,7 +2278,7 @@ struct Solver final : pa_ctx {
                 dots(Vb(r), Nu, j + 1, wk, y.h.data());
                 vupdate(Vb(r), Nu, j + 1, y.h.data(), -1.0, wk);
                 const int nb = (int)mdot_blocks(Nu);
-                k_mdot_part<<<nb, MD_THREADS, 0, st>>>(Vb(r), Nu, j + 1, 1, wk, Nu, part, nullptr);
+                k_mdot_part<<<dim3(nb, mdot_chunks(j + 2)), MD_THREADS, 0, st>>>(Vb(r), Nu, j + 1, 1, wk, Nu, part, nullptr);
                 k_mdot_fin<<<1, MD_THREADS, 0, st>>>(part, nb, j + 2, hdev);
                 LAUNCHCHK();
                 HIPCHK(hipMemcpyAsync(y.h2.data(), hdev, sizeof(double) * (j + 2), hipMemcpyDeviceToHost, st));

@@ -269,19 +269,80 @@ __device__ __forceinline__ void mdot_finish(const double* __restrict__ partial, 
     __syncthreads();
 }
 
-// partial[b][c] of <X_c, w> (c < ncols) and <w, w> (if with_ww).  Several
-// independent systems r = blockIdx.y (right-hand sides sharing an operator)
-// are addressed by the strides sV, sw, sP; system r is skipped when its GMRES
-// state st[r] (optional) is done.
+// Eight-column variant of the wave sums: on exit p[0] of lane l holds the
+// wave total of column (l >> 3) & 7 for lanes with l % 8 == 0 (halving
+// exchanges at offsets 32, 16, 8, then plain sums over the low three bits).
+__device__ __forceinline__ void wave_colsum8(double (&p)[8])
+{
+    const int lane = threadIdx.x & 63;
+#pragma unroll
+    for (int s = 0; s < 3; ++s) {
+        const int k = 4 >> s, o = 32 >> s;
+        const bool up = (lane & o) != 0;
+#pragma unroll
+        for (int c = 0; c < k; ++c) {
+            const double keep = up ? p[c + k] : p[c];
+            const double send = up ? p[c] : p[c + k];
+            p[c] = keep + __shfl_xor(send, o, 64);
+        }
+    }
+    p[0] += __shfl_xor(p[0], 4, 64);
+    p[0] += __shfl_xor(p[0], 2, 64);
+    p[0] += __shfl_xor(p[0], 1, 64);
+}
+
+// partial[b][c] of <X_c, w> (c < ncols) and <w, w> (if with_ww), nc = ncols +
+// with_ww columns in chunks of eight: grid (mdot_blocks(n), chunks x R), one
+// chunk of one system per block, so every chunk's loads are in flight at
+// once.  Systems r (right-hand sides sharing an operator) are addressed by
+// the strides sV, sw, sP; system r is skipped when st[r] (optional) is done.
+__host__ __device__ inline int mdot_chunks(int nc) { return (nc + 7) / 8; }
 template <class T>
 __global__ void __launch_bounds__(MD_THREADS) k_mdot_part(const T* __restrict__ V, int64_t ldv, int ncols,
                                                           int with_ww, const T* __restrict__ w, int64_t n,
                                                           double* __restrict__ partial, const GmState* __restrict__ st,
                                                           int64_t sV = 0, int64_t sw = 0, int64_t sP = 0)
 {
-    const int r = blockIdx.y;
+    __shared__ double sred[MD_THREADS / 64][8];
+    const int nc = ncols + with_ww, nch = mdot_chunks(nc);
+    const int r = blockIdx.y / nch, cb = 8 * (blockIdx.y % nch);
     if (st && st[r].done) return;
-    mdot_partials(V + r * sV, ldv, ncols, with_ww, w + r * sw, n, partial + r * sP);
+    V += r * sV;
+    w += r * sw;
+    partial += r * sP;
+    const int tid = threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * MD_TILE + 2 * tid, i1 = i0 + 2 * MD_THREADS;
+    const bool in0 = i0 < n, in1 = i1 < n;
+    const int64_t a0 = in0 ? i0 : 0, a1 = in1 ? i1 : 0;   // clamped (valid) addresses
+    double2 a[8], b[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int c = cb + u;
+        const T* vc = V + (int64_t)(c < ncols ? c : ncols - 1) * ldv;
+        a[u] = ld2(vc + a0);
+        b[u] = ld2(vc + a1);
+    }
+    double2 w0 = make_double2(0.0, 0.0), w1 = make_double2(0.0, 0.0);
+    if (in0) w0 = ld2(w + i0);
+    if (in1) w1 = ld2(w + i1);
+    const double ww = w0.x * w0.x + w0.y * w0.y + w1.x * w1.x + w1.y * w1.y;
+    double p[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+        const int c = cb + u;
+        const double sdot = a[u].x * w0.x + a[u].y * w0.y + b[u].x * w1.x + b[u].y * w1.y;
+        p[u] = c < ncols ? sdot : (c == ncols && with_ww ? ww : 0.0);
+    }
+    wave_colsum8(p);
+    const int lane = tid & 63, wv = tid >> 6;
+    if ((lane & 7) == 0) sred[wv][lane >> 3] = p[0];
+    __syncthreads();
+    if (tid < 8 && cb + tid < nc) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < MD_THREADS / 64; ++k) s += sred[k][tid];
+        partial[(int64_t)blockIdx.x * nc + cb + tid] = s;
+    }
 }
 
 // out[c] = sum_b partial[b][c]; one block
