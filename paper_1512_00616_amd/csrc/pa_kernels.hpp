@@ -367,6 +367,8 @@ struct JacSmem {
     double D[NQ][4][2][12];                  // volume pointwise Jacobians
 };
 
+typedef double mf_d4 __attribute__((ext_vector_type(4)));   // FP64 MFMA accumulator
+
 template <int P>
 __global__ void __launch_bounds__(320) k_jacobian(DevMesh M, const Ref<P>* __restrict__ R, Phys ph, Motion<double> mo,
                                                   const double* __restrict__ u, const double* __restrict__ gb,
@@ -629,107 +631,116 @@ __global__ void __launch_bounds__(320) k_jacobian(DevMesh M, const Ref<P>* __res
         for (int m = 0; m < 4; ++m) S.E[f][j][m][sd] = Fh[m].d[0];
     }
     __syncthreads();
-    // phase 4: contract into the four blocks of row K.  Every term has the
-    // form  sum_p  phi_a(p) * z_p(m, n, b)  over quadrature points p, with
-    // z_p a short sum of pointwise-Jacobian entries times trial-side
-    // operators.  A thread owns one column (m, n, b) of a block for all
-    // test functions a: it forms z_p once per point and applies it to its
-    // NP accumulators with the test-side values read as LDS broadcasts
-    // (a rank-1 update per point instead of recomputing z_p for every a).
-    // Tasks: the diagonal block's columns, then the same columns of the
-    // three neighbour blocks (similar work), one task per thread at 320.
-    const double w2K = 2.0 * M.area[K];
-    for (int task = tid; task < 2 * 16 * NP; task += nth) {
-        const int cc = task % (16 * NP);
-        const int b = cc % NP, n = (cc / NP) & 3, m = cc / (4 * NP);
-        double* Jrow = J + (int64_t)K * 4 * B * B + m * B + b * 4 + n;   // + s*B*B + a*4*B
-        double acc[NP];
-        if (task >= 16 * NP) goto neighbours;
-        // ---- diagonal block
+    // phase 4: contract into the four blocks of row K on the FP64 matrix
+    // cores.  Every term of a block has the form
+    //   J[a][(m,n,b)] = sum_p  L_p[a] * Z_p[(m,n,b)]
+    // over pseudo-points p (volume point and gradient direction, or face
+    // point): L_p holds the test side (weighted basis or gradient values),
+    // Z_p a short sum of pointwise-Jacobian entries times trial-side
+    // operators.  That is a product (NP x P) x (P x 16 NP): M = test
+    // function a (padded to 16), N = column (m, n, b) in NP tiles of 16,
+    // K = pseudo-points in steps of 4 (v_mfma_f64_16x16x4).  Each lane
+    // forms its A value L_p[a] and its B value Z_p[col] on the fly from LDS.
+    // Lane layout: A[i][k] from lane i + 16 k, B[k][j] from lane j + 16 k,
+    // result (lane / 16 + 4 r, lane % 16) in register r.  Tasks: (block s,
+    // column tile), spread over the waves.
+    {
+        const double w2K = 2.0 * M.area[K];
+        const int wave = tid >> 6, nwaves = nth >> 6, lane = tid & 63;
+        const int li = lane & 15, lk = lane >> 4;
+        // a task is two column tiles of one block: they share the test-side
+        // A values, and their two accumulator chains run side by side
+        constexpr int NT2 = (NP + 1) / 2;
+        for (int task = wave; task < 4 * NT2; task += nwaves) {
+            const int s_ = task / NT2, tile0 = 2 * (task % NT2);
+            const bool two = tile0 + 1 < NP;
+            int bb[2], nn[2], mm[2];
 #pragma unroll
-        for (int a = 0; a < NP; ++a) acc[a] = 0.0;
-        for (int q = 0; q < NQ; ++q) {
-            const double bu = S.Buq[q][b], p0 = S.Psi0[q][b][0], p1 = S.Psi0[q][b][1], w = R->wq[q];
-            const double z0 = w * (S.D[q][m][0][n] * bu + S.D[q][m][0][4 + 2 * n] * p0 + S.D[q][m][0][5 + 2 * n] * p1);
-            const double z1 = w * (S.D[q][m][1][n] * bu + S.D[q][m][1][4 + 2 * n] * p0 + S.D[q][m][1][5 + 2 * n] * p1);
-#pragma unroll
-            for (int a = 0; a < NP; ++a) acc[a] += S.gphq[q][a][0] * z0 + S.gphq[q][a][1] * z1;
-        }
-#pragma unroll
-        for (int a = 0; a < NP; ++a) acc[a] *= w2K;
-        for (int f = 0; f < 3; ++f) {
-            const double len = M.elen[3 * K + f];
-            if (nb[f] >= 0) {
-                const bool KL = K < nb[f];
-                const int L = KL ? K : nb[f], fL = KL ? f : tw[f];
-                const double* N = M.enrm + 2 * (3 * L + fL);
-                const double sg = (KL ? 1.0 : -1.0) * len;
-                for (int j = 0; j < NF; ++j) {
-                    double tt;
-                    if (KL)
-                        tt = S.E[f][j][m][n] * S.BuL[f][j][b] + S.E[f][j][m][8 + 2 * n] * S.PsiL[f][j][b][0] +
-                             S.E[f][j][m][9 + 2 * n] * S.PsiL[f][j][b][1];
-                    else
-                        tt = S.E[f][j][m][4 + n] * S.BuR[f][j][b] +
-                             (S.E[f][j][m][8 + 2 * n] * N[0] + S.E[f][j][m][9 + 2 * n] * N[1]) * S.LRf[f][j][b];
-                    const double z = sg * R->wf[j] * tt;
-                    const double* pa = KL ? R->phf[f][j] : R->phr[f][j];
-#pragma unroll
-                    for (int a = 0; a < NP; ++a) acc[a] -= pa[a] * z;
-                }
-            } else {
-                for (int j = 0; j < NF; ++j) {
-                    const double tt = S.E[f][j][m][n] * S.BuL[f][j][b] + S.E[f][j][m][4 + 2 * n] * S.PsiL[f][j][b][0] +
-                                      S.E[f][j][m][5 + 2 * n] * S.PsiL[f][j][b][1];
-                    const double z = len * R->wf[j] * tt;
-#pragma unroll
-                    for (int a = 0; a < NP; ++a) acc[a] -= R->phf[f][j][a] * z;
-                }
+            for (int t = 0; t < 2; ++t) {
+                const int cc = (tile0 + (two ? t : 0)) * 16 + li;   // B column of this lane
+                bb[t] = cc % NP;
+                nn[t] = (cc / NP) & 3;
+                mm[t] = cc / (4 * NP);
             }
-        }
+            mf_d4 acc0 = { 0.0, 0.0, 0.0, 0.0 }, acc1 = { 0.0, 0.0, 0.0, 0.0 };
+            const int f = s_ - 1;
+            const bool volume = s_ == 0 || (nb[f] >= 0 && K < nb[f]);
+            if (volume) {
+                const double* NK = s_ == 0 ? nullptr : M.enrm + 2 * (3 * K + f);
 #pragma unroll
-        for (int a = 0; a < NP; ++a) Jrow[a * 4 * B] = acc[a];
-        continue;
-    neighbours:
-        // ---- the block of each face neighbour
-        for (int f = 0; f < 3; ++f) {
-            double* Jf = Jrow + (1 + f) * B * B;
+                for (int ks = 0; ks < (2 * NQ + 3) / 4; ++ks) {
+                    const int kk = 4 * ks + lk;
+                    double av = 0.0, bv[2] = { 0.0, 0.0 };
+                    if (kk < 2 * NQ) {
+                        const int q = kk >> 1, d = kk & 1;
+                        if (li < NP) av = w2K * R->wq[q] * S.gphq[q][li][d];
 #pragma unroll
-            for (int a = 0; a < NP; ++a) acc[a] = 0.0;
-            if (nb[f] >= 0) {
-                const bool KL = K < nb[f];
-                if (KL) {
-                    // lifting of this face inside K's volume gradient
-                    const double* NK = M.enrm + 2 * (3 * K + f);
-                    for (int q = 0; q < NQ; ++q) {
-                        const double lr = S.LRv[f][q][b] * R->wq[q];
-                        const double z0 = (S.D[q][m][0][4 + 2 * n] * NK[0] + S.D[q][m][0][5 + 2 * n] * NK[1]) * lr;
-                        const double z1 = (S.D[q][m][1][4 + 2 * n] * NK[0] + S.D[q][m][1][5 + 2 * n] * NK[1]) * lr;
-#pragma unroll
-                        for (int a = 0; a < NP; ++a) acc[a] += S.gphq[q][a][0] * z0 + S.gphq[q][a][1] * z1;
+                        for (int t = 0; t < 2; ++t) {
+                            const int m = mm[t], n = nn[t], b = bb[t];
+                            if (s_ == 0)
+                                bv[t] = S.D[q][m][d][n] * S.Buq[q][b] + S.D[q][m][d][4 + 2 * n] * S.Psi0[q][b][0] +
+                                        S.D[q][m][d][5 + 2 * n] * S.Psi0[q][b][1];
+                            else
+                                bv[t] = (S.D[q][m][d][4 + 2 * n] * NK[0] + S.D[q][m][d][5 + 2 * n] * NK[1]) *
+                                        S.LRv[f][q][b];
+                        }
                     }
-#pragma unroll
-                    for (int a = 0; a < NP; ++a) acc[a] *= w2K;
-                }
-                const int L = KL ? K : nb[f], fL = KL ? f : tw[f];
-                const double* N = M.enrm + 2 * (3 * L + fL);
-                const double sg = (KL ? 1.0 : -1.0) * M.elen[3 * K + f];
-                for (int j = 0; j < NF; ++j) {
-                    double tt;
-                    if (KL)
-                        tt = S.E[f][j][m][4 + n] * S.BuR[f][j][b] +
-                             (S.E[f][j][m][8 + 2 * n] * N[0] + S.E[f][j][m][9 + 2 * n] * N[1]) * S.LRf[f][j][b];
-                    else
-                        tt = S.E[f][j][m][n] * S.BuL[f][j][b] + S.E[f][j][m][8 + 2 * n] * S.PsiL[f][j][b][0] +
-                             S.E[f][j][m][9 + 2 * n] * S.PsiL[f][j][b][1];
-                    const double z = sg * R->wf[j] * tt;
-                    const double* pa = KL ? R->phf[f][j] : R->phr[f][j];
-#pragma unroll
-                    for (int a = 0; a < NP; ++a) acc[a] -= pa[a] * z;
+                    acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[0], acc0, 0, 0, 0);
+                    acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[1], acc1, 0, 0, 0);
                 }
             }
+            // face terms: the three faces of K (diagonal block) or face f
+            const int npts = s_ == 0 ? 3 * NF : (nb[f] >= 0 ? NF : 0);
+            for (int ks = 0; ks < (npts + 3) / 4; ++ks) {
+                const int kk = 4 * ks + lk;
+                double av = 0.0, bv[2] = { 0.0, 0.0 };
+                if (kk < npts) {
+                    const int ff = s_ == 0 ? kk / NF : f, j = s_ == 0 ? kk % NF : kk;
+                    const double len = M.elen[3 * K + ff];
+                    if (nb[ff] >= 0) {
+                        const bool KL = K < nb[ff];
+                        const int L = KL ? K : nb[ff], fL = KL ? ff : tw[ff];
+                        const double* N = M.enrm + 2 * (3 * L + fL);
+                        const double sg = (KL ? 1.0 : -1.0) * len;
+                        // the diagonal block takes K's own trace, a neighbour block the other side's
+                        const bool own = (s_ == 0) == KL;
 #pragma unroll
-            for (int a = 0; a < NP; ++a) Jf[a * 4 * B] = acc[a];
+                        for (int t = 0; t < 2; ++t) {
+                            const int m = mm[t], n = nn[t], b = bb[t];
+                            if (own)
+                                bv[t] = S.E[ff][j][m][n] * S.BuL[ff][j][b] +
+                                        S.E[ff][j][m][8 + 2 * n] * S.PsiL[ff][j][b][0] +
+                                        S.E[ff][j][m][9 + 2 * n] * S.PsiL[ff][j][b][1];
+                            else
+                                bv[t] = S.E[ff][j][m][4 + n] * S.BuR[ff][j][b] +
+                                        (S.E[ff][j][m][8 + 2 * n] * N[0] + S.E[ff][j][m][9 + 2 * n] * N[1]) *
+                                            S.LRf[ff][j][b];
+                        }
+                        if (li < NP) av = -sg * R->wf[j] * (KL ? R->phf[ff][j][li] : R->phr[ff][j][li]);
+                    } else {
+#pragma unroll
+                        for (int t = 0; t < 2; ++t) {
+                            const int m = mm[t], n = nn[t], b = bb[t];
+                            bv[t] = S.E[ff][j][m][n] * S.BuL[ff][j][b] + S.E[ff][j][m][4 + 2 * n] * S.PsiL[ff][j][b][0] +
+                                    S.E[ff][j][m][5 + 2 * n] * S.PsiL[ff][j][b][1];
+                        }
+                        if (li < NP) av = -len * R->wf[j] * R->phf[ff][j][li];
+                    }
+                }
+                acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[0], acc0, 0, 0, 0);
+                acc1 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[1], acc1, 0, 0, 0);
+            }
+#pragma unroll
+            for (int t = 0; t < 2; ++t) {
+                if (t == 1 && !two) break;
+                double* Jb = J + (int64_t)K * 4 * B * B + (int64_t)s_ * B * B + mm[t] * B + bb[t] * 4 + nn[t];
+                const mf_d4& ac = t == 0 ? acc0 : acc1;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int a = lk + 4 * r;
+                    if (a < NP) Jb[a * 4 * B] = ac[r];
+                }
+            }
         }
     }
 }
