@@ -42,7 +42,10 @@ HBM_PEAK_GBS = 8000.0
 # on the 32x96 p=3 workload (FETCH_SIZE and WRITE_SIZE calibrated against a
 # plain copy; profiles/k_ahat_fwd_32x96_p3.md); valid for that kernel as
 # measured, to be re-taken when it changes
-TRAFFIC_BYTES = {"pa::k_ahat_fwd<10, double, double>": 243.1e6}
+TRAFFIC_BYTES = {"pa::k_ahat_fwd<10, double, double, 0>": 243.1e6}
+# the forward apply as launched by the benchmark step: default tile shape
+# (four 16-byte chunks per lane task); pa_config.autotune picks among 1, 2, 4
+FWD_KERNEL = "pa::k_ahat_fwd<10, double, double, 0>"
 
 
 def spmv_bytes(Nr, Nth, p, mat_bytes=8, vec_bytes=8):
@@ -120,6 +123,21 @@ def time_to_gradient(pa, mu):
             "tangent_sweeps": rep.krylov_its, "periodicity": rep.res, "adjoint_krylov": list(arep.krylov_its),
             "qoi": list(q), "dJdmu": dJ.tolist(),
             "floquet_leading": [[float(z.real), float(z.imag)] for z in ritz[:4]]}
+
+
+def apply_tiles(pa, work):
+    """Autotuning of the forward apply's tile shape (chunks of 16 bytes per
+    lane task) on the first stored operator of a short run on the benchmark
+    mesh; the benchmark step itself uses the default shape (4)."""
+    phys = dict(inputs.PHYSICS, T=0.03)
+    s = pa.Solver(autotune=1, **dict(work, Nt=3), **phys)
+    s.set_params(np.zeros(3))
+    s.set_freestream()
+    s.primal_period()
+    q, us = s.tuning()
+    s.close()
+    return {"chosen_chunks_per_task": q, "us_per_launch": dict(zip(("1", "2", "4"), us)),
+            "default_chunks_per_task": 4}
 
 
 def learned(pa, args):
@@ -257,6 +275,7 @@ def main():
         return 0
 
     out, dJ64 = run_step(pa, name, work, mu, args, pa.PREC_FP64)
+    out["apply_tiles"] = apply_tiles(pa, work)
     if not args.no_mixed:
         # the same step with the mixed-precision stage solves (FP64 refinement
         # to the same tolerances): wall time and gradient against the FP64 run
@@ -351,9 +370,9 @@ def run_step(pa, name, work, mu, args, precision):
                    "newton_atol": 1e-10, "outer_krylov_cap": args.krylov, "shoot_eta": 1e-3, "adj_rtol": 1e-8},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": TRAFFIC_BYTES.get("pa::k_ahat_fwd<10, double, double>")
+                     "traffic": TRAFFIC_BYTES.get(FWD_KERNEL)
                      if (work["Nr"], work["Nth"], work["p"]) == (32, 96, 3) else None,
-                     "kernel": "pa::k_ahat_fwd<10, double, double>",
+                     "kernel": FWD_KERNEL,
                      "bytes_per_launch": bytes_spmv, "avg_launch_us": avg_spmv_s * 1e6, "launches": n_spmv},
         # transposed applies: k_ahat_tr<10, double, double> for one right-hand
         # side, k_ahat_tr_m<10> when the two QoIs' adjoints ride together

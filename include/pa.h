@@ -64,6 +64,9 @@ typedef struct pa_config {
     int32_t max_krylov;         /* outer Krylov basis size (shooting, periodic adjoint) */
     int32_t device;             /* HIP device ordinal */
     int32_t precision;          /* stage solves: PA_PREC_FP64, PA_PREC_FP32 or PA_PREC_BF16 */
+    int32_t autotune;           /* 1: time the forward-apply tile shapes on the first stored operator and
+                                   keep the fastest (results may then differ from run to run in the last
+                                   bits); 0: fixed shape (default) */
 } pa_config;
 
 /* Precision of the stage linear solves (Sec. 2.2 eq. dirk, each stage's
@@ -290,6 +293,11 @@ pa_status pa_kernel_time(pa_ctx* ctx, int32_t kernel, double* total_ms, int64_t*
  * (M - dt a_11 J) P^{-1} with P its diagonal blocks (timed with HIP events on
  * the library stream; needs a stored trajectory) */
 pa_status pa_bench_spmv(pa_ctx* ctx, int32_t reps, int32_t transpose, double* avg_ms);
+/* tile shape of the FP64 forward apply: chunks of 16 bytes per lane task
+ * (1, 2 or 4; 0 = built-in default) and, after autotuning, the measured
+ * microseconds per launch of each shape (-1: not valid for this block size,
+ * 0: not measured) */
+pa_status pa_tuning(pa_ctx* ctx, int32_t* fwd_chunks, double fwd_us[3]);
 /* as pa_bench_spmv for the FP32/BF16 copy of the operator with FP32 vectors;
  * PA_ESTATE unless the context was created with precision FP32 or BF16 */
 pa_status pa_bench_spmv_lo(pa_ctx* ctx, int32_t reps, int32_t transpose, double* avg_ms);

@@ -520,6 +520,7 @@ struct pa_ctx {
     virtual void kernel_time(int k, double* ms, int64_t* cnt) = 0;
     virtual double bench_spmv(int reps, int tr) = 0;
     virtual double bench_spmv_lo(int reps, int tr) = 0;
+    virtual void tuning(int32_t* q, double us[3]) = 0;
     virtual double bench_copy(int reps, int64_t* bytes) = 0;
 };
 
@@ -958,12 +959,68 @@ struct Solver final : pa_ctx {
         k_bsr_apply<NP><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, dm.area, dmh, J, x, y, alpha, beta, tr, skip);
         LAUNCHCHK();
     }
+    // forward FP64 apply with the tile shape q (chunks per task; 0 = default)
+    int fwd_q = 0;
+    void launch_fwd(int q, const double* Ah, const double* x, double* y, const int* skip)
+    {
+        if (q == 1 && ahat_fwd_valid<NP, double>(1))
+            k_ahat_fwd<NP, double, double, 1><<<Ne, 64, 0, st>>>(Ne, dm.enb, Ah, x, y, skip);
+        else if (q == 2 && ahat_fwd_valid<NP, double>(2))
+            k_ahat_fwd<NP, double, double, 2><<<Ne, 64, 0, st>>>(Ne, dm.enb, Ah, x, y, skip);
+        else if (q == 4 && ahat_fwd_valid<NP, double>(4)) {
+            if constexpr (ahat_fwd_valid<NP, double>(4))
+                k_ahat_fwd<NP, double, double, 4><<<Ne, 64, 0, st>>>(Ne, dm.enb, Ah, x, y, skip);
+        } else
+            k_ahat_fwd<NP, double, double><<<Ne, 64, 0, st>>>(Ne, dm.enb, Ah, x, y, skip);
+    }
+    // autotune (pa_config.autotune): time each valid tile shape on the first
+    // stored stage operator (after its formation, 10 launches each, HIP
+    // events, scratch vectors of its own) and keep the fastest.  Off by
+    // default: the shape fixes the summation order, so a timing-dependent
+    // choice would make otherwise identical runs differ in the last bits.
+    bool fwd_tuned = false;
+    double fwd_tune_us[3] = { 0, 0, 0 };
+    double *tune_x = nullptr, *tune_y = nullptr;
+    void tune_fwd(const double* Ah)
+    {
+        fwd_tuned = true;
+        if (!tune_x) {
+            tune_x = dalloc<double>(Nu);
+            tune_y = dalloc<double>(Nu);
+            zero(tune_x);
+        }
+        const int qs[3] = { 1, 2, 4 };
+        hipEvent_t a, b;
+        HIPCHK(hipEventCreate(&a));
+        HIPCHK(hipEventCreate(&b));
+        double best = 1e300;
+        for (int k = 0; k < 3; ++k) {
+            const int q = qs[k];
+            const bool ok = q == 1 ? ahat_fwd_valid<NP, double>(1)
+                            : q == 2 ? ahat_fwd_valid<NP, double>(2) : ahat_fwd_valid<NP, double>(4);
+            if (!ok) { fwd_tune_us[k] = -1; continue; }
+            launch_fwd(q, Ah, tune_x, tune_y, nullptr);   // warm
+            HIPCHK(hipEventRecord(a, st));
+            for (int r = 0; r < 10; ++r) launch_fwd(q, Ah, tune_x, tune_y, nullptr);
+            HIPCHK(hipEventRecord(b, st));
+            HIPCHK(hipEventSynchronize(b));
+            float ms = 0;
+            HIPCHK(hipEventElapsedTime(&ms, a, b));
+            fwd_tune_us[k] = ms * 100.0;   // us per launch
+            if (fwd_tune_us[k] < best) { best = fwd_tune_us[k]; fwd_q = q; }
+        }
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        if (verbose)
+            fprintf(stderr, "[pa] forward apply tiles: 1/2/4 chunks per task %.1f/%.1f/%.1f us -> %d\n",
+                    fwd_tune_us[0], fwd_tune_us[1], fwd_tune_us[2], fwd_q);
+    }
     void ahat(const double* Ah, int tr, const double* x, double* y, const int* skip = nullptr)
     {
         hipEvent_t e;
         tstart(tr ? PA_K_SPMV_T : PA_K_SPMV, &e);
         if (tr) k_ahat_tr<NP, double, double><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, Ah, x, y, skip);
-        else k_ahat_fwd<NP, double, double><<<Ne, 64, 0, st>>>(Ne, dm.enb, Ah, x, y, skip);
+        else launch_fwd(fwd_q, Ah, x, y, skip);
         LAUNCHCHK();
         tstop(e);
     }
@@ -1895,6 +1952,7 @@ struct Solver final : pa_ctx {
                                           dstatus);
         k_form_ahat_mfma<NP><<<Ne * 3, 64, 0, st>>>(Ne, dm.enb, J, c, tAi + (int64_t)s * Isz, tAh + (int64_t)s * 3 * Isz);
         LAUNCHCHK();
+        if (cfg.autotune && !fwd_tuned) tune_fwd(tAh + (int64_t)s * 3 * Isz);
         const int64_t n3 = 3 * Isz;
         if (pmode == PA_PREC_FP32)
             k_to_lo<float><<<grid1(n3), 256, 0, st>>>(tAh + s * n3, (float*)tAl + s * n3, n3);
@@ -2536,6 +2594,11 @@ struct Solver final : pa_ctx {
         return ms / reps;
     }
 
+    void tuning(int32_t* q, double us[3]) override
+    {
+        if (q) *q = fwd_q;
+        if (us) for (int k = 0; k < 3; ++k) us[k] = fwd_tune_us[k];
+    }
     double bench_spmv_lo(int reps, int tr) override
     {
         if (!have_traj) raise(PA_ESTATE, "no trajectory");
@@ -2625,6 +2688,7 @@ void pa_default_config(pa_config* c)
     c->newton_atol = 1e-10; c->newton_maxit = 20;
     c->max_krylov = 100;
     c->precision = PA_PREC_FP64;
+    c->autotune = 0;
     c->device = 0;
 }
 
@@ -2928,6 +2992,11 @@ pa_status pa_bench_copy(pa_ctx* c, int32_t reps, double* avg, int64_t* bytes)
         *avg = c->bench_copy(reps, bytes);
     });
 }
+pa_status pa_tuning(pa_ctx* c, int32_t* fwd_chunks, double fwd_us[3])
+{
+    return guard(c, [&] { c->tuning(fwd_chunks, fwd_us); });
+}
+
 pa_status pa_bench_spmv_lo(pa_ctx* c, int32_t reps, int32_t tr, double* avg)
 {
     return guard(c, [&] {

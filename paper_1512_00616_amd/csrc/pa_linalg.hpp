@@ -903,7 +903,16 @@ constexpr int fwd_chunks_per_task()
     return (8 % EPL == 0 && B % 8 == 0) ? 8 / EPL : (B % (2 * EPL) == 0 && 2 * EPL <= 8 ? 2 : 1);
 }
 
-template <int NP, class TM, class TV>
+// tile shape of the forward apply: chunks per task Q (0 = the default above);
+// a context times the valid shapes on its first stored operator and keeps
+// the fastest (ahat_fwd_valid tells which Q fit the block size)
+template <int NP, class TM>
+constexpr bool ahat_fwd_valid(int Q)
+{
+    return (4 * NP) % (int)(16 / sizeof(TM) * Q) == 0 && (int)(16 / sizeof(TM)) * Q <= 8;
+}
+
+template <int NP, class TM, class TV, int QT = 0>
 __global__ void __launch_bounds__(64) k_ahat_fwd(int Ne, const int32_t* __restrict__ enb, const TM* __restrict__ Ah,
                                                  const TV* __restrict__ x, TV* __restrict__ y,
                                                  const int* __restrict__ skip)
@@ -911,7 +920,7 @@ __global__ void __launch_bounds__(64) k_ahat_fwd(int Ne, const int32_t* __restri
     constexpr int B = 4 * NP, BB = B * B;
     constexpr int EPL = 16 / sizeof(TM);              // entries per 16-byte chunk
     static_assert(B % EPL == 0, "a chunk must not straddle rows");
-    constexpr int Q = fwd_chunks_per_task<B, EPL>();  // chunks per task
+    constexpr int Q = QT > 0 ? QT : fwd_chunks_per_task<B, EPL>();  // chunks per task
     constexpr int EPT = Q * EPL;                      // entries per task
     static_assert(B % EPT == 0, "a task must not straddle rows");
     constexpr int H = BB / EPT, TPR = B / EPT;        // tasks per block / per row

@@ -22,7 +22,7 @@ EXPORTED = [
     "pa_ws_train", "pa_ws_predict", "pa_ws_shoot", "pa_ws_save", "pa_ws_load", "pa_dbg_mlp", "pa_tangent_sweep",
     "pa_adjoint_sweep", "pa_dbg_gbar", "pa_dbg_dgbar", "pa_dbg_residual", "pa_dbg_jacobian", "pa_dbg_dr_dmu",
     "pa_dbg_qoi", "pa_dbg_bsr_apply", "pa_dbg_blockinv", "pa_dbg_stage_solve", "pa_dbg_traj", "pa_set_timing",
-    "pa_kernel_time", "pa_bench_spmv", "pa_bench_spmv_lo", "pa_bench_copy",
+    "pa_kernel_time", "pa_bench_spmv", "pa_bench_spmv_lo", "pa_bench_copy", "pa_tuning",
 ]
 
 
@@ -34,7 +34,7 @@ class pa_config(C.Structure):
         ("T", C.c_double), ("r_blend0", C.c_double), ("r_blend1", C.c_double),
         ("wall_is_farfield", C.c_int32), ("gmres_restart", C.c_int32), ("lin_rtol", C.c_double),
         ("newton_atol", C.c_double), ("newton_maxit", C.c_int32), ("max_krylov", C.c_int32),
-        ("device", C.c_int32), ("precision", C.c_int32),
+        ("device", C.c_int32), ("precision", C.c_int32), ("autotune", C.c_int32),
     ]
 
 
@@ -128,6 +128,7 @@ def lib():
             "pa_kernel_time": [P, C.c_int32, P, P],
             "pa_bench_spmv": [P, C.c_int32, C.c_int32, P],
             "pa_bench_spmv_lo": [P, C.c_int32, C.c_int32, P],
+            "pa_tuning": [P, P, P],
             "pa_bench_copy": [P, C.c_int32, P, P],
         }
         for fn, args in sig.items():
@@ -422,6 +423,13 @@ class Solver:
         ms = C.c_double()
         self._chk(lib().pa_bench_spmv(self._c, reps, int(transpose), C.byref(ms)))
         return ms.value
+
+    def tuning(self):
+        """(chunks per task of the forward apply, [us per launch for 1, 2, 4])"""
+        q = np.zeros(1, dtype=np.int32)
+        us = np.zeros(3)
+        self._chk(lib().pa_tuning(self._c, _ptr(q), _ptr(us)))
+        return int(q[0]), us.tolist()
 
     def bench_spmv_lo(self, reps=50, transpose=False):
         ms = C.c_double()
