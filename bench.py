@@ -42,7 +42,7 @@ HBM_PEAK_GBS = 8000.0
 # on the 32x96 p=3 workload (FETCH_SIZE and WRITE_SIZE calibrated against a
 # plain copy; profiles/k_ahat_fwd_32x96_p3.md); valid for that kernel as
 # measured, to be re-taken when it changes
-TRAFFIC_BYTES = {"pa::k_ahat_fwd<10, double, double, 0>": 243.1e6}
+TRAFFIC_BYTES = {"pa::k_ahat_fwd<10, double, double, 0>": 243.2e6}
 # the forward apply as launched by the benchmark step: default tile shape
 # (four 16-byte chunks per lane task); pa_config.autotune picks among 1, 2, 4
 FWD_KERNEL = "pa::k_ahat_fwd<10, double, double, 0>"
