@@ -147,6 +147,25 @@ pa_status pa_shoot(pa_ctx* ctx, double tol, double eta, int32_t maxit, pa_shoot_
  * the last period.  The stored trajectory is invalidated. */
 pa_status pa_fixed_point(pa_ctx* ctx, int32_t periods, double* res);
 
+/* Shooting as the unconstrained minimisation of j(u0) = 1/2 ||u^(Nt)(u0) -
+ * u0||_2^2 (Sec. 2.3 eq. opt-obj), the gradient-based alternative to Alg. 1
+ * and 2: memory = 0 is steepest descent, memory = 1..32 L-BFGS with that
+ * many correction pairs.  Each iterate's gradient costs one backward
+ * (adjoint) sweep (eq. uns-disc-adj-dirk started from lam^(Nt) = u^(Nt) -
+ * u0, gradient lam^(0) + u0 - u^(Nt)); steps are accepted by backtracking
+ * (alpha = 1, 1/2, ..., 1/2^15) on sufficient decrease of j.  Stops at
+ * ||u^(Nt) - u0||_2 <= tol.  The report reuses pa_shoot_report:
+ * newton_its = iterations, krylov_its = backward sweeps, primal_sweeps,
+ * res0 / res.  PA_EINVAL for tol <= 0, memory outside 0..32 or maxit < 0;
+ * PA_ENOCONV after maxit iterations or a failed line search, leaving the
+ * last accepted iterate (with its trajectory) and the report. */
+pa_status pa_shoot_descent(pa_ctx* ctx, double tol, int32_t memory, int32_t maxit, pa_shoot_report* rep);
+
+/* grad[Nu] (may be NULL) = dj/du0 of j(u0) above at the current u0 from its
+ * stored trajectory (one backward sweep), *j (may be NULL) = j(u0).
+ * PA_ESTATE without a trajectory. */
+pa_status pa_periodicity_gradient(pa_ctx* ctx, double* grad, double* j);
+
 /* Floquet multipliers (eigenvalues of the flow-map Jacobian Phi of Sec. 2.3)
  * about the stored trajectory, e.g. a periodic one after pa_shoot: k steps
  * of Arnoldi with tangent sweeps from a seeded random start (splitmix64),
@@ -288,6 +307,13 @@ enum {
  * timing was switched on and the sampled mean duration times that count */
 pa_status pa_set_timing(pa_ctx* ctx, int32_t on);
 pa_status pa_kernel_time(pa_ctx* ctx, int32_t kernel, double* total_ms, int64_t* launches);
+/* of those launches, the stage-operator applies (PA_K_SPMV, PA_K_SPMV_T,
+ * PA_K_SPMV_LO) that returned at once without work: GMRES enqueues several
+ * iterations ahead of its host-side convergence check, and an apply whose
+ * systems have all converged exits on entry.  Bytes moved by a kernel are
+ * its per-launch bytes times (launches - skipped).  0 for other kernels;
+ * reset by pa_set_timing.  PA_EINVAL for a bad id or a NULL output. */
+pa_status pa_kernel_skipped(pa_ctx* ctx, int32_t kernel, int64_t* skipped);
 /* averaged over reps launches of the preconditioned stage-operator apply
  * y = Ahat x (transposed: Ahat^T x) of the stored first stage, Ahat =
  * (M - dt a_11 J) P^{-1} with P its diagonal blocks (timed with HIP events on

@@ -498,6 +498,8 @@ struct pa_ctx {
     virtual void primal_period(double qoi[2], double* res) = 0;
     virtual void shoot(double tol, double eta, int maxit, pa_shoot_report* rep) = 0;
     virtual void fixed_point(int periods, double* res) = 0;
+    virtual void shoot_descent(double tol, int memory, int maxit, pa_shoot_report* rep) = 0;
+    virtual double periodicity_gradient(double* grad) = 0;
     virtual int floquet(int k, uint64_t seed, double* re, double* im, double* hsub) = 0;
     virtual void adjoint_gradient(double rtol, double qoi[2], double dJ[6], pa_adjoint_report* rep) = 0;
     virtual void tangent_gradient(double rtol, double dJ[6], int32_t its[3]) = 0;
@@ -518,6 +520,7 @@ struct pa_ctx {
     virtual void dbg_traj(int which, int n, int i, double* out) = 0;
     virtual void set_timing(bool on) = 0;
     virtual void kernel_time(int k, double* ms, int64_t* cnt) = 0;
+    virtual int64_t kernel_skipped(int k) = 0;
     virtual double bench_spmv(int reps, int tr) = 0;
     virtual double bench_spmv_lo(int reps, int tr) = 0;
     virtual void tuning(int32_t* q, double us[3]) = 0;
@@ -843,6 +846,13 @@ struct Solver final : pa_ctx {
     // sample of the launch durations with little host overhead)
     static constexpr int TSTRIDE = 8;
     int64_t tseen[PA_K_COUNT] = { 0 };
+    // launches that returned at once because their GMRES system had already
+    // converged (an apply enqueued ahead of the host's convergence check)
+    int64_t kskip[PA_K_COUNT] = { 0 };
+    void tskip(int k, int64_t n)
+    {
+        if (timing) kskip[k] += n;
+    }
     void tstart(int k, hipEvent_t* out)
     {
         *out = nullptr;
@@ -882,7 +892,7 @@ struct Solver final : pa_ctx {
     {
         harvest();
         timing = on;
-        for (int k = 0; k < PA_K_COUNT; ++k) { ktime[k] = 0; kcount[k] = 0; tseen[k] = 0; }
+        for (int k = 0; k < PA_K_COUNT; ++k) { ktime[k] = 0; kcount[k] = 0; tseen[k] = 0; kskip[k] = 0; }
     }
     void kernel_time(int k, double* ms, int64_t* cnt) override
     {
@@ -896,6 +906,11 @@ struct Solver final : pa_ctx {
         double avg = kcount[k] ? ktime[k] / (double)kcount[k] : 0.0;
         if (ms) *ms = avg * (double)tseen[k];
         if (cnt) *cnt = tseen[k];
+    }
+    int64_t kernel_skipped(int k) override
+    {
+        if (k < 0 || k >= PA_K_COUNT) raise(PA_EINVAL, "bad kernel id %d", k);
+        return kskip[k];
     }
 
     // ---------------------------------------------------------------- motion
@@ -1217,10 +1232,11 @@ struct Solver final : pa_ctx {
             k_mdot_part<<<nb, MD_THREADS, 0, st>>>(r, 0, 1, 0, r, Nu, part, nullptr);
             k_gm_begin<<<nb, MD_THREADS, 0, st>>>(r, V, Nu, part, nb, GmTol{ { tol } }, gms);
             LAUNCHCHK();
-            int pending = -1, slot = 0;
+            int pending = -1, slot = 0, launched = 0;
             for (int j = 0; j < m; ++j) {
                 double* vj = V + (int64_t)j * Nu;
                 ahat(op.Ah, tr, vj, w, skip);
+                ++launched;
                 // one classical Gram-Schmidt pass; the cycle closes on cancellation
                 k_mdot_part<<<dim3(nb, mdot_chunks(j + 2)), MD_THREADS, 0, st>>>(V, Nu, j + 1, 1, w, Nu, part, gms);
                 k_gm_upd<<<nb, MD_THREADS, 0, st>>>(V, Nu, j, m, w, Nu, part, nb, gms);
@@ -1250,6 +1266,7 @@ struct Solver final : pa_ctx {
             const double rn = norm(r);   // synchronises: hstat[2] is valid below
             const bool done = hstat[2].done != 0;
             total += done ? hstat[2].its : m;
+            tskip(tr ? PA_K_SPMV_T : PA_K_SPMV, launched - (done ? hstat[2].its : m));
             if (done && !std::isfinite(hstat[2].res)) raise(PA_ENUMERIC, "NaN in stage GMRES");
             if (!std::isfinite(rn)) raise(PA_ENUMERIC, "NaN in stage GMRES");
             if (done && rn <= 2.0 * tol) break;
@@ -1293,10 +1310,11 @@ struct Solver final : pa_ctx {
             k_gm_begin<<<nb, MD_THREADS, 0, st>>>(r32, V32, Nu, part, nb, GmTol{ { std::max(tol / rn, floor_red) } },
                                                   gms);
             LAUNCHCHK();
-            int pending = -1, slot = 0;
+            int pending = -1, slot = 0, launched = 0;
             for (int j = 0; j < m; ++j) {
                 float* vj = V32 + (int64_t)j * Nu;
                 ahat_lo(op.Al, tr, vj, w32, skip);
+                ++launched;
                 k_mdot_part<<<dim3(nb, mdot_chunks(j + 2)), MD_THREADS, 0, st>>>((const float*)V32, Nu, j + 1, 1,
                                                                                   (const float*)w32, Nu, part,
                                                        gms);
@@ -1323,6 +1341,7 @@ struct Solver final : pa_ctx {
             lincomb(1.0, b, -1.0, r, r);
             rn = norm(r);   // synchronises: hstat[2] is valid below
             total += hstat[2].done ? hstat[2].its : m;
+            tskip(PA_K_SPMV_LO, launched - (hstat[2].done ? hstat[2].its : m));
             if (!std::isfinite(rn) || !std::isfinite(hstat[2].res)) raise(PA_ENUMERIC, "NaN in stage GMRES");
             if (rn <= tol) break;
             if (total >= maxit)
@@ -1640,7 +1659,6 @@ struct Solver final : pa_ctx {
                     pending = 0;
                 }
             }
-            (void)jlast;
             k_gm_solve<<<R, 256, 0, st>>>(m, gmsm);
             k_gm_combine<<<dim3(grid1(Nu), R), 256, 0, st>>>(Vm, Nu, m, wm, Nu, gmsm, sV, Nu);
             LAUNCHCHK();
@@ -1661,6 +1679,8 @@ struct Solver final : pa_ctx {
                 all = all && acc[r];
             }
             total += cyc;
+            // the applies of the cycle return at once when every system is done
+            tskip(tr ? PA_K_SPMV_T : PA_K_SPMV, jlast + 1 - cyc);
             if (!all && total >= maxit) raise(PA_ENOCONV, "stage GMRES (%d systems) did not converge in %d iterations", R, total);
         }
         for (int r = 0; r < R; ++r) {
@@ -2247,6 +2267,167 @@ struct Solver final : pa_ctx {
             if (verbose) fprintf(stderr, "[pa] fixed-point period %d |R| = %.3e\n", k + 1, res);
         }
         if (res_out) *res_out = res;
+    }
+
+    // Gradient of j(u0) = 1/2 ||u^(Nt)(u0) - u0||^2 (Sec. 2.3 eq. opt-obj) on
+    // the stored trajectory: the backward sweep started from lam^(Nt) = R =
+    // u^(Nt) - u0 returns lam^(0) = Phi^T R, and dj/du0 = lam^(0) - R (eq.
+    // funcl-grad-nosens-dirk).  R and g are device vectors; returns j.
+    double periodicity_grad_dev(double* R, double* g)
+    {
+        if (!have_traj) raise(PA_ESTATE, "no trajectory (run pa_primal_period first)");
+        lincomb(1.0, tu + (int64_t)Nt * Nu, -1.0, u0, R);
+        adjoint(R, -1, g, nullptr);
+        axpby(-1.0, R, 1.0, g);
+        const double rn = norm(R);
+        return 0.5 * rn * rn;
+    }
+    static constexpr int DS_MAXMEM = 32;
+    double *ds_R = nullptr, *ds_g = nullptr, *ds_d = nullptr, *ds_u = nullptr, *ds_q = nullptr, *ds_S = nullptr,
+           *ds_Y = nullptr;
+    int ds_mem = -1;
+    void ensure_descent(int memory)
+    {
+        if (!ds_R) {
+            ds_R = dalloc<double>(Nu);
+            ds_g = dalloc<double>(Nu);
+            ds_d = dalloc<double>(Nu);
+            ds_u = dalloc<double>(Nu);
+            ds_q = dalloc<double>(Nu);
+        }
+        if (memory > ds_mem) {
+            ds_S = dalloc<double>((int64_t)std::max(memory, 1) * Nu);
+            ds_Y = dalloc<double>((int64_t)std::max(memory, 1) * Nu);
+            ds_mem = memory;
+        }
+    }
+    double periodicity_gradient(double* grad) override
+    {
+        ensure_descent(0);
+        const double j = periodicity_grad_dev(ds_R, ds_g);
+        if (grad) d2h(grad, ds_g, sizeof(double) * Nu);
+        return j;
+    }
+    double dot1(const double* a, const double* b)
+    {
+        double v;
+        dots(a, Nu, 1, b, &v);
+        return v;
+    }
+
+    // Shooting as unconstrained minimisation of j(u0) (Sec. 2.3, the
+    // gradient-based alternative to Alg. 1 and 2): steepest descent
+    // (memory 0) or L-BFGS with `memory` correction pairs.  Every iterate
+    // costs one backward sweep for its gradient.  The step u0 + alpha d is
+    // accepted when its primal period succeeds and j falls by at least
+    // 1e-4 alpha |g^T d| (alpha = 1, 1/2, ..., 1/2^15).  The L-BFGS direction
+    // is the two-loop recursion over the stored pairs (s, y) = (step,
+    // gradient change), newest first, with the initial matrix s^T y / y^T y I
+    // of the newest pair; a pair enters only when s^T y > 0, and a direction
+    // that is not downhill restarts from steepest descent.  With Phi = 0 the
+    // unit steepest-descent step is one fixed-point period.
+    void shoot_descent(double tol, int memory, int maxit, pa_shoot_report* rep) override
+    {
+        double t0 = now_ms();
+        pa_shoot_report r{};
+        cnt_newton = cnt_gmres = 0;
+        auto finish = [&]() {
+            r.stage_newton_its = (int32_t)cnt_newton;
+            r.stage_gmres_its = cnt_gmres;
+            r.ms = now_ms() - t0;
+            if (rep) *rep = r;
+        };
+        ensure_descent(memory);
+        double *R = ds_R, *g = ds_g, *d = ds_d, *us = ds_u, *q = ds_q;
+        auto S = [&](int i) { return ds_S + (int64_t)i * Nu; };
+        auto Y = [&](int i) { return ds_Y + (int64_t)i * Nu; };
+        std::vector<double> rho(std::max(memory, 1)), al(std::max(memory, 1));
+        int npair = 0, newest = -1;
+        double qoi[2], res;
+        primal_sweep(qoi, &res);
+        ++r.primal_sweeps;
+        r.res0 = r.res = res;
+        double j = periodicity_grad_dev(R, g);
+        ++r.krylov_its;
+        while (!(res <= tol)) {
+            if (r.newton_its >= maxit) {
+                finish();
+                raise(PA_ENOCONV, "descent shooting did not converge: |R| = %.3e after %d iterations", res,
+                      r.newton_its);
+            }
+            if (npair == 0) {
+                lincomb(-1.0, g, 0.0, g, d);
+            } else {
+                copy(g, q);
+                for (int k = 0; k < npair; ++k) {   // newest to oldest
+                    const int i = (newest - k + memory) % memory;
+                    al[i] = rho[i] * dot1(S(i), q);
+                    axpby(-al[i], Y(i), 1.0, q);
+                }
+                const double gam = dot1(S(newest), Y(newest)) / dot1(Y(newest), Y(newest));
+                lincomb(-gam, q, 0.0, q, d);   // d = -H0 q; the second loop acts on -d
+                for (int k = npair - 1; k >= 0; --k) {   // oldest to newest
+                    const int i = (newest - k + memory) % memory;
+                    const double beta = -rho[i] * dot1(Y(i), d);
+                    axpby(-(al[i] - beta), S(i), 1.0, d);
+                }
+            }
+            double gd = dot1(g, d);
+            if (!(gd < 0.0)) {
+                npair = 0;
+                newest = -1;
+                lincomb(-1.0, g, 0.0, g, d);
+                gd = dot1(g, d);
+            }
+            copy(u0, us);
+            double alpha = 1.0, rnew = 0.0;
+            bool ok = false;
+            for (int trial = 0; trial < 16; ++trial, alpha *= 0.5) {
+                lincomb(1.0, us, alpha, d, u0);
+                try {
+                    primal_sweep(qoi, &rnew);
+                    ++r.primal_sweeps;
+                    ok = 0.5 * rnew * rnew <= j + 1e-4 * alpha * gd;
+                } catch (const PaError& e) {
+                    if (e.code != PA_ENOCONV && e.code != PA_ENUMERIC) throw;
+                    ++r.primal_sweeps;
+                    ok = false;
+                }
+                if (ok) break;
+            }
+            if (!ok) {
+                copy(us, u0);
+                primal_sweep(qoi, &res);
+                ++r.primal_sweeps;
+                finish();
+                raise(PA_ENOCONV, "descent shooting line search failed at |R| = %.3e", res);
+            }
+            const int slot = memory > 0 ? (newest + 1) % memory : 0;
+            if (memory > 0) {
+                lincomb(alpha, d, 0.0, d, S(slot));
+                lincomb(-1.0, g, 0.0, g, Y(slot));
+            }
+            j = periodicity_grad_dev(R, g);
+            ++r.krylov_its;
+            res = rnew;
+            r.res = res;
+            ++r.newton_its;
+            if (memory > 0) {
+                axpby(1.0, g, 1.0, Y(slot));   // y = g_new - g_old
+                const double sy = dot1(S(slot), Y(slot));
+                if (sy > 0.0) {
+                    rho[slot] = 1.0 / sy;
+                    newest = slot;
+                    npair = std::min(npair + 1, memory);
+                } else if (npair == memory) {
+                    --npair;   // the slot held the oldest pair, now overwritten
+                }
+            }
+            if (verbose)
+                fprintf(stderr, "[pa] descent it %d alpha %.3g |R| = %.3e  %.1f s\n", r.newton_its, alpha, res,
+                        (now_ms() - t0) / 1e3);
+        }
+        finish();
     }
 
     // Outer matrix-free GMRES on (Phi - I) (tangent_op) or (Phi^T - I), zero
@@ -2894,6 +3075,20 @@ pa_status pa_shoot(pa_ctx* c, double tol, double eta, int32_t maxit, pa_shoot_re
         c->shoot(tol, eta, maxit, rep);
     });
 }
+pa_status pa_shoot_descent(pa_ctx* c, double tol, int32_t memory, int32_t maxit, pa_shoot_report* rep)
+{
+    return guard(c, [&] {
+        if (!(tol > 0) || memory < 0 || memory > 32 || maxit < 0) raise(PA_EINVAL, "bad descent options");
+        c->shoot_descent(tol, memory, maxit, rep);
+    });
+}
+pa_status pa_periodicity_gradient(pa_ctx* c, double* grad, double* j)
+{
+    return guard(c, [&] {
+        const double v = c->periodicity_gradient(grad);
+        if (j) *j = v;
+    });
+}
 pa_status pa_floquet(pa_ctx* c, int32_t k, uint64_t seed, double* re, double* im, int32_t* nritz, double* hsub)
 {
     return guard(c, [&] {
@@ -2984,6 +3179,13 @@ pa_status pa_set_timing(pa_ctx* c, int32_t on) { return guard(c, [&] { c->set_ti
 pa_status pa_kernel_time(pa_ctx* c, int32_t k, double* ms, int64_t* cnt)
 {
     return guard(c, [&] { c->kernel_time(k, ms, cnt); });
+}
+pa_status pa_kernel_skipped(pa_ctx* c, int32_t k, int64_t* skipped)
+{
+    return guard(c, [&] {
+        if (!skipped) raise(PA_EINVAL, "null output");
+        *skipped = c->kernel_skipped(k);
+    });
 }
 pa_status pa_bench_copy(pa_ctx* c, int32_t reps, double* avg, int64_t* bytes)
 {

@@ -14,15 +14,16 @@ LIB_PATH = os.path.join(_HERE, "libpa.so")
 
 PA_OK, PA_EINVAL, PA_ENOMEM, PA_EDEVICE, PA_ENOCONV, PA_ENUMERIC, PA_ESTATE = 0, -1, -2, -3, -4, -5, -6
 PA_K_SPMV, PA_K_PRECOND, PA_K_JACOBIAN, PA_K_RESIDUAL, PA_K_BLOCKINV, PA_K_SPMV_LO, PA_K_SPMV_T = range(7)
+PA_K_COUNT = 7
 
 EXPORTED = [
     "pa_default_config", "pa_create", "pa_destroy", "pa_last_error", "pa_num_dofs", "pa_num_elems",
     "pa_block_size", "pa_device_bytes", "pa_get_mesh", "pa_set_params", "pa_set_state", "pa_set_freestream",
-    "pa_get_state", "pa_primal_period", "pa_shoot", "pa_fixed_point", "pa_floquet", "pa_adjoint_gradient", "pa_tangent_gradient", "pa_batch_gradients",
+    "pa_get_state", "pa_primal_period", "pa_shoot", "pa_fixed_point", "pa_shoot_descent", "pa_periodicity_gradient", "pa_floquet", "pa_adjoint_gradient", "pa_tangent_gradient", "pa_batch_gradients",
     "pa_ws_train", "pa_ws_predict", "pa_ws_shoot", "pa_ws_save", "pa_ws_load", "pa_dbg_mlp", "pa_tangent_sweep",
     "pa_adjoint_sweep", "pa_dbg_gbar", "pa_dbg_dgbar", "pa_dbg_residual", "pa_dbg_jacobian", "pa_dbg_dr_dmu",
     "pa_dbg_qoi", "pa_dbg_bsr_apply", "pa_dbg_blockinv", "pa_dbg_stage_solve", "pa_dbg_traj", "pa_set_timing",
-    "pa_kernel_time", "pa_bench_spmv", "pa_bench_spmv_lo", "pa_bench_copy", "pa_tuning",
+    "pa_kernel_time", "pa_kernel_skipped", "pa_bench_spmv", "pa_bench_spmv_lo", "pa_bench_copy", "pa_tuning",
 ]
 
 
@@ -110,6 +111,8 @@ def lib():
             "pa_ws_load": [P, C.c_char_p],
             "pa_dbg_mlp": [C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P],
             "pa_fixed_point": [P, C.c_int32, P],
+            "pa_shoot_descent": [P, C.c_double, C.c_int32, C.c_int32, P],
+            "pa_periodicity_gradient": [P, P, P],
             "pa_adjoint_gradient": [P, C.c_double, P, P, P],
             "pa_tangent_gradient": [P, C.c_double, P, P],
             "pa_tangent_sweep": [P, P, P],
@@ -126,6 +129,7 @@ def lib():
             "pa_dbg_traj": [P, C.c_int32, C.c_int32, C.c_int32, P],
             "pa_set_timing": [P, C.c_int32],
             "pa_kernel_time": [P, C.c_int32, P, P],
+            "pa_kernel_skipped": [P, C.c_int32, P],
             "pa_bench_spmv": [P, C.c_int32, C.c_int32, P],
             "pa_bench_spmv_lo": [P, C.c_int32, C.c_int32, P],
             "pa_tuning": [P, P, P],
@@ -292,6 +296,24 @@ class Solver:
         self._chk(lib().pa_fixed_point(self._c, periods, _ptr(r)))
         return float(r[0])
 
+    def shoot_descent(self, tol=1e-8, memory=5, maxit=200, allow_unconverged=False):
+        """Shooting by minimising 1/2 ||u^(Nt) - u0||^2: steepest descent
+        (memory 0) or L-BFGS.  Report fields: newton_its = iterations,
+        krylov_its = backward sweeps, primal_sweeps, res0, res."""
+        rep = pa_shoot_report()
+        rc = lib().pa_shoot_descent(self._c, tol, memory, maxit, C.byref(rep))
+        if rc == PA_ENOCONV and allow_unconverged and rep.primal_sweeps > 0:
+            return rep
+        self._chk(rc)
+        return rep
+
+    def periodicity_gradient(self):
+        """(dj/du0, j) of j = 1/2 ||u^(Nt) - u0||^2 at the stored trajectory"""
+        g = np.zeros(self.Nu)
+        j = C.c_double()
+        self._chk(lib().pa_periodicity_gradient(self._c, _ptr(g), C.byref(j)))
+        return g, j.value
+
     def adjoint_gradient(self, rtol=1e-8):
         q = np.zeros(2)
         g = np.zeros(6)
@@ -412,6 +434,13 @@ class Solver:
         cnt = C.c_int64()
         self._chk(lib().pa_kernel_time(self._c, k, C.byref(ms), C.byref(cnt)))
         return ms.value, cnt.value
+
+    def kernel_skipped(self, k):
+        """launches of kernel k (since set_timing(True)) that returned at once
+        because their GMRES systems had already converged"""
+        n = C.c_int64()
+        self._chk(lib().pa_kernel_skipped(self._c, k, C.byref(n)))
+        return n.value
 
     def bench_copy(self, reps=20):
         ms = C.c_double()

@@ -1,0 +1,107 @@
+"""Gradient-based shooting (Sec. 2.3, minimisation of j(u0) = 1/2 ||u^(Nt)
+- u0||^2 by steepest descent or L-BFGS): the adjoint gradient of j against
+central differences of j itself, and the descent iterations against the
+orbit found by Newton-Krylov shooting."""
+import numpy as np
+import pytest
+
+from paper_1512_00616_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+TINY = dict(Nr=2, Nth=6, p=1, Nt=8, lin_rtol=1e-13, newton_atol=1e-12)
+
+
+def j_at(s, u):
+    s.set_state(u)
+    _, res = s.primal_period()
+    return 0.5 * res * res
+
+
+def test_periodicity_gradient_matches_central_differences():
+    from paper_1512_00616_amd import pa
+    s = pa.Solver(**TINY)
+    s.set_params(np.array(inputs.MU_NOMINAL))
+    s.set_freestream(inputs.perturbation(s.Nu, seed=4, sigma=1e-2))
+    u0 = s.get_state(0)
+    with pytest.raises(pa.PaError):
+        s.periodicity_gradient()                 # no trajectory yet
+    _, res = s.primal_period()
+    g, j = s.periodicity_gradient()
+    assert abs(j - 0.5 * res * res) <= 1e-14 * j
+    # the stored trajectory is untouched: the same gradient again
+    g2, _ = s.periodicity_gradient()
+    assert np.array_equal(g, g2)
+    rng = inputs.rng(5)
+    h = 1e-5
+    for _ in range(3):
+        v = rng.standard_normal(s.Nu)
+        v /= np.linalg.norm(v)
+        fd = (j_at(s, u0 + h * v) - j_at(s, u0 - h * v)) / (2 * h)
+        # O(h^2) truncation and Newton noise (1e-12 / h relative) are far below
+        assert abs(fd - g @ v) <= 1e-5 * np.linalg.norm(g)
+    s.close()
+
+
+@pytest.fixture(scope="module")
+def orbit():
+    from paper_1512_00616_amd import pa
+    s = pa.Solver(**TINY)
+    s.set_params(np.array(inputs.MU_NOMINAL))
+    s.set_freestream(inputs.perturbation(s.Nu, seed=1))
+    s.shoot(tol=1e-10, eta=1e-6, maxit=30)
+    u_per = s.get_state(0)
+    start = u_per + 1e-3 * inputs.rng(6).standard_normal(s.Nu)
+    yield s, u_per, start
+    s.close()
+
+
+def test_gradient_vanishes_on_the_orbit(orbit):
+    # R = 0 on the periodic orbit, so dj/du0 = Phi^T R - R = 0 there
+    s, u_per, start = orbit
+    s.set_state(start)
+    s.primal_period()
+    g0, _ = s.periodicity_gradient()
+    s.set_state(u_per)
+    s.primal_period()
+    g1, j1 = s.periodicity_gradient()
+    assert j1 <= 1e-19
+    assert np.linalg.norm(g1) <= 1e-5 * np.linalg.norm(g0)
+
+
+def test_lbfgs_approaches_the_newton_krylov_orbit(orbit):
+    # minimisation of 1/2 ||R||^2 is slow (the paper finds the optimisation
+    # solvers the slowest): L-BFGS must still cut the residual tenfold in 150
+    # iterations, move towards the Newton-Krylov orbit, and beat steepest
+    # descent over the same iteration count
+    s, u_per, start = orbit
+    s.set_state(start)
+    r = s.shoot_descent(tol=1e-12, memory=8, maxit=150, allow_unconverged=True)
+    assert r.newton_its == 150
+    assert r.res <= 0.1 * r.res0
+    assert r.krylov_its == r.newton_its + 1          # one backward sweep per iterate
+    assert r.primal_sweeps >= r.newton_its + 1
+    u = s.get_state(0)
+    assert np.linalg.norm(u - u_per) < np.linalg.norm(start - u_per)
+    s.set_state(start)
+    sd = s.shoot_descent(tol=1e-12, memory=0, maxit=150, allow_unconverged=True)
+    assert sd.res < sd.res0
+    assert r.res < sd.res
+
+
+def test_steepest_descent_decreases_the_residual(orbit):
+    s, u_per, start = orbit
+    s.set_state(start)
+    r = s.shoot_descent(tol=1e-12, memory=0, maxit=20, allow_unconverged=True)
+    assert r.newton_its >= 1 and r.res < r.res0
+    # the stored trajectory belongs to the last accepted iterate
+    _, res = s.primal_period()
+    assert res == pytest.approx(r.res, rel=1e-12)
+
+
+def test_descent_rejects_bad_options(orbit):
+    from paper_1512_00616_amd import pa
+    s, _, _ = orbit
+    for kw in (dict(tol=0.0), dict(memory=-1), dict(memory=33), dict(maxit=-1)):
+        with pytest.raises(pa.PaError):
+            s.shoot_descent(**{**dict(tol=1e-8, memory=2, maxit=5), **kw})

@@ -153,6 +153,32 @@ def test_stage_solve_parity(libs, tr):
     assert rel(xg, xo) <= 1e-10
 
 
+@pytest.mark.parametrize("tr", [0, 1])
+def test_skipped_applies_are_counted(libs, tr):
+    # GMRES enqueues iterations ahead of its convergence check; the applies
+    # of converged systems return at once and are reported as skipped, so
+    # that launches - skipped = GMRES iterations + one true-residual apply
+    # per cycle (between its + 1 and 2 its)
+    from paper_1512_00616_amd import pa
+    g, o = make_pair(libs, Nr=3, Nth=8, p=2, Nt=2, gpu_kw=dict(lin_rtol=1e-13), orc_kw=dict(lin_solver=0))
+    u = o.freestream(inputs.perturbation(o.Nu, seed=18, sigma=1e-2))
+    J = o.jacobian(1, 2, u)
+    rhs = inputs.random_vectors(o.Nu, 1, seed=19)[0]
+    k = pa.PA_K_SPMV_T if tr else pa.PA_K_SPMV
+    g.set_timing(True)
+    _, its = g.stage_solve(J, 0.5 * 0.4358665215084590, rhs, transpose=tr)
+    _, n = g.kernel_time(k)
+    skipped = g.kernel_skipped(k)
+    other = g.kernel_skipped(pa.PA_K_SPMV if tr else pa.PA_K_SPMV_T)
+    g.set_timing(False)
+    assert its + 1 <= n - skipped <= 2 * its
+    assert 0 <= skipped < n
+    assert other == 0
+    assert g.kernel_skipped(pa.PA_K_JACOBIAN) == 0
+    with pytest.raises(pa.PaError):
+        g.kernel_skipped(pa.PA_K_COUNT)
+
+
 # ---------------------------------------------------------------- sweeps
 TIGHT_G = dict(lin_rtol=1e-13, newton_atol=1e-12)
 TIGHT_O = dict(lin_solver=0, newton_atol=1e-12)
