@@ -67,6 +67,12 @@ typedef struct pa_config {
     int32_t autotune;           /* 1: time the forward-apply tile shapes on the first stored operator and
                                    keep the fastest (results may then differ from run to run in the last
                                    bits); 0: fixed shape (default) */
+    int32_t block_krylov;       /* outer solves with several right-hand sides (the two QoIs' periodic
+                                   adjoints, the three parameter tangents of the direct gradient): 1: one
+                                   block Krylov space shared by all (block GMRES; falls back to 0 when the
+                                   right-hand sides or a new block are numerically dependent); 0: one
+                                   space per system, advanced in lockstep through the same sweeps
+                                   (default) */
 } pa_config;
 
 /* Precision of the stage linear solves (Sec. 2.2 eq. dirk, each stage's

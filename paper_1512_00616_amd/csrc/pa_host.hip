@@ -2467,9 +2467,145 @@ struct Solver final : pa_ctx {
     {
         outer_multi(false, R, rhs, rtol, its, rel);
     }
+    // <V_c, w> and w += sign sum_c h_c V_c over more columns than one
+    // multi-dot launch holds (chunks of the partials buffer's width)
+    void dots_n(const double* V0, int ncols, const double* w, double* h)
+    {
+        const int ch = std::max(restart, max_kry);
+        for (int c = 0; c < ncols; c += ch) dots(V0 + (int64_t)c * Nu, Nu, std::min(ch, ncols - c), w, h + c);
+    }
+    void vupdate_n(const double* V0, int ncols, const double* h, double sign, double* w)
+    {
+        const int ch = std::max(restart, max_kry);
+        for (int c = 0; c < ncols; c += ch) vupdate(V0 + (int64_t)c * Nu, Nu, std::min(ch, ncols - c), h + c, sign, w);
+    }
+
+    // Block GMRES on (Phi - I) or (Phi^T - I) for R right-hand sides that
+    // share one Krylov space (the multiple-right-hand-side setting of Sec.
+    // 3.2: the operator is fixed, only b varies).  Zero initial guess, no
+    // restart, block size R, at most max_krylov block iterations:
+    //  - V_0 S_0 = B by Gram-Schmidt with a second pass;
+    //  - iteration j applies one sweep carrying the R vectors of block j,
+    //    orthogonalises each result against every basis vector so far (two
+    //    passes) and normalises it, which gives column jR + l of the banded
+    //    block Hessenberg matrix (R subdiagonals);
+    //  - each new column is reduced by the earlier Givens rotations and R new
+    //    ones; the same rotations act on the R columns of E_1 S_0, whose rows
+    //    (j+1)R .. (j+2)R-1 then hold every system's residual.
+    // Returns false, leaving outm untouched, when the right-hand sides or a
+    // new block are numerically dependent (the caller then solves the
+    // systems in separate spaces).
+    bool outer_block(bool tangent_op, int R, const double* rhs, double rtol, int32_t* its, double* rel)
+    {
+        ensure_multi();
+        if (!VoM) VoM = dalloc<double>((int64_t)GM_RMAX * (max_kry + 1) * Nu);
+        const int kmax = std::min(max_kry, GM_RMAX * (max_kry + 1) / R - 1);
+        const int nrow = (kmax + 1) * R, ncol = kmax * R;
+        auto V = [&](int c) { return VoM + (int64_t)c * Nu; };
+        std::vector<double> Hc((size_t)nrow * ncol, 0.0), G((size_t)nrow * R, 0.0);
+        std::vector<double> h(nrow), h2(nrow), col(nrow), bn(R), res(R);
+        struct Rot { int a, b; double c, s; };
+        std::vector<Rot> rots;
+        for (int q = 0; q < R; ++q) {
+            its[q] = 0;
+            rel[q] = 0.0;
+            bn[q] = norm(rhs + (int64_t)q * Nu);
+            if (!(bn[q] > 0.0)) return false;
+        }
+        for (int l = 0; l < R; ++l) {
+            double* w = V(l);
+            copy(rhs + (int64_t)l * Nu, w);
+            if (l > 0) {
+                dots_n(V(0), l, w, h.data());
+                vupdate_n(V(0), l, h.data(), -1.0, w);
+                dots_n(V(0), l, w, h2.data());
+                vupdate_n(V(0), l, h2.data(), -1.0, w);
+                for (int i = 0; i < l; ++i) G[(size_t)i * R + l] = h[i] + h2[i];
+            }
+            const double nr = norm(w);
+            if (!(nr > 1e-10 * bn[l])) return false;
+            G[(size_t)l * R + l] = nr;
+            lincomb(1.0 / nr, w, 0.0, w, w);
+        }
+        const int fq[GM_RMAX] = { -1, -1, -1, -1, -1, -1, -1, -1 };
+        double t0 = now_ms();
+        int k = 0;
+        bool conv = false;
+        for (int j = 0; j < kmax && !conv; ++j) {
+            HIPCHK(hipMemcpyAsync(stgX, V(j * R), sizeof(double) * R * Nu, hipMemcpyDeviceToDevice, st));
+            if (tangent_op) tangent_multi(R, stgX, fq, stgY, nullptr);
+            else adjoint_multi(R, stgX, fq, stgY, nullptr);
+            for (int q = 0; q < R; ++q) ++its[q];
+            for (int l = 0; l < R; ++l) {
+                const int c = j * R + l, nc = c + R;   // column of H; basis vectors before the new one
+                double* w = stgY + (int64_t)l * Nu;
+                axpby(-1.0, stgX + (int64_t)l * Nu, 1.0, w);   // (Phi - I) v or (Phi^T - I) v
+                dots_n(V(0), nc, w, h.data());
+                vupdate_n(V(0), nc, h.data(), -1.0, w);
+                dots_n(V(0), nc, w, h2.data());
+                vupdate_n(V(0), nc, h2.data(), -1.0, w);
+                const double hn = norm(w);
+                if (!std::isfinite(hn)) raise(PA_ENUMERIC, "NaN in block GMRES");
+                double cn = hn * hn;
+                for (int i = 0; i < nc; ++i) {
+                    col[i] = h[i] + h2[i];
+                    cn += col[i] * col[i];
+                }
+                col[nc] = hn;
+                if (!(hn > 1e-13 * std::sqrt(cn))) return false;
+                lincomb(1.0 / hn, w, 0.0, w, V(nc));
+                for (const Rot& r : rots) {
+                    const double a = col[r.a], b = col[r.b];
+                    col[r.a] = r.c * a + r.s * b;
+                    col[r.b] = -r.s * a + r.c * b;
+                }
+                for (int i = c + 1; i <= nc; ++i) {
+                    const double a = col[c], b = col[i];
+                    const double rr = std::hypot(a, b);
+                    if (rr == 0.0) continue;
+                    const Rot r{ c, i, a / rr, b / rr };
+                    col[c] = rr;
+                    col[i] = 0.0;
+                    for (int q = 0; q < R; ++q) {
+                        const double ga = G[(size_t)c * R + q], gb = G[(size_t)i * R + q];
+                        G[(size_t)c * R + q] = r.c * ga + r.s * gb;
+                        G[(size_t)i * R + q] = -r.s * ga + r.c * gb;
+                    }
+                    rots.push_back(r);
+                }
+                for (int i = 0; i <= c; ++i) Hc[(size_t)i * ncol + c] = col[i];
+            }
+            k = j + 1;
+            conv = true;
+            for (int q = 0; q < R; ++q) {
+                double s2 = 0.0;
+                for (int i = k * R; i < (k + 1) * R; ++i) s2 += G[(size_t)i * R + q] * G[(size_t)i * R + q];
+                res[q] = std::sqrt(s2);
+                conv = conv && res[q] <= rtol * bn[q];
+            }
+            if (verbose && k % 10 == 0)
+                fprintf(stderr, "[pa]   block %s sweeps %d (%d systems)  %.1f s\n", tangent_op ? "tangent" : "adjoint",
+                        k, R, (now_ms() - t0) / 1e3);
+        }
+        const int n = k * R;
+        std::vector<double> y(std::max(n, 1));
+        for (int q = 0; q < R; ++q) {
+            for (int i = n - 1; i >= 0; --i) {
+                double t = G[(size_t)i * R + q];
+                for (int p2 = i + 1; p2 < n; ++p2) t -= Hc[(size_t)i * ncol + p2] * y[p2];
+                y[i] = t / Hc[(size_t)i * ncol + i];
+            }
+            zero(outm + (int64_t)q * Nu);
+            if (n > 0) vupdate_n(V(0), n, y.data(), 1.0, outm + (int64_t)q * Nu);
+            rel[q] = res[q] / bn[q];
+        }
+        return true;
+    }
+
     // as above on (Phi - I) with tangent sweeps (tangent_op) or (Phi^T - I)
     void outer_multi(bool tangent_op, int R, const double* rhs, double rtol, int32_t* its, double* rel)
     {
+        if (cfg.block_krylov && R > 1 && outer_block(tangent_op, R, rhs, rtol, its, rel)) return;
         ensure_multi();
         if (!VoM) VoM = dalloc<double>((int64_t)GM_RMAX * (max_kry + 1) * Nu);
         const int m = max_kry;
@@ -2870,6 +3006,7 @@ void pa_default_config(pa_config* c)
     c->max_krylov = 100;
     c->precision = PA_PREC_FP64;
     c->autotune = 0;
+    c->block_krylov = 0;
     c->device = 0;
 }
 

@@ -35,7 +35,7 @@ class pa_config(C.Structure):
         ("T", C.c_double), ("r_blend0", C.c_double), ("r_blend1", C.c_double),
         ("wall_is_farfield", C.c_int32), ("gmres_restart", C.c_int32), ("lin_rtol", C.c_double),
         ("newton_atol", C.c_double), ("newton_maxit", C.c_int32), ("max_krylov", C.c_int32),
-        ("device", C.c_int32), ("precision", C.c_int32), ("autotune", C.c_int32),
+        ("device", C.c_int32), ("precision", C.c_int32), ("autotune", C.c_int32), ("block_krylov", C.c_int32),
     ]
 
 
