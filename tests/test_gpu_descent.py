@@ -43,6 +43,31 @@ def test_periodicity_gradient_matches_central_differences():
     s.close()
 
 
+def test_periodicity_gradient_matches_oracle():
+    # the oracle's primal period and backward sweep on the same state give
+    # dj/du0 = Phi^T R - R with R = u^(Nt) - u0.  R is a difference of
+    # states that agree to the sweep bar (1e-10 of max |u| ~ 45) while
+    # max |R| is O(1), so the gradient is held to 1e-8.
+    from paper_1512_00616_amd import pa
+    from oracle.oracle import Oracle
+    s = pa.Solver(**TINY)
+    o = Oracle(lin_solver=0, **{k: v for k, v in TINY.items() if k not in ("lin_rtol",)})
+    mu = np.array(inputs.MU_NOMINAL)
+    s.set_params(mu)
+    o.set_params(mu)
+    pert = inputs.perturbation(s.Nu, seed=4, sigma=1e-2)
+    s.set_freestream(pert)
+    u0 = o.freestream(pert)
+    s.primal_period()
+    g, j = s.periodicity_gradient()
+    uNt, _, res = o.primal_period(u0)
+    R = uNt - u0
+    go = o.adjoint(R) - R
+    assert abs(j - 0.5 * (R @ R)) <= 1e-8 * j
+    assert np.abs(g - go).max() <= 1e-8 * np.abs(go).max()
+    s.close()
+
+
 @pytest.fixture(scope="module")
 def orbit():
     from paper_1512_00616_amd import pa
