@@ -2755,8 +2755,9 @@ struct Solver final : pa_ctx {
         r.sweeps += std::max(its[0], its[1]);
         r.rhs_sweeps += its[0] + its[1];
         if (verbose)
-            fprintf(stderr, "[pa] adjoint (2 QoIs in lockstep): %d / %d krylov its, rel res %.2e / %.2e, %.1f s\n",
-                    its[0], its[1], rel[0], rel[1], (now_ms() - t0) / 1e3);
+            fprintf(stderr, "[pa] adjoint (2 QoIs, %s): %d / %d krylov its, rel res %.2e / %.2e, %.1f s\n",
+                    cfg.block_krylov ? "one block space" : "lockstep", its[0], its[1], rel[0], rel[1],
+                    (now_ms() - t0) / 1e3);
         HIPCHK(hipMemcpyAsync(stgX, outm, sizeof(double) * 2 * Nu, hipMemcpyDeviceToDevice, st));
         adjoint_multi(2, stgX, fq, stgY, grad);
         r.sweeps += 1;
