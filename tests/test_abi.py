@@ -31,3 +31,25 @@ def test_oracle_library_exports_its_header():
     syms = sorted(set(re.findall(r"\b(pao_[a-z_0-9]+)\s*\(", src)))
     lib = ctypes.CDLL(os.path.join(ROOT, "oracle", "liboracle.so"))
     assert [s for s in syms if not hasattr(lib, s)] == []
+
+
+def test_binding_fails_loudly_without_the_library(monkeypatch, tmp_path):
+    # no CPU fallback: with libpa.so absent every call raises
+    from paper_1512_00616_amd import pa
+    monkeypatch.setattr(pa, "LIB_PATH", str(tmp_path / "libpa.so"))
+    monkeypatch.setattr(pa, "_lib", None)
+    import pytest
+    with pytest.raises(RuntimeError, match="HIP library not built"):
+        pa.lib()
+    with pytest.raises(RuntimeError, match="HIP library not built"):
+        pa.Solver(Nr=2, Nth=6, p=1, Nt=2)
+
+
+def test_bench_refuses_more_than_one_gpu():
+    import subprocess
+    import sys
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr
+    assert r.stdout == ""
