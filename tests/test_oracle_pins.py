@@ -259,6 +259,29 @@ def test_tangent_sweep_is_derivative_of_flow_map(oracle_mod):
     assert np.linalg.norm((a - b) / (2 * h) - Pv) <= 1e-8 * np.linalg.norm(Pv)
 
 
+def test_periodicity_gradient_matches_central_differences(oracle_mod):
+    """Sec. 2.3 eqs. opt-obj and funcl-grad-nosens-dirk: the backward sweep
+    started from lam^(Nt) = R = u^(Nt) - u0 gives lam^(0), and
+    lam^(0) - R is the gradient of j(u0) = 1/2 ||R||^2 (the quantity the
+    descent shooting methods minimise)."""
+    o = make(oracle_mod, Nr=2, Nth=6, p=1, Nt=4, lin_solver=0, newton_atol=1e-12)
+    o.set_params(MU)
+    u0 = o.freestream(inputs.perturbation(o.Nu, seed=4, sigma=1e-2))
+
+    def j(u):
+        uNt, _, _ = o.primal_period(u)
+        return 0.5 * np.sum((uNt - u) ** 2)
+
+    uNt, _, _ = o.primal_period(u0)
+    R = uNt - u0
+    g = o.adjoint(R) - R
+    h = 1e-5
+    for v in inputs.random_vectors(o.Nu, 2, seed=8):
+        v = v / np.linalg.norm(v)
+        fd = (j(u0 + h * v) - j(u0 - h * v)) / (2 * h)
+        assert abs(fd - g @ v) <= 1e-6 * np.linalg.norm(g)
+
+
 def test_adjoint_sweep_is_transpose_of_tangent_sweep(tiny_periodic):
     """Appendix theorem: d lambda^(0) / d lambda_Nt = Phi^T, so
     <w, Phi v> = <Phi^T w, v> for the unforced adjoint sweep."""
