@@ -239,6 +239,21 @@ pa_status pa_dbg_mlp(int32_t in, int32_t width, int32_t out, int32_t batch, cons
                      const float* T, float* loss, float* grads);
 /* trajectory: which = 0 stage state u_i^(n), 1 stage k_i^(n), 2 step state u^(n) */
 pa_status pa_dbg_traj(pa_ctx* ctx, int32_t which, int32_t n, int32_t i, double* out);
+/* Host-only checks of the library's small dense eigen-solvers (no device
+ * work, callable without a GPU):
+ *   pa_dbg_hess_eig: eigenvalues of the real n x n upper Hessenberg matrix
+ *     H (row-major; entries below the subdiagonal are ignored) by complex
+ *     shifted QR, the routine pa_floquet applies to its Arnoldi matrix;
+ *     re[n], im[n] by decreasing modulus.  PA_ENOCONV if QR does not
+ *     converge in 100 n iterations.
+ *   pa_dbg_sym_eig: eigenvalues w[n] (descending) and eigenvectors V
+ *     (row-major n x n, column k belongs to w[k]) of the symmetric matrix A
+ *     by cyclic Jacobi rotations, the routine behind the warm start's POD
+ *     basis.
+ * PA_EINVAL for n outside 1..1024 or a NULL array; pa_last_error(NULL)
+ * describes a failure. */
+pa_status pa_dbg_hess_eig(int32_t n, const double* H, double* re, double* im);
+pa_status pa_dbg_sym_eig(int32_t n, const double* A, double* w, double* V);
 
 /* ---- many parameter instances ---- */
 typedef struct pa_batch_opts {

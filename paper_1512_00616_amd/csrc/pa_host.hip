@@ -3044,6 +3044,40 @@ pa_status pa_create(const pa_config* cfg, pa_ctx** out)
 void pa_destroy(pa_ctx* c) { delete c; }
 const char* pa_last_error(const pa_ctx* c) { return c ? c->err.c_str() : g_create_err.c_str(); }
 int64_t pa_num_dofs(const pa_ctx* c) { return c ? c->num_dofs() : -1; }
+
+// host-only entry points of the small dense eigen-solvers (no device work)
+pa_status pa_dbg_hess_eig(int32_t n, const double* H, double* re, double* im)
+{
+    try {
+        if (n < 1 || n > 1024 || !H || !re || !im) raise(PA_EINVAL, "bad arguments");
+        std::vector<std::complex<double>> Hc((size_t)n * n), ev;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) Hc[(size_t)i * n + j] = j >= i - 1 ? H[(size_t)i * n + j] : 0.0;
+        hess_eig(Hc, n, ev);
+        std::sort(ev.begin(), ev.end(), [](const std::complex<double>& a, const std::complex<double>& b) {
+            return std::abs(a) > std::abs(b);
+        });
+        for (int i = 0; i < n; ++i) { re[i] = ev[i].real(); im[i] = ev[i].imag(); }
+        return PA_OK;
+    } catch (const PaError& e) {
+        g_create_err = e.msg;
+        return e.code;
+    }
+}
+pa_status pa_dbg_sym_eig(int32_t n, const double* A, double* w, double* V)
+{
+    try {
+        if (n < 1 || n > 1024 || !A || !w || !V) raise(PA_EINVAL, "bad arguments");
+        std::vector<double> M(A, A + (size_t)n * n), lam, vec;
+        sym_eig(M, n, lam, vec);
+        std::copy(lam.begin(), lam.end(), w);
+        std::copy(vec.begin(), vec.end(), V);
+        return PA_OK;
+    } catch (const PaError& e) {
+        g_create_err = e.msg;
+        return e.code;
+    }
+}
 int32_t pa_num_elems(const pa_ctx* c) { return c ? c->num_elems() : -1; }
 int32_t pa_block_size(const pa_ctx* c) { return c ? c->block_size() : -1; }
 int64_t pa_device_bytes(const pa_ctx* c) { return c ? c->device_bytes() : -1; }

@@ -22,7 +22,7 @@ EXPORTED = [
     "pa_get_state", "pa_primal_period", "pa_shoot", "pa_fixed_point", "pa_shoot_descent", "pa_periodicity_gradient", "pa_floquet", "pa_adjoint_gradient", "pa_tangent_gradient", "pa_batch_gradients",
     "pa_ws_train", "pa_ws_predict", "pa_ws_shoot", "pa_ws_save", "pa_ws_load", "pa_dbg_mlp", "pa_tangent_sweep",
     "pa_adjoint_sweep", "pa_dbg_gbar", "pa_dbg_dgbar", "pa_dbg_residual", "pa_dbg_jacobian", "pa_dbg_dr_dmu",
-    "pa_dbg_qoi", "pa_dbg_bsr_apply", "pa_dbg_blockinv", "pa_dbg_stage_solve", "pa_dbg_traj", "pa_set_timing",
+    "pa_dbg_qoi", "pa_dbg_bsr_apply", "pa_dbg_blockinv", "pa_dbg_stage_solve", "pa_dbg_traj", "pa_dbg_hess_eig", "pa_dbg_sym_eig", "pa_set_timing",
     "pa_kernel_time", "pa_kernel_skipped", "pa_bench_spmv", "pa_bench_spmv_lo", "pa_bench_copy", "pa_tuning",
 ]
 
@@ -127,6 +127,8 @@ def lib():
             "pa_dbg_blockinv": [P, P, C.c_double, P],
             "pa_dbg_stage_solve": [P, P, C.c_double, C.c_int32, P, P, P],
             "pa_dbg_traj": [P, C.c_int32, C.c_int32, C.c_int32, P],
+            "pa_dbg_hess_eig": [C.c_int32, P, P, P],
+            "pa_dbg_sym_eig": [C.c_int32, P, P, P],
             "pa_set_timing": [P, C.c_int32],
             "pa_kernel_time": [P, C.c_int32, P, P],
             "pa_kernel_skipped": [P, C.c_int32, P],
@@ -199,6 +201,32 @@ def dbg_mlp(params, X, T, width):
     if rc != PA_OK:
         raise PaError(rc, lib().pa_last_error(None).decode())
     return float(loss[0]), grads
+
+
+def dbg_hess_eig(H):
+    """Eigenvalues (complex, by decreasing modulus) of an upper Hessenberg
+    matrix by the library's host-side shifted QR (no device work)."""
+    H = np.ascontiguousarray(H, dtype=np.float64)
+    n = H.shape[0]
+    re = np.zeros(n)
+    im = np.zeros(n)
+    rc = lib().pa_dbg_hess_eig(n, _ptr(H), _ptr(re), _ptr(im))
+    if rc != PA_OK:
+        raise PaError(rc, lib().pa_last_error(None).decode())
+    return re + 1j * im
+
+
+def dbg_sym_eig(A):
+    """(eigenvalues descending, eigenvectors as columns) of a symmetric
+    matrix by the library's host-side cyclic Jacobi (no device work)."""
+    A = np.ascontiguousarray(A, dtype=np.float64)
+    n = A.shape[0]
+    w = np.zeros(n)
+    V = np.zeros((n, n))
+    rc = lib().pa_dbg_sym_eig(n, _ptr(A), _ptr(w), _ptr(V))
+    if rc != PA_OK:
+        raise PaError(rc, lib().pa_last_error(None).decode())
+    return w, V
 
 
 class Solver:
