@@ -68,7 +68,8 @@ typedef struct pa_config {
                                    keep the fastest (results may then differ from run to run in the last
                                    bits); 0: fixed shape (default) */
     int32_t block_krylov;       /* outer solves with several right-hand sides (the two QoIs' periodic
-                                   adjoints, the three parameter tangents of the direct gradient): 1: one
+                                   adjoints, the three parameter tangents of the direct gradient; Sec.
+                                   3.2: the matrix is fixed, only the right-hand side changes): 1: one
                                    block Krylov space shared by all (block GMRES; falls back to 0 when the
                                    right-hand sides or a new block are numerically dependent); 0: one
                                    space per system, advanced in lockstep through the same sweeps
