@@ -18,10 +18,17 @@ On this mesh the T-periodic orbit is unstable (fixed-point periods diverge
 after ~11 periods: the cylinder wake sheds), so shooting to 1e-8 from the free
 stream takes far more sweeps than a bounded benchmark run; the full
 time-to-gradient at 1e-8 is measured on the 8x24 p=1 workload, whose orbit
-shooting reaches in seven Newton steps, and reported beside the value.
+shooting reaches in eight Newton steps, and reported beside the value.
+
+Beside the step: the forward apply's tile timings, the step with FP32 and
+BF16 operator copies, batched instances on concurrent contexts, the learned
+warm start (and the combined learned + mixed-precision + block-Krylov form),
+the time to gradient with a block-Krylov adjoint, and the oracle timed on
+the host.  --solver-comparison runs only the shooting-solver comparison;
+--spmv-only runs only the isolated applies used for hardware counters.
 
 Prints progress on stderr and one JSON line on stdout.  --gpus N > 1 is
-refused: this build measures one GPU.
+refused: the benchmark measures one GPU.
 """
 import argparse
 import json
@@ -332,7 +339,7 @@ def main():
                     help="only the shooting-solver comparison on the 8x24 p=1 workload (about 15 minutes)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the sweeps are sequential in time and this build runs on a single "
+        print("bench.py measures one GPU: the sweeps are sequential in time and the library runs on a single "
               "MI355X; --gpus above 1 is not supported", file=sys.stderr)
         return 2
 
