@@ -1,7 +1,7 @@
 """Compile the CPU oracle (plain C, gcc) into oracle/liboracle.so.
 
-Building the checker is not using it: this is called by the build entry so
-that the test-suite finds the library.
+Compiling the oracle does not use it: the build entry calls this so that the
+test suite finds the library.
 """
 import os
 import subprocess
