@@ -1779,6 +1779,61 @@ int pao_traj_jacobian(pao_ctx* c, int32_t n, int32_t i, double* blk)
     return 0;
 }
 
+/* ------------------------------------------------------------------ */
+/* test hooks: the pointwise fluxes and the face lifting                 */
+/* ------------------------------------------------------------------ */
+void pao_flux_vis(const pao_ctx* c, const double U[4], const double dU[8], int32_t heat, double F[8])
+{
+    cplx Uc[4], dUc[4][2], Fc[4][2];
+    for (int m = 0; m < 4; ++m) {
+        Uc[m] = U[m];
+        dUc[m][0] = dU[2 * m];
+        dUc[m][1] = dU[2 * m + 1];
+    }
+    flux_vis(c, Uc, dUc, Fc, heat);
+    for (int m = 0; m < 4; ++m) {
+        F[2 * m] = creal(Fc[m][0]);
+        F[2 * m + 1] = creal(Fc[m][1]);
+    }
+}
+
+void pao_flux_h(const pao_ctx* c, const double U[4], const double n[2], double vn, double H[4])
+{
+    cplx Uc[4] = { U[0], U[1], U[2], U[3] }, nc[2] = { n[0], n[1] }, Hc[4];
+    flux_H(c, Uc, nc, vn, Hc);
+    for (int m = 0; m < 4; ++m) H[m] = creal(Hc[m]);
+}
+
+void pao_flux_lf(const pao_ctx* c, const double UL[4], const double UR[4], const double n[2], double vn, double F[4])
+{
+    cplx L[4] = { UL[0], UL[1], UL[2], UL[3] }, R[4] = { UR[0], UR[1], UR[2], UR[3] }, nc[2] = { n[0], n[1] }, Fc[4];
+    flux_lf(c, L, R, nc, vn, Fc);
+    for (int m = 0; m < 4; ++m) F[m] = creal(Fc[m]);
+}
+
+int pao_face_lift(pao_ctx* c, int32_t n, int32_t i, const double* u, int32_t K, int32_t f, double* lift)
+{
+    int rc = check_stage(c, n, i);
+    if (rc) return rc;
+    if (K < 0 || K >= c->Ne || f < 0 || f > 2) return fail(c, -1, "bad face (%d, %d)", K, f);
+    int nb = c->enb[3 * K + f];
+    if (nb < 0) return fail(c, -1, "face (%d, %d) is on the boundary", K, f);
+    int tw = c->etw[3 * K + f];
+    int L, fL, R, fR;
+    if (K < nb) { L = K; fL = f; R = nb; fR = tw; }
+    else { L = nb; fL = tw; R = K; fR = f; }
+    Motion m;
+    motion_alloc(c, &m);
+    Stage S = stage_make(c, n, i, 0, &m);
+    cplx* uc = to_cplx(c, u);
+    cplx Fh[8 * 4], lf[16 * 8];
+    face_interior(c, &S, L, fL, R, fR, uc, Fh, lf);
+    for (int k = 0; k < c->np * 8; ++k) lift[k] = creal(lf[k]);
+    free(uc);
+    motion_free(&m);
+    return K == L ? 1 : 0;
+}
+
 void pao_counters(const pao_ctx* c, int64_t* newton, int64_t* linear)
 {
     if (newton) *newton = c->cnt_newton;

@@ -141,6 +141,22 @@ int     pao_tangent_gradient(pao_ctx* c, double rtol, int32_t max_krylov, double
 int     pao_traj(pao_ctx* c, int32_t which, int32_t n, int32_t i, double* out);
 /* stored Jacobian of stage (n, i) */
 int     pao_traj_jacobian(pao_ctx* c, int32_t n, int32_t i, double* blk);
+/* Pointwise fluxes with this context's gas constants, for closed-form pins
+ * (real arguments):
+ *   pao_flux_vis: viscous flux F[m][d] (F[2*m + d]) of the state U[4] and its
+ *     physical gradient dU[m][d] (dU[2*m + d]); heat = 0 drops the heat flux;
+ *   pao_flux_h:   H(U) = F_inv(U) n - U (v_G . n) for a unit normal n, vn = v_G . n;
+ *   pao_flux_lf:  the interior numerical flux Fhat(UL, UR, n, vn). */
+void    pao_flux_vis(const pao_ctx* c, const double U[4], const double dU[8], int32_t heat, double F[8]);
+void    pao_flux_h(const pao_ctx* c, const double U[4], const double n[2], double vn, double H[4]);
+void    pao_flux_lf(const pao_ctx* c, const double UL[4], const double UR[4], const double n[2], double vn,
+                    double F[4]);
+/* Lifting of the interior face f of element K at stage (n, i) for the state
+ * u: nodal coefficients lift[(a*4 + m)*2 + D] on the element that carries it
+ * (the lower-index side L).  Returns 1 if that is K, 0 if it is the
+ * neighbour, a negative code for a boundary face or a bad argument. */
+int     pao_face_lift(pao_ctx* c, int32_t n, int32_t i, const double* u, int32_t K, int32_t f, double* lift);
+
 /* counters: total Newton iterations and linear iterations of the last sweep */
 void    pao_counters(const pao_ctx* c, int64_t* newton, int64_t* linear);
 

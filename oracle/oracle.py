@@ -76,6 +76,11 @@ def lib():
         L.pao_traj.argtypes = [P, C.c_int32, C.c_int32, C.c_int32, P]
         L.pao_traj_jacobian.argtypes = [P, C.c_int32, C.c_int32, P]
         L.pao_counters.argtypes = [P, P, P]
+        L.pao_flux_vis.argtypes = [P, P, P, C.c_int32, P]
+        L.pao_flux_h.argtypes = [P, P, P, C.c_double, P]
+        L.pao_flux_lf.argtypes = [P, P, P, P, C.c_double, P]
+        L.pao_face_lift.argtypes = [P, C.c_int32, C.c_int32, P, C.c_int32, C.c_int32, P]
+        L.pao_face_lift.restype = C.c_int
         for fn in ("pao_set_params", "pao_gbar", "pao_gcl_rhs", "pao_residual", "pao_jacobian",
                    "pao_dr_dmu", "pao_qoi", "pao_stage_solve", "pao_primal_period",
                    "pao_tangent_sweep", "pao_adjoint_sweep", "pao_shoot", "pao_periodic_adjoint",
@@ -295,6 +300,36 @@ class Oracle:
         blk = np.zeros(self.Ne * 4 * self.b * self.b)
         self._chk(lib().pao_traj_jacobian(self._c, n, i, _ptr(blk)))
         return blk.reshape(self.Ne, 4, self.b, self.b)
+
+    # pointwise fluxes and the face lifting (closed-form pins)
+    def flux_vis(self, U, dU, heat=True):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        dU = np.ascontiguousarray(dU, dtype=np.float64).reshape(8)
+        F = np.zeros(8)
+        lib().pao_flux_vis(self._c, _ptr(U), _ptr(dU), int(heat), _ptr(F))
+        return F.reshape(4, 2)
+
+    def flux_h(self, U, n, vn=0.0):
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        n = np.ascontiguousarray(n, dtype=np.float64)
+        H = np.zeros(4)
+        lib().pao_flux_h(self._c, _ptr(U), _ptr(n), float(vn), _ptr(H))
+        return H
+
+    def flux_lf(self, UL, UR, n, vn=0.0):
+        UL = np.ascontiguousarray(UL, dtype=np.float64)
+        UR = np.ascontiguousarray(UR, dtype=np.float64)
+        n = np.ascontiguousarray(n, dtype=np.float64)
+        F = np.zeros(4)
+        lib().pao_flux_lf(self._c, _ptr(UL), _ptr(UR), _ptr(n), float(vn), _ptr(F))
+        return F
+
+    def face_lift(self, n, i, u, K, f):
+        """(lifting [np][4][2] on the lower-index side, True if that side is K)"""
+        u = self._vec(u)
+        lift = np.zeros(self.np * 8)
+        rc = self._chk(lib().pao_face_lift(self._c, n, i, _ptr(u), K, f, _ptr(lift)))
+        return lift.reshape(self.np, 4, 2), rc == 1
 
     def counters(self):
         a = np.zeros(1, np.int64)
