@@ -13,24 +13,24 @@
  * schedule; no reduction crosses threads.
  *
  * Paper map (sections and equations of arXiv:1512.00616):
- *   semi-discrete ODE M du/dt = r(u, mu, t), constant M ........ Sec. 2.2, eq. semidisc
- *   s-stage DIRK, stage equations ............................... Sec. 2.2, eqs. dirk, dirk-stage
- *   solver-consistent QoI F(u^(0..Nt), k) ........................ Sec. 2.2, eq. qoi-disc
- *   flow map u0 -> u^(Nt) (primal sweep) ........................ Sec. 2.3, eq. dirk2
- *   R(u0) = u^(Nt) - u0, Jacobian Phi - I ........................ Sec. 2.3, eqs. nlsys, jac-prim
- *   directional sensitivity (tangent sweep) ..................... Sec. 2.3, eq. dirk-sens-mvp
- *   Newton-Krylov shooting ....................................... Sec. 2.3, Alg. 2
+ *   semi-discrete ODE M du/dt = r(u, mu, t), constant M ........ Sec. 2.1, eq. semidisc
+ *   s-stage DIRK, stage equations ............................... Sec. 2.1, eqs. dirk, dirk-stage
+ *   solver-consistent QoI F(u^(0..Nt), k) ........................ Sec. 2.1, eq. qoi-disc
+ *   flow map u0 -> u^(Nt) (primal sweep) ........................ Sec. 2.2, eq. dirk2
+ *   R(u0) = u^(Nt) - u0, Jacobian Phi - I ........................ Sec. 2.2, eqs. nlsys, jac-prim
+ *   directional sensitivity (tangent sweep) ..................... Sec. 2.2, eq. dirk-sens-mvp
+ *   Newton-Krylov shooting ....................................... Sec. 2.2, Alg. 2
  *   DIRK adjoint equations, gradient ............................. Sec. 3.1, eqs. uns-disc-adj-dirk,
  *                                                                   funcl-grad-nosens-dirk
  *   backward adjoint map, periodic adjoint system ................ Sec. 3.2, eqs. uns-disc-adj-dirk2,
  *                                                                   fixedpt-dual, jac-dual
  *   adjoint-sensitivity sweep (matvec of Alg. 3) ................. Sec. 3.2, eq. uns-disc-adj-dirk-sens-mvp
  *   gradient on the periodic manifold ............................ Sec. 3.2, Alg. 3 and Alg. 4
- *   Navier-Stokes, stress, heat flux, ideal gas .................. Sec. 5, eqs. ns1-ns5
- *   ALE transformation to a fixed reference domain ............... Sec. 5, eqs. ns-cons-ref,
+ *   Navier-Stokes, stress, heat flux, ideal gas .................. Sec. 4, eqs. ns1-ns5
+ *   ALE transformation to a fixed reference domain ............... Sec. 4, eqs. ns-cons-ref,
  *                                                                   transform1-nogcl, transform2-nogcl
- *   rigid heave/pitch kinematics ................................. Sec. 5.1, eq. defmap
- *   QoIs: power and x-force on the body .......................... Sec. 5, eq. qoi
+ *   rigid heave/pitch kinematics ................................. Sec. 4.1, eq. defmap
+ *   QoIs: power and x-force on the body .......................... Sec. 4, eq. qoi
  *
  * Where the paper delegates a detail to other work (DG fluxes, CDG viscous
  * treatment, GCL modification, boundary conditions, DIRK tableau), the
@@ -356,7 +356,7 @@ static void mesh_init(pao_ctx* c)
 }
 
 /* ------------------------------------------------------------------ */
-/* kinematics and mesh motion (Sec. 5.1 eq. defmap; blended per the     */
+/* kinematics and mesh motion (Sec. 4.1 eq. defmap; blended per the     */
 /* stated reading: rigid for r <= 2, cubic blend to rest at r = 8)      */
 /* ------------------------------------------------------------------ */
 typedef struct { const cplx *xn, *vg, *gb; } Stage;
@@ -424,7 +424,7 @@ static void edge_geom(const pao_ctx* c, int K, int f, double* len, double N[2])
 }
 
 /* ------------------------------------------------------------------ */
-/* GCL field gbar (reading of the GCL modification delegated in Sec. 5):  */
+/* GCL field gbar (reading of the GCL modification delegated in Sec. 4):  */
 /*   M dgbar/dt = r_g(t),  r_g,a = -int grad phi_a . (cof G^T v_G)       */
 /*                                 + oint phi_a v_G . (cof G N)           */
 /* integrated with the same DIRK; gbar(0) = L2 projection of det G(0).   */
@@ -527,7 +527,7 @@ static void gbar_compute(pao_ctx* c, const cplx mu[3], cplx* gb)
 }
 
 /* ------------------------------------------------------------------ */
-/* physics: compressible Navier-Stokes (Sec. 5, eqs. ns1-ns5), 2-D       */
+/* physics: compressible Navier-Stokes (Sec. 4, eqs. ns1-ns5), 2-D       */
 /* ------------------------------------------------------------------ */
 static void flux_inv(const pao_ctx* c, const cplx U[4], cplx F[4][2])
 {
@@ -632,7 +632,7 @@ static void grad_X(const pao_ctx* c, int K, const double* dphi, double* dX)
 }
 
 /* Interior face between L < R (local faces fL, fR), in L's orientation.
- * Viscous treatment (reading of the compact DG method cited in Sec. 5):
+ * Viscous treatment (reading of the compact DG method cited in Sec. 4):
  *   trace  Uhat = U^R;  lifting r_e on L:
  *     int_L r_e : tau = - int_e (U^L - U^R) (x) N^L : tau
  *   face viscous flux  F_vis(U^L, grad_X U^L + r_e) (one-sided, C11 = 0).
@@ -806,7 +806,7 @@ static void elem_residual(const pao_ctx* c, const Stage* S, int K, const cplx* u
     }
 }
 
-/* instantaneous QoI contributions of element K's wall faces (Sec. 5 eq. qoi,
+/* instantaneous QoI contributions of element K's wall faces (Sec. 4 eq. qoi,
  * solver-consistent reading): the force on the body is the momentum part of
  * the wall numerical flux integrated over the wall; P = f . v_G, F_x = f . e1 */
 static void elem_qoi(const pao_ctx* c, const Stage* S, int K, const cplx* u, cplx f[2])

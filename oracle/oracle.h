@@ -13,7 +13,7 @@
  * Jacobian, not a hand-derived formula.
  *
  * State ordering: u[(K*np + a)*4 + m]  (element K, node a, conserved variable
- * m), the reference-domain state U_X of the ALE formulation (Sec. 5, eqs.
+ * m), the reference-domain state U_X of the ALE formulation (Sec. 4, eqs.
  * ns-cons-ref / transform1-nogcl).
  *
  * Jacobian block layout ("BSR, fixed width 4"): blk[((K*4 + s)*b + row)*b + col]
@@ -22,7 +22,7 @@
  * is on the boundary).
  *
  * Stage indexing: stage (n, i) with n = 1..Nt and i = 1..3 is the DIRK stage
- * at t = (n-1+c_i) dt (Sec. 2.2, eq. dirk).  (n, i) = (0, 0) means t = 0.
+ * at t = (n-1+c_i) dt (Sec. 2.1, eq. dirk).  (n, i) = (0, 0) means t = 0.
  *
  * Errors: functions returning int return 0 on success and a negative code on
  * failure (-1 bad argument, -2 no convergence, -3 NaN/Inf, -4 state error);

@@ -260,7 +260,7 @@ def test_tangent_sweep_is_derivative_of_flow_map(oracle_mod):
 
 
 def test_periodicity_gradient_matches_central_differences(oracle_mod):
-    """Sec. 2.3 eqs. opt-obj and funcl-grad-nosens-dirk: the backward sweep
+    """Sec. 2.2 eqs. opt-obj and funcl-grad-nosens-dirk: the backward sweep
     started from lam^(Nt) = R = u^(Nt) - u0 gives lam^(0), and
     lam^(0) - R is the gradient of j(u0) = 1/2 ||R||^2 (the quantity the
     descent shooting methods minimise)."""
@@ -325,7 +325,7 @@ def test_adjoint_gradient_equals_tangent_gradient(tiny_periodic):
 
 @pytest.mark.slow
 def test_adjoint_gradient_matches_central_differences(oracle_mod, tiny_periodic):
-    """Sec. 5.1 verification: central differences with tau = 1e-6 of the
+    """Sec. 4.1 verification: central differences with tau = 1e-6 of the
     periodic QoIs, periodic solves to 1e-12 warm-started from u0*."""
     o, us, _ = tiny_periodic
     o.set_params(MU)
@@ -346,3 +346,34 @@ def test_adjoint_gradient_matches_central_differences(oracle_mod, tiny_periodic)
     o.set_params(MU)
     o.primal_period(us)
     assert np.linalg.norm(G - FD) <= 1e-6 * np.linalg.norm(FD), (G, FD)
+
+
+# ---------------------------------------------------------------- dense monolithic solve
+def test_trajectory_solves_the_monolithic_system(tiny_periodic):
+    """The shot orbit satisfies every row of Sec. 3 eq. abs-govern-disc
+    (periodicity, state updates, stage equations) to the Newton and shooting
+    tolerances."""
+    from oracle import monolithic
+    o, us, _ = tiny_periodic
+    o.primal_period(us)
+    r = monolithic.residual(o)
+    assert np.abs(r).max() <= 1e-10
+
+
+def test_periodic_adjoint_matches_dense_monolithic_solve(tiny_periodic):
+    """Alg. 3 + eq. funcl-grad-nosens-dirk (sweeps, matrix-free GMRES on
+    (Phi^T - I)) against one dense LU solve of the transposed Jacobian of the
+    whole fully discrete periodic system (Sec. 3.1 eqs. abs-govern-disc,
+    uns-disc-adj, funcl-grad-nosens); the direct (tangent) gradient against
+    the same matrix untransposed."""
+    from oracle import monolithic
+    o, us, _ = tiny_periodic
+    o.primal_period(us)
+    g_adj, g_dir, _ = monolithic.gradients(o)
+    # the dense adjoint and direct gradients come from one matrix: they
+    # agree to its LU round-off
+    assert np.abs(g_adj - g_dir).max() <= 1e-11 * np.abs(g_adj).max()
+    G = np.stack([o.periodic_adjoint(q, rtol=1e-13)[0] for q in (0, 1)])
+    assert np.abs(G - g_adj).max() <= 1e-10 * np.abs(g_adj).max(), (G, g_adj)
+    T = o.tangent_gradient(rtol=1e-13)
+    assert np.abs(T - g_dir).max() <= 1e-10 * np.abs(g_dir).max(), (T, g_dir)
