@@ -14,17 +14,31 @@ that size:
 Every stage solve inside the step is converged to 1e-10; the reported value is
 the stage-solve throughput (DOFs x stage solves per second).
 
+A step takes tens of seconds, so --steps and --warmup are upper bounds: the
+timed steps stop when the next one would end past --budget-s (default 100 s;
+at least one step is timed) and the warm-up steps likewise within
+--warmup-budget-s.  The JSON line reports the steps actually run.
+
+The roofline object names the stage-operator apply with the largest total
+time over the timed steps (HIP events on the library stream, every 8th
+launch bracketed); the other applies and the stage-GMRES vector kernels are
+reported beside it.  The oracle is timed on the host on a bounded sample
+(one residual, one Jacobian, one stage solve at the same size) and composed
+with the step's counts.
+
 On this mesh the T-periodic orbit is unstable (fixed-point periods diverge
 after ~11 periods: the cylinder wake sheds), so shooting to 1e-8 from the free
 stream takes far more sweeps than a bounded benchmark run; the full
-time-to-gradient at 1e-8 is measured on the 8x24 p=1 workload, whose orbit
-shooting reaches in eight Newton steps, and reported beside the value.
+time-to-gradient at 1e-8 is measured on the 8x24 p=1 workload (section
+'ttg').
 
-Beside the step: the forward apply's tile timings, the step with FP32 and
-BF16 operator copies, batched instances on concurrent contexts, the learned
-warm start (and the combined learned + mixed-precision + block-Krylov form),
-the time to gradient with a block-Krylov adjoint, and the oracle timed on
-the host.  --solver-comparison runs only the shooting-solver comparison;
+Extra sections (--sections, comma-separated, or 'all'): 'tiles' (forward
+apply tile timings), 'mixed' (the step with FP32 and BF16 operator copies),
+'batched' (instances on concurrent contexts), 'learned' (the learned warm
+start and the combined learned + mixed-precision + block-Krylov form), 'ttg'
+(the time to gradient on the 8x24 p=1 workload with a block-Krylov adjoint),
+'oracle-sweeps' (the oracle's sweeps on that workload on 1 and all host
+threads).  --solver-comparison runs only the shooting-solver comparison;
 --spmv-only runs only the isolated applies used for hardware counters.
 
 Prints progress on stderr and one JSON line on stdout.  --gpus N > 1 is
@@ -56,16 +70,17 @@ TRAFFIC_BYTES = {"pa::k_ahat_fwd<10, double, double, 0>": 243.2e6}
 FWD_KERNEL = "pa::k_ahat_fwd<10, double, double, 0>"
 
 
-def spmv_bytes(Nr, Nth, p, mat_bytes=8, vec_bytes=8):
+def spmv_bytes(Nr, Nth, p, mat_bytes=8, vec_bytes=8, nrhs=1):
     """Algorithmic bytes of one apply of the preconditioned stage operator
     y = Ahat x = x + (A P^{-1} - I) x: every stored off-diagonal block once
-    (two per interior face; the diagonal blocks are the identity), x and y once."""
+    (two per interior face; the diagonal blocks are the identity), x and y
+    once per right-hand side carried by the launch."""
     np_ = (p + 1) * (p + 2) // 2
     b = 4 * np_
     Ne = 2 * Nr * Nth
     n_int_faces = 3 * Ne // 2 - Nth          # wall and far-field edges are unpaired
     Nu = Ne * b
-    return 2 * n_int_faces * b * b * mat_bytes + 2 * Nu * vec_bytes
+    return 2 * n_int_faces * b * b * mat_bytes + nrhs * 2 * Nu * vec_bytes
 
 
 def log(msg):
@@ -78,7 +93,8 @@ def cpu_baseline(work, counts, mu):
     GMRES stage solve at the benchmark discretisation; the step time is
     composed from these unit times and the GPU step's own counts."""
     from oracle.oracle import Oracle
-    nthreads = min(os.cpu_count() or 1, 16)
+    ci = cpu_info()
+    nthreads = min(ci["nproc"], 16)
     o = Oracle(lin_solver=1, lin_rtol=1e-10, nthreads=nthreads, **work)
     o.set_params(mu)
     u = o.freestream()
@@ -101,7 +117,7 @@ def cpu_baseline(work, counts, mu):
     dofs = counts["stage_solves"] * o.Nu / est
     return {
         "value": dofs, "unit": "DOF/s", "cores": nthreads, "kind": "oracle",
-        "step_s": est,
+        "cpu_model": ci["model"], "nproc": ci["nproc"], "step_s": est, "composed": True,
         "sample": ("one residual (%.3f s), one complex-step Jacobian (%.2f s) and one block-Jacobi GMRES "
                    "stage solve (%d its, %.4f s/it) at 32x96 p=3; step time composed with the GPU step's "
                    "counts (%d residuals, %d Jacobians, %d GMRES its, %d stage solves)"
@@ -141,6 +157,8 @@ def time_to_gradient(pa, mu):
     b.close()
     return {"workload": "circle-8x24-p1-nt20", "seconds": t, "newton": rep.newton_its,
             "tangent_sweeps": rep.krylov_its, "periodicity": rep.res, "adjoint_krylov": list(arep.krylov_its),
+            "counts": {"primal_sweeps": rep.primal_sweeps, "tangent_sweeps": rep.krylov_its,
+                       "backward_rhs": arep.rhs_sweeps},
             "adjoint_seconds": t0 + t - t1, "qoi": list(q), "dJdmu": dJ.tolist(),
             "block_adjoint": {"krylov": list(brep.krylov_its), "sweeps": brep.sweeps, "seconds": tb,
                               "rel_res": list(brep.rel_res),
@@ -149,7 +167,7 @@ def time_to_gradient(pa, mu):
 
 
 def solver_comparison(pa, mu, descent_maxit=150):
-    """Shooting solvers on the 8x24 p=1, 20-step workload (Sec. 2.3: Alg. 1,
+    """Shooting solvers on the 8x24 p=1, 20-step workload (Sec. 2.2: Alg. 1,
     Newton-Krylov shooting, and minimisation of 1/2 ||R||^2 by L-BFGS or
     steepest descent), from the free stream with the seeded N(0, 1e-3)
     perturbation after m = 0, 1, 5 fixed-point periods used as nonlinear
@@ -317,20 +335,93 @@ def batched(pa, args):
             "speedup": t_seq / t_bat, "bitwise_equal": bool(np.array_equal(g1, gb) and np.array_equal(q1, qb))}
 
 
+def cpu_info():
+    """Host CPU model and the cores visible to this process."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return {"model": model, "nproc": avail}
+
+
+def oracle_sweeps(mu, nthreads, counts=None):
+    """The oracle's sweeps on the 8x24 p=1, 20-step workload on nthreads host
+    threads: one primal period from the seeded perturbed free stream, one
+    tangent sweep and one unforced backward sweep about it (block-Jacobi
+    GMRES(30) stage solves at 1e-10).  With the GPU run's sweep counts of the
+    whole method (shooting to 1e-8 and both QoIs' periodic adjoints), the
+    oracle's time to gradient is composed from these unit times."""
+    from oracle.oracle import Oracle
+    work = inputs.WORKLOADS["circle-8x24-p1-nt20"]
+    o = Oracle(lin_solver=1, lin_rtol=1e-10, newton_atol=1e-10, nthreads=nthreads, **work)
+    o.set_params(mu)
+    u0 = o.freestream(inputs.perturbation(o.Nu, seed=1))
+    v = inputs.random_vectors(o.Nu, 1, seed=7)[0]
+    t0 = time.perf_counter()
+    o.primal_period(u0)
+    t1 = time.perf_counter()
+    o.tangent(v)
+    t2 = time.perf_counter()
+    o.adjoint(v)
+    t3 = time.perf_counter()
+    o.close()
+    r = {"threads": nthreads, "primal_period_s": t1 - t0, "tangent_sweep_s": t2 - t1, "adjoint_sweep_s": t3 - t2}
+    if counts:
+        r["composed_time_to_gradient_s"] = (counts["primal_sweeps"] * r["primal_period_s"]
+                                            + counts["tangent_sweeps"] * r["tangent_sweep_s"]
+                                            + counts["backward_rhs"] * r["adjoint_sweep_s"])
+        r["composed_from"] = counts
+    return r
+
+
+def roofline_entry(name, ms, launches, skipped, nbytes):
+    """Achieved bandwidth of one kernel from the sampled HIP-event times over
+    the timed steps: algorithmic bytes per working launch / (total time /
+    working launches).  Launches that exited at once (their GMRES system had
+    converged) move no bytes; their short time stays in the total."""
+    work = launches - skipped
+    if work <= 0 or ms <= 0:
+        return None
+    avg_s = ms / work / 1e3
+    ach = nbytes / avg_s / 1e9
+    return {"kernel": name, "total_ms": ms, "launches": launches, "launches_skipped": skipped,
+            "bytes_per_launch": nbytes, "avg_launch_us": avg_s * 1e6, "achieved_gbs": ach,
+            "frac": ach / HBM_PEAK_GBS, "avg_launch_us_all": ms / launches * 1e3}
+
+
+SECTIONS = ("tiles", "mixed", "batched", "learned", "ttg", "oracle-sweeps")
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=1)
-    ap.add_argument("--warmup", type=int, default=0)
+    ap.add_argument("--steps", type=int, default=3, help="timed steps (at most; see --budget-s)")
+    ap.add_argument("--warmup", type=int, default=1, help="warm-up steps (at most; see --warmup-budget-s)")
+    ap.add_argument("--budget-s", type=float, default=100.0,
+                    help="wall-time budget of the timed steps: a further step starts only if the mean step time "
+                         "says it ends inside the budget (at least one step is timed); the steps actually timed "
+                         "are reported")
+    ap.add_argument("--warmup-budget-s", type=float, default=45.0,
+                    help="the same budget for the warm-up steps (at least one when --warmup > 0)")
     ap.add_argument("--krylov", type=int, default=6, help="outer Krylov basis cap of the step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-ttg", action="store_true", help="skip the 8x24 time-to-gradient")
-    ap.add_argument("--no-mixed", action="store_true", help="skip the FP32/BF16 mixed-precision steps")
+    ap.add_argument("--sections", default="",
+                    help="comma-separated extra sections after the headline step: " + ", ".join(SECTIONS)
+                         + " (or 'all'); none by default")
     ap.add_argument("--batch", type=int, default=8,
-                    help="instances of the 16x48 p=2 batched comparison (0 skips it)")
+                    help="instances of the 16x48 p=2 batched comparison (section 'batched')")
     ap.add_argument("--batch-workers", type=int, default=4)
     ap.add_argument("--learned-train", type=int, default=16,
-                    help="periodic orbits that train the warm start on the 8x24 p=1 workload (0 skips it)")
+                    help="periodic orbits that train the warm start on the 8x24 p=1 workload (section 'learned')")
     ap.add_argument("--learned-test", type=int, default=2, help="held-out parameter draws of the warm-start test")
     ap.add_argument("--spmv-only", action="store_true",
                     help="short run for hardware counters: a 3-stage period on the 32x96 p=3 mesh, then timed "
@@ -342,6 +433,12 @@ def main():
         print("bench.py measures one GPU: the sweeps are sequential in time and the library runs on a single "
               "MI355X; --gpus above 1 is not supported", file=sys.stderr)
         return 2
+    sections = set(SECTIONS) if args.sections.strip() == "all" else \
+        {x.strip() for x in args.sections.split(",") if x.strip()}
+    bad = sections - set(SECTIONS)
+    if bad:
+        print("unknown sections: %s (known: %s)" % (sorted(bad), ", ".join(SECTIONS)), file=sys.stderr)
+        return 2
 
     from paper_1512_00616_amd import pa
 
@@ -352,60 +449,10 @@ def main():
         print(json.dumps({"solver_comparison": solver_comparison(pa, mu)}), flush=True)
         return 0
     if args.spmv_only:
-        # same mesh, degree and time step (dt = 0.01) as the workload, three
-        # steps of a motionless cylinder: stores the operators of 9 stages
-        phys = dict(inputs.PHYSICS, T=0.03)
-        outj = {}
-        for prec, tag in ((pa.PREC_FP32, "fp32"), (pa.PREC_BF16, "bf16")):
-            s = pa.Solver(gmres_restart=30, lin_rtol=1e-10, newton_atol=1e-10, precision=prec,
-                          **dict(work, Nt=3), **phys)
-            s.set_params(np.zeros(3))
-            s.set_freestream()
-            s.primal_period()
-            if prec == pa.PREC_FP32:
-                fwd = s.bench_spmv(20)
-                trn = s.bench_spmv(20, transpose=True)
-                nbytes = spmv_bytes(work["Nr"], work["Nth"], work["p"])
-                outj.update({"spmv_us": fwd * 1e3, "spmv_t_us": trn * 1e3, "spmv_bytes": nbytes,
-                             "spmv_gbs": nbytes / (fwd * 1e-3) / 1e9, "spmv_t_gbs": nbytes / (trn * 1e-3) / 1e9})
-            lo = s.bench_spmv_lo(20)
-            lot = s.bench_spmv_lo(20, transpose=True)
-            lb = spmv_bytes(work["Nr"], work["Nth"], work["p"], 4 if tag == "fp32" else 2, 4)
-            outj.update({"spmv_%s_us" % tag: lo * 1e3, "spmv_%s_t_us" % tag: lot * 1e3, "spmv_%s_bytes" % tag: lb,
-                         "spmv_%s_gbs" % tag: lb / (lo * 1e-3) / 1e9})
-            if prec == pa.PREC_BF16:
-                cp_ms, cp_bytes = s.bench_copy(20)
-                outj.update({"copy_us": cp_ms * 1e3, "copy_bytes": cp_bytes,
-                             "copy_gbs": 2 * cp_bytes / (cp_ms * 1e-3) / 1e9})
-            s.close()
-        print(json.dumps(outj), flush=True)
+        print(json.dumps(spmv_only(pa, work)), flush=True)
         return 0
 
     out, dJ64 = run_step(pa, name, work, mu, args, pa.PREC_FP64)
-    out["apply_tiles"] = apply_tiles(pa, work)
-    if not args.no_mixed:
-        # the same step with the mixed-precision stage solves (FP64 refinement
-        # to the same tolerances): wall time and gradient against the FP64 run
-        out["mixed_precision"] = {}
-        for prec, tag in ((pa.PREC_FP32, "fp32"), (pa.PREC_BF16, "bf16")):
-            log("mixed precision (%s operator copy, FP32 inner GMRES)" % tag)
-            m, dJm = run_step(pa, name, work, mu, args, prec)
-            out["mixed_precision"][tag] = {
-                "ms_per_step": m["ms_per_step"], "value": m["value"], "unit": "DOF/s",
-                "speedup_vs_fp64": out["ms_per_step"] / m["ms_per_step"],
-                "dJdmu_rel_diff_vs_fp64": float(np.abs(dJm - dJ64).max() / np.abs(dJ64).max()),
-                "counts": m["counts"], "kernels_ms": m["kernels_ms"],
-                "spmv_lo": m["spmv_lo"],
-            }
-    if args.batch > 0:
-        log("batched instances on the 16x48 p=2 workload")
-        out["batched"] = batched(pa, args)
-    if args.learned_train > 0:
-        log("learned warm start on the 8x24 p=1 workload")
-        out["learned_warm_start"] = learned(pa, args)
-    if not args.no_ttg:
-        log("time to gradient on the 8x24 p=1 workload")
-        out["time_to_gradient"] = time_to_gradient(pa, mu)
     if not args.no_cpu_baseline:
         log("oracle sample on the host")
         c = out.pop("_cpu_counts")
@@ -414,13 +461,84 @@ def main():
         except Exception as e:  # report, do not fail the benchmark
             out["cpu_baseline"] = {"value": None, "error": str(e)}
     out.pop("_cpu_counts", None)
+    if "tiles" in sections:
+        out["apply_tiles"] = apply_tiles(pa, work)
+    if "mixed" in sections:
+        # the same step with the mixed-precision stage solves (FP64 refinement
+        # to the same tolerances): wall time and gradient against the FP64 run
+        out["mixed_precision"] = {}
+        for prec, tag in ((pa.PREC_FP32, "fp32"), (pa.PREC_BF16, "bf16")):
+            log("mixed precision (%s operator copy, FP32 inner GMRES)" % tag)
+            m, dJm = run_step(pa, name, work, mu, args, prec)
+            out["mixed_precision"][tag] = {
+                "ms_per_step": m["ms_per_step"], "value": m["value"], "unit": "DOF/s", "steps": m["steps"],
+                "speedup_vs_fp64": out["ms_per_step"] / m["ms_per_step"],
+                "dJdmu_rel_diff_vs_fp64": float(np.abs(dJm - dJ64).max() / np.abs(dJ64).max()),
+                "counts": m["counts"], "kernels_ms": m["kernels_ms"],
+                "spmv_lo": m["spmv_lo"],
+            }
+    if "batched" in sections:
+        log("batched instances on the 16x48 p=2 workload")
+        out["batched"] = batched(pa, args)
+    if "learned" in sections:
+        log("learned warm start on the 8x24 p=1 workload")
+        out["learned_warm_start"] = learned(pa, args)
+    if "ttg" in sections:
+        log("time to gradient on the 8x24 p=1 workload")
+        out["time_to_gradient"] = time_to_gradient(pa, mu)
+    if "oracle-sweeps" in sections:
+        log("oracle sweeps on the 8x24 p=1 workload (1 thread, all threads)")
+        ci = cpu_info()
+        cnt = out.get("time_to_gradient", {}).get("counts")
+        out["oracle_sweeps"] = {"cpu": ci, "runs": [oracle_sweeps(mu, 1, cnt),
+                                                    oracle_sweeps(mu, min(ci["nproc"], 16), cnt)]}
     print(json.dumps(out), flush=True)
     return 0
 
 
+def spmv_only(pa, work):
+    """Isolated applies for hardware counters: the same mesh, degree and time
+    step (dt = 0.01) as the workload, three steps of a motionless cylinder
+    (stores the operators of 9 stages), then timed launches of the stored
+    first-stage operator (forward, transposed, two right-hand sides) in FP64,
+    of its FP32 and BF16 copies, and of a plain device copy."""
+    phys = dict(inputs.PHYSICS, T=0.03)
+    outj = {}
+    for prec, tag in ((pa.PREC_FP32, "fp32"), (pa.PREC_BF16, "bf16")):
+        s = pa.Solver(gmres_restart=30, lin_rtol=1e-10, newton_atol=1e-10, precision=prec,
+                      **dict(work, Nt=3), **phys)
+        s.set_params(np.zeros(3))
+        s.set_freestream()
+        s.primal_period()
+        if prec == pa.PREC_FP32:
+            fwd = s.bench_spmv(20)
+            trn = s.bench_spmv(20, transpose=True)
+            trm = s.bench_spmv(20, transpose=True, nrhs=2)
+            fwm = s.bench_spmv(20, transpose=False, nrhs=3)
+            nbytes = spmv_bytes(work["Nr"], work["Nth"], work["p"])
+            outj.update({"spmv_us": fwd * 1e3, "spmv_t_us": trn * 1e3, "spmv_bytes": nbytes,
+                         "spmv_gbs": nbytes / (fwd * 1e-3) / 1e9, "spmv_t_gbs": nbytes / (trn * 1e-3) / 1e9,
+                         "spmv_tm2_us": trm * 1e3,
+                         "spmv_tm2_gbs": spmv_bytes(work["Nr"], work["Nth"], work["p"], nrhs=2) / (trm * 1e-3) / 1e9,
+                         "spmv_fm3_us": fwm * 1e3,
+                         "spmv_fm3_gbs": spmv_bytes(work["Nr"], work["Nth"], work["p"], nrhs=3) / (fwm * 1e-3) / 1e9})
+        lo = s.bench_spmv_lo(20)
+        lot = s.bench_spmv_lo(20, transpose=True)
+        lb = spmv_bytes(work["Nr"], work["Nth"], work["p"], 4 if tag == "fp32" else 2, 4)
+        outj.update({"spmv_%s_us" % tag: lo * 1e3, "spmv_%s_t_us" % tag: lot * 1e3, "spmv_%s_bytes" % tag: lb,
+                     "spmv_%s_gbs" % tag: lb / (lo * 1e-3) / 1e9})
+        if prec == pa.PREC_BF16:
+            cp_ms, cp_bytes = s.bench_copy(20)
+            outj.update({"copy_us": cp_ms * 1e3, "copy_bytes": cp_bytes,
+                         "copy_gbs": 2 * cp_bytes / (cp_ms * 1e-3) / 1e9})
+        s.close()
+    return outj
+
+
 def run_step(pa, name, work, mu, args, precision):
-    """Warmup, then the timed steps, on a fresh context of the given stage-solve
-    precision; returns the report and dJ/dmu of the last step."""
+    """Warm-up, then the timed steps, on a fresh context of the given
+    stage-solve precision, both within their wall-time budgets; returns the
+    report and dJ/dmu of the last step."""
     t_setup = time.perf_counter()
     s = pa.Solver(gmres_restart=30, lin_rtol=1e-10, newton_atol=1e-10, max_krylov=args.krylov,
                   precision=precision, **work, **inputs.PHYSICS)
@@ -434,17 +552,26 @@ def run_step(pa, name, work, mu, args, precision):
         q, dJ, arep = s.adjoint_gradient(rtol=1e-8)
         return rep, q, dJ, arep
 
-    for _ in range(args.warmup):
-        step()
+    def budgeted(k_max, budget, tag):
+        res, t0 = [], time.perf_counter()
+        while len(res) < k_max:
+            el = time.perf_counter() - t0
+            if res and el + el / len(res) > budget:
+                break
+            res.append(step())
+            log("%s step %d: %.1f s" % (tag, len(res), time.perf_counter() - t0))
+        return res, time.perf_counter() - t0
+
+    warm, _ = budgeted(args.warmup, args.warmup_budget_s, "warm-up")
     s.set_timing(True)
-    t0 = time.perf_counter()
-    results = [step() for _ in range(args.steps)]
-    t1 = time.perf_counter()
-    kt = {k: s.kernel_time(getattr(pa, "PA_K_" + k.upper())) for k in ("spmv", "spmv_t", "spmv_lo", "precond",
-                                                                       "jacobian", "residual", "blockinv")}
-    ksk = {k: s.kernel_skipped(getattr(pa, "PA_K_" + k.upper())) for k in ("spmv", "spmv_t", "spmv_lo")}
+    results, t_run = budgeted(max(args.steps, 1), args.budget_s, "timed")
+    ids = ("spmv", "spmv_t", "spmv_m", "spmv_tm", "spmv_lo", "mdot", "gmupd", "precond", "jacobian", "residual",
+           "blockinv")
+    kt = {k: s.kernel_time(getattr(pa, "PA_K_" + k.upper())) for k in ids}
+    ksk = {k: s.kernel_skipped(getattr(pa, "PA_K_" + k.upper())) for k in ids}
     s.set_timing(False)
-    step_s = (t1 - t0) / args.steps
+    nsteps = len(results)
+    step_s = t_run / nsteps
     rep, q, dJ, arep = results[-1]
     nst = 3 * work["Nt"]
     gmres_its = rep.stage_gmres_its + arep.stage_gmres_its
@@ -453,50 +580,50 @@ def run_step(pa, name, work, mu, args, precision):
     # adjoints ride in the same sweeps)
     stage_solves = rep.stage_newton_its + nst * (rep.krylov_its + arep.rhs_sweeps)
     Nu = s.Nu
-    bytes_spmv = spmv_bytes(work["Nr"], work["Nth"], work["p"])
-    # GMRES enqueues iterations ahead of its convergence check; applies whose
-    # systems have converged return at once.  Their (short) time stays in the
-    # total, their bytes do not: achieved = bytes x working launches / total
-    # time of all launches, i.e. time per launch is taken per working launch.
-    ms_spmv, n_spmv = kt["spmv"]
-    work_spmv = n_spmv - ksk["spmv"]
-    avg_spmv_s = ms_spmv / max(work_spmv, 1) / 1e3
-    achieved = bytes_spmv / avg_spmv_s / 1e9
-    ms_t, n_t = kt["spmv_t"]
-    avg_t_s = ms_t / max(n_t - ksk["spmv_t"], 1) / 1e3
+    Nr, Nth, p = work["Nr"], work["Nth"], work["p"]
+    fwd_name = FWD_KERNEL if Nr * Nth > 0 else None
+    cand = [roofline_entry(fwd_name, kt["spmv"][0], kt["spmv"][1], ksk["spmv"], spmv_bytes(Nr, Nth, p)),
+            roofline_entry("pa::k_ahat_tr<%d, double, double>" % ((p + 1) * (p + 2) // 2), kt["spmv_t"][0],
+                           kt["spmv_t"][1], ksk["spmv_t"], spmv_bytes(Nr, Nth, p)),
+            # the two QoIs' adjoints in one transposed launch
+            roofline_entry("pa::k_ahat_tr_m<%d>" % ((p + 1) * (p + 2) // 2), kt["spmv_tm"][0], kt["spmv_tm"][1],
+                           ksk["spmv_tm"], spmv_bytes(Nr, Nth, p, nrhs=2)),
+            roofline_entry("pa::k_ahat_fwd_m<%d>" % ((p + 1) * (p + 2) // 2), kt["spmv_m"][0], kt["spmv_m"][1],
+                           ksk["spmv_m"], spmv_bytes(Nr, Nth, p, nrhs=3))]
+    cand = [c for c in cand if c]
+    dom = max(cand, key=lambda c: c["total_ms"])
+    full = (Nr, Nth, p) == (32, 96, 3)
+    traffic = TRAFFIC_BYTES.get(dom["kernel"]) if full else None
+    # the Krylov vector kernels: one pass over the basis columns each; their
+    # bytes depend on the column index, so only the mean per working launch
+    # is reported
+    vec = {k: {"total_ms": kt[k][0], "launches": kt[k][1], "launches_skipped": ksk[k],
+               "avg_launch_us": kt[k][0] / max(kt[k][1] - ksk[k], 1) * 1e3} for k in ("mdot", "gmupd")}
+    lo_bytes = spmv_bytes(Nr, Nth, p, 4 if precision == pa.PREC_FP32 else 2, 4)
     ms_lo, n_lo = kt["spmv_lo"]
     work_lo = n_lo - ksk["spmv_lo"]
-    lo_bytes = spmv_bytes(work["Nr"], work["Nth"], work["p"], 4 if precision == pa.PREC_FP32 else 2, 4)
     out = {
         "metric": "stage-solve DOF/s (periodic adjoint hot path, 32x96 p=3)",
         "value": stage_solves * Nu / step_s,
         "unit": "DOF/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
+        "steps": nsteps,
+        "warmup": len(warm),
+        "steps_requested": args.steps,
+        "warmup_requested": args.warmup,
+        "budget_s": args.budget_s,
         "ms_per_step": step_s * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f64" if precision == pa.PREC_FP64 else ("f32+f64" if precision == pa.PREC_FP32 else "bf16+f32+f64"),
         "data": "synthetic",
         "config": {"workload": name, **work, "mu": list(mu), "stage_gmres": "block-Jacobi GMRES(30) rtol 1e-10",
                    "newton_atol": 1e-10, "outer_krylov_cap": args.krylov, "shoot_eta": 1e-3, "adj_rtol": 1e-8},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS,
-                     "traffic": TRAFFIC_BYTES.get(FWD_KERNEL)
-                     if (work["Nr"], work["Nth"], work["p"]) == (32, 96, 3) else None,
-                     "kernel": FWD_KERNEL,
-                     "bytes_per_launch": bytes_spmv, "avg_launch_us": avg_spmv_s * 1e6, "launches": n_spmv,
-                     "launches_skipped": ksk["spmv"],
-                     # over every launch, early exits included (what a profiler's average counts)
-                     "avg_launch_us_all": ms_spmv / max(n_spmv, 1) * 1e3},
-        # transposed applies: k_ahat_tr<10, double, double> for one right-hand
-        # side, k_ahat_tr_m<10> when the two QoIs' adjoints ride together
-        # (then one launch reads the operator once for both vectors)
-        "spmv_transposed": {"kernels": ["pa::k_ahat_tr<10, double, double>", "pa::k_ahat_tr_m<10>"],
-                            "avg_launch_us": avg_t_s * 1e6, "launches": n_t, "launches_skipped": ksk["spmv_t"],
-                            "matrix_gbs": bytes_spmv / max(avg_t_s, 1e-30) / 1e9},
+        "roofline": {"bound": "hbm", "achieved": dom["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": dom["frac"], "traffic": traffic, **dom},
+        "applies": cand,
+        "gmres_vector_kernels": vec,
         "spmv_lo": ({"avg_launch_us": ms_lo / work_lo * 1e3, "launches": n_lo, "launches_skipped": ksk["spmv_lo"],
                      "bytes_per_launch": lo_bytes, "achieved_gbs": lo_bytes / (ms_lo / work_lo * 1e-3) / 1e9}
                     if work_lo > 0 else None),
@@ -509,8 +636,8 @@ def run_step(pa, name, work, mu, args, precision):
         "qoi": list(q), "dJdmu": dJ.tolist(),
         "setup_s": setup_s,
         "device_gb": s.device_bytes / 1e9,
-        "_cpu_counts": {"residuals": kt["residual"][1] // max(args.steps, 1),
-                        "jacobians": kt["jacobian"][1] // max(args.steps, 1),
+        "_cpu_counts": {"residuals": kt["residual"][1] // nsteps,
+                        "jacobians": kt["jacobian"][1] // nsteps,
                         "gmres_its": gmres_its, "stage_solves": stage_solves},
     }
     if precision == pa.PREC_FP64:

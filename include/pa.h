@@ -16,12 +16,12 @@
  *    pointer after the call returns.  Device memory is owned by the context.
  *  - State ordering: u[(K*np + a)*4 + m], element K, node a of the element's
  *    equispaced nodal set (t outer, s inner), conserved variable m of the
- *    reference-domain state U_X (Sec. 5 eq. transform1-nogcl with gbar).
+ *    reference-domain state U_X (Sec. 4 eq. transform1-nogcl with gbar).
  *  - Block layout of dr/du: blk[((K*4 + s)*b + row)*b + col], b = 4*np, slot
  *    s = 0 the diagonal block, s = 1 + f the block coupling element K to its
  *    neighbour across local face f (zero where f lies on the boundary).
  *  - Stage (n, i), n = 1..Nt, i = 1..3 is the DIRK stage at
- *    t = (n - 1 + c_i) dt (Sec. 2.2 eq. dirk); (0, 0) means t = 0.
+ *    t = (n - 1 + c_i) dt (Sec. 2.1 eq. dirk); (0, 0) means t = 0.
  *  - Errors: every call returns pa_status; no exception crosses the ABI.
  *    pa_last_error() describes the last failure.  After PA_EDEVICE the
  *    context must be destroyed; after any other error it stays usable.
@@ -74,9 +74,26 @@ typedef struct pa_config {
                                    right-hand sides or a new block are numerically dependent); 0: one
                                    space per system, advanced in lockstep through the same sweeps
                                    (default) */
+    /* Stream and device memory (for a host framework such as PyTorch that
+     * owns both).  stream: a hipStream_t on which the context enqueues all
+     * its device work, in order; NULL: the context creates its own
+     * non-blocking stream.  A caller's stream is never destroyed by the
+     * library, and every call that returns host results waits for it.
+     * dev_alloc / dev_free: when both are set, every device buffer of the
+     * context (trajectory checkpoints, Krylov bases, warm-start model and
+     * work storage) is obtained as dev_alloc(bytes, user), which returns
+     * device memory of at least that size, 256-byte aligned, or NULL on
+     * failure (the call then fails with PA_ENOMEM), and released with
+     * dev_free(ptr, user) by pa_destroy or when the buffer is dropped;
+     * otherwise hipMalloc / hipFree.  The callbacks are called on the host
+     * thread that calls into the context. */
+    void*   stream;
+    void* (*dev_alloc)(uint64_t bytes, void* user);
+    void  (*dev_free)(void* ptr, void* user);
+    void*   user;
 } pa_config;
 
-/* Precision of the stage linear solves (Sec. 2.2 eq. dirk, each stage's
+/* Precision of the stage linear solves (Sec. 2.1 eq. dirk, each stage's
  * (M - dt a_ii dr/du) or its transpose):
  *   PA_PREC_FP64: GMRES in FP64 on the FP64 operator;
  *   PA_PREC_FP32 / PA_PREC_BF16: iterative refinement -- the residual
@@ -112,7 +129,7 @@ int64_t pa_device_bytes(const pa_ctx* ctx);
 pa_status pa_get_mesh(const pa_ctx* ctx, int32_t* elem_vert, int32_t* elem_nbr, int8_t* twin, double* vert_xy);
 
 /* kinematic parameters mu = (h0, theta0 [rad], phi [rad]) of heave
- * h0 sin(2 pi t/T) and pitch theta0 sin(2 pi t/T + phi) (Sec. 5.1 eq.
+ * h0 sin(2 pi t/T) and pitch theta0 sin(2 pi t/T + phi) (Sec. 4.1 eq.
  * defmap with one Fourier mode).  Recomputes the GCL field gbar and its
  * mu-derivatives for every stage; invalidates the trajectory. */
 pa_status pa_set_params(pa_ctx* ctx, const double mu[3]);
@@ -124,7 +141,7 @@ pa_status pa_set_freestream(pa_ctx* ctx, const double* perturb);
 /* which = 0: current u0, 1: u^(Nt) of the last primal period */
 pa_status pa_get_state(pa_ctx* ctx, int32_t which, double* out, int64_t n);
 
-/* One primal period from u0 (Sec. 2.3 eq. dirk2): Newton per stage, stores
+/* One primal period from u0 (Sec. 2.2 eq. dirk2): Newton per stage, stores
  * the trajectory (u^(n), k_i^(n), u_i^(n), dr/du and the block-Jacobi
  * inverses of every stage) on the device.  qoi[2] = time-averaged
  * (power, x-force); res = ||u^(Nt) - u0||_2.  Either output may be NULL. */
@@ -138,6 +155,18 @@ typedef struct pa_shoot_report {
     int64_t stage_gmres_its;    /* summed over all stage solves */
     double  res0, res;          /* initial and final ||u^(Nt) - u0||_2 */
     double  ms;                 /* wall time */
+    /* optional history, caller-owned host buffers of hist_cap entries (any
+     * may be NULL; set them before the call, the library keeps the
+     * pointers it was given): res_hist[k] = ||u^(Nt) - u0||_2 after Newton
+     * step k (k = 0: the start), krylov_hist[k] = tangent sweeps (outer
+     * GMRES iterations) of Newton step k + 1, step_hist[k] = the accepted
+     * line-search step of Newton step k + 1.  Entries past min(newton_its +
+     * 1, hist_cap) (res_hist) or min(newton_its, hist_cap) (the others) are
+     * left as they were. */
+    double*  res_hist;
+    int32_t* krylov_hist;
+    double*  step_hist;
+    int32_t  hist_cap;
 } pa_shoot_report;
 
 /* Newton-Krylov shooting (Alg. 2 with the Jacobian Phi - I of eq. jac-prim)
@@ -155,7 +184,7 @@ pa_status pa_shoot(pa_ctx* ctx, double tol, double eta, int32_t maxit, pa_shoot_
 pa_status pa_fixed_point(pa_ctx* ctx, int32_t periods, double* res);
 
 /* Shooting as the unconstrained minimisation of j(u0) = 1/2 ||u^(Nt)(u0) -
- * u0||_2^2 (Sec. 2.3 eq. opt-obj), the gradient-based alternative to Alg. 1
+ * u0||_2^2 (Sec. 2.2 eq. opt-obj), the gradient-based alternative to Alg. 1
  * and 2: memory = 0 is steepest descent, memory = 1..32 L-BFGS with that
  * many correction pairs.  Each iterate's gradient costs one backward
  * (adjoint) sweep (eq. uns-disc-adj-dirk started from lam^(Nt) = u^(Nt) -
@@ -198,7 +227,7 @@ typedef struct pa_adjoint_report {
 pa_status pa_adjoint_gradient(pa_ctx* ctx, double rtol, double qoi[2], double dJdmu[6], pa_adjoint_report* rep);
 
 /* Direct (tangent) gradient about the stored periodic trajectory, the
- * dual of pa_adjoint_gradient (Sec. 2.3: eq. dirk-sens-mvp with the
+ * dual of pa_adjoint_gradient (Sec. 2.2: eq. dirk-sens-mvp with the
  * parameter forcing dt dr/dmu_k at every stage; the periodic tangent solves
  * (Phi - I) du0_k = -s_k with s_k the forced sweep from zero).  The three
  * parameter tangents ride in the same sweeps.  dJdmu[2*3] (QoI-major),
@@ -292,22 +321,40 @@ typedef struct pa_ws_opts {
 } pa_ws_opts;
 
 /* Learned warm start for shooting (a start closer to the periodic orbit cuts
- * Newton-Krylov steps, Sec. 2.3).  Training data: S method-generated periodic
- * initial states (e.g. from pa_batch_gradients) and their parameters,
- * params[S][3], states[S][N_u] (host).  Builds the POD of the centred states
- * on the device (method of snapshots) and trains, on the device with FP32
- * kernels, a perceptron from normalised parameters to normalised POD
- * coefficients by full-batch Adam on the mean squared error; *final_loss
- * (may be NULL) receives the last training loss.  Replaces any previous model. */
+ * Newton-Krylov steps, Sec. 2.2).  Training data: S method-generated periodic
+ * initial states (e.g. from pa_batch_gradients, or prolonged from a coarser
+ * discretisation with pa_prolong) and the inputs they were computed with,
+ * params[S][4] = (h0, theta0, phi, Mach), states[S][N_u] (host).  Each
+ * state's own free stream gbar(0) U_inf(Mach) is removed, then the POD of the
+ * centred deviations is built on the device (method of snapshots) and a
+ * perceptron from the normalised inputs to normalised POD coefficients is
+ * trained on the device with FP32 kernels by full-batch Adam on the mean
+ * squared error; *final_loss (may be NULL) receives the last training loss.
+ * Replaces any previous model.  PA_EINVAL for a non-positive Mach number. */
 pa_status pa_ws_train(pa_ctx* ctx, const double* params, const double* states, int32_t S, const pa_ws_opts* opts,
                       double* final_loss);
-/* u0 = mean + POD modes x predicted coefficients for mu[3]; invalidates the
+/* u0 = gbar(0) U_inf + mean deviation + POD modes x the coefficients
+ * predicted for (mu[3], this context's Mach number); invalidates the
  * trajectory.  PA_ESTATE without a model. */
 pa_status pa_ws_predict(pa_ctx* ctx, const double mu[3]);
+/* the trained POD (FP64): mean[N_u] deviation from the free stream, modes
+ * [min(kmax, k)][N_u] (orthonormal), eig[min(kmax, k)] the eigenvalues of
+ * the snapshots' Gram matrix (descending); *k receives the number of modes
+ * kept.  Any output may be NULL.  PA_ESTATE without a model. */
+pa_status pa_ws_pod(pa_ctx* ctx, int32_t kmax, double* mean, double* modes, double* eig, int32_t* k);
 /* pa_shoot from the predicted state for the current parameters; when the
  * first Newton step fails or does not lower ||u^(Nt) - u0||, shooting starts
- * again from the free stream (*fell_back = 1).  The report sums both runs. */
+ * again from the free stream (*fell_back = 1).  The report sums both runs;
+ * its history buffers describe the last one. */
 pa_status pa_ws_shoot(pa_ctx* ctx, double tol, double eta, int32_t maxit, pa_shoot_report* rep, int32_t* fell_back);
+/* Prolongation for warm starts across discretisations (orbits computed on a
+ * coarse O-grid used as snapshots of a finer one): u_fine[N_u of fine]
+ * (host) = the coarse DG state u_coarse (host, canonical order of the
+ * discretisation `coarse`, which must share r_far and stretch with fine)
+ * evaluated at every node of `fine` in the fixed reference domain, from the
+ * coarse triangle containing the node.  Host-only work; `fine` provides the
+ * node coordinates.  PA_EINVAL for a NULL argument or mismatched grids. */
+pa_status pa_prolong(const pa_config* coarse, const double* u_coarse, pa_ctx* fine, double* u_fine);
 /* model file (binary, this library's layout); load checks N_u */
 pa_status pa_ws_save(pa_ctx* ctx, const char* path);
 pa_status pa_ws_load(pa_ctx* ctx, const char* path);
@@ -322,7 +369,11 @@ enum {
     PA_K_BLOCKINV = 4,  /* diagonal-block LU/inverse and operator formation */
     PA_K_SPMV_LO = 5,   /* low-precision stage-operator apply (mixed-precision modes) */
     PA_K_SPMV_T = 6,    /* FP64 stage-operator apply, transposed */
-    PA_K_COUNT = 7
+    PA_K_SPMV_M = 7,    /* FP64 forward apply carrying several right-hand sides in one launch */
+    PA_K_SPMV_TM = 8,   /* FP64 transposed apply carrying several right-hand sides in one launch */
+    PA_K_MDOT = 9,      /* stage GMRES: multi-column dot-product partials */
+    PA_K_GMUPD = 10,    /* stage GMRES: final sums, Givens update and next basis vector */
+    PA_K_COUNT = 11
 };
 /* when on, every 8th launch of each listed kernel is bracketed by HIP events
  * on the library's stream; pa_kernel_time returns the launch count since
@@ -330,7 +381,8 @@ enum {
 pa_status pa_set_timing(pa_ctx* ctx, int32_t on);
 pa_status pa_kernel_time(pa_ctx* ctx, int32_t kernel, double* total_ms, int64_t* launches);
 /* of those launches, the stage-operator applies (PA_K_SPMV, PA_K_SPMV_T,
- * PA_K_SPMV_LO) that returned at once without work: GMRES enqueues several
+ * PA_K_SPMV_LO, PA_K_SPMV_M, PA_K_SPMV_TM) and the FP64 stage-GMRES vector
+ * kernels (PA_K_MDOT, PA_K_GMUPD) that returned at once without work: GMRES enqueues several
  * iterations ahead of its host-side convergence check, and an apply whose
  * systems have all converged exits on entry.  Bytes moved by a kernel are
  * its per-launch bytes times (launches - skipped).  0 for other kernels;
@@ -341,6 +393,10 @@ pa_status pa_kernel_skipped(pa_ctx* ctx, int32_t kernel, int64_t* skipped);
  * (M - dt a_11 J) P^{-1} with P its diagonal blocks (timed with HIP events on
  * the library stream; needs a stored trajectory) */
 pa_status pa_bench_spmv(pa_ctx* ctx, int32_t reps, int32_t transpose, double* avg_ms);
+/* as pa_bench_spmv for the apply that carries nrhs (1..8) right-hand sides
+ * in one launch (the form the lockstep solves of several systems use); the
+ * stored blocks are read once per launch for all of them */
+pa_status pa_bench_spmv_m(pa_ctx* ctx, int32_t reps, int32_t transpose, int32_t nrhs, double* avg_ms);
 /* tile shape of the FP64 forward apply: chunks of 16 bytes per lane task
  * (1, 2 or 4; 0 = built-in default) and, after autotuning, the measured
  * microseconds per launch of each shape (-1: not valid for this block size,

@@ -1,7 +1,7 @@
 // Device-side arithmetic for the periodic-adjoint HIP library (gfx950).
 //
 // * forward-mode dual numbers (exact pointwise Jacobians and mu-derivatives)
-// * compressible Navier-Stokes fluxes (arXiv:1512.00616 Sec. 5, eqs. ns1-ns5)
+// * compressible Navier-Stokes fluxes (arXiv:1512.00616 Sec. 4, eqs. ns1-ns5)
 //   and their ALE pull-back to the fixed reference domain (eqs. ns-cons-ref,
 //   transform1-nogcl, transform2-nogcl) with the GCL-consistent factor gbar
 // * the numerical fluxes and boundary conditions of the discretisation

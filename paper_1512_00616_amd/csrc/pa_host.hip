@@ -2,7 +2,7 @@
 //
 // Implements, on one MI355X, the fully discrete time-periodic adjoint method
 // of arXiv:1512.00616:
-//   primal period (Sec. 2.3 eq. dirk2): per DIRK stage a Newton solve with
+//   primal period (Sec. 2.2 eq. dirk2): per DIRK stage a Newton solve with
 //     the exact Jacobian and block-Jacobi GMRES;
 //   tangent sweep (eq. dirk-sens-mvp) = matvec of Newton-Krylov shooting
 //     (Alg. 2, Jacobian Phi - I of eq. jac-prim);
@@ -217,7 +217,7 @@ void build_ref(Ref<P>& R)
 }
 
 // Alexander's three-stage, L-stable, stiffly accurate DIRK of order 3
-// (reading of the third-order DIRK of Sec. 5.1; the paper gives no tableau)
+// (reading of the third-order DIRK of Sec. 4.1; the paper gives no tableau)
 struct Dirk3 {
     double A[3][3], b[3], c[3];
     Dirk3()
@@ -246,50 +246,130 @@ inline int grid1(int64_t n, int bs = 256) { return (int)((n + bs - 1) / bs); }
 // Multilayer perceptron on the device (FP32): widths dims[0] -> ... -> dims[L],
 // tanh on hidden layers, linear output, parameters flat [W_1 b_1 W_2 b_2 ...]
 // with W_l [dims[l]][dims[l-1]] row-major; batches column-major [feature][sample].
-struct Mlp {
-    std::vector<int> dims;
-    std::vector<int64_t> woff, boff;
-    int64_t nparam = 0;
-    int cap = 0, maxw = 0;
-    float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
-    float *X = nullptr, *T = nullptr, *dA = nullptr, *dB = nullptr, *loss = nullptr;
-    std::vector<float*> H;
-    hipStream_t st = nullptr;
-    int step = 0;
-    static void fr(float*& q) { if (q) (void)hipFree(q); q = nullptr; }
-    static float* al(int64_t n)
+// Device memory of a context: the caller's callbacks (pa_config dev_alloc /
+// dev_free) when both are given, else hipMalloc / hipFree.
+struct DevAlloc {
+    void* (*fa)(uint64_t, void*) = nullptr;
+    void (*ff)(void*, void*) = nullptr;
+    void* user = nullptr;
+    void* get(size_t bytes) const
     {
-        float* q = nullptr;
-        hipError_t e = hipMalloc((void**)&q, sizeof(float) * (size_t)std::max<int64_t>(n, 1));
-        if (e != hipSuccess) raise(PA_ENOMEM, "hipMalloc failed: %s", hipGetErrorString(e));
+        if (bytes == 0) bytes = 1;
+        if (fa && ff) {
+            void* q = fa((uint64_t)bytes, user);
+            if (!q) raise(PA_ENOMEM, "device allocation callback returned NULL for %.3f GB", bytes / 1e9);
+            return q;
+        }
+        void* q = nullptr;
+        const hipError_t e = hipMalloc(&q, bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            raise(PA_ENOMEM, "hipMalloc of %.3f GB failed: %s", bytes / 1e9, hipGetErrorString(e));
+        }
         return q;
     }
+    void put(void* q) const
+    {
+        if (!q) return;
+        if (fa && ff) ff(q, user);
+        else (void)hipFree(q);
+    }
+};
+
+// Shape of the perceptron in -> w -> w -> w -> out: parameter offsets in the
+// flat layout [W1 b1 W2 b2 W3 b3 W4 b4] (W_l row-major [out_l][in_l]).
+struct MlpShape {
+    int dims[5] = { 0, 0, 0, 0, 0 };
+    int64_t woff[4] = { 0, 0, 0, 0 }, boff[4] = { 0, 0, 0, 0 };
+    int64_t nparam = 0;
+    int maxw = 0;
+    MlpShape() = default;
+    MlpShape(int in, int width, int out)
+    {
+        const int d[5] = { in, width, width, width, out };
+        for (int l = 0; l < 5; ++l) dims[l] = d[l];
+        for (int l = 0; l < 4; ++l) {
+            woff[l] = nparam;
+            nparam += (int64_t)dims[l + 1] * dims[l];
+            boff[l] = nparam;
+            nparam += dims[l + 1];
+            maxw = std::max(maxw, std::max(dims[l], dims[l + 1]));
+        }
+    }
+};
+
+// One pass of the perceptron on raw device buffers (no allocation): forward
+// into the activations H[0..3] ([dims[l+1]][S]), the mean squared error
+// against T with dY in dA, and the gradients into g (dA, dB [maxw][S] are
+// work buffers).
+inline void mlp_gemm(int M, int N, int K, const float* A, int tA, const float* B, int tB, float* C, hipStream_t st)
+{
+    dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
+    k_gemm_f32<<<grid, GT * GT, 0, st>>>(M, N, K, 1.0f, A, tA, B, tB, 0.0f, C);
+    LAUNCHCHK();
+}
+inline void mlp_forward(const MlpShape& sh, const float* p, const float* X, float* const H[4], int S, hipStream_t st)
+{
+    const float* in = X;
+    for (int l = 0; l < 4; ++l) {
+        mlp_gemm(sh.dims[l + 1], S, sh.dims[l], p + sh.woff[l], 0, in, 0, H[l], st);
+        k_bias_act<<<grid1((int64_t)sh.dims[l + 1] * S), 256, 0, st>>>(H[l], p + sh.boff[l], sh.dims[l + 1], S, l < 3);
+        LAUNCHCHK();
+        in = H[l];
+    }
+}
+inline void mlp_mse(const MlpShape& sh, const float* const H[4], const float* T, float* dA, int S, float* loss,
+                    hipStream_t st)
+{
+    k_mse<<<1, 256, 0, st>>>(H[3], T, dA, (int64_t)sh.dims[4] * S, loss);
+    LAUNCHCHK();
+}
+inline void mlp_backward(const MlpShape& sh, const float* p, const float* X, const float* const H[4], float* dA,
+                         float* dB, float* g, int S, hipStream_t st)
+{
+    float* cur = dA;
+    for (int l = 3; l >= 0; --l) {
+        const float* in = l == 0 ? X : H[l - 1];
+        mlp_gemm(sh.dims[l + 1], sh.dims[l], S, cur, 0, in, 1, g + sh.woff[l], st);
+        k_row_sum<<<grid1(sh.dims[l + 1]), 256, 0, st>>>(cur, g + sh.boff[l], sh.dims[l + 1], S);
+        LAUNCHCHK();
+        if (l > 0) {
+            float* nxt = cur == dA ? dB : dA;
+            mlp_gemm(sh.dims[l], S, sh.dims[l + 1], p + sh.woff[l], 1, cur, 0, nxt, st);
+            k_tanh_back<<<grid1((int64_t)sh.dims[l] * S), 256, 0, st>>>(nxt, H[l - 1], (int64_t)sh.dims[l] * S);
+            LAUNCHCHK();
+            cur = nxt;
+        }
+    }
+}
+
+struct Mlp {
+    MlpShape sh;
+    int64_t nparam = 0;
+    int cap = 0;
+    float *p = nullptr, *g = nullptr, *m = nullptr, *v = nullptr;
+    float *X = nullptr, *T = nullptr, *dA = nullptr, *dB = nullptr, *loss = nullptr;
+    float* H[4] = { nullptr, nullptr, nullptr, nullptr };
+    hipStream_t st = nullptr;
+    int step = 0;
+    DevAlloc da;
+    void fr(float*& q) { da.put(q); q = nullptr; }
+    float* al(int64_t n) { return static_cast<float*>(da.get(sizeof(float) * (size_t)std::max<int64_t>(n, 1))); }
     void release()
     {
         fr(p); fr(g); fr(m); fr(v); fr(X); fr(T); fr(dA); fr(dB); fr(loss);
         for (auto& h : H) fr(h);
-        H.clear();
         cap = 0;
     }
     ~Mlp() { release(); }
-    void init(const std::vector<int>& d, hipStream_t s)
+    int width() const { return sh.dims[1]; }
+    void init(int in, int width, int out, hipStream_t s)
     {
         release();
-        dims = d;
+        sh = MlpShape(in, width, out);
+        nparam = sh.nparam;
         st = s;
         step = 0;
-        const int L = (int)d.size() - 1;
-        woff.assign(L, 0);
-        boff.assign(L, 0);
-        nparam = 0;
-        maxw = 0;
-        for (int l = 0; l < L; ++l) {
-            woff[l] = nparam;
-            nparam += (int64_t)d[l + 1] * d[l];
-            boff[l] = nparam;
-            nparam += d[l + 1];
-            maxw = std::max(maxw, std::max(d[l], d[l + 1]));
-        }
         p = al(nparam); g = al(nparam); m = al(nparam); v = al(nparam);
         HIPCHK(hipMemsetAsync(m, 0, sizeof(float) * nparam, st));
         HIPCHK(hipMemsetAsync(v, 0, sizeof(float) * nparam, st));
@@ -300,59 +380,19 @@ struct Mlp {
         if (batch <= cap) return;
         for (auto& h : H) fr(h);
         fr(X); fr(T); fr(dA); fr(dB);
-        const int L = (int)dims.size() - 1;
-        H.assign(L, nullptr);
-        for (int l = 0; l < L; ++l) H[l] = al((int64_t)dims[l + 1] * batch);
-        X = al((int64_t)dims[0] * batch);
-        T = al((int64_t)dims[L] * batch);
-        dA = al((int64_t)maxw * batch);
-        dB = al((int64_t)maxw * batch);
+        for (int l = 0; l < 4; ++l) H[l] = al((int64_t)sh.dims[l + 1] * batch);
+        X = al((int64_t)sh.dims[0] * batch);
+        T = al((int64_t)sh.dims[4] * batch);
+        dA = al((int64_t)sh.maxw * batch);
+        dB = al((int64_t)sh.maxw * batch);
         cap = batch;
     }
-    void gemm(int M, int N, int K, const float* A, int tA, const float* B, int tB, float* C)
-    {
-        dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
-        k_gemm_f32<<<grid, GT * GT, 0, st>>>(M, N, K, 1.0f, A, tA, B, tB, 0.0f, C);
-        LAUNCHCHK();
-    }
-    const float* out() const { return H.back(); }
-    void forward(int S)
-    {
-        const int L = (int)dims.size() - 1;
-        const float* in = X;
-        for (int l = 0; l < L; ++l) {
-            gemm(dims[l + 1], S, dims[l], p + woff[l], 0, in, 0, H[l]);
-            k_bias_act<<<grid1((int64_t)dims[l + 1] * S), 256, 0, st>>>(H[l], p + boff[l], dims[l + 1], S, l < L - 1);
-            LAUNCHCHK();
-            in = H[l];
-        }
-    }
+    const float* out() const { return H[3]; }
+    void forward(int S) { mlp_forward(sh, p, X, H, S, st); }
     // loss and dY = d loss / d output into dA
-    void mse(int S)
-    {
-        const int L = (int)dims.size() - 1;
-        k_mse<<<1, 256, 0, st>>>(H[L - 1], T, dA, (int64_t)dims[L] * S, loss);
-        LAUNCHCHK();
-    }
+    void mse(int S) { mlp_mse(sh, H, T, dA, S, loss, st); }
     // gradients into g from dY in dA (after forward and mse)
-    void backward(int S)
-    {
-        const int L = (int)dims.size() - 1;
-        float* cur = dA;
-        for (int l = L - 1; l >= 0; --l) {
-            const float* in = l == 0 ? X : H[l - 1];
-            gemm(dims[l + 1], dims[l], S, cur, 0, in, 1, g + woff[l]);
-            k_row_sum<<<grid1(dims[l + 1]), 256, 0, st>>>(cur, g + boff[l], dims[l + 1], S);
-            LAUNCHCHK();
-            if (l > 0) {
-                float* nxt = cur == dA ? dB : dA;
-                gemm(dims[l], S, dims[l + 1], p + woff[l], 1, cur, 0, nxt);
-                k_tanh_back<<<grid1((int64_t)dims[l] * S), 256, 0, st>>>(nxt, H[l - 1], (int64_t)dims[l] * S);
-                LAUNCHCHK();
-                cur = nxt;
-            }
-        }
-    }
+    void backward(int S) { mlp_backward(sh, p, X, H, dA, dB, g, S, st); }
     void adam(float lr)
     {
         ++step;
@@ -485,6 +525,7 @@ inline void sym_eig(std::vector<double>& A, int n, std::vector<double>& w, std::
 struct pa_ctx {
     pa_config cfg;
     std::string err;
+    DevAlloc da;
     virtual ~pa_ctx() {}
     virtual int64_t num_dofs() const = 0;
     virtual int32_t num_elems() const = 0;
@@ -507,6 +548,8 @@ struct pa_ctx {
     virtual void ws_predict(const double m[3]) = 0;
     virtual void ws_shoot(double tol, double eta, int maxit, pa_shoot_report* rep, int32_t* fell_back) = 0;
     virtual void ws_save(const char* path) = 0;
+    virtual int ws_pod(int kmax, double* mean, double* modes, double* eig) = 0;
+    virtual void node_coords(double* xy) const = 0;
     virtual void ws_load(const char* path) = 0;
     virtual void tangent_sweep_h(const double* v, double* out) = 0;
     virtual void adjoint_sweep_h(const double* lam, int fq, double* lam0, double* grad) = 0;
@@ -522,6 +565,7 @@ struct pa_ctx {
     virtual void kernel_time(int k, double* ms, int64_t* cnt) = 0;
     virtual int64_t kernel_skipped(int k) = 0;
     virtual double bench_spmv(int reps, int tr) = 0;
+    virtual double bench_spmv_m(int reps, int tr, int R) = 0;
     virtual double bench_spmv_lo(int reps, int tr) = 0;
     virtual void tuning(int32_t* q, double us[3]) = 0;
     virtual double bench_copy(int reps, int64_t* bytes) = 0;
@@ -562,7 +606,9 @@ struct Solver final : pa_ctx {
     Ref<P> href{};
 
     hipStream_t st = nullptr;
+    bool own_stream = false;
     DevMesh dm{};
+    const int4 *nb4f = nullptr, *nb4t = nullptr;   // face tables of the applies
     Ref<P>* dref = nullptr;
     double* dmh = nullptr;
     int32_t* dwall = nullptr;
@@ -597,13 +643,8 @@ struct Solver final : pa_ctx {
     template <class T>
     T* dalloc(int64_t n)
     {
-        void* p = nullptr;
         if (n <= 0) n = 1;
-        hipError_t e = hipMalloc(&p, sizeof(T) * (size_t)n);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            raise(PA_ENOMEM, "hipMalloc of %.3f GB failed: %s", sizeof(T) * (double)n / 1e9, hipGetErrorString(e));
-        }
+        void* p = da.get(sizeof(T) * (size_t)n);
         allocs.push_back(p);
         bytes += sizeof(T) * n;
         return static_cast<T*>(p);
@@ -612,8 +653,16 @@ struct Solver final : pa_ctx {
     explicit Solver(const pa_config& c)
     {
         cfg = c;
+        da.fa = c.dev_alloc;
+        da.ff = c.dev_free;
+        da.user = c.user;
+        mlp.da = da;
         HIPCHK(hipSetDevice(c.device));
-        HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+        if (c.stream) st = static_cast<hipStream_t>(c.stream);
+        else {
+            HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
+            own_stream = true;
+        }
         Nt = c.Nt;
         nst = 3 * Nt;
         dt = c.T / c.Nt;
@@ -638,12 +687,12 @@ struct Solver final : pa_ctx {
     {
         if (st) (void)hipStreamSynchronize(st);
         for (auto& e : evpool) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
-        for (void* p : allocs) (void)hipFree(p);
+        for (void* p : allocs) da.put(p);
         if (hstat) (void)hipHostFree(hstat);
         if (hstm) (void)hipHostFree(hstm);
         for (auto& e : gm_ev)
             if (e) (void)hipEventDestroy(e);
-        if (st) (void)hipStreamDestroy(st);
+        if (st && own_stream) (void)hipStreamDestroy(st);
     }
 
     // O-grid around the unit circle: radii 1 + (r_far - 1)(q^i - 1)/(q^Nr - 1),
@@ -743,6 +792,9 @@ struct Solver final : pa_ctx {
         nwall = (int)wall.size();
     }
 
+    // reference-domain coordinates of every element node [Ne][NP][2]
+    void node_coords(double* xy) const override { std::memcpy(xy, xn.data(), sizeof(double) * 2 * nn); }
+
     // host <-> device copies are ordered on the library stream (which does not
     // synchronise with the null stream) and complete before returning
     void h2d(void* dst, const void* src, size_t bytes)
@@ -776,6 +828,30 @@ struct Solver final : pa_ctx {
         dm.wbl = upload_vec(wbl);
         dm.elen = upload_vec(elen);
         dm.enrm = upload_vec(enrm);
+        // face tables of the stage-operator applies (one int4 per element):
+        // neighbours / transposed block indices, boundary faces pointing at
+        // the element itself and its own (zero) slot, bit f of .w = interior
+        {
+            std::vector<int4> f4(Ne), t4(Ne);
+            for (int K = 0; K < Ne; ++K) {
+                int nbv[3], tbv[3], mask = 0;
+                for (int f = 0; f < 3; ++f) {
+                    const int nb = enb[3 * K + f];
+                    if (nb >= 0) {
+                        mask |= 1 << f;
+                        nbv[f] = nb;
+                        tbv[f] = 3 * nb + etw[3 * K + f];
+                    } else {
+                        nbv[f] = K;
+                        tbv[f] = 3 * K + f;
+                    }
+                }
+                f4[K] = make_int4(nbv[0], nbv[1], nbv[2], mask);
+                t4[K] = make_int4(tbv[0], tbv[1], tbv[2], mask);
+            }
+            nb4f = upload_vec(f4);
+            nb4t = upload_vec(t4);
+        }
         dref = dalloc<Ref<P>>(1);
         h2d(dref, &href, sizeof(Ref<P>));
         std::vector<double> mhf(NP * NP);
@@ -979,14 +1055,14 @@ struct Solver final : pa_ctx {
     void launch_fwd(int q, const double* Ah, const double* x, double* y, const int* skip)
     {
         if (q == 1 && ahat_fwd_valid<NP, double>(1))
-            k_ahat_fwd<NP, double, double, 1><<<Ne, 64, 0, st>>>(Ne, dm.enb, Ah, x, y, skip);
+            k_ahat_fwd<NP, double, double, 1><<<Ne, 64, 0, st>>>(Ne, nb4f, Ah, x, y, skip);
         else if (q == 2 && ahat_fwd_valid<NP, double>(2))
-            k_ahat_fwd<NP, double, double, 2><<<Ne, 64, 0, st>>>(Ne, dm.enb, Ah, x, y, skip);
+            k_ahat_fwd<NP, double, double, 2><<<Ne, 64, 0, st>>>(Ne, nb4f, Ah, x, y, skip);
         else if (q == 4 && ahat_fwd_valid<NP, double>(4)) {
             if constexpr (ahat_fwd_valid<NP, double>(4))
-                k_ahat_fwd<NP, double, double, 4><<<Ne, 64, 0, st>>>(Ne, dm.enb, Ah, x, y, skip);
+                k_ahat_fwd<NP, double, double, 4><<<Ne, 64, 0, st>>>(Ne, nb4f, Ah, x, y, skip);
         } else
-            k_ahat_fwd<NP, double, double><<<Ne, 64, 0, st>>>(Ne, dm.enb, Ah, x, y, skip);
+            k_ahat_fwd<NP, double, double><<<Ne, 64, 0, st>>>(Ne, nb4f, Ah, x, y, skip);
     }
     // autotune (pa_config.autotune): time each valid tile shape on the first
     // stored stage operator (after its formation, 10 launches each, HIP
@@ -1034,7 +1110,7 @@ struct Solver final : pa_ctx {
     {
         hipEvent_t e;
         tstart(tr ? PA_K_SPMV_T : PA_K_SPMV, &e);
-        if (tr) k_ahat_tr<NP, double, double><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, Ah, x, y, skip);
+        if (tr) k_ahat_tr<NP, double, double><<<Ne, 64, 0, st>>>(Ne, nb4t, Ah, x, y, skip);
         else launch_fwd(fwd_q, Ah, x, y, skip);
         LAUNCHCHK();
         tstop(e);
@@ -1045,16 +1121,16 @@ struct Solver final : pa_ctx {
         tstart(PA_K_SPMV_LO, &e);
         if (tr) {
             if (pmode == PA_PREC_FP32)
-                k_ahat_tr<NP, float, float><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, (const float*)Al, x, y, skip);
+                k_ahat_tr<NP, float, float><<<Ne, 64, 0, st>>>(Ne, nb4t, (const float*)Al, x, y, skip);
             else if constexpr (B % 8 == 0)
-                k_ahat_tr<NP, bf16_t, float><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, (const bf16_t*)Al, x, y, skip);
+                k_ahat_tr<NP, bf16_t, float><<<Ne, 64, 0, st>>>(Ne, nb4t, (const bf16_t*)Al, x, y, skip);
             else   // 16-byte BF16 chunks would straddle rows
                 k_ahat_apply_lo<NP, bf16_t><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, (const bf16_t*)Al, x, y, tr, skip);
         } else {
             if (pmode == PA_PREC_FP32)
-                k_ahat_fwd<NP, float, float><<<Ne, 64, 0, st>>>(Ne, dm.enb, (const float*)Al, x, y, skip);
+                k_ahat_fwd<NP, float, float><<<Ne, 64, 0, st>>>(Ne, nb4f, (const float*)Al, x, y, skip);
             else if constexpr (B % 8 == 0)
-                k_ahat_fwd<NP, bf16_t, float><<<Ne, 64, 0, st>>>(Ne, dm.enb, (const bf16_t*)Al, x, y, skip);
+                k_ahat_fwd<NP, bf16_t, float><<<Ne, 64, 0, st>>>(Ne, nb4f, (const bf16_t*)Al, x, y, skip);
             else   // 16-byte BF16 chunks would straddle rows
                 k_ahat_apply_lo<NP, bf16_t><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, (const bf16_t*)Al, x, y, tr, skip);
         }
@@ -1238,8 +1314,13 @@ struct Solver final : pa_ctx {
                 ahat(op.Ah, tr, vj, w, skip);
                 ++launched;
                 // one classical Gram-Schmidt pass; the cycle closes on cancellation
+                hipEvent_t e;
+                tstart(PA_K_MDOT, &e);
                 k_mdot_part<<<dim3(nb, mdot_chunks(j + 2)), MD_THREADS, 0, st>>>(V, Nu, j + 1, 1, w, Nu, part, gms);
+                tstop(e);
+                tstart(PA_K_GMUPD, &e);
                 k_gm_upd<<<nb, MD_THREADS, 0, st>>>(V, Nu, j, m, w, Nu, part, nb, gms);
+                tstop(e);
                 LAUNCHCHK();
                 if ((j + 1) % GM_CHECK == 0 && j < m - 1) {
                     if (pending >= 0) {
@@ -1267,6 +1348,8 @@ struct Solver final : pa_ctx {
             const bool done = hstat[2].done != 0;
             total += done ? hstat[2].its : m;
             tskip(tr ? PA_K_SPMV_T : PA_K_SPMV, launched - (done ? hstat[2].its : m));
+            tskip(PA_K_MDOT, launched - (done ? hstat[2].its : m));
+            tskip(PA_K_GMUPD, launched - (done ? hstat[2].its : m));
             if (done && !std::isfinite(hstat[2].res)) raise(PA_ENUMERIC, "NaN in stage GMRES");
             if (!std::isfinite(rn)) raise(PA_ENUMERIC, "NaN in stage GMRES");
             if (done && rn <= 2.0 * tol) break;
@@ -1363,8 +1446,27 @@ struct Solver final : pa_ctx {
     double *ws_mean = nullptr, *ws_psi = nullptr;
     float* ws_cs = nullptr;                   // device coefficient scales [ws_k]
     std::vector<float> ws_cs_h;
-    float ws_xm[3] = { 0, 0, 0 }, ws_xs[3] = { 1, 1, 1 };
+    // perceptron inputs (h0, theta0, phi, Mach): normalisation offsets and scales
+    static constexpr int WS_NIN = 4;
+    float ws_xm[WS_NIN] = { 0, 0, 0, 0 }, ws_xs[WS_NIN] = { 1, 1, 1, 1 };
+    std::vector<double> ws_lam;               // Gram-matrix eigenvalues of the kept modes
     static constexpr int WS_MAXK = 128;
+    // free stream gbar(0; m) U_inf(mach) at t = 0 for kinematics m, into out [Nu]
+    void freestream_for(const double m[3], double mach, double* out)
+    {
+        Motion<double> mo;
+        const double w = 2.0 * M_PI / cfg.T;
+        mo.h = 0.0;
+        mo.hd = m[0] * w;
+        mo.th = m[1] * std::sin(m[2]);
+        mo.thd = m[1] * w * std::cos(m[2]);
+        k_gbar0<P, double><<<Ne, 64, 0, st>>>(dm, dref, mo, rg4, nn);
+        LAUNCHCHK();
+        const double pinf = 1.0 / (cfg.gamma * mach * mach);
+        const double4 Ui{ 1.0, 1.0, 0.0, pinf / (cfg.gamma - 1.0) + 0.5 };
+        k_scale_state<<<grid1(nn), 256, 0, st>>>(rg4, Ui, out, nn);
+        LAUNCHCHK();
+    }
     void ws_alloc()
     {
         if (ws_mean) return;
@@ -1377,11 +1479,17 @@ struct Solver final : pa_ctx {
         if (S < 2 || !params || !states) raise(PA_EINVAL, "need at least two training states");
         if (o.modes < 1 || o.width < 1 || o.epochs < 0 || !(o.lr > 0)) raise(PA_EINVAL, "bad warm-start options");
         ws_alloc();
-        double* D = nullptr;
-        if (hipMalloc((void**)&D, sizeof(double) * (size_t)S * Nu) != hipSuccess) raise(PA_ENOMEM, "snapshot storage");
-        struct Free { double* q; ~Free() { (void)hipFree(q); } } fd{ D };
+        double* D = static_cast<double*>(da.get(sizeof(double) * (size_t)S * Nu));
+        struct Free { const DevAlloc& a; double* q; ~Free() { a.put(q); } } fd{ da, D };
         h2d(D, states, sizeof(double) * (size_t)S * Nu);
-        // mean and centred snapshots
+        // deviation of each snapshot from the free stream of its own
+        // kinematics and Mach number, then mean and centred snapshots
+        for (int i = 0; i < S; ++i) {
+            const double* pm = params + (size_t)WS_NIN * i;
+            if (!(pm[3] > 0.0)) raise(PA_EINVAL, "training Mach number must be positive");
+            freestream_for(pm, pm[3], wf);
+            axpby(-1.0, wf, 1.0, D + (int64_t)i * Nu);
+        }
         zero(ws_mean);
         for (int i = 0; i < S; ++i) axpby(1.0 / S, D + (int64_t)i * Nu, 1.0, ws_mean);
         for (int i = 0; i < S; ++i) axpby(-1.0, ws_mean, 1.0, D + (int64_t)i * Nu);
@@ -1396,6 +1504,7 @@ struct Solver final : pa_ctx {
         while (k > 1 && !(lam[k - 1] > 1e-13 * lam[0])) --k;
         if (!(lam[0] > 0.0)) raise(PA_EINVAL, "training states are all equal");
         ws_k = k;
+        ws_lam.assign(lam.begin(), lam.begin() + k);
         ws_cs_h.assign(k, 0.0f);
         std::vector<double> coef(S);
         std::vector<float> Th((size_t)k * S);
@@ -1411,26 +1520,26 @@ struct Solver final : pa_ctx {
         }
         h2d(ws_cs, ws_cs_h.data(), sizeof(float) * k);
         // normalised inputs
-        std::vector<float> Xh((size_t)3 * S);
-        for (int c = 0; c < 3; ++c) {
+        std::vector<float> Xh((size_t)WS_NIN * S);
+        for (int c = 0; c < WS_NIN; ++c) {
             double mean = 0, var = 0;
-            for (int i = 0; i < S; ++i) mean += params[3 * i + c];
+            for (int i = 0; i < S; ++i) mean += params[WS_NIN * i + c];
             mean /= S;
-            for (int i = 0; i < S; ++i) var += (params[3 * i + c] - mean) * (params[3 * i + c] - mean);
+            for (int i = 0; i < S; ++i) var += (params[WS_NIN * i + c] - mean) * (params[WS_NIN * i + c] - mean);
             const double sd = std::sqrt(var / S);
             ws_xm[c] = (float)mean;
             ws_xs[c] = (float)(sd > 1e-12 ? sd : 1.0);
-            for (int i = 0; i < S; ++i) Xh[(size_t)c * S + i] = (float)((params[3 * i + c] - mean) / ws_xs[c]);
+            for (int i = 0; i < S; ++i) Xh[(size_t)c * S + i] = (float)((params[WS_NIN * i + c] - mean) / ws_xs[c]);
         }
-        mlp.init({ 3, o.width, o.width, o.width, k }, st);
+        mlp.init(WS_NIN, o.width, k, st);
         std::vector<float> P0(mlp.nparam, 0.0f);
         uint64_t sd = o.seed;
-        for (size_t l = 0; l + 1 < mlp.dims.size(); ++l) {
-            const int fi = mlp.dims[l], fo = mlp.dims[l + 1];
+        for (int l = 0; l < 4; ++l) {
+            const int fi = mlp.sh.dims[l], fo = mlp.sh.dims[l + 1];
             const double a = std::sqrt(6.0 / (fi + fo));
             for (int64_t q = 0; q < (int64_t)fi * fo; ++q) {
                 const double u = (double)(splitmix64(sd) >> 11) * (1.0 / 9007199254740992.0);
-                P0[mlp.woff[l] + q] = (float)((2.0 * u - 1.0) * a);
+                P0[mlp.sh.woff[l] + q] = (float)((2.0 * u - 1.0) * a);
             }
         }
         h2d(mlp.p, P0.data(), sizeof(float) * mlp.nparam);
@@ -1453,13 +1562,18 @@ struct Solver final : pa_ctx {
     void ws_predict(const double m[3]) override
     {
         if (!ws_k) raise(PA_ESTATE, "no trained warm-start model");
-        float x[3];
-        for (int c = 0; c < 3; ++c) x[c] = (float)((m[c] - ws_xm[c]) / ws_xs[c]);
+        // inputs: the kinematics and this context's Mach number
+        const double in[WS_NIN] = { m[0], m[1], m[2], cfg.mach };
+        float x[WS_NIN];
+        for (int c = 0; c < WS_NIN; ++c) x[c] = (float)((in[c] - ws_xm[c]) / ws_xs[c]);
         mlp.reserve(1);
-        // a single column: X [3][1]
+        // a single column: X [WS_NIN][1]
         h2d(mlp.X, x, sizeof x);
         mlp.forward(1);
-        k_pod_expand<<<grid1(Nu), 256, 0, st>>>(ws_mean, ws_psi, ws_k, Nu, mlp.out(), ws_cs, u0, Nu);
+        // u0 = free stream + mean deviation + modes x coefficients
+        freestream_for(m, cfg.mach, wf);
+        axpby(1.0, ws_mean, 1.0, wf);
+        k_pod_expand<<<grid1(Nu), 256, 0, st>>>(wf, ws_psi, ws_k, Nu, mlp.out(), ws_cs, u0, Nu);
         LAUNCHCHK();
         HIPCHK(hipStreamSynchronize(st));
         have_traj = false;
@@ -1471,6 +1585,14 @@ struct Solver final : pa_ctx {
         if (!have_params) raise(PA_ESTATE, "set the parameters first");
         ws_predict(mu);
         pa_shoot_report r1{}, r2{};
+        if (rep) {   // the history describes the last shooting run
+            for (pa_shoot_report* q : { &r1, &r2 }) {
+                q->res_hist = rep->res_hist;
+                q->krylov_hist = rep->krylov_hist;
+                q->step_hist = rep->step_hist;
+                q->hist_cap = rep->hist_cap;
+            }
+        }
         bool progressed = false, converged = false;
         try {
             shoot(tol, eta, 1, &r1);
@@ -1503,6 +1625,17 @@ struct Solver final : pa_ctx {
             *rep = r;
         }
     }
+    // the trained POD: mean deviation [Nu], modes [kmax][Nu], eigenvalues [kmax]
+    int ws_pod(int kmax, double* mean, double* modes, double* eig) override
+    {
+        if (!ws_k) raise(PA_ESTATE, "no trained warm-start model");
+        const int k = std::min(kmax, ws_k);
+        if (mean) d2h(mean, ws_mean, sizeof(double) * Nu);
+        if (modes && k > 0) d2h(modes, ws_psi, sizeof(double) * (size_t)k * Nu);
+        if (eig)
+            for (int j = 0; j < k; ++j) eig[j] = ws_lam[j];
+        return ws_k;
+    }
     void ws_save(const char* path) override
     {
         if (!ws_k) raise(PA_ESTATE, "no trained warm-start model");
@@ -1513,11 +1646,12 @@ struct Solver final : pa_ctx {
         d2h(mean.data(), ws_mean, sizeof(double) * Nu);
         d2h(psi.data(), ws_psi, sizeof(double) * psi.size());
         d2h(W.data(), mlp.p, sizeof(float) * W.size());
-        const char magic[8] = { 'P', 'A', 'W', 'S', '1', 0, 0, 0 };
-        const int64_t hdr[3] = { Nu, ws_k, mlp.dims[1] };
+        const char magic[8] = { 'P', 'A', 'W', 'S', '2', 0, 0, 0 };
+        const int64_t hdr[3] = { Nu, ws_k, mlp.width() };
         bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(hdr, sizeof hdr, 1, f) == 1 &&
                   std::fwrite(ws_xm, sizeof ws_xm, 1, f) == 1 && std::fwrite(ws_xs, sizeof ws_xs, 1, f) == 1 &&
                   std::fwrite(ws_cs_h.data(), sizeof(float), ws_k, f) == (size_t)ws_k &&
+                  std::fwrite(ws_lam.data(), sizeof(double), ws_k, f) == (size_t)ws_k &&
                   std::fwrite(mean.data(), sizeof(double), Nu, f) == (size_t)Nu &&
                   std::fwrite(psi.data(), sizeof(double), psi.size(), f) == psi.size() &&
                   std::fwrite(W.data(), sizeof(float), W.size(), f) == W.size();
@@ -1531,21 +1665,22 @@ struct Solver final : pa_ctx {
         struct Close { FILE* f; ~Close() { std::fclose(f); } } cl{ f };
         char magic[8];
         int64_t hdr[3];
-        if (std::fread(magic, 1, 8, f) != 8 || std::memcmp(magic, "PAWS1", 5) != 0) raise(PA_EINVAL, "not a warm-start file");
+        if (std::fread(magic, 1, 8, f) != 8 || std::memcmp(magic, "PAWS2", 5) != 0) raise(PA_EINVAL, "not a warm-start file");
         if (std::fread(hdr, sizeof hdr, 1, f) != 1 || hdr[0] != Nu || hdr[1] < 1 || hdr[1] > WS_MAXK || hdr[2] < 1 ||
             hdr[2] > 4096)
             raise(PA_EINVAL, "warm-start file does not match this discretisation");
         const int k = (int)hdr[1], width = (int)hdr[2];
         std::vector<float> cs(k);
-        std::vector<double> mean(Nu), psi((size_t)k * Nu);
-        float xm[3], xs[3];
+        std::vector<double> mean(Nu), psi((size_t)k * Nu), lam(k);
+        float xm[WS_NIN], xs[WS_NIN];
         if (std::fread(xm, sizeof xm, 1, f) != 1 || std::fread(xs, sizeof xs, 1, f) != 1 ||
             std::fread(cs.data(), sizeof(float), k, f) != (size_t)k ||
+            std::fread(lam.data(), sizeof(double), k, f) != (size_t)k ||
             std::fread(mean.data(), sizeof(double), Nu, f) != (size_t)Nu ||
             std::fread(psi.data(), sizeof(double), psi.size(), f) != psi.size())
             raise(PA_EINVAL, "truncated warm-start file");
         ws_alloc();
-        mlp.init({ 3, width, width, width, k }, st);
+        mlp.init(WS_NIN, width, k, st);
         std::vector<float> W(mlp.nparam);
         if (std::fread(W.data(), sizeof(float), W.size(), f) != W.size()) raise(PA_EINVAL, "truncated warm-start file");
         h2d(mlp.p, W.data(), sizeof(float) * W.size());
@@ -1553,6 +1688,7 @@ struct Solver final : pa_ctx {
         h2d(ws_psi, psi.data(), sizeof(double) * psi.size());
         h2d(ws_cs, cs.data(), sizeof(float) * k);
         ws_cs_h = cs;
+        ws_lam = lam;
         std::memcpy(ws_xm, xm, sizeof xm);
         std::memcpy(ws_xs, xs, sizeof xs);
         ws_k = k;
@@ -1589,9 +1725,17 @@ struct Solver final : pa_ctx {
                 const GmState* skip = nullptr)
     {
         hipEvent_t e;
-        tstart(tr ? PA_K_SPMV_T : PA_K_SPMV, &e);
-        if (tr) k_ahat_tr_m<NP><<<Ne, 64, ahat_tr_m_smem<NP>(R), st>>>(Ne, dm.enb, dm.etw, Ah, R, x, sx, y, sy, skip);
-        else k_ahat_fwd_m<NP><<<Ne, 64, 0, st>>>(Ne, dm.enb, Ah, R, x, sx, y, sy, skip);
+        tstart(tr ? PA_K_SPMV_TM : PA_K_SPMV_M, &e);
+        switch (R) {
+#define PA_AHAT_M(RR)                                                                                         \
+    case RR:                                                                                                  \
+        if (tr) k_ahat_tr_m<NP, RR><<<Ne, 64, 0, st>>>(Ne, nb4t, Ah, x, sx, y, sy, skip);                     \
+        else k_ahat_fwd_m<NP, RR><<<Ne, 64, 0, st>>>(Ne, nb4f, Ah, x, sx, y, sy, skip);                       \
+        break;
+            PA_AHAT_M(1) PA_AHAT_M(2) PA_AHAT_M(3) PA_AHAT_M(4) PA_AHAT_M(5) PA_AHAT_M(6) PA_AHAT_M(7) PA_AHAT_M(8)
+#undef PA_AHAT_M
+        default: raise(PA_EINVAL, "%d right-hand sides per apply (1..%d)", R, GM_RMAX);
+        }
         LAUNCHCHK();
         tstop(e);
     }
@@ -1680,7 +1824,7 @@ struct Solver final : pa_ctx {
             }
             total += cyc;
             // the applies of the cycle return at once when every system is done
-            tskip(tr ? PA_K_SPMV_T : PA_K_SPMV, jlast + 1 - cyc);
+            tskip(tr ? PA_K_SPMV_TM : PA_K_SPMV_M, jlast + 1 - cyc);
             if (!all && total >= maxit) raise(PA_ENOCONV, "stage GMRES (%d systems) did not converge in %d iterations", R, total);
         }
         for (int r = 0; r < R; ++r) {
@@ -2151,6 +2295,12 @@ struct Solver final : pa_ctx {
     {
         double t0 = now_ms();
         pa_shoot_report r{};
+        if (rep) {   // the caller's history buffers
+            r.res_hist = rep->res_hist;
+            r.krylov_hist = rep->krylov_hist;
+            r.step_hist = rep->step_hist;
+            r.hist_cap = rep->hist_cap;
+        }
         cnt_newton = cnt_gmres = 0;
         auto finish = [&]() {
             r.stage_newton_its = (int32_t)cnt_newton;
@@ -2162,6 +2312,7 @@ struct Solver final : pa_ctx {
         primal_sweep(qoi, &res);
         ++r.primal_sweeps;
         r.res0 = r.res = res;
+        if (r.res_hist && r.hist_cap > 0) r.res_hist[0] = res;
         if (verbose) fprintf(stderr, "[pa] shoot start |R| = %.3e  %.1f s\n", res, (now_ms() - t0) / 1e3);
         while (!(res <= tol)) {
             if (r.newton_its >= maxit) {
@@ -2201,6 +2352,12 @@ struct Solver final : pa_ctx {
             }
             res = rnew;
             r.res = res;
+            const int k = r.newton_its;
+            if (k < r.hist_cap) {
+                if (r.krylov_hist) r.krylov_hist[k] = r.krylov_its - k0;
+                if (r.step_hist) r.step_hist[k] = lam;
+            }
+            if (k + 1 < r.hist_cap && r.res_hist) r.res_hist[k + 1] = res;
             ++r.newton_its;
             if (verbose)
                 fprintf(stderr, "[pa] shoot it %d |R| = %.3e (krylov %d, rel %.2e)  %.1f s\n", r.newton_its, res,
@@ -2269,7 +2426,7 @@ struct Solver final : pa_ctx {
         if (res_out) *res_out = res;
     }
 
-    // Gradient of j(u0) = 1/2 ||u^(Nt)(u0) - u0||^2 (Sec. 2.3 eq. opt-obj) on
+    // Gradient of j(u0) = 1/2 ||u^(Nt)(u0) - u0||^2 (Sec. 2.2 eq. opt-obj) on
     // the stored trajectory: the backward sweep started from lam^(Nt) = R =
     // u^(Nt) - u0 returns lam^(0) = Phi^T R, and dj/du0 = lam^(0) - R (eq.
     // funcl-grad-nosens-dirk).  R and g are device vectors; returns j.
@@ -2315,7 +2472,7 @@ struct Solver final : pa_ctx {
         return v;
     }
 
-    // Shooting as unconstrained minimisation of j(u0) (Sec. 2.3, the
+    // Shooting as unconstrained minimisation of j(u0) (Sec. 2.2, the
     // gradient-based alternative to Alg. 1 and 2): steepest descent
     // (memory 0) or L-BFGS with `memory` correction pairs.  Every iterate
     // costs one backward sweep for its gradient.  The step u0 + alpha d is
@@ -2700,7 +2857,7 @@ struct Solver final : pa_ctx {
         }
     }
 
-    // Direct (tangent) gradient, Sec. 2.3 with the parameter forcing: for the
+    // Direct (tangent) gradient, Sec. 2.2 with the parameter forcing: for the
     // three parameters together, the forced tangent sweeps from zero give
     // s_k, the periodic tangents solve (Phi - I) du0_k = -s_k, and one forced
     // sweep from du0_k accumulates dJ_q/dmu_k.  Independent of the adjoint.
@@ -2892,6 +3049,30 @@ struct Solver final : pa_ctx {
             src = which == 0 ? stU(s) : stK(s);
         }
         d2h(out, src, sizeof(double) * Nu);
+    }
+    // reps launches of the apply that carries R right-hand sides at once
+    // (x = R zero vectors: the timing does not depend on the values)
+    double bench_spmv_m(int reps, int tr, int R) override
+    {
+        if (!have_traj) raise(PA_ESTATE, "no trajectory");
+        if (R < 1 || R > GM_RMAX) raise(PA_EINVAL, "right-hand sides must be 1..%d", GM_RMAX);
+        if (reps < 1) raise(PA_EINVAL, "reps must be positive");
+        ensure_multi();
+        zero(lamm, (int64_t)R * Nu);
+        hipEvent_t a, b;
+        HIPCHK(hipEventCreate(&a));
+        HIPCHK(hipEventCreate(&b));
+        const double* Ah = ops(0).Ah;
+        ahat_m(Ah, tr, R, lamm, Nu, rhsm, Nu);
+        HIPCHK(hipEventRecord(a, st));
+        for (int r = 0; r < reps; ++r) ahat_m(Ah, tr, R, lamm, Nu, rhsm, Nu);
+        HIPCHK(hipEventRecord(b, st));
+        HIPCHK(hipEventSynchronize(b));
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, a, b));
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        return ms / reps;
     }
     double bench_spmv(int reps, int tr) override
     {
@@ -3127,6 +3308,82 @@ pa_status pa_ws_shoot(pa_ctx* c, double tol, double eta, int32_t maxit, pa_shoot
         c->ws_shoot(tol, eta, maxit, rep, fell_back);
     });
 }
+// Prolongation of a state of a coarser O-grid discretisation to the nodes of
+// `fine`: each fine node X (in the fixed reference domain) is located in the
+// coarse triangle that contains it -- among the coarse quads around its
+// polar cell, the triangle whose smallest barycentric coordinate is largest
+// (a node between a coarse chord and the circle, where the coarse mesh does
+// not reach, takes the nearest triangle's polynomial) -- and the coarse
+// degree-p_c Lagrange interpolant of U_X is evaluated there.  Host only.
+pa_status pa_prolong(const pa_config* coarse, const double* u_coarse, pa_ctx* fine, double* u_fine)
+{
+    if (!fine) return PA_EINVAL;
+    return guard(fine, [&] {
+        if (!coarse || !u_coarse || !u_fine) raise(PA_EINVAL, "NULL argument");
+        const pa_config& C = *coarse;
+        if (C.Nr < 1 || C.Nth < 3 || C.p < 1 || C.p > 3) raise(PA_EINVAL, "bad coarse discretisation");
+        if (std::fabs(C.r_far - fine->cfg.r_far) > 1e-14 || std::fabs(C.stretch - fine->cfg.stretch) > 1e-14)
+            raise(PA_EINVAL, "coarse and fine O-grids must share the far-field radius and stretching");
+        const int Nr = C.Nr, Nth = C.Nth, pc = C.p, npc = (pc + 1) * (pc + 2) / 2;
+        std::vector<double> rad(Nr + 1);
+        const double q = std::pow(C.stretch, 8.0 / Nr), qN = std::pow(q, Nr);
+        for (int i = 0; i <= Nr; ++i) rad[i] = 1.0 + (C.r_far - 1.0) * (std::pow(q, i) - 1.0) / (qN - 1.0);
+        auto vert = [&](int i, int j, double* X) {
+            const double th = 2.0 * M_PI * (((j % Nth) + Nth) % Nth) / Nth;
+            X[0] = rad[i] * std::cos(th);
+            X[1] = rad[i] * std::sin(th);
+        };
+        const Basis basis(pc);
+        const int64_t nnf = (int64_t)fine->num_elems() * (fine->block_size() / 4);
+        std::vector<double> xy(2 * nnf), phi(npc), dphi_buf(2 * npc);
+        fine->node_coords(xy.data());
+        for (int64_t k = 0; k < nnf; ++k) {
+            const double X = xy[2 * k], Y = xy[2 * k + 1];
+            const double r = std::sqrt(X * X + Y * Y);
+            double th = std::atan2(Y, X);
+            if (th < 0) th += 2.0 * M_PI;
+            const int j0 = std::min((int)(th / (2.0 * M_PI / Nth)), Nth - 1);
+            int i0 = 0;
+            while (i0 + 1 < Nr && rad[i0 + 1] <= r) ++i0;
+            double best = -1e300, bs = 0, bt = 0;
+            int bestK = -1;
+            for (int di = -1; di <= 1; ++di)
+                for (int dj = -1; dj <= 1; ++dj) {
+                    const int i = i0 + di, j = j0 + dj;
+                    if (i < 0 || i >= Nr) continue;
+                    double a[2], b[2], cc[2], d[2];
+                    vert(i, j, a); vert(i + 1, j, b); vert(i + 1, j + 1, cc); vert(i, j + 1, d);
+                    const double* tri[2][3] = { { a, b, cc }, { a, cc, d } };
+                    for (int h = 0; h < 2; ++h) {
+                        const double *p0 = tri[h][0], *p1 = tri[h][1], *p2 = tri[h][2];
+                        const double j00 = p1[0] - p0[0], j01 = p2[0] - p0[0], j10 = p1[1] - p0[1], j11 = p2[1] - p0[1];
+                        const double det = j00 * j11 - j01 * j10;
+                        const double s_ = ((X - p0[0]) * j11 - (Y - p0[1]) * j01) / det;
+                        const double t_ = (-(X - p0[0]) * j10 + (Y - p0[1]) * j00) / det;
+                        const double mn = std::min({ s_, t_, 1.0 - s_ - t_ });
+                        if (mn > best) {
+                            best = mn; bs = s_; bt = t_;
+                            bestK = 2 * (i * Nth + (((j % Nth) + Nth) % Nth)) + h;
+                        }
+                    }
+                }
+            basis.eval(bs, bt, phi.data(), reinterpret_cast<double(*)[2]>(dphi_buf.data()));
+            for (int m = 0; m < 4; ++m) {
+                double v = 0.0;
+                for (int a = 0; a < npc; ++a) v += phi[a] * u_coarse[((int64_t)bestK * npc + a) * 4 + m];
+                u_fine[4 * k + m] = v;
+            }
+        }
+    });
+}
+pa_status pa_ws_pod(pa_ctx* c, int32_t kmax, double* mean, double* modes, double* eig, int32_t* k)
+{
+    return guard(c, [&] {
+        if (kmax < 0) raise(PA_EINVAL, "kmax must be non-negative");
+        const int n = c->ws_pod(kmax, mean, modes, eig);
+        if (k) *k = n;
+    });
+}
 pa_status pa_ws_save(pa_ctx* c, const char* path)
 {
     return guard(c, [&] {
@@ -3154,7 +3411,7 @@ pa_status pa_dbg_mlp(int32_t in, int32_t width, int32_t out, int32_t batch, cons
         HIPCHK(hipStreamCreateWithFlags(&st, hipStreamNonBlocking));
         {
             Mlp m;
-            m.init({ in, width, width, width, out }, st);
+            m.init(in, width, out, st);
             m.reserve(batch);
             HIPCHK(hipMemcpyAsync(m.p, params, sizeof(float) * m.nparam, hipMemcpyHostToDevice, st));
             HIPCHK(hipMemcpyAsync(m.X, X, sizeof(float) * (size_t)in * batch, hipMemcpyHostToDevice, st));
@@ -3379,6 +3636,11 @@ pa_status pa_bench_spmv_lo(pa_ctx* c, int32_t reps, int32_t tr, double* avg)
     });
 }
 
+pa_status pa_bench_spmv_m(pa_ctx* c, int32_t reps, int32_t tr, int32_t nrhs, double* avg)
+{
+    if (!avg) return c ? (c->err = "NULL output", PA_EINVAL) : PA_EINVAL;
+    return guard(c, [&] { *avg = c->bench_spmv_m(reps, tr, nrhs); });
+}
 pa_status pa_bench_spmv(pa_ctx* c, int32_t reps, int32_t tr, double* avg)
 {
     return guard(c, [&] {

@@ -1,6 +1,6 @@
 // HIP kernels of the periodic-adjoint library (gfx950, wave64).
 //
-// Discretisation (arXiv:1512.00616 Sec. 5 names nodal DG on triangles with
+// Discretisation (arXiv:1512.00616 Sec. 4 names nodal DG on triangles with
 // the compact DG viscous treatment and an ALE map to a fixed reference
 // domain; the details below are this library's reading):
 //   r_{K,a} = int_K grad_X phi_a . F_X dX - oint_{dK} phi_a Fhat . N dS
@@ -55,7 +55,7 @@ struct DevMesh {
     const double* enrm;     // [Ne][3][2] outward unit normal (reference domain)
 };
 
-// rigid heave/pitch values at one time (Sec. 5.1 eq. defmap): h, dh/dt,
+// rigid heave/pitch values at one time (Sec. 4.1 eq. defmap): h, dh/dt,
 // theta, dtheta/dt; T = Dual<3> carries their derivatives in (h0, theta0, phi)
 template <class T>
 struct Motion {
@@ -889,7 +889,7 @@ __global__ void k_gcl_kstage(DevMesh M, const Ref<P>* __restrict__ R, const doub
 
 // ------------------------------------------------------------------ QoI
 // Force on the body: momentum part of the wall numerical flux integrated over
-// the wall (Sec. 5 eq. qoi, solver-consistent reading); P = f . v_G, F_x = f . e1.
+// the wall (Sec. 4 eq. qoi, solver-consistent reading); P = f . v_G, F_x = f . e1.
 // One thread per (wall element, dual seed): seed < B differentiates w.r.t.
 // U_X[K][seed]; outputs per wall element: f [2] and df/du [2][B].
 template <int P>

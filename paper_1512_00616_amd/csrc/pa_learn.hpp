@@ -116,6 +116,18 @@ __global__ void k_adam(float* __restrict__ p, const float* __restrict__ g, float
 }
 
 // out = base + sum_k c[k] Psi_k (FP64), c on the device
+// out[4k + m] = g[k] U[m]: a nodal scalar field times a constant state
+__global__ void k_scale_state(const double* __restrict__ g, double4 U, double* __restrict__ out, int64_t nn)
+{
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nn) return;
+    const double gk = g[k];
+    out[4 * k + 0] = gk * U.x;
+    out[4 * k + 1] = gk * U.y;
+    out[4 * k + 2] = gk * U.z;
+    out[4 * k + 3] = gk * U.w;
+}
+
 __global__ void k_pod_expand(const double* __restrict__ base, const double* __restrict__ Psi, int k, int64_t ld,
                              const float* __restrict__ c, const float* __restrict__ cscale, double* __restrict__ out,
                              int64_t n)

@@ -1,6 +1,6 @@
 // Block-sparse and Krylov kernels of the periodic-adjoint library (gfx950).
 //
-// Operators of one DIRK stage (arXiv:1512.00616 Sec. 2.2 eq. dirk):
+// Operators of one DIRK stage (arXiv:1512.00616 Sec. 2.1 eq. dirk):
 //   A_i = M - dt a_ii dr/du(u_i),  M = blockdiag(2|K| Mhat (x) I_4)  (constant)
 // dr/du is stored as fixed-width block rows: row K holds its diagonal block
 // and the blocks coupling K to its neighbours across faces 0, 1, 2.
@@ -912,8 +912,25 @@ constexpr bool ahat_fwd_valid(int Q)
     return (4 * NP) % (int)(16 / sizeof(TM) * Q) == 0 && (int)(16 / sizeof(TM)) * Q <= 8;
 }
 
+// Per-element face tables of the stage-operator applies, one int4 per
+// element so that a wave reads them with one scalar load:
+//   fwd: {nb_0, nb_1, nb_2, mask}, nb_f the neighbour across face f;
+//   tr:  {b_0, b_1, b_2, mask}, b_f = 3 nb_f + twin_f, the neighbour's block
+//        that points back at this element;
+// bit f of mask is set for an interior face.  For a boundary face nb_f is the
+// element itself and b_f its own slot f, whose stored block is zero: every
+// load of the applies then has a valid address and is issued without a
+// branch, and the face's contribution is removed by a zero weight.
+
+// Forward apply y = x + Ahat x (Ahat's diagonal blocks are the identity):
+// y_i = x_i + sum_f sum_j A_f[i][j] x_nb_f[j] over the three stored
+// off-diagonal blocks of block row K.  Each block is split into tasks of Q
+// 16-byte chunks lying in one row; lane l holds tasks l, l + 64, ... of the
+// three blocks in registers (every load issued before any arithmetic, no
+// matrix entry through LDS), leaves one partial per task in LDS, and lane i
+// adds row i's partials to x_i.
 template <int NP, class TM, class TV, int QT = 0>
-__global__ void __launch_bounds__(64) k_ahat_fwd(int Ne, const int32_t* __restrict__ enb, const TM* __restrict__ Ah,
+__global__ void __launch_bounds__(64) k_ahat_fwd(int Ne, const int4* __restrict__ nb4, const TM* __restrict__ Ah,
                                                  const TV* __restrict__ x, TV* __restrict__ y,
                                                  const int* __restrict__ skip)
 {
@@ -929,14 +946,16 @@ __global__ void __launch_bounds__(64) k_ahat_fwd(int Ne, const int32_t* __restri
     __shared__ TV sx[3][B];
     if (skip && *skip) return;
     const int K = blockIdx.x, lane = threadIdx.x;
+    const int4 t4 = nb4[K];
     int nbs[3];
     const uint4* src[3];
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
-        const int nb = enb[3 * K + f];
-        nbs[f] = nb;
-        src[f] = nb >= 0 ? reinterpret_cast<const uint4*>(Ah + ((int64_t)K * 3 + f) * BB) : nullptr;
+        nbs[f] = (t4.w >> f) & 1 ? (f == 0 ? t4.x : f == 1 ? t4.y : t4.z) : -1;
+        src[f] = nbs[f] >= 0 ? reinterpret_cast<const uint4*>(Ah + ((int64_t)K * 3 + f) * BB) : nullptr;
     }
+    // own entry of x, needed only at the end, loaded with the others
+    const TV xo = x[(int64_t)K * B + lane % B];
     uint4 v[3][PER][Q];
 #pragma unroll
     for (int f = 0; f < 3; ++f)
@@ -970,7 +989,7 @@ __global__ void __launch_bounds__(64) k_ahat_fwd(int Ne, const int32_t* __restri
         }
     __syncthreads();
     if (lane < B) {
-        TV acc = x[(int64_t)K * B + lane];
+        TV acc = xo;
 #pragma unroll
         for (int f = 0; f < 3; ++f) {
             if (nbs[f] < 0) continue;
@@ -981,19 +1000,19 @@ __global__ void __launch_bounds__(64) k_ahat_fwd(int Ne, const int32_t* __restri
     }
 }
 
-// Transposed apply y = x + Ahat^T x for any storage type (as k_ahat_fwd).
-// Row K of Ahat^T takes, for each neighbour nb across face f, the block of
-// nb that points back at K (slot twin) transposed, so y[j] sums column j of
-// those blocks weighted by x_nb.  Lanes 0..59 of the wave are (row group g,
-// column chunk c) with G = 60 / CPR groups: lane (g, c) loads chunk c of
-// rows g, g + G, g + 2G, ... -- for every row step the 60 lanes read 60
-// consecutive 16-byte chunks -- and sums its rows in registers, leaving one
-// partial per (g, column) in LDS; lane j then adds the G partials of column
-// j in group order.
-template <int NP, class TM, class TV>
-__global__ void __launch_bounds__(64) k_ahat_tr(int Ne, const int32_t* __restrict__ enb, const int8_t* __restrict__ etw,
-                                                const TM* __restrict__ Ah, const TV* __restrict__ x,
-                                                TV* __restrict__ y, const int* __restrict__ skip)
+// Transposed apply y = x + Ahat^T x: row K of Ahat^T takes, for each
+// neighbour nb across face f, the block of nb that points back at K (slot
+// twin) transposed, so y[j] = x[j] + sum_f sum_i A_f[i][j] x_nb_f[i].
+// Lanes 0..59 of the wave are (row group g, column chunk c) with G = 60 /
+// CPR groups: lane (g, c) loads chunk c of rows g, g + G, g + 2G, ... of the
+// three blocks -- for every row step the 60 lanes read 60 consecutive
+// 16-byte chunks -- and sums over the faces and its rows in registers.  The
+// G partials of a column chunk are added by lane (0, c) with cross-lane
+// reads in group order, and that lane writes the chunk's EPL entries of y.
+// One barrier: the neighbours' entries of x are staged in LDS.
+template <int NP, class TM, class TV, int R>
+__device__ __forceinline__ void ahat_tr_body(int K, const int4* __restrict__ tb4, const TM* __restrict__ Ah,
+                                             const TV* __restrict__ x, int64_t sx, TV* __restrict__ y, int64_t sy)
 {
     constexpr int B = 4 * NP, BB = B * B;
     constexpr int EPL = 16 / sizeof(TM);
@@ -1001,92 +1020,131 @@ __global__ void __launch_bounds__(64) k_ahat_tr(int Ne, const int32_t* __restric
     constexpr int CPR = B / EPL;
     static_assert(60 % CPR == 0, "row groups must tile 60 lanes");
     constexpr int G = 60 / CPR, RPL = (B + G - 1) / G;
-    __shared__ TV sp[3][G][B + 1];
-    __shared__ TV sx[3][B];
-    if (skip && *skip) return;
-    const int K = blockIdx.x, lane = threadIdx.x;
-    const int c = lane % CPR, g = lane / CPR;   // active when lane < 60
-    int nbs[3];
-    const uint4* src[3];
+    __shared__ TV sxs[R][3][B + G];                  // rows B.. B+G-1 zero: the last row step needs no test
+    const int lane = threadIdx.x;
+    const int c = lane % CPR, g = lane < 60 ? lane / CPR : 0;   // lanes 60..63 repeat group 0 (unused)
+    const int4 t4 = tb4[K];
+    const int blk[3] = { t4.x, t4.y, t4.z };
+    const int mask = t4.w;
+    const int li = lane % B;
+    // x first, into registers (staging it in LDS before the barrier then
+    // waits for these loads only); the own chunk for lanes (0, c)
+    TV xo[R][EPL], xn[R][3];
 #pragma unroll
-    for (int f = 0; f < 3; ++f) {
-        const int nb = enb[3 * K + f];
-        nbs[f] = nb;
-        src[f] = nb >= 0 ? reinterpret_cast<const uint4*>(Ah + ((int64_t)nb * 3 + etw[3 * K + f]) * BB) : nullptr;
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int q = 0; q < EPL; ++q) xo[r][q] = x[r * sx + (int64_t)K * B + c * EPL + q];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) xn[r][f] = x[r * sx + (int64_t)(blk[f] / 3) * B + li];
     }
+    asm volatile("" ::: "memory");   // compiler-only fence: the loads of x stay ahead of the block loads
     uint4 v[3][RPL];
 #pragma unroll
-    for (int f = 0; f < 3; ++f)
+    for (int f = 0; f < 3; ++f) {
+        const uint4* src = reinterpret_cast<const uint4*>(Ah + (int64_t)blk[f] * BB);
 #pragma unroll
         for (int k = 0; k < RPL; ++k) {
-            const int i = g + G * k;
-            if (src[f] && lane < 60 && i < B) v[f][k] = src[f][i * CPR + c];
+            const int i = g + G * k < B ? g + G * k : B - 1;
+            v[f][k] = src[i * CPR + c];
         }
+    }
+    // every lane stores (lanes past the block repeat the value of lane
+    // li), so no branch lets the compiler sink the loads of x past the
+    // block loads
 #pragma unroll
-    for (int f = 0; f < 3; ++f)
-        if (nbs[f] >= 0 && lane < B) sx[f][lane] = x[(int64_t)nbs[f] * B + lane];
+    for (int r = 0; r < R; ++r) {
+#pragma unroll
+        for (int f = 0; f < 3; ++f) sxs[r][f][li] = xn[r][f];
+        if (lane < G)
+#pragma unroll
+            for (int f = 0; f < 3; ++f) sxs[r][f][B + lane] = TV(0);
+    }
     __syncthreads();
+    TV p[R][EPL];
+#pragma unroll
+    for (int r = 0; r < R; ++r)
+#pragma unroll
+        for (int q = 0; q < EPL; ++q) p[r][q] = 0;
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
-        if (!src[f] || lane >= 60) continue;
-        TV p[EPL];
-#pragma unroll
-        for (int q = 0; q < EPL; ++q) p[q] = 0;
+        // interior faces only (a uniform branch, which also keeps the LDS
+        // reads of one face from being hoisted ahead of the others'
+        // arithmetic and held in registers all at once)
+        if (!((mask >> f) & 1)) continue;
 #pragma unroll
         for (int k = 0; k < RPL; ++k) {
             const int i = g + G * k;
-            if (i < B) {
-                const TV xi = sx[f][i];
-                const TM* e = reinterpret_cast<const TM*>(&v[f][k]);
+            const TM* e = reinterpret_cast<const TM*>(&v[f][k]);
 #pragma unroll
-                for (int q = 0; q < EPL; ++q) p[q] += to_acc<TV>(e[q]) * xi;
+            for (int r = 0; r < R; ++r) {
+                const TV xi = sxs[r][f][i];
+#pragma unroll
+                for (int q = 0; q < EPL; ++q) p[r][q] += to_acc<TV>(e[q]) * xi;
             }
         }
-#pragma unroll
-        for (int q = 0; q < EPL; ++q) sp[f][g][c * EPL + q] = p[q];
     }
-    __syncthreads();
-    if (lane < B) {
-        TV acc = x[(int64_t)K * B + lane];
+    // group sums: lane (0, c) adds the partials of lanes (gg, c), gg = 1..G-1
 #pragma unroll
-        for (int f = 0; f < 3; ++f) {
-            if (nbs[f] < 0) continue;
+    for (int r = 0; r < R; ++r)
 #pragma unroll
-            for (int gg = 0; gg < G; ++gg) acc += sp[f][gg][lane];
+        for (int q = 0; q < EPL; ++q) {
+            TV t = p[r][q];
+#pragma unroll
+            for (int gg = 1; gg < G; ++gg) t += __shfl(p[r][q], c + gg * CPR, 64);
+            p[r][q] = t;
         }
-        y[(int64_t)K * B + lane] = acc;
-    }
+    if (lane < CPR)
+#pragma unroll
+        for (int r = 0; r < R; ++r)
+#pragma unroll
+            for (int q = 0; q < EPL; ++q) y[r * sy + (int64_t)K * B + c * EPL + q] = xo[r][q] + p[r][q];
+}
+
+template <int NP, class TM, class TV>
+__global__ void __launch_bounds__(64) k_ahat_tr(int Ne, const int4* __restrict__ tb4, const TM* __restrict__ Ah,
+                                                const TV* __restrict__ x, TV* __restrict__ y,
+                                                const int* __restrict__ skip)
+{
+    if (skip && *skip) return;
+    ahat_tr_body<NP, TM, TV, 1>(blockIdx.x, tb4, Ah, x, 0, y, 0);
 }
 
 // ------------------------------------------------------------------ several right-hand sides
-// y_r = x_r + Ahat x_r (forward) for R systems sharing the stored operator
-// (x_r = x + r sx, y_r = y + r sy): the three blocks of the row are read
-// from HBM once into registers and applied to every x_r (same per-task
-// partials as k_ahat_fwd, one LDS pass per system).  The launch returns at
-// once when every system's GMRES state (optional) is done.
-template <int NP>
-__global__ void __launch_bounds__(64) k_ahat_fwd_m(int Ne, const int32_t* __restrict__ enb, const double* __restrict__ Ah,
-                                                   int R, const double* __restrict__ x, int64_t sx,
-                                                   double* __restrict__ y, int64_t sy, const GmState* __restrict__ st)
+// R systems sharing the stored operator (x_r = x + r sx, y_r = y + r sy):
+// the three blocks of the row are read from HBM once into registers and
+// applied to every x_r.  The launch returns at once when every system's
+// GMRES state (optional) is done.
+__device__ __forceinline__ bool all_done(const GmState* __restrict__ st, int R)
 {
+    if (!st) return false;
+    bool all = true;
+    for (int r = 0; r < R; ++r) all = all && st[r].done;
+    return all;
+}
+template <int NP, int RT>
+__global__ void __launch_bounds__(64) k_ahat_fwd_m(int Ne, const int4* __restrict__ nb4, const double* __restrict__ Ah,
+                                                   const double* __restrict__ x, int64_t sx, double* __restrict__ y,
+                                                   int64_t sy, const GmState* __restrict__ st)
+{
+    constexpr int R = RT;
     constexpr int B = 4 * NP, BB = B * B, EPL = 2;
     constexpr int Q = fwd_chunks_per_task<B, EPL>(), EPT = Q * EPL;   // tasks as in k_ahat_fwd
     constexpr int H = BB / EPT, TPR = B / EPT, PER = (H + 63) / 64;
     __shared__ double sp[3][TPR][B + 1];
-    __shared__ double sxr[GM_RMAX][3][B];
+    __shared__ double sxr[R][3][B];
     if (st) {
         bool all = true;
         for (int r = 0; r < R; ++r) all = all && st[r].done;
         if (all) return;
     }
     const int K = blockIdx.x, lane = threadIdx.x;
+    const int4 t4 = nb4[K];
     int nbs[3];
     const uint4* src[3];
 #pragma unroll
     for (int f = 0; f < 3; ++f) {
-        const int nb = enb[3 * K + f];
-        nbs[f] = nb;
-        src[f] = nb >= 0 ? reinterpret_cast<const uint4*>(Ah + ((int64_t)K * 3 + f) * BB) : nullptr;
+        nbs[f] = (t4.w >> f) & 1 ? (f == 0 ? t4.x : f == 1 ? t4.y : t4.z) : -1;
+        src[f] = nbs[f] >= 0 ? reinterpret_cast<const uint4*>(Ah + ((int64_t)K * 3 + f) * BB) : nullptr;
     }
     uint4 v[3][PER][Q];
 #pragma unroll
@@ -1135,92 +1193,13 @@ __global__ void __launch_bounds__(64) k_ahat_fwd_m(int Ne, const int32_t* __rest
     }
 }
 
-// transposed counterpart of k_ahat_fwd_m (layout of k_ahat_tr); dynamic LDS
-// of ahat_tr_m_smem<NP>(R) bytes, sized for the R systems of the launch
-template <int NP>
-constexpr size_t ahat_tr_m_row_doubles()
+template <int NP, int R>
+__global__ void __launch_bounds__(64) k_ahat_tr_m(int Ne, const int4* __restrict__ tb4, const double* __restrict__ Ah,
+                                                  const double* __restrict__ x, int64_t sx, double* __restrict__ y,
+                                                  int64_t sy, const GmState* __restrict__ st)
 {
-    return (size_t)3 * (60 / (4 * NP / 2)) * (4 * NP + 1) + 3 * (4 * NP);
-}
-template <int NP>
-inline size_t ahat_tr_m_smem(int R)
-{
-    return sizeof(double) * (size_t)R * ahat_tr_m_row_doubles<NP>();
-}
-template <int NP>
-__global__ void __launch_bounds__(64) k_ahat_tr_m(int Ne, const int32_t* __restrict__ enb, const int8_t* __restrict__ etw,
-                                                  const double* __restrict__ Ah, int R, const double* __restrict__ x,
-                                                  int64_t sx, double* __restrict__ y, int64_t sy,
-                                                  const GmState* __restrict__ st)
-{
-    constexpr int B = 4 * NP, BB = B * B, EPL = 2;
-    constexpr int CPR = B / EPL;
-    static_assert(60 % CPR == 0, "row groups must tile 60 lanes");
-    constexpr int G = 60 / CPR, RPL = (B + G - 1) / G;
-    extern __shared__ double dsm[];
-    // sp[r][f][g][col] and sxr[r][f][i], R systems
-    double* sp = dsm;
-    double* sxr = dsm + (size_t)R * 3 * G * (B + 1);
-    auto SP = [&](int r, int f, int g_, int col) -> double& { return sp[(((size_t)r * 3 + f) * G + g_) * (B + 1) + col]; };
-    auto SX = [&](int r, int f, int i) -> double& { return sxr[((size_t)r * 3 + f) * B + i]; };
-    if (st) {
-        bool all = true;
-        for (int r = 0; r < R; ++r) all = all && st[r].done;
-        if (all) return;
-    }
-    const int K = blockIdx.x, lane = threadIdx.x;
-    const int c = lane % CPR, g = lane / CPR;
-    int nbs[3];
-    const uint4* src[3];
-#pragma unroll
-    for (int f = 0; f < 3; ++f) {
-        const int nb = enb[3 * K + f];
-        nbs[f] = nb;
-        src[f] = nb >= 0 ? reinterpret_cast<const uint4*>(Ah + ((int64_t)nb * 3 + etw[3 * K + f]) * BB) : nullptr;
-    }
-    uint4 v[3][RPL];
-#pragma unroll
-    for (int f = 0; f < 3; ++f)
-#pragma unroll
-        for (int k = 0; k < RPL; ++k) {
-            const int i = g + G * k;
-            if (src[f] && lane < 60 && i < B) v[f][k] = src[f][i * CPR + c];
-        }
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int f = 0; f < 3; ++f)
-            if (nbs[f] >= 0 && lane < B) SX(r, f, lane) = x[r * sx + (int64_t)nbs[f] * B + lane];
-    __syncthreads();
-    for (int r = 0; r < R; ++r)
-#pragma unroll
-        for (int f = 0; f < 3; ++f) {
-            if (!src[f] || lane >= 60) continue;
-            double p0 = 0.0, p1 = 0.0;
-#pragma unroll
-            for (int k = 0; k < RPL; ++k) {
-                const int i = g + G * k;
-                if (i < B) {
-                    const double xi = SX(r, f, i);
-                    const double* e = reinterpret_cast<const double*>(&v[f][k]);
-                    p0 += e[0] * xi;
-                    p1 += e[1] * xi;
-                }
-            }
-            SP(r, f, g, c * EPL) = p0;
-            SP(r, f, g, c * EPL + 1) = p1;
-        }
-    __syncthreads();
-    if (lane < B)
-        for (int r = 0; r < R; ++r) {
-            double acc = x[r * sx + (int64_t)K * B + lane];
-#pragma unroll
-            for (int f = 0; f < 3; ++f) {
-                if (nbs[f] < 0) continue;
-#pragma unroll
-                for (int gg = 0; gg < G; ++gg) acc += SP(r, f, gg, lane);
-            }
-            y[r * sy + (int64_t)K * B + lane] = acc;
-        }
+    if (all_done(st, R)) return;
+    ahat_tr_body<NP, double, double, R>(blockIdx.x, tb4, Ah, x, sx, y, sy);
 }
 
 // z = a * x (FP64 -> FP32), y += a * x (FP32 -> FP64)

@@ -13,17 +13,18 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libpa.so")
 
 PA_OK, PA_EINVAL, PA_ENOMEM, PA_EDEVICE, PA_ENOCONV, PA_ENUMERIC, PA_ESTATE = 0, -1, -2, -3, -4, -5, -6
-PA_K_SPMV, PA_K_PRECOND, PA_K_JACOBIAN, PA_K_RESIDUAL, PA_K_BLOCKINV, PA_K_SPMV_LO, PA_K_SPMV_T = range(7)
-PA_K_COUNT = 7
+(PA_K_SPMV, PA_K_PRECOND, PA_K_JACOBIAN, PA_K_RESIDUAL, PA_K_BLOCKINV, PA_K_SPMV_LO, PA_K_SPMV_T, PA_K_SPMV_M,
+ PA_K_SPMV_TM, PA_K_MDOT, PA_K_GMUPD) = range(11)
+PA_K_COUNT = 11
 
 EXPORTED = [
     "pa_default_config", "pa_create", "pa_destroy", "pa_last_error", "pa_num_dofs", "pa_num_elems",
     "pa_block_size", "pa_device_bytes", "pa_get_mesh", "pa_set_params", "pa_set_state", "pa_set_freestream",
     "pa_get_state", "pa_primal_period", "pa_shoot", "pa_fixed_point", "pa_shoot_descent", "pa_periodicity_gradient", "pa_floquet", "pa_adjoint_gradient", "pa_tangent_gradient", "pa_batch_gradients",
-    "pa_ws_train", "pa_ws_predict", "pa_ws_shoot", "pa_ws_save", "pa_ws_load", "pa_dbg_mlp", "pa_tangent_sweep",
+    "pa_ws_train", "pa_ws_predict", "pa_ws_pod", "pa_prolong", "pa_ws_shoot", "pa_ws_save", "pa_ws_load", "pa_dbg_mlp", "pa_tangent_sweep",
     "pa_adjoint_sweep", "pa_dbg_gbar", "pa_dbg_dgbar", "pa_dbg_residual", "pa_dbg_jacobian", "pa_dbg_dr_dmu",
     "pa_dbg_qoi", "pa_dbg_bsr_apply", "pa_dbg_blockinv", "pa_dbg_stage_solve", "pa_dbg_traj", "pa_dbg_hess_eig", "pa_dbg_sym_eig", "pa_set_timing",
-    "pa_kernel_time", "pa_kernel_skipped", "pa_bench_spmv", "pa_bench_spmv_lo", "pa_bench_copy", "pa_tuning",
+    "pa_kernel_time", "pa_kernel_skipped", "pa_bench_spmv", "pa_bench_spmv_m", "pa_bench_spmv_lo", "pa_bench_copy", "pa_tuning",
 ]
 
 
@@ -36,6 +37,7 @@ class pa_config(C.Structure):
         ("wall_is_farfield", C.c_int32), ("gmres_restart", C.c_int32), ("lin_rtol", C.c_double),
         ("newton_atol", C.c_double), ("newton_maxit", C.c_int32), ("max_krylov", C.c_int32),
         ("device", C.c_int32), ("precision", C.c_int32), ("autotune", C.c_int32), ("block_krylov", C.c_int32),
+        ("stream", C.c_void_p), ("dev_alloc", C.c_void_p), ("dev_free", C.c_void_p), ("user", C.c_void_p),
     ]
 
 
@@ -45,7 +47,25 @@ PREC_FP64, PREC_FP32, PREC_BF16 = 0, 1, 2
 class pa_shoot_report(C.Structure):
     _fields_ = [("newton_its", C.c_int32), ("krylov_its", C.c_int32), ("primal_sweeps", C.c_int32),
                 ("stage_newton_its", C.c_int32), ("stage_gmres_its", C.c_int64), ("res0", C.c_double),
-                ("res", C.c_double), ("ms", C.c_double)]
+                ("res", C.c_double), ("ms", C.c_double), ("res_hist", C.POINTER(C.c_double)),
+                ("krylov_hist", C.POINTER(C.c_int32)), ("step_hist", C.POINTER(C.c_double)),
+                ("hist_cap", C.c_int32)]
+
+    def attach_history(self, cap):
+        """caller-owned history buffers of cap entries (kept alive on the report)"""
+        self._res_hist = np.full(cap, np.nan)
+        self._krylov_hist = np.full(cap, -1, dtype=np.int32)
+        self._step_hist = np.full(cap, np.nan)
+        self.res_hist = self._res_hist.ctypes.data_as(C.POINTER(C.c_double))
+        self.krylov_hist = self._krylov_hist.ctypes.data_as(C.POINTER(C.c_int32))
+        self.step_hist = self._step_hist.ctypes.data_as(C.POINTER(C.c_double))
+        self.hist_cap = cap
+
+    def history(self):
+        """(||R|| after each Newton step incl. the start, tangent sweeps and
+        accepted step of each Newton step)"""
+        n = self.newton_its
+        return (self._res_hist[:n + 1].copy(), self._krylov_hist[:n].copy(), self._step_hist[:n].copy())
 
 
 class pa_adjoint_report(C.Structure):
@@ -106,6 +126,8 @@ def lib():
             "pa_floquet": [P, C.c_int32, C.c_uint64, P, P, P, P],
             "pa_ws_train": [P, P, P, C.c_int32, P, P],
             "pa_ws_predict": [P, P],
+            "pa_ws_pod": [P, C.c_int32, P, P, P, P],
+            "pa_prolong": [C.POINTER(pa_config), P, P, P],
             "pa_ws_shoot": [P, C.c_double, C.c_double, C.c_int32, P, P],
             "pa_ws_save": [P, C.c_char_p],
             "pa_ws_load": [P, C.c_char_p],
@@ -133,6 +155,7 @@ def lib():
             "pa_kernel_time": [P, C.c_int32, P, P],
             "pa_kernel_skipped": [P, C.c_int32, P],
             "pa_bench_spmv": [P, C.c_int32, C.c_int32, P],
+            "pa_bench_spmv_m": [P, C.c_int32, C.c_int32, C.c_int32, P],
             "pa_bench_spmv_lo": [P, C.c_int32, C.c_int32, P],
             "pa_tuning": [P, P, P],
             "pa_bench_copy": [P, C.c_int32, P, P],
@@ -229,11 +252,46 @@ def dbg_sym_eig(A):
     return w, V
 
 
-class Solver:
-    """One discretised problem on one GPU (a ``pa_ctx``)."""
+class TorchMemory:
+    """PyTorch owns a context's device memory and stream: every device buffer
+    comes from torch's caching allocator (pa_config dev_alloc / dev_free)
+    and all device work is enqueued on a torch stream (pa_config stream).
+    Keep the object alive as long as the context (Solver keeps a reference)."""
 
-    def __init__(self, **kw):
+    def __init__(self, device=0, stream=None):
+        import torch
+        self.device = torch.device("cuda", device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
+        AF = C.CFUNCTYPE(C.c_void_p, C.c_uint64, C.c_void_p)
+        FF = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+        def alloc(nbytes, user):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), device=self.device, stream=self.stream)
+            except RuntimeError:
+                return None
+
+        def free(ptr, user):
+            torch.cuda.caching_allocator_delete(ptr)
+
+        self._af, self._ff = AF(alloc), FF(free)
+
+    def apply(self, cfg):
+        cfg.stream = self.stream.cuda_stream
+        cfg.dev_alloc = C.cast(self._af, C.c_void_p).value
+        cfg.dev_free = C.cast(self._ff, C.c_void_p).value
+        cfg.user = None
+
+
+class Solver:
+    """One discretised problem on one GPU (a ``pa_ctx``).  memory: a
+    TorchMemory to let PyTorch own the device memory and the stream."""
+
+    def __init__(self, memory=None, **kw):
         self.cfg = default_config(**kw)
+        self._memory = memory
+        if memory is not None:
+            memory.apply(self.cfg)
         h = C.c_void_p()
         rc = lib().pa_create(C.byref(self.cfg), C.byref(h))
         if rc != PA_OK:
@@ -244,6 +302,7 @@ class Solver:
         self.b = lib().pa_block_size(h)
         self.np = self.b // 4
         self.Nt = self.cfg.Nt
+        self.mach = self.cfg.mach
 
     def close(self):
         if getattr(self, "_c", None):
@@ -303,6 +362,7 @@ class Solver:
         """Newton-Krylov shooting; with allow_unconverged the report of a run
         that stopped at maxit Newton steps is returned instead of raising."""
         rep = pa_shoot_report()
+        rep.attach_history(maxit + 1)
         rc = lib().pa_shoot(self._c, tol, eta, maxit, C.byref(rep))
         if rc == PA_ENOCONV and allow_unconverged and rep.primal_sweeps > 0:
             return rep
@@ -350,8 +410,14 @@ class Solver:
         return q, g.reshape(2, 3), rep
 
     # learned warm start
-    def ws_train(self, params, states, modes=16, width=256, epochs=2000, lr=1e-3, seed=5):
-        params = np.ascontiguousarray(np.asarray(params, dtype=np.float64).reshape(-1, 3))
+    def ws_train(self, params, states, modes=16, width=256, epochs=2000, lr=1e-3, seed=5, mach=None):
+        """params [S][4] = (h0, theta0, phi, Mach), or [S][3] with every state
+        at `mach` (default: this context's Mach number)"""
+        params = np.asarray(params, dtype=np.float64)
+        if params.ndim == 2 and params.shape[1] == 3:
+            m = self.mach if mach is None else mach
+            params = np.concatenate([params, np.full((params.shape[0], 1), m)], axis=1)
+        params = np.ascontiguousarray(params.reshape(-1, 4))
         states = np.ascontiguousarray(np.asarray(states, dtype=np.float64).reshape(params.shape[0], self.Nu))
         o = pa_ws_opts(modes, width, epochs, lr, seed)
         loss = np.zeros(1)
@@ -362,8 +428,29 @@ class Solver:
         mu = np.ascontiguousarray(mu, dtype=np.float64)
         self._chk(lib().pa_ws_predict(self._c, _ptr(mu)))
 
+    def ws_pod(self, kmax=128):
+        """(mean deviation [Nu], modes [k][Nu], Gram eigenvalues [k])"""
+        k = np.zeros(1, dtype=np.int32)
+        self._chk(lib().pa_ws_pod(self._c, 0, None, None, None, _ptr(k)))
+        kk = min(int(k[0]), kmax)
+        mean = np.zeros(self.Nu)
+        modes = np.zeros((kk, self.Nu))
+        eig = np.zeros(kk)
+        self._chk(lib().pa_ws_pod(self._c, kk, _ptr(mean), _ptr(modes), _ptr(eig), _ptr(k)))
+        return mean, modes, eig
+
+    def prolong_from(self, coarse, u_coarse):
+        """a state of the discretisation `coarse` (dict of pa_config fields)
+        evaluated at this context's nodes"""
+        cfg = default_config(**coarse)
+        u_coarse = np.ascontiguousarray(u_coarse, dtype=np.float64)
+        out = np.zeros(self.Nu)
+        self._chk(lib().pa_prolong(C.byref(cfg), _ptr(u_coarse), self._c, _ptr(out)))
+        return out
+
     def ws_shoot(self, tol=1e-8, eta=1e-3, maxit=30):
         rep = pa_shoot_report()
+        rep.attach_history(maxit + 1)
         fb = np.zeros(1, dtype=np.int32)
         self._chk(lib().pa_ws_shoot(self._c, tol, eta, maxit, C.byref(rep), _ptr(fb)))
         return rep, bool(fb[0])
@@ -476,9 +563,12 @@ class Solver:
         self._chk(lib().pa_bench_copy(self._c, reps, C.byref(ms), C.byref(nb)))
         return ms.value, nb.value
 
-    def bench_spmv(self, reps=50, transpose=False):
+    def bench_spmv(self, reps=50, transpose=False, nrhs=None):
         ms = C.c_double()
-        self._chk(lib().pa_bench_spmv(self._c, reps, int(transpose), C.byref(ms)))
+        if nrhs is None:
+            self._chk(lib().pa_bench_spmv(self._c, reps, int(transpose), C.byref(ms)))
+        else:
+            self._chk(lib().pa_bench_spmv_m(self._c, reps, int(transpose), int(nrhs), C.byref(ms)))
         return ms.value
 
     def tuning(self):
