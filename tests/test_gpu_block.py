@@ -27,7 +27,7 @@ def pair():
     for s in (a, b):
         s.set_params(np.array(inputs.MU_NOMINAL))
     a.set_freestream(inputs.perturbation(a.Nu, seed=1))
-    a.shoot(tol=1e-11, eta=1e-6, maxit=30)
+    a.shoot(tol=1e-12, eta=1e-8, maxit=30)
     b.set_state(a.get_state(0))
     b.primal_period()
     yield a, b
@@ -35,25 +35,37 @@ def pair():
     b.close()
 
 
-def test_block_adjoint_gradient_matches_lockstep(pair):
+def test_block_adjoint_gradient_matches_lockstep_and_oracle(pair):
+    from oracle.oracle import Oracle
     a, b = pair
-    qa, ga, ra = a.adjoint_gradient(rtol=1e-12)
-    qb, gb, rb = b.adjoint_gradient(rtol=1e-12)
+    qa, ga, ra = a.adjoint_gradient(rtol=1e-13)
+    qb, gb, rb = b.adjoint_gradient(rtol=1e-13)
     assert np.array_equal(qa, qb)                      # the same stored trajectory
-    assert rel(gb, ga) <= 1e-8
+    assert rel(gb, ga) <= 1e-10
+    # Alg. 3 of the oracle (one Krylov space per QoI, exact stage solves)
+    # about the same orbit
+    o = Oracle(lin_solver=0, newton_atol=1e-12, **{k: TINY[k] for k in ("Nr", "Nth", "p", "Nt")})
+    o.set_params(np.array(inputs.MU_NOMINAL))
+    o.primal_period(a.get_state(0))
+    go = np.stack([o.periodic_adjoint(q, rtol=1e-13)[0] for q in (0, 1)])
+    assert rel(gb, go) <= 1e-10
+    to = o.tangent_gradient(rtol=1e-13)
+    gt, _ = b.tangent_gradient(rtol=1e-13)
+    assert rel(gt, to) <= 1e-10
+    o.close()
     ka, kb = list(ra.krylov_its), list(rb.krylov_its)
     assert kb[0] == kb[1] >= 1                         # one block iteration = one sweep for both QoIs
     # no more sweeps than the slower lockstep system (one more at most where
     # rounding moves the residual estimate across the threshold)
     assert kb[0] <= max(ka) + 1
-    assert max(rb.rel_res) <= 1e-12
+    assert max(rb.rel_res) <= 1e-13
     assert rb.sweeps == 2 + kb[0]                      # g_F sweep, Krylov sweeps, final sweep
 
 
 def test_block_tangent_gradient_matches_lockstep(pair):
     a, b = pair
-    ga, ia = a.tangent_gradient(rtol=1e-12)
-    gb, ib = b.tangent_gradient(rtol=1e-12)
-    assert rel(gb, ga) <= 1e-8
+    ga, ia = a.tangent_gradient(rtol=1e-13)
+    gb, ib = b.tangent_gradient(rtol=1e-13)
+    assert rel(gb, ga) <= 1e-10
     assert ib[0] == ib[1] == ib[2] >= 1
     assert ib[0] <= max(ia) + 1

@@ -1,4 +1,4 @@
-"""Gradient-based shooting (Sec. 2.3, minimisation of j(u0) = 1/2 ||u^(Nt)
+"""Gradient-based shooting (Sec. 2.2, minimisation of j(u0) = 1/2 ||u^(Nt)
 - u0||^2 by steepest descent or L-BFGS): the adjoint gradient of j against
 central differences of j itself, and the descent iterations against the
 orbit found by Newton-Krylov shooting."""

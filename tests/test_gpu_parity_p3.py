@@ -1,0 +1,76 @@
+"""Parity at p = 3 (40 x 40 blocks, the benchmark's block size) on a small
+mesh: one primal period, the tangent and backward sweeps, and the periodic
+adjoint (Alg. 3, both QoIs in the same backward sweeps: the two-system
+transposed apply) and direct gradients (three parameter tangents in the
+same forward sweeps: the three-system forward apply) about the same stored
+trajectory, against the oracle.  The trajectory is one period from the
+perturbed free stream, not a periodic orbit: the two-point boundary-value
+problem of Sec. 3.1 is well posed about any trajectory (the machinery
+reading of the one-period configuration), so both sides solve the same
+linear problem."""
+import numpy as np
+import pytest
+
+from paper_1512_00616_amd import inputs
+
+pytestmark = pytest.mark.gpu
+
+MU = np.array(inputs.MU_NOMINAL)
+KW = dict(Nr=2, Nth=6, p=3, Nt=16)   # 8 steps give the oracle a singular diagonal block at p = 3
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+
+
+@pytest.fixture(scope="module")
+def pair():
+    from paper_1512_00616_amd import pa
+    from oracle.oracle import Oracle
+    g = pa.Solver(lin_rtol=1e-13, newton_atol=1e-12, **KW)
+    o = Oracle(lin_solver=1, lin_rtol=1e-13, newton_atol=1e-12, **KW)
+    g.set_params(MU)
+    o.set_params(MU)
+    pert = inputs.perturbation(g.Nu, seed=1)
+    g.set_freestream(pert)
+    u0 = o.freestream(pert)
+    qg, rg = g.primal_period()
+    uNt, qo, ro = o.primal_period(u0)
+    yield g, o, (qg, rg), (uNt, qo, ro)
+    g.close()
+    o.close()
+
+
+def test_primal_period_p3(pair):
+    g, o, (qg, rg), (uNt, qo, ro) = pair
+    assert rel(g.get_state(1), uNt) <= 1e-10
+    assert rel(qg, qo) <= 1e-10
+    for n, i in [(1, 1), (7, 2), (16, 3)]:
+        assert rel(g.traj(0, n, i), o.traj(0, n, i)) <= 1e-10
+
+
+def test_sweeps_p3(pair):
+    g, o, *_ = pair
+    v, w = inputs.random_vectors(g.Nu, 2, seed=7)
+    assert rel(g.tangent_sweep(v), o.tangent(v)) <= 1e-10
+    assert rel(g.adjoint_sweep(w), o.adjoint(w)) <= 1e-10
+    for q in (0, 1):
+        lg, gg = g.adjoint_sweep(w, forced_qoi=q)
+        lo, go = o.adjoint(w, forced_qoi=q)
+        assert rel(lg, lo) <= 1e-10
+        assert rel(gg, go) <= 1e-10
+
+
+def test_two_system_adjoint_and_three_system_direct_gradient_p3(pair):
+    g, o, *_ = pair
+    _, dJ, rep = g.adjoint_gradient(rtol=1e-13)
+    assert rep.rhs_sweeps > rep.sweeps                    # the QoIs share backward sweeps
+    go = np.stack([o.periodic_adjoint(q, rtol=1e-13)[0] for q in (0, 1)])
+    assert rel(dJ, go) <= 1e-10
+    tg, its = g.tangent_gradient(rtol=1e-13)
+    assert all(its > 0)
+    to = o.tangent_gradient(rtol=1e-13)
+    assert rel(tg, to) <= 1e-10
+    assert rel(go, to) <= 1e-10

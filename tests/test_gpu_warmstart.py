@@ -93,3 +93,120 @@ def test_saved_model_predicts_the_same_bits(trained):
     s2.ws_predict(mu)
     assert np.array_equal(s2.get_state(0), a)
     s2.close()
+
+
+# ---------------------------------------------------------------- POD, Mach input, prolongation
+def _smooth_snapshots(s, mus, machs, seed):
+    """snapshots = the free stream of each (mu, Mach) plus deviations from a
+    few fixed directions with well separated amplitudes (so that the POD
+    modes are well conditioned)"""
+    from oracle.oracle import Oracle
+    g = np.random.default_rng(seed)
+    dirs = g.standard_normal((5, s.Nu))
+    amp = 0.5 ** np.arange(5)
+    out = []
+    for mu, m in zip(mus, machs):
+        o = Oracle(mach=m, **TINY)
+        o.set_params(mu)
+        fs = o.freestream()
+        o.close()
+        c = g.standard_normal(5) * amp
+        out.append(fs + 1e-1 * (c @ dirs))
+    return np.array(out), dirs
+
+
+def test_pod_matches_fp64_reference():
+    """Device POD (Gram matrix of the centred deviations, Jacobi eigenpairs,
+    modes) against the oracle's FP64 method of snapshots on the same data,
+    each snapshot's own free stream (its kinematics and Mach number)
+    removed by each side independently."""
+    from paper_1512_00616_amd import pa
+    from oracle import pod
+    from oracle.oracle import Oracle
+    mus = inputs.warmstart_params(10, seed=5)
+    machs = np.linspace(0.15, 0.25, 10)
+    s = pa.Solver(**TINY)
+    X, _ = _smooth_snapshots(s, mus, machs, seed=21)
+    params = np.concatenate([mus, machs[:, None]], axis=1)
+    s.ws_train(params, X, modes=4, width=16, epochs=10, lr=1e-3, seed=5)
+    mean_g, modes_g, eig_g = s.ws_pod()
+    dev = []
+    for x, mu, m in zip(X, mus, machs):
+        o = Oracle(mach=m, **TINY)
+        o.set_params(mu)
+        dev.append(x - o.freestream())
+        o.close()
+    mean_o, modes_o, eig_o, _ = pod.pod(np.array(dev), 4)
+    assert len(eig_g) == 4
+    # the deviations are differences of O(|X|) = 45 states and free streams,
+    # so they carry an absolute rounding of about 1e-14 |X| on both sides
+    scale = np.abs(X).max()
+    assert np.abs(mean_g - mean_o).max() <= 1e-13 * scale
+    assert rel(eig_g, eig_o) <= 1e-9
+    assert rel(pod.align_signs(modes_g, modes_o), modes_o) <= 1e-8
+    s.close()
+
+
+def test_mach_input_reproduces_training_states(tmp_path):
+    """Inputs (h0, theta0, phi, Mach): a model trained on snapshots of two Mach
+    numbers, loaded into a context of either Mach number, predicts for a
+    training input the training state (that Mach's free stream plus the POD
+    expansion) up to the fitting error, far below the difference between
+    the Mach numbers' states."""
+    from paper_1512_00616_amd import pa
+    mus = inputs.warmstart_params(8, seed=5)
+    machs = np.array([0.2, 0.25] * 4)
+    s = pa.Solver(**TINY)
+    X, _ = _smooth_snapshots(s, mus, machs, seed=22)
+    params = np.concatenate([mus, machs[:, None]], axis=1)
+    loss = s.ws_train(params, X, modes=7, width=64, epochs=3000, lr=1e-3, seed=5)
+    assert loss < 1e-2   # normalised coefficients start near 1
+    path = tmp_path / "m.bin"
+    s.ws_save(path)
+    s.close()
+    for i in (2, 3):
+        c = pa.Solver(mach=float(machs[i]), **TINY)
+        c.ws_load(path)
+        c.set_params(mus[i])
+        c.ws_predict(mus[i])
+        err = np.abs(c.get_state(0) - X[i]).max()
+        gap = np.abs(X[i] - X[i - 1]).max()
+        assert err <= 2e-2 * gap, (i, err, gap)
+        c.close()
+
+
+# coefficients of 1, x, y, x^2, xy, y^2, x^3, x^2 y, x y^2, y^3
+POLY = np.array([1.0, 0.3, -0.2, 0.05, 0.02, -0.03, 0.004, -0.002, 0.001, 0.003])
+
+
+@pytest.mark.parametrize("pc,pf", [(1, 2), (2, 3), (3, 3)])
+def test_prolongation_is_exact_for_polynomials(pc, pf):
+    """pa_prolong from a coarse O-grid (4x12) to the nested refined one (8x24):
+    a field that is one polynomial of degree <= pc in X on every coarse
+    element is reproduced at every fine node (each fine node lies in a
+    coarse triangle, or between a coarse chord and the circle, where the
+    same polynomial is extrapolated)."""
+    from paper_1512_00616_amd import pa
+    from oracle.oracle import Oracle
+    coarse = dict(Nr=4, Nth=12, p=pc, Nt=2)
+    oc = Oracle(**coarse)
+    Xc, _ = oc.nodes()
+    of = Oracle(Nr=8, Nth=24, p=pf, Nt=2)
+    Xf, _ = of.nodes()
+    k = (pc + 1) * (pc + 2) // 2
+
+    def field(X):
+        x, y = X[..., 0], X[..., 1]
+        base = [np.ones_like(x), x, y, x * x, x * y, y * y, x ** 3, x * x * y, x * y * y, y ** 3][:k]
+        out = np.zeros(X.shape[:-1] + (4,))
+        for m in range(4):
+            for j in range(k):
+                out[..., m] += (m + 1) * POLY[j] * base[j]
+        return out
+
+    fine = pa.Solver(Nr=8, Nth=24, p=pf, Nt=2)
+    uf = fine.prolong_from(coarse, field(Xc).ravel())
+    assert rel(uf, field(Xf).ravel()) <= 1e-12
+    fine.close()
+    oc.close()
+    of.close()
