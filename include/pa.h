@@ -285,6 +285,60 @@ pa_status pa_dbg_traj(pa_ctx* ctx, int32_t which, int32_t n, int32_t i, double* 
 pa_status pa_dbg_hess_eig(int32_t n, const double* H, double* re, double* im);
 pa_status pa_dbg_sym_eig(int32_t n, const double* A, double* w, double* V);
 
+/* ---- periodic-constrained optimisation ---- */
+typedef struct pa_opt_opts {
+    int32_t obj;                /* QoI minimised (0: time-averaged power, 1: x-force) ... */
+    double  obj_sign;           /* ... as obj_sign * J[obj] (-1: minimise the work done on the fluid, -P) */
+    int32_t con;                /* QoI constrained to con_value (J[con] = con_value); -1: none */
+    double  con_value;
+    double  lo[3], hi[3];       /* bounds on mu = (h0, theta0, phi) */
+    int32_t maxit;              /* SQP iterations */
+    double  tol_kkt;            /* stop: projected gradient of the Lagrangian (inf-norm, variables scaled */
+    double  tol_c;              /*   to the box) <= tol_kkt and |J[con] - con_value| <= tol_c */
+    double  trust;              /* initial step bound in the scaled variables (0: 0.25) */
+    double  shoot_tol, shoot_eta;   /* shooting at every evaluation (pa_shoot) */
+    int32_t shoot_maxit;
+    double  adj_rtol;           /* periodic adjoint tolerance (pa_adjoint_gradient) */
+} pa_opt_opts;
+
+typedef struct pa_opt_report {
+    int32_t iterations;         /* SQP iterations (accepted or rejected steps) */
+    int32_t shoots, gradients;  /* periodic solves and periodic adjoint gradients */
+    int32_t newton_its, tangent_sweeps, adjoint_sweeps;
+    int32_t converged;          /* 1: both tolerances met; 2: step vanished at a feasible point; 0: neither */
+    double  f, c, kkt, lam;     /* objective, constraint violation, KKT measure, multiplier at the end */
+    double  mu[3];
+    double  ms;
+    /* optional history (caller-owned, hist_cap entries, NULL allowed): mu_hist[3k..3k+2], f_hist[k],
+       c_hist[k] after iteration k (k = 0: the start) */
+    double* mu_hist;
+    double* f_hist;
+    double* c_hist;
+    int32_t hist_cap;
+} pa_opt_report;
+
+/* Optimisation over the manifold of periodic solutions (the generalized
+ * reduced-gradient method of Sec. 3.3, eqs. opt:disc0-opt:disc2; the
+ * problem of Sec. 4.2 with this library's kinematics): minimise
+ * obj_sign J[obj](mu) subject to J[con](mu) = con_value and lo <= mu <= hi,
+ * where every evaluation shoots to the periodic orbit at mu (Alg. 2, from
+ * the previous orbit; the first from the context's current u0) and every
+ * accepted point takes the periodic adjoint gradients of both QoIs (Alg. 3,
+ * Alg. 4).  The optimiser is a line-search SQP (three-variable QP steps in
+ * a trust box, damped BFGS, l1 merit).  mu: start on input, the last
+ * accepted point on output; the context is left at that point's periodic
+ * orbit.  PA_EINVAL for bad options or a start outside the box;
+ * PA_ENOCONV if shooting fails at the start. */
+pa_status pa_optimize(pa_ctx* ctx, const pa_opt_opts* opts, double mu[3], pa_opt_report* rep);
+/* Host-only check of the SQP subproblem: minimise g.d + 1/2 d^T B d subject
+ * to a.d = -c and lo <= d <= hi (3 variables, B row-major symmetric
+ * positive definite); when the equality cannot hold in the box its target
+ * is clamped to the nearest attainable value.  *lam receives the equality
+ * multiplier (g + B d = lam a + bound multipliers).  PA_ENUMERIC if no
+ * solution is found. */
+pa_status pa_dbg_qp3(const double B[9], const double g[3], const double a[3], double c, const double lo[3],
+                     const double hi[3], double d[3], double* lam);
+
 /* ---- many parameter instances ---- */
 typedef struct pa_batch_opts {
     int32_t workers;            /* contexts run concurrently, each with its own host thread and stream */

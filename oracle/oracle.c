@@ -1336,8 +1336,9 @@ int pao_gcl_rhs(pao_ctx* c, int32_t n, int32_t i, double* out)
     return 0;
 }
 
-void pao_freestream(pao_ctx* c, const double* pert, double* u)
+int pao_freestream(pao_ctx* c, const double* pert, double* u)
 {
+    if (!c->gb[0]) return -1;   /* the parameters (and with them gbar at t = 0) are not set yet */
     int np = c->np;
     for (int K = 0; K < c->Ne; ++K)
         for (int a = 0; a < np; ++a) {
@@ -1347,6 +1348,7 @@ void pao_freestream(pao_ctx* c, const double* pert, double* u)
                 u[idx] = g * c->Uinf[m] + (pert ? pert[idx] : 0.0);
             }
         }
+    return 0;
 }
 
 int pao_residual(pao_ctx* c, int32_t n, int32_t i, const double* u, double* r)

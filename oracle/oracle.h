@@ -82,7 +82,7 @@ int     pao_gbar(pao_ctx* c, int32_t n, int32_t i, double* out);
 /* GCL right-hand side r_g at stage (n, i) [Ne*np] */
 int     pao_gcl_rhs(pao_ctx* c, int32_t n, int32_t i, double* out);
 /* free stream u = gbar(0) U_inf, plus an optional perturbation */
-void    pao_freestream(pao_ctx* c, const double* perturb, double* u);
+int     pao_freestream(pao_ctx* c, const double* perturb, double* u);   /* -1 before set_params */
 /* mass-matrix product y = M x */
 void    pao_mass_apply(const pao_ctx* c, const double* x, double* y);
 

@@ -199,7 +199,8 @@ class Oracle:
     def freestream(self, perturb=None):
         u = np.zeros(self.Nu)
         pp = None if perturb is None else self._vec(perturb)
-        lib().pao_freestream(self._c, _ptr(pp), _ptr(u))
+        if lib().pao_freestream(self._c, _ptr(pp), _ptr(u)) != 0:
+            raise RuntimeError("freestream before set_params")
         return u
 
     def mass(self, x):

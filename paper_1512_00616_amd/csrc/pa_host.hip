@@ -537,6 +537,8 @@ struct pa_ctx {
     virtual void set_freestream(const double* pert) = 0;
     virtual void get_state(int which, double* out, int64_t n) = 0;
     virtual void primal_period(double qoi[2], double* res) = 0;
+    virtual void last_qois(double q[2]) const = 0;
+    void optimize(const pa_opt_opts& o, double mu[3], pa_opt_report* rep);
     virtual void shoot(double tol, double eta, int maxit, pa_shoot_report* rep) = 0;
     virtual void fixed_point(int periods, double* res) = 0;
     virtual void shoot_descent(double tol, int memory, int maxit, pa_shoot_report* rep) = 0;
@@ -2215,6 +2217,8 @@ struct Solver final : pa_ctx {
             J1 += dt * rk.b[s % 3] * f1 / cfg.T;
         }
         if (qoi) { qoi[0] = J0; qoi[1] = J1; }
+        last_qoi[0] = J0;
+        last_qoi[1] = J1;
         lincomb(1.0, tu + (int64_t)Nt * Nu, -1.0, u0, wa);
         double rn = norm(wa);
         if (res) *res = rn;
@@ -2222,6 +2226,8 @@ struct Solver final : pa_ctx {
     }
 
     void primal_period(double qoi[2], double* res) override { primal_sweep(qoi, res); }
+    double last_qoi[2] = { 0, 0 };   // time-averaged QoIs of the last primal sweep
+    void last_qois(double q[2]) const override { q[0] = last_qoi[0]; q[1] = last_qoi[1]; }
 
     // tangent sweep: out = Phi v (device vectors; out may alias nothing used here)
     void tangent(const double* v, double* out)
@@ -3307,6 +3313,343 @@ pa_status pa_ws_shoot(pa_ctx* c, double tol, double eta, int32_t maxit, pa_shoot
         if (!(tol > 0) || !(eta > 0) || maxit < 1) raise(PA_EINVAL, "bad shooting options");
         c->ws_shoot(tol, eta, maxit, rep, fell_back);
     });
+}
+// ---- periodic-constrained optimisation (generalized reduced gradient) ----
+// QP subproblem of the SQP step in n = 3 scaled variables:
+//   minimise g.d + 1/2 d^T B d  subject to  a.d = -c,  lo <= d <= hi
+// with B symmetric positive definite.  The minimiser lies in the relative
+// interior of one face of the box, where it minimises the quadratic with the
+// face's variables fixed at their bounds and the equality kept, so every
+// face (each variable free, at its lower or at its upper bound: 27 faces)
+// is solved and the feasible solution with the smallest objective is
+// taken.  When no point of the box satisfies the equality, its target -c is
+// first clamped to the range of a.d over the box (the least violation).
+// Returns the equality multiplier in *lam (the constraint's Lagrange
+// multiplier, sign convention g + B d = lam a + bound multipliers) and 0, or
+// -1 when no face has a solution.
+int qp3(const double B[9], const double g[3], const double a[3], double c, const double lo[3], const double hi[3],
+        double d[3], double* lam)
+{
+    double amin = 0, amax = 0, anorm = 0;
+    for (int i = 0; i < 3; ++i) {
+        amin += a[i] > 0 ? a[i] * lo[i] : a[i] * hi[i];
+        amax += a[i] > 0 ? a[i] * hi[i] : a[i] * lo[i];
+        anorm = std::max(anorm, std::fabs(a[i]));
+    }
+    const bool has_eq = anorm > 0.0;         // a = 0: no equality (bounds only)
+    const double target = has_eq ? std::min(std::max(-c, amin), amax) : 0.0;
+    const double etol = 1e-9 * (1.0 + std::fabs(amin) + std::fabs(amax));   // equality tolerance
+    double best = 1e300;
+    int found = -1;
+    for (int code = 0; code < 27; ++code) {
+        int st[3] = { code % 3, (code / 3) % 3, code / 9 };   // 0 free, 1 lower, 2 upper
+        double x[3] = { 0, 0, 0 };
+        int fr[3], nf = 0;
+        double fixed_a = 0.0, free_a = 0.0;
+        for (int i = 0; i < 3; ++i) {
+            if (st[i] == 1) x[i] = lo[i];
+            else if (st[i] == 2) x[i] = hi[i];
+            else fr[nf++] = i;
+            if (st[i] != 0) fixed_a += a[i] * x[i];
+            else free_a = std::max(free_a, std::fabs(a[i]));
+        }
+        // the equality constrains the free variables only when one of them enters it; otherwise the
+        // fixed ones must satisfy it already
+        const bool eq_row = has_eq && free_a > 0.0;
+        if (has_eq && !eq_row && std::fabs(fixed_a - target) > etol) continue;
+        // KKT of the free variables (with the equality when it binds them):
+        // [Bff -aF; aF^T 0] [xF; l] = [-gF - Bfx x_fixed; t - a_fixed . x_fixed]
+        const int m = nf + (eq_row ? 1 : 0);
+        double K[4][5] = {};
+        for (int r = 0; r < nf; ++r) {
+            const int i = fr[r];
+            double rhs = -g[i];
+            for (int j = 0; j < 3; ++j)
+                if (st[j] != 0) rhs -= B[i * 3 + j] * x[j];
+            for (int q = 0; q < nf; ++q) K[r][q] = B[i * 3 + fr[q]];
+            if (eq_row) K[r][nf] = -a[i];
+            K[r][m] = rhs;
+        }
+        if (eq_row) {
+            for (int q = 0; q < nf; ++q) K[nf][q] = a[fr[q]];
+            K[nf][m] = target - fixed_a;
+        }
+        // Gauss-Jordan elimination with partial pivoting: K becomes diagonal, row k holding unknown k
+        bool ok = true;
+        for (int col = 0; col < m && ok; ++col) {
+            int pv = col;
+            for (int r = col + 1; r < m; ++r)
+                if (std::fabs(K[r][col]) > std::fabs(K[pv][col])) pv = r;
+            if (std::fabs(K[pv][col]) < 1e-300) { ok = false; break; }
+            if (pv != col)
+                for (int q = 0; q <= m; ++q) std::swap(K[col][q], K[pv][q]);
+            for (int r = 0; r < m; ++r) {
+                if (r == col) continue;
+                const double f = K[r][col] / K[col][col];
+                for (int q = col; q <= m; ++q) K[r][q] -= f * K[col][q];
+            }
+        }
+        if (!ok) continue;
+        const double l = eq_row ? K[nf][m] / K[nf][nf] : 0.0;
+        for (int r = 0; r < nf; ++r) x[fr[r]] = K[r][m] / K[r][r];
+        bool feas = true;
+        for (int i = 0; i < 3; ++i) feas = feas && x[i] >= lo[i] - 1e-12 && x[i] <= hi[i] + 1e-12;
+        if (has_eq) {
+            double ax = 0.0;
+            for (int i = 0; i < 3; ++i) ax += a[i] * x[i];
+            feas = feas && std::fabs(ax - target) <= etol;
+        }
+        if (!feas) continue;
+        double obj = 0.0;
+        for (int i = 0; i < 3; ++i) {
+            obj += g[i] * x[i];
+            for (int j = 0; j < 3; ++j) obj += 0.5 * x[i] * B[i * 3 + j] * x[j];
+        }
+        if (obj < best) {
+            best = obj;
+            for (int i = 0; i < 3; ++i) d[i] = std::min(std::max(x[i], lo[i]), hi[i]);
+            *lam = l;
+            found = 0;
+        }
+    }
+    if (found == 0 && has_eq) {
+        // where the minimiser is degenerate (a vertex, or a face whose free variables the equality
+        // does not bind, e.g. when the target was clamped) the face's multiplier need not carry the
+        // right signs on the bound variables: take the valid multiplier nearest to it, from
+        // w_i = (g + B d)_i = lam a_i on free variables, w_i - lam a_i >= 0 at a lower bound and
+        // <= 0 at an upper bound
+        double lmin = -1e300, lmax = 1e300;
+        for (int i = 0; i < 3; ++i) {
+            double w = g[i];
+            for (int j = 0; j < 3; ++j) w += B[i * 3 + j] * d[j];
+            const bool atl = d[i] <= lo[i] + 1e-12 * (1.0 + std::fabs(lo[i]));
+            const bool atu = d[i] >= hi[i] - 1e-12 * (1.0 + std::fabs(hi[i]));
+            if (a[i] == 0.0 || (atl && atu)) continue;
+            const double q = w / a[i];
+            if (!atl && !atu) { lmin = std::max(lmin, q); lmax = std::min(lmax, q); }
+            else if (atl == (a[i] > 0)) lmax = std::min(lmax, q);   // lam a_i <= w_i
+            else lmin = std::max(lmin, q);                          // lam a_i >= w_i
+        }
+        if (lmin <= lmax) *lam = std::min(std::max(*lam, lmin), lmax);
+    }
+    return found;
+}
+
+// Generalized reduced-gradient loop of Sec. 3.3 (eq. opt:disc2 reduced to
+// eq. opt:disc1 on the manifold of periodic solutions): every evaluation at
+// parameters mu shoots to the periodic orbit (Alg. 2, warm-started from the
+// previous periodic state) and every accepted point takes both QoIs' periodic
+// adjoint gradients (Alg. 3, Alg. 4).  The optimiser is a line-search SQP
+// in variables scaled to the box [lo, hi]: QP steps (qp3) within a trust box,
+// damped BFGS on the Hessian of the Lagrangian, l1 merit f + rho |c| with
+// backtracking.  Minimises obj_sign J[obj] subject to J[con] = con_value
+// (con < 0: no constraint).
+void pa_ctx::optimize(const pa_opt_opts& o, double mu[3], pa_opt_report* rep)
+{
+    const double t0 = now_ms();
+    pa_opt_report r{};
+    if (rep) {
+        r.mu_hist = rep->mu_hist;
+        r.f_hist = rep->f_hist;
+        r.c_hist = rep->c_hist;
+        r.hist_cap = rep->hist_cap;
+    }
+    const bool constrained = o.con >= 0;
+    double sc[3];
+    for (int k = 0; k < 3; ++k) {
+        if (!(o.hi[k] > o.lo[k])) raise(PA_EINVAL, "empty parameter box in variable %d", k);
+        if (!(mu[k] >= o.lo[k] && mu[k] <= o.hi[k])) raise(PA_EINVAL, "start outside the parameter box");
+        sc[k] = o.hi[k] - o.lo[k];
+    }
+    const int nu = (int)num_dofs();
+    std::vector<double> uper(nu), ustart(nu);
+    get_state(0, ustart.data(), nu);     // the first shooting starts from the context's current u0
+    bool have_orbit = false;
+    // one evaluation: periodic orbit at m, QoIs; gradient on request
+    auto evaluate = [&](const double m[3], bool grad, double q[2], double dq[6]) -> bool {
+        set_params(m);
+        set_state(have_orbit ? uper.data() : ustart.data(), nu);
+        pa_shoot_report sr{};
+        try {
+            shoot(o.shoot_tol, o.shoot_eta, o.shoot_maxit, &sr);
+        } catch (const PaError& e) {
+            if (e.code != PA_ENOCONV && e.code != PA_ENUMERIC) throw;
+            r.shoots += 1;
+            return false;
+        }
+        r.shoots += 1;
+        r.newton_its += sr.newton_its;
+        r.tangent_sweeps += sr.krylov_its;
+        last_qois(q);
+        if (grad) {
+            pa_adjoint_report ar{};
+            double qq[2];
+            adjoint_gradient(o.adj_rtol, qq, dq, &ar);
+            r.gradients += 1;
+            r.adjoint_sweeps += ar.sweeps;
+        }
+        return true;
+    };
+    auto fval = [&](const double q[2]) { return o.obj_sign * q[o.obj]; };
+    auto cval = [&](const double q[2]) { return constrained ? q[o.con] - o.con_value : 0.0; };
+    double x[3], q[2], dq[6];
+    for (int k = 0; k < 3; ++k) x[k] = (mu[k] - o.lo[k]) / sc[k];
+    auto to_mu = [&](const double* y, double* m) { for (int k = 0; k < 3; ++k) m[k] = o.lo[k] + sc[k] * y[k]; };
+    double m[3];
+    to_mu(x, m);
+    if (!evaluate(m, true, q, dq)) raise(PA_ENOCONV, "shooting failed at the starting parameters");
+    get_state(0, uper.data(), nu);
+    have_orbit = true;
+    double f = fval(q), c = cval(q), g[3], a[3];
+    for (int k = 0; k < 3; ++k) {
+        g[k] = o.obj_sign * dq[3 * o.obj + k] * sc[k];
+        a[k] = constrained ? dq[3 * o.con + k] * sc[k] : 0.0;
+    }
+    double B[9] = { 0 };
+    {   // initial Hessian: identity scaled so that a unit gradient step moves a tenth of the box
+        double gn = 0;
+        for (int k = 0; k < 3; ++k) gn = std::max(gn, std::fabs(g[k]));
+        const double s0 = gn > 0 ? 10.0 * gn : 1.0;
+        for (int k = 0; k < 3; ++k) B[k * 4] = s0;
+    }
+    double lam = 0.0, rho = 0.0, delta = o.trust > 0 ? o.trust : 0.25;
+    auto record = [&]() {
+        const int k = r.iterations;
+        if (k < r.hist_cap) {
+            if (r.mu_hist) to_mu(x, r.mu_hist + 3 * k);
+            if (r.f_hist) r.f_hist[k] = f;
+            if (r.c_hist) r.c_hist[k] = c;
+        }
+    };
+    auto kkt = [&]() {
+        // projected gradient of the Lagrangian on the box (inf-norm, scaled variables)
+        double e = 0;
+        for (int k = 0; k < 3; ++k) {
+            double gl = g[k] - lam * a[k];
+            if (x[k] <= 1e-12 && gl > 0) gl = 0;
+            if (x[k] >= 1 - 1e-12 && gl < 0) gl = 0;
+            e = std::max(e, std::fabs(gl));
+        }
+        return e;
+    };
+    // multiplier estimate at the start: least squares g = lam a
+    if (constrained) {
+        double aa = 0, ga = 0;
+        for (int k = 0; k < 3; ++k) { aa += a[k] * a[k]; ga += g[k] * a[k]; }
+        lam = aa > 0 ? ga / aa : 0.0;
+    }
+    record();
+    for (;;) {
+        r.kkt = kkt();
+        r.f = f;
+        r.c = c;
+        if (r.kkt <= o.tol_kkt && std::fabs(c) <= o.tol_c) { r.converged = 1; break; }
+        if (r.iterations >= o.maxit) break;
+        double lo3[3], hi3[3], d[3], lq = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            lo3[k] = std::max(-x[k], -delta);
+            hi3[k] = std::min(1.0 - x[k], delta);
+        }
+        if (qp3(B, g, a, c, lo3, hi3, d, &lq) != 0) raise(PA_ENUMERIC, "SQP subproblem has no solution");
+        double dn = 0;
+        for (int k = 0; k < 3; ++k) dn = std::max(dn, std::fabs(d[k]));
+        if (dn < 1e-10) { r.converged = std::fabs(c) <= o.tol_c ? 2 : 0; break; }
+        rho = std::max(rho, 2.0 * std::fabs(lq) + 1e-8);
+        const double phi0 = f + rho * std::fabs(c);
+        double gd = 0;
+        for (int k = 0; k < 3; ++k) gd += g[k] * d[k];
+        // directional derivative of the merit along d (the QP step removes the violation it can)
+        double cd = c;
+        for (int k = 0; k < 3; ++k) cd += a[k] * d[k];
+        const double D = gd + rho * (std::fabs(cd) - std::fabs(c));
+        double alpha = 1.0, xn[3], qn[2], dqn[6];
+        bool acc = false;
+        for (int t = 0; t < 6 && !acc; ++t, alpha *= 0.5) {
+            for (int k = 0; k < 3; ++k) xn[k] = std::min(std::max(x[k] + alpha * d[k], 0.0), 1.0);
+            to_mu(xn, m);
+            if (!evaluate(m, false, qn, dqn)) continue;
+            const double phi = fval(qn) + rho * std::fabs(cval(qn));
+            if (phi <= phi0 + 1e-4 * alpha * std::min(D, 0.0) || (D >= 0 && phi < phi0)) acc = true;
+            if (acc) break;
+        }
+        if (!acc) {
+            delta *= 0.25;
+            set_params(mu);   // back to the current point's parameters (its orbit is kept in uper)
+            if (delta < 1e-6) break;
+            ++r.iterations;
+            record();
+            continue;
+        }
+        // the accepted point's gradient (shoot again from its orbit: one more cheap period)
+        get_state(0, uper.data(), nu);
+        to_mu(xn, m);
+        if (!evaluate(m, true, qn, dqn)) raise(PA_ENOCONV, "shooting failed at an accepted point");
+        get_state(0, uper.data(), nu);
+        double gn[3], an[3];
+        for (int k = 0; k < 3; ++k) {
+            gn[k] = o.obj_sign * dqn[3 * o.obj + k] * sc[k];
+            an[k] = constrained ? dqn[3 * o.con + k] * sc[k] : 0.0;
+        }
+        // damped BFGS on the Hessian of the Lagrangian with the QP multiplier
+        double sv[3], yv[3], Bs[3] = { 0, 0, 0 }, sBs = 0, sy = 0;
+        for (int k = 0; k < 3; ++k) {
+            sv[k] = xn[k] - x[k];
+            yv[k] = (gn[k] - lq * an[k]) - (g[k] - lq * a[k]);
+        }
+        for (int k = 0; k < 3; ++k)
+            for (int j = 0; j < 3; ++j) Bs[k] += B[k * 3 + j] * sv[j];
+        for (int k = 0; k < 3; ++k) { sBs += sv[k] * Bs[k]; sy += sv[k] * yv[k]; }
+        if (sBs > 0) {
+            const double th = sy >= 0.2 * sBs ? 1.0 : 0.8 * sBs / (sBs - sy);
+            double rv[3], sr = 0;
+            for (int k = 0; k < 3; ++k) rv[k] = th * yv[k] + (1 - th) * Bs[k];
+            for (int k = 0; k < 3; ++k) sr += sv[k] * rv[k];
+            if (sr > 0)
+                for (int k = 0; k < 3; ++k)
+                    for (int j = 0; j < 3; ++j) B[k * 3 + j] += rv[k] * rv[j] / sr - Bs[k] * Bs[j] / sBs;
+        }
+        if (alpha >= 1.0 && dn >= 0.99 * delta) delta = std::min(2.0 * delta, 1.0);
+        for (int k = 0; k < 3; ++k) { x[k] = xn[k]; g[k] = gn[k]; a[k] = an[k]; }
+        q[0] = qn[0];
+        q[1] = qn[1];
+        f = fval(q);
+        c = cval(q);
+        lam = lq;
+        to_mu(x, mu);
+        ++r.iterations;
+        record();
+    }
+    to_mu(x, mu);
+    set_params(mu);
+    set_state(uper.data(), nu);
+    r.lam = lam;
+    for (int k = 0; k < 3; ++k) r.mu[k] = mu[k];
+    r.ms = now_ms() - t0;
+    if (rep) *rep = r;
+}
+
+pa_status pa_optimize(pa_ctx* c, const pa_opt_opts* o, double mu[3], pa_opt_report* rep)
+{
+    return guard(c, [&] {
+        if (!o || !mu) raise(PA_EINVAL, "NULL argument");
+        if (o->obj < 0 || o->obj > 1 || o->con > 1 || (o->con >= 0 && o->con == o->obj) || o->maxit < 0 ||
+            !(o->shoot_tol > 0) || !(o->shoot_eta > 0) || !(o->adj_rtol > 0) || o->shoot_maxit < 0)
+            raise(PA_EINVAL, "bad optimisation options");
+        c->optimize(*o, mu, rep);
+    });
+}
+pa_status pa_dbg_qp3(const double B[9], const double g[3], const double a[3], double cval, const double lo[3],
+                     const double hi[3], double d[3], double* lam)
+{
+    if (!B || !g || !a || !lo || !hi || !d || !lam) {
+        g_create_err = "NULL argument";
+        return PA_EINVAL;
+    }
+    if (qp3(B, g, a, cval, lo, hi, d, lam) != 0) {
+        g_create_err = "no face of the box gives a solution";
+        return PA_ENUMERIC;
+    }
+    return PA_OK;
 }
 // Prolongation of a state of a coarser O-grid discretisation to the nodes of
 // `fine`: each fine node X (in the fixed reference domain) is located in the

@@ -404,7 +404,8 @@ namespace pa {
 
 
 // relaxed read of the done flag (block 0 of k_gm_upd may set it while
-// other blocks of the same launch read it; either value is correct there)
+// other blocks of the same launch read it; either value is correct there,
+// as long as all threads of a block act on the same one)
 __device__ __forceinline__ int gm_done(const GmState* st)
 {
     return __hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -422,8 +423,13 @@ __device__ __forceinline__ int gm_done(const GmState* st)
 // column and the caller's true-residual check decides whether to restart.
 // V_{j+1} is written even when the cycle ends here; it is then unused.
 // Blocks cover the same MD_TILE ranges as k_mdot_part; each thread owns two
-// double2 and the loads of eight basis columns are issued together
-// (columns past j re-read column j with weight zero).
+// double2.  The loads of w and of the first GU_PRE basis columns are issued
+// before the partials are summed, so that their latency overlaps the
+// summation; later columns follow in groups of eight.  The partial sums are
+// spread over the threads as (column, row group): thread (c, g) adds rows g,
+// g + 8, ... of column c, then the 8 group sums of a column are added in
+// group order (the same order in every block).
+constexpr int GU_PRE = 16;   // basis columns loaded before the final sums
 template <class T>
 __global__ void __launch_bounds__(MD_THREADS) k_gm_upd(const T* __restrict__ V, int64_t ldv, int j, int m,
                                                        const T* __restrict__ w, int64_t n,
@@ -439,37 +445,59 @@ __global__ void __launch_bounds__(MD_THREADS) k_gm_upd(const T* __restrict__ V, 
         st += r;
     }
     T* __restrict__ vnext = const_cast<T*>(V) + (int64_t)(j + 1) * ldv;
-    if (gm_done(st)) return;
+    __shared__ int sdone;
+    if (threadIdx.x == 0) sdone = gm_done(st);   // one read per block, so that the whole block leaves or stays
+    __syncthreads();
+    if (sdone) return;
     __shared__ double s1[GM_MAXM + 2];
     __shared__ double scs[GM_MAXM], ssn[GM_MAXM];
     __shared__ double col[GM_MAXM + 2];
+    __shared__ double red[MD_THREADS / 32][33];
     const int ncols = j + 1, nc = j + 2;
     const bool lead = blockIdx.x == 0;
-    // this thread's entries of w and of the first eight basis columns are
-    // loaded before the partials are summed, so both latencies overlap
-    const int64_t i0 = (int64_t)blockIdx.x * MD_TILE + 2 * threadIdx.x, i1 = i0 + 2 * MD_THREADS;
+    const int tid = threadIdx.x;
+    const int64_t i0 = (int64_t)blockIdx.x * MD_TILE + 2 * tid, i1 = i0 + 2 * MD_THREADS;
     const bool in0 = i0 < n, in1 = i1 < n;
     const int64_t a0 = in0 ? i0 : 0, a1 = in1 ? i1 : 0;   // clamped (valid) addresses
-    double2 pa[8], pb[8];
+    double2 pa[GU_PRE], pb[GU_PRE];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < GU_PRE; ++u) {
         const T* vc = V + (int64_t)(u < ncols ? u : ncols - 1) * ldv;
         pa[u] = ld2(vc + a0);
         pb[u] = ld2(vc + a1);
     }
     const double2 wa = ld2(w + a0), wb = ld2(w + a1);
     if (lead)
-        for (int i = threadIdx.x; i < j; i += blockDim.x) {
+        for (int i = tid; i < j; i += blockDim.x) {
             scs[i] = st->cs[i];
             ssn[i] = st->sn[i];
         }
-    mdot_finish(partial, nblk, nc, s1);
+    // final sums of the partials
+    {
+        const int cl = tid & 31, g = tid >> 5;
+        constexpr int NG = MD_THREADS / 32;
+        for (int c0 = 0; c0 < nc; c0 += 32) {
+            const int c = c0 + cl;
+            double acc = 0.0;
+            if (c < nc)
+                for (int b = g; b < nblk; b += NG) acc += partial[(int64_t)b * nc + c];
+            red[g][cl] = acc;
+            __syncthreads();
+            if (tid < 32 && c < nc) {
+                double sum = 0.0;
+#pragma unroll
+                for (int gg = 0; gg < NG; ++gg) sum += red[gg][tid];
+                s1[c] = sum;
+            }
+            __syncthreads();
+        }
+    }
     double proj = 0.0;
     for (int i = 0; i < ncols; ++i) proj += s1[i] * s1[i];
     const double ww = s1[ncols], rem = ww - proj;
     const double hn = rem > 0.0 ? sqrt(rem) : 0.0;
     const double ih = hn > 0.0 ? 1.0 / hn : 0.0;
-    if (lead && threadIdx.x == 0) {
+    if (lead && tid == 0) {
         const bool close = !(rem > 1e-4 * ww);
         for (int i = 0; i < ncols; ++i) col[i] = s1[i];
         col[j + 1] = hn;
@@ -498,7 +526,7 @@ __global__ void __launch_bounds__(MD_THREADS) k_gm_upd(const T* __restrict__ V, 
     }
     if (lead) {
         __syncthreads();
-        for (int i = threadIdx.x; i <= j + 1; i += blockDim.x) {
+        for (int i = tid; i <= j + 1; i += blockDim.x) {
             st->H[i * m + j] = col[i];
             if (i <= j) st->hc[i] = s1[i];
         }
@@ -506,14 +534,14 @@ __global__ void __launch_bounds__(MD_THREADS) k_gm_upd(const T* __restrict__ V, 
     // V_{j+1}
     double2 s0 = make_double2(0.0, 0.0), s1v = make_double2(0.0, 0.0);
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
+    for (int u = 0; u < GU_PRE; ++u) {
         const double h = u < ncols ? s1[u] : 0.0;
         s0.x += h * pa[u].x;
         s0.y += h * pa[u].y;
         s1v.x += h * pb[u].x;
         s1v.y += h * pb[u].y;
     }
-    for (int cb = 8; cb < ncols; cb += 8) {
+    for (int cb = GU_PRE; cb < ncols; cb += 8) {
         double2 a[8], b[8];
 #pragma unroll
         for (int u = 0; u < 8; ++u) {
@@ -623,18 +651,25 @@ namespace pa {
 // Transposed solves (left preconditioning): Ahat^T x = P^{-T} b.
 // Only the three off-diagonal blocks of a row are streamed per iteration.
 
-// P (diagonal blocks of A) and P^{-1}: LU with partial pivoting (lowest row
-// on ties) of each diagonal block in LDS, then the explicit inverse.
+// P (diagonal blocks of A) and P^{-1}: LU with partial pivoting (largest
+// magnitude, lowest row on ties) of each diagonal block in LDS, one wave per
+// block, then the explicit inverse.
+//  - pivot search: lane i holds |a[i][k]| (i >= k) and the wave finds the
+//    largest by a butterfly of cross-lane exchanges;
+//  - row swap, multipliers and the trailing update run across the lanes
+//    (the update over the (B-k-1)^2 trailing entries);
+//  - inverse: lane j computes column j of P^{-1} = U^{-1} L^{-1} Pi e_j in
+//    registers (forward then back substitution, fully unrolled, the factor
+//    entries read from LDS as broadcasts) and writes it.
 template <int NP>
 __global__ void __launch_bounds__(64) k_blockprep(int Ne, const double* __restrict__ area, const double* __restrict__ mh,
                                                   const double* __restrict__ J, double c, double* __restrict__ Pd,
                                                   double* __restrict__ Pinv, int* __restrict__ status)
 {
     constexpr int B = 4 * NP, BB = B * B;
+    static_assert(B <= 64, "one lane per row");
     __shared__ double a[B][B + 1];
-    __shared__ double inv[B][B + 1];
-    __shared__ int piv[B];
-    __shared__ int sp;
+    __shared__ int perm[B];
     const int K = blockIdx.x, lane = threadIdx.x;
     const double* src = J + (int64_t)K * 4 * BB;
     const double s2 = 2.0 * area[K];
@@ -646,69 +681,71 @@ __global__ void __launch_bounds__(64) k_blockprep(int Ne, const double* __restri
         a[i][j] = v;
         pd[t] = v;
     }
+    if (lane < B) perm[lane] = lane;
     __syncthreads();
     for (int k = 0; k < B; ++k) {
-        if (lane == 0) {
-            int p = k;
-            double best = fabs(a[k][k]);
-            for (int i = k + 1; i < B; ++i) {
-                double v = fabs(a[i][k]);
-                if (v > best) { best = v; p = i; }
+        // pivot: the largest |a[i][k]|, i >= k, lowest i on ties
+        double v = (lane >= k && lane < B) ? fabs(a[lane][k]) : -1.0;
+        int idx = lane;
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) {
+            const double ov = __shfl_xor(v, off, 64);
+            const int oi = __shfl_xor(idx, off, 64);
+            if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
+        }
+        const int p = idx;
+        if (lane == 0 && v == 0.0) status[0] = 1;
+        if (p != k) {
+            if (lane < B) {
+                const double t = a[k][lane];
+                a[k][lane] = a[p][lane];
+                a[p][lane] = t;
             }
-            piv[k] = p;
-            sp = p;
-            if (best == 0.0) status[0] = 1;
+            if (lane == 0) {
+                const int t = perm[k];
+                perm[k] = perm[p];
+                perm[p] = t;
+            }
         }
         __syncthreads();
-        int p = sp;
-        if (p != k)
-            for (int j = lane; j < B; j += 64) {
-                double t = a[k][j];
-                a[k][j] = a[p][j];
-                a[p][j] = t;
-            }
+        const double d = a[k][k];
+        if (lane > k && lane < B) a[lane][k] /= d;
         __syncthreads();
-        double d = a[k][k];
-        for (int i = k + 1 + lane; i < B; i += 64) a[i][k] /= d;
-        __syncthreads();
-        for (int t = lane; t < (B - k - 1) * (B - k - 1); t += 64) {
-            int i = k + 1 + t / (B - k - 1), j = k + 1 + t % (B - k - 1);
+        const int w = B - k - 1;
+        for (int t = lane; t < w * w; t += 64) {
+            const int i = k + 1 + t / w, j = k + 1 + t % w;
             a[i][j] -= a[i][k] * a[k][j];
         }
         __syncthreads();
     }
     if (lane < B) {
         const int col = lane;
-        for (int i = 0; i < B; ++i) inv[i][col] = (i == col) ? 1.0 : 0.0;
-        for (int k = 0; k < B; ++k) {
-            int p = piv[k];
-            if (p != k) { double t = inv[k][col]; inv[k][col] = inv[p][col]; inv[p][col] = t; }
+        double x[B];
+        // x = Pi e_col: row i of the permuted system is row perm[i] of P
+#pragma unroll
+        for (int i = 0; i < B; ++i) x[i] = perm[i] == col ? 1.0 : 0.0;
+        // L (unit lower) forward substitution
+#pragma unroll
+        for (int i = 1; i < B; ++i) {
+            double s = x[i];
+#pragma unroll
+            for (int j = 0; j < i; ++j) s -= a[i][j] * x[j];
+            x[i] = s;
         }
-        for (int i = 0; i < B; ++i) {
-            double s = inv[i][col];
-            for (int j = 0; j < i; ++j) s -= a[i][j] * inv[j][col];
-            inv[i][col] = s;
-        }
+        // U back substitution
+#pragma unroll
         for (int i = B - 1; i >= 0; --i) {
-            double s = inv[i][col];
-            for (int j = i + 1; j < B; ++j) s -= a[i][j] * inv[j][col];
-            inv[i][col] = s / a[i][i];
+            double s = x[i];
+#pragma unroll
+            for (int j = i + 1; j < B; ++j) s -= a[i][j] * x[j];
+            x[i] = s / a[i][i];
         }
+        double* dst = Pinv + (int64_t)K * BB;
+#pragma unroll
+        for (int i = 0; i < B; ++i) dst[i * B + col] = x[i];
     }
-    __syncthreads();
-    double* dst = Pinv + (int64_t)K * BB;
-    for (int t = lane; t < BB; t += 64) dst[t] = inv[t / B][t % B];
 }
 
-// Ahat_{K,f} = -c J_{K,1+f} Pinv_nb (zero block when face f is on the boundary);
-// one workgroup per (element, face)
-// Ahat_{K,f} = -c J_{K,nb} P_nb^{-1} on the matrix cores (FP64 MFMA
-// 16x16x4): one wave per product; both factors staged in LDS (J scaled by
-// -c), the 40 x 40 output as 3 x 3 tiles of 16 x 16 (rows and columns past B
-// padded with zeros), B / 4 steps of k each.  Lane layout of the builtin
-// (checked on the device): A[i][k] from lane i + 16 k, B[k][j] from lane
-// j + 16 k, result element (lane / 16 + 4 r, lane % 16) in register r.
-typedef double mf_d4 __attribute__((ext_vector_type(4)));
 template <int NP>
 __global__ void __launch_bounds__(64) k_form_ahat_mfma(int Ne, const int32_t* __restrict__ enb,
                                                        const double* __restrict__ J, double c,

@@ -23,7 +23,7 @@ EXPORTED = [
     "pa_get_state", "pa_primal_period", "pa_shoot", "pa_fixed_point", "pa_shoot_descent", "pa_periodicity_gradient", "pa_floquet", "pa_adjoint_gradient", "pa_tangent_gradient", "pa_batch_gradients",
     "pa_ws_train", "pa_ws_predict", "pa_ws_pod", "pa_prolong", "pa_ws_shoot", "pa_ws_save", "pa_ws_load", "pa_dbg_mlp", "pa_tangent_sweep",
     "pa_adjoint_sweep", "pa_dbg_gbar", "pa_dbg_dgbar", "pa_dbg_residual", "pa_dbg_jacobian", "pa_dbg_dr_dmu",
-    "pa_dbg_qoi", "pa_dbg_bsr_apply", "pa_dbg_blockinv", "pa_dbg_stage_solve", "pa_dbg_traj", "pa_dbg_hess_eig", "pa_dbg_sym_eig", "pa_set_timing",
+    "pa_dbg_qoi", "pa_dbg_bsr_apply", "pa_dbg_blockinv", "pa_dbg_stage_solve", "pa_dbg_traj", "pa_dbg_hess_eig", "pa_dbg_sym_eig", "pa_optimize", "pa_dbg_qp3", "pa_set_timing",
     "pa_kernel_time", "pa_kernel_skipped", "pa_bench_spmv", "pa_bench_spmv_m", "pa_bench_spmv_lo", "pa_bench_copy", "pa_tuning",
 ]
 
@@ -78,6 +78,37 @@ class pa_batch_opts(C.Structure):
     _fields_ = [("workers", C.c_int32), ("shoot_maxit", C.c_int32), ("shoot_tol", C.c_double),
                 ("shoot_eta", C.c_double), ("allow_unconverged", C.c_int32), ("adj_rtol", C.c_double),
                 ("keep_going", C.c_int32)]
+
+
+class pa_opt_opts(C.Structure):
+    _fields_ = [("obj", C.c_int32), ("obj_sign", C.c_double), ("con", C.c_int32), ("con_value", C.c_double),
+                ("lo", C.c_double * 3), ("hi", C.c_double * 3), ("maxit", C.c_int32), ("tol_kkt", C.c_double),
+                ("tol_c", C.c_double), ("trust", C.c_double), ("shoot_tol", C.c_double),
+                ("shoot_eta", C.c_double), ("shoot_maxit", C.c_int32), ("adj_rtol", C.c_double)]
+
+
+class pa_opt_report(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("shoots", C.c_int32), ("gradients", C.c_int32),
+                ("newton_its", C.c_int32), ("tangent_sweeps", C.c_int32), ("adjoint_sweeps", C.c_int32),
+                ("converged", C.c_int32), ("f", C.c_double), ("c", C.c_double), ("kkt", C.c_double),
+                ("lam", C.c_double), ("mu", C.c_double * 3), ("ms", C.c_double),
+                ("mu_hist", C.POINTER(C.c_double)), ("f_hist", C.POINTER(C.c_double)),
+                ("c_hist", C.POINTER(C.c_double)), ("hist_cap", C.c_int32)]
+
+    def attach_history(self, cap):
+        self._mu_hist = np.full((cap, 3), np.nan)
+        self._f_hist = np.full(cap, np.nan)
+        self._c_hist = np.full(cap, np.nan)
+        self.mu_hist = self._mu_hist.ctypes.data_as(C.POINTER(C.c_double))
+        self.f_hist = self._f_hist.ctypes.data_as(C.POINTER(C.c_double))
+        self.c_hist = self._c_hist.ctypes.data_as(C.POINTER(C.c_double))
+        self.hist_cap = cap
+
+    def history(self):
+        """(mu, objective, constraint violation) at the start and after each
+        iteration"""
+        n = min(self.iterations + 1, self.hist_cap)
+        return self._mu_hist[:n].copy(), self._f_hist[:n].copy(), self._c_hist[:n].copy()
 
 
 class pa_ws_opts(C.Structure):
@@ -151,6 +182,8 @@ def lib():
             "pa_dbg_traj": [P, C.c_int32, C.c_int32, C.c_int32, P],
             "pa_dbg_hess_eig": [C.c_int32, P, P, P],
             "pa_dbg_sym_eig": [C.c_int32, P, P, P],
+            "pa_optimize": [P, C.POINTER(pa_opt_opts), P, C.POINTER(pa_opt_report)],
+            "pa_dbg_qp3": [P, P, P, C.c_double, P, P, P, P],
             "pa_set_timing": [P, C.c_int32],
             "pa_kernel_time": [P, C.c_int32, P, P],
             "pa_kernel_skipped": [P, C.c_int32, P],
@@ -226,6 +259,18 @@ def dbg_mlp(params, X, T, width):
     return float(loss[0]), grads
 
 
+def dbg_qp3(B, g, a, c, lo, hi):
+    """pa_dbg_qp3: (d, lam) of min g.d + d^T B d / 2, a.d = -c, lo <= d <= hi"""
+    B = np.ascontiguousarray(B, dtype=np.float64).reshape(9)
+    g, a, lo, hi = (np.ascontiguousarray(v, dtype=np.float64).reshape(3) for v in (g, a, lo, hi))
+    d = np.zeros(3)
+    lam = np.zeros(1)
+    rc = lib().pa_dbg_qp3(_ptr(B), _ptr(g), _ptr(a), float(c), _ptr(lo), _ptr(hi), _ptr(d), _ptr(lam))
+    if rc != PA_OK:
+        raise PaError(rc, lib().pa_last_error(None).decode())
+    return d, float(lam[0])
+
+
 def dbg_hess_eig(H):
     """Eigenvalues (complex, by decreasing modulus) of an upper Hessenberg
     matrix by the library's host-side shifted QR (no device work)."""
@@ -252,14 +297,38 @@ def dbg_sym_eig(A):
     return w, V
 
 
+def loaded_hip_runtimes():
+    """paths of the HIP runtime libraries mapped into this process"""
+    paths = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                part = line.split()
+                if len(part) >= 6 and "libamdhip64" in part[-1]:
+                    paths.add(part[-1])
+    except OSError:
+        pass
+    return sorted(paths)
+
+
 class TorchMemory:
     """PyTorch owns a context's device memory and stream: every device buffer
     comes from torch's caching allocator (pa_config dev_alloc / dev_free)
     and all device work is enqueued on a torch stream (pa_config stream).
-    Keep the object alive as long as the context (Solver keeps a reference)."""
+    Keep the object alive as long as the context (Solver keeps a reference).
+
+    Streams are objects of one HIP runtime, so the library and torch must
+    share it: import torch before this library is loaded (the dynamic
+    linker then resolves the library's HIP runtime to the one torch
+    loaded).  A process that mapped two different HIP runtimes is refused."""
 
     def __init__(self, device=0, stream=None):
         import torch
+        lib()
+        rts = loaded_hip_runtimes()
+        if len(rts) > 1:
+            raise RuntimeError("PyTorch and libpa use different HIP runtimes (%s); import torch before the "
+                               "library is loaded" % ", ".join(rts))
         self.device = torch.device("cuda", device)
         self.stream = stream if stream is not None else torch.cuda.Stream(device=self.device)
         AF = C.CFUNCTYPE(C.c_void_p, C.c_uint64, C.c_void_p)
@@ -378,6 +447,23 @@ class Solver:
         h = np.zeros(1)
         self._chk(lib().pa_floquet(self._c, k, seed, _ptr(re), _ptr(im), _ptr(n), _ptr(h)))
         return (re + 1j * im)[: n[0]], float(h[0])
+
+    def optimize(self, mu0, obj=0, obj_sign=-1.0, con=1, con_value=0.0, lo=(0.0, 0.0, 0.0),
+                 hi=(1.0, 1.0, 1.0), maxit=20, tol_kkt=1e-6, tol_c=1e-8, trust=0.0, shoot_tol=1e-10,
+                 shoot_eta=1e-6, shoot_maxit=30, adj_rtol=1e-10):
+        """Periodic-constrained optimisation (pa_optimize); returns (mu,
+        report) with the report's history attached."""
+        o = pa_opt_opts(obj=obj, obj_sign=obj_sign, con=con, con_value=con_value, maxit=maxit,
+                        tol_kkt=tol_kkt, tol_c=tol_c, trust=trust, shoot_tol=shoot_tol, shoot_eta=shoot_eta,
+                        shoot_maxit=shoot_maxit, adj_rtol=adj_rtol)
+        o.lo[:] = [float(v) for v in lo]
+        o.hi[:] = [float(v) for v in hi]
+        mu = np.array(mu0, dtype=np.float64).copy()
+        assert mu.size == 3
+        rep = pa_opt_report()
+        rep.attach_history(maxit + 1)
+        self._chk(lib().pa_optimize(self._c, C.byref(o), _ptr(mu), C.byref(rep)))
+        return mu, rep
 
     def fixed_point(self, periods):
         r = np.zeros(1)
