@@ -267,6 +267,22 @@ pa_status pa_dbg_stage_solve(pa_ctx* ctx, const double* blk, double a_dt, int32_
  * *loss = mean squared error, grads laid out as params */
 pa_status pa_dbg_mlp(int32_t in, int32_t width, int32_t out, int32_t batch, const float* params, const float* X,
                      const float* T, float* loss, float* grads);
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the pass
+ * of pa_dbg_mlp with every array in DEVICE memory of the current device --
+ * params, X, T (inputs) and *loss, grads (outputs), laid out as in
+ * pa_dbg_mlp -- enqueued on `stream` (hipStream_t; NULL = the null stream)
+ * and not waited for.  The activations and back-propagation buffers live in
+ * a fixed work array of PA_MLP_SCRATCH_FLOATS floats per GPU, which the
+ * library holds until the process ends; the call allocates nothing.  It
+ * needs (3 width + out + 2 max(in, width, out)) batch floats of it and
+ * returns PA_EINVAL beyond that.  Calls that overlap on one GPU share the
+ * array and race: order them on one stream.  Nothing in the array needs
+ * clearing between calls (every entry is written before it is read).
+ * pa_last_error(NULL) describes a failure. */
+#define PA_MLP_SCRATCH_FLOATS (1 << 20)
+pa_status pa_mlp_grad_noalloc(int32_t in, int32_t width, int32_t out, int32_t batch, const float* params,
+                              const float* X, const float* T, float* loss, float* grads, void* stream);
 /* trajectory: which = 0 stage state u_i^(n), 1 stage k_i^(n), 2 step state u^(n) */
 pa_status pa_dbg_traj(pa_ctx* ctx, int32_t which, int32_t n, int32_t i, double* out);
 /* Host-only checks of the library's small dense eigen-solvers (no device

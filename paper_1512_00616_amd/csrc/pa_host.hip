@@ -3742,6 +3742,67 @@ pa_status pa_ws_load(pa_ctx* c, const char* path)
     });
 }
 
+// ---- allocation-free perceptron pass ----
+// Work memory of pa_mlp_grad_noalloc: a file-scope device array of
+// PA_MLP_SCRATCH_FLOATS floats (one copy per GPU, held until the process
+// ends).  Host code never passes the array's name to a kernel (on the host
+// it only stands in for the symbol): its device address is looked up once
+// per device with hipGetSymbolAddress and that pointer is used.
+static __device__ __align__(256) float scratch[PA_MLP_SCRATCH_FLOATS];
+static std::mutex g_scratch_mu;
+static float* g_scratch_ptr[64] = {};
+
+static float* scratch_on_current_device()
+{
+    int dev = 0;
+    HIPCHK(hipGetDevice(&dev));
+    if (dev < 0 || dev >= 64) raise(PA_EDEVICE, "device ordinal %d out of range", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            raise(PA_EDEVICE, "hipGetSymbolAddress(scratch) failed on device %d: %s", dev, hipGetErrorString(e));
+        g_scratch_ptr[dev] = static_cast<float*>(ptr);
+    }
+    return g_scratch_ptr[dev];
+}
+
+pa_status pa_mlp_grad_noalloc(int32_t in, int32_t width, int32_t out, int32_t batch, const float* params,
+                              const float* X, const float* T, float* loss, float* grads, void* stream)
+{
+    if (in < 1 || width < 1 || out < 1 || batch < 1 || !params || !X || !T || !loss || !grads) {
+        g_create_err = "bad arguments";
+        return PA_EINVAL;
+    }
+    try {
+        const MlpShape sh(in, width, out);
+        // activations H_1..H_4 and the two back-propagation buffers
+        const int64_t need = ((int64_t)3 * width + out + 2 * (int64_t)sh.maxw) * batch;
+        if (need > PA_MLP_SCRATCH_FLOATS) {
+            g_create_err = "perceptron pass needs " + std::to_string(need) + " floats of work memory, more than the " +
+                           std::to_string((long long)PA_MLP_SCRATCH_FLOATS) + " available";
+            return PA_EINVAL;
+        }
+        float* w = scratch_on_current_device();
+        float* H[4];
+        for (int l = 0; l < 4; ++l) {
+            H[l] = w;
+            w += (int64_t)sh.dims[l + 1] * batch;
+        }
+        float* dA = w;
+        float* dB = dA + (int64_t)sh.maxw * batch;
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        mlp_forward(sh, params, X, H, batch, st);
+        mlp_mse(sh, H, T, dA, batch, loss, st);
+        mlp_backward(sh, params, X, H, dA, dB, grads, batch, st);
+        return PA_OK;
+    } catch (const PaError& e) {
+        g_create_err = e.msg;
+        return e.code;
+    }
+}
+
 pa_status pa_dbg_mlp(int32_t in, int32_t width, int32_t out, int32_t batch, const float* params, const float* X,
                      const float* T, float* loss, float* grads)
 {

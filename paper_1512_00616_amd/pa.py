@@ -21,7 +21,7 @@ EXPORTED = [
     "pa_default_config", "pa_create", "pa_destroy", "pa_last_error", "pa_num_dofs", "pa_num_elems",
     "pa_block_size", "pa_device_bytes", "pa_get_mesh", "pa_set_params", "pa_set_state", "pa_set_freestream",
     "pa_get_state", "pa_primal_period", "pa_shoot", "pa_fixed_point", "pa_shoot_descent", "pa_periodicity_gradient", "pa_floquet", "pa_adjoint_gradient", "pa_tangent_gradient", "pa_batch_gradients",
-    "pa_ws_train", "pa_ws_predict", "pa_ws_pod", "pa_prolong", "pa_ws_shoot", "pa_ws_save", "pa_ws_load", "pa_dbg_mlp", "pa_tangent_sweep",
+    "pa_ws_train", "pa_ws_predict", "pa_ws_pod", "pa_prolong", "pa_ws_shoot", "pa_ws_save", "pa_ws_load", "pa_dbg_mlp", "pa_mlp_grad_noalloc", "pa_tangent_sweep",
     "pa_adjoint_sweep", "pa_dbg_gbar", "pa_dbg_dgbar", "pa_dbg_residual", "pa_dbg_jacobian", "pa_dbg_dr_dmu",
     "pa_dbg_qoi", "pa_dbg_bsr_apply", "pa_dbg_blockinv", "pa_dbg_stage_solve", "pa_dbg_traj", "pa_dbg_hess_eig", "pa_dbg_sym_eig", "pa_optimize", "pa_dbg_qp3", "pa_set_timing",
     "pa_kernel_time", "pa_kernel_skipped", "pa_bench_spmv", "pa_bench_spmv_m", "pa_bench_spmv_lo", "pa_bench_copy", "pa_tuning",
@@ -163,6 +163,7 @@ def lib():
             "pa_ws_save": [P, C.c_char_p],
             "pa_ws_load": [P, C.c_char_p],
             "pa_dbg_mlp": [C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P],
+            "pa_mlp_grad_noalloc": [C.c_int32, C.c_int32, C.c_int32, C.c_int32, P, P, P, P, P, P],
             "pa_fixed_point": [P, C.c_int32, P],
             "pa_shoot_descent": [P, C.c_double, C.c_int32, C.c_int32, P],
             "pa_periodicity_gradient": [P, P, P],
@@ -269,6 +270,16 @@ def dbg_qp3(B, g, a, c, lo, hi):
     if rc != PA_OK:
         raise PaError(rc, lib().pa_last_error(None).decode())
     return d, float(lam[0])
+
+
+def mlp_grad_noalloc(n_in, width, n_out, batch, params, X, T, loss, grads, stream=0):
+    """pa_mlp_grad_noalloc on device pointers (integers, e.g. torch
+    tensors' data_ptr()) enqueued on `stream` (integer handle, 0 = null
+    stream); nothing is allocated and nothing is waited for."""
+    rc = lib().pa_mlp_grad_noalloc(n_in, width, n_out, batch, C.c_void_p(params), C.c_void_p(X), C.c_void_p(T),
+                                   C.c_void_p(loss), C.c_void_p(grads), C.c_void_p(stream))
+    if rc != PA_OK:
+        raise PaError(rc, lib().pa_last_error(None).decode())
 
 
 def dbg_hess_eig(H):
