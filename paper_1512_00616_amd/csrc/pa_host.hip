@@ -1321,7 +1321,7 @@ struct Solver final : pa_ctx {
                 k_mdot_part<<<dim3(nb, mdot_chunks(j + 2)), MD_THREADS, 0, st>>>(V, Nu, j + 1, 1, w, Nu, part, gms);
                 tstop(e);
                 tstart(PA_K_GMUPD, &e);
-                k_gm_upd<<<nb, MD_THREADS, 0, st>>>(V, Nu, j, m, w, Nu, part, nb, gms);
+                k_gm_upd<<<(unsigned)gm_upd_blocks(Nu), GU_THREADS, 0, st>>>(V, Nu, j, m, w, Nu, part, nb, gms);
                 tstop(e);
                 LAUNCHCHK();
                 if ((j + 1) % GM_CHECK == 0 && j < m - 1) {
@@ -1401,9 +1401,9 @@ struct Solver final : pa_ctx {
                 ahat_lo(op.Al, tr, vj, w32, skip);
                 ++launched;
                 k_mdot_part<<<dim3(nb, mdot_chunks(j + 2)), MD_THREADS, 0, st>>>((const float*)V32, Nu, j + 1, 1,
-                                                                                  (const float*)w32, Nu, part,
-                                                       gms);
-                k_gm_upd<<<nb, MD_THREADS, 0, st>>>((const float*)V32, Nu, j, m, (const float*)w32, Nu, part, nb, gms);
+                                                                                  (const float*)w32, Nu, part, gms);
+                k_gm_upd<<<(unsigned)gm_upd_blocks(Nu), GU_THREADS, 0, st>>>((const float*)V32, Nu, j, m,
+                                                                             (const float*)w32, Nu, part, nb, gms);
                 LAUNCHCHK();
                 if ((j + 1) % GM_CHECK == 0 && j < m - 1) {
                     if (pending >= 0) {
@@ -1790,7 +1790,8 @@ struct Solver final : pa_ctx {
                 ahat_m(op.Ah, tr, R, Vm + (int64_t)j * Nu, sV, wm, Nu, gmsm);
                 k_mdot_part<<<dim3(nb, mdot_chunks(j + 2) * R), MD_THREADS, 0, st>>>(Vm, Nu, j + 1, 1, wm, Nu, partm, gmsm,
                                                                                      sV, Nu, sP);
-                k_gm_upd<<<g2, MD_THREADS, 0, st>>>(Vm, Nu, j, m, wm, Nu, partm, nb, gmsm, sV, Nu, sP);
+                k_gm_upd<<<dim3((unsigned)gm_upd_blocks(Nu), R), GU_THREADS, 0, st>>>(Vm, Nu, j, m, wm, Nu, partm, nb,
+                                                                                      gmsm, sV, Nu, sP);
                 LAUNCHCHK();
                 if ((j + 1) % GM_CHECK == 0 && j < m - 1) {
                     if (pending >= 0) {

@@ -638,7 +638,7 @@ __global__ void __launch_bounds__(320) k_jacobian(DevMesh M, const Ref<P>* __res
     // point): L_p holds the test side (weighted basis or gradient values),
     // Z_p a short sum of pointwise-Jacobian entries times trial-side
     // operators.  That is a product (NP x P) x (P x 16 NP): M = test
-    // function a (padded to 16), N = column (m, n, b) in NP tiles of 16,
+    // function a (padded to 16), N = column (m, b, n) in NP tiles of 16,
     // K = pseudo-points in steps of 4 (v_mfma_f64_16x16x4).  Each lane
     // forms its A value L_p[a] and its B value Z_p[col] on the fly from LDS.
     // Lane layout: A[i][k] from lane i + 16 k, B[k][j] from lane j + 16 k,
@@ -654,13 +654,17 @@ __global__ void __launch_bounds__(320) k_jacobian(DevMesh M, const Ref<P>* __res
         for (int task = wave; task < 4 * NT2; task += nwaves) {
             const int s_ = task / NT2, tile0 = 2 * (task % NT2);
             const bool two = tile0 + 1 < NP;
+            // B column cc of this lane = (row variable m, trial function b,
+            // column variable n) with n fastest: consecutive lanes hold
+            // consecutive columns b * 4 + n of the block row, so the stores
+            // of a result row are contiguous
             int bb[2], nn[2], mm[2];
 #pragma unroll
             for (int t = 0; t < 2; ++t) {
-                const int cc = (tile0 + (two ? t : 0)) * 16 + li;   // B column of this lane
-                bb[t] = cc % NP;
-                nn[t] = (cc / NP) & 3;
-                mm[t] = cc / (4 * NP);
+                const int cc = (tile0 + (two ? t : 0)) * 16 + li;
+                nn[t] = cc & 3;
+                bb[t] = (cc >> 2) % NP;
+                mm[t] = (cc >> 2) / NP;
             }
             mf_d4 acc0 = { 0.0, 0.0, 0.0, 0.0 }, acc1 = { 0.0, 0.0, 0.0, 0.0 };
             const int f = s_ - 1;

@@ -135,10 +135,10 @@ struct GmState {
 //   2. the 32 per-thread products of a column group are summed over the
 //      wave by a halving exchange (32 shuffles for 32 columns instead of
 //      6 per column), then over the four waves through LDS;
-//   3. the block's row of partials goes to `partial[b][nc]`; the last block
-//      to finish (integer counter, reset by that block) sums the rows in
-//      block order and finishes the step (plain sums, or the Givens update
-//      of GMRES).
+//   3. the block's row of partials goes to `partial[b][nc]`; every block of
+//      the next kernel sums the rows in the same fixed order (a
+//      completion count inside one launch would need device-scope fences
+//      in every block, which write back the XCD's L2 on this GPU).
 constexpr int MD_THREADS = 256;
 constexpr int MD_TILE = 4 * MD_THREADS;   // doubles per block
 constexpr int MD_GROUP = 32;              // columns per reduction group
@@ -291,25 +291,15 @@ __device__ __forceinline__ void wave_colsum8(double (&p)[8])
     p[0] += __shfl_xor(p[0], 1, 64);
 }
 
-// partial[b][c] of <X_c, w> (c < ncols) and <w, w> (if with_ww), nc = ncols +
-// with_ww columns in chunks of eight: grid (mdot_blocks(n), chunks x R), one
-// chunk of one system per block, so every chunk's loads are in flight at
-// once.  Systems r (right-hand sides sharing an operator) are addressed by
-// the strides sV, sw, sP; system r is skipped when st[r] (optional) is done.
-__host__ __device__ inline int mdot_chunks(int nc) { return (nc + 7) / 8; }
+// One block's partial sums of eight columns cb..cb+7 (those < nc = ncols +
+// with_ww; column ncols is <w, w> when with_ww) over its MD_TILE entries,
+// written to partial[blockIdx.x][nc].
 template <class T>
-__global__ void __launch_bounds__(MD_THREADS) k_mdot_part(const T* __restrict__ V, int64_t ldv, int ncols,
-                                                          int with_ww, const T* __restrict__ w, int64_t n,
-                                                          double* __restrict__ partial, const GmState* __restrict__ st,
-                                                          int64_t sV = 0, int64_t sw = 0, int64_t sP = 0)
+__device__ __forceinline__ void mdot_chunk8(const T* __restrict__ V, int64_t ldv, int ncols, int with_ww,
+                                            const T* __restrict__ w, int64_t n, double* __restrict__ partial, int cb)
 {
     __shared__ double sred[MD_THREADS / 64][8];
-    const int nc = ncols + with_ww, nch = mdot_chunks(nc);
-    const int r = blockIdx.y / nch, cb = 8 * (blockIdx.y % nch);
-    if (st && st[r].done) return;
-    V += r * sV;
-    w += r * sw;
-    partial += r * sP;
+    const int nc = ncols + with_ww;
     const int tid = threadIdx.x;
     const int64_t i0 = (int64_t)blockIdx.x * MD_TILE + 2 * tid, i1 = i0 + 2 * MD_THREADS;
     const bool in0 = i0 < n, in1 = i1 < n;
@@ -343,6 +333,24 @@ __global__ void __launch_bounds__(MD_THREADS) k_mdot_part(const T* __restrict__ 
         for (int k = 0; k < MD_THREADS / 64; ++k) s += sred[k][tid];
         partial[(int64_t)blockIdx.x * nc + cb + tid] = s;
     }
+}
+
+// partial[b][c] of <X_c, w> (c < ncols) and <w, w> (if with_ww), nc = ncols +
+// with_ww columns in chunks of eight: grid (mdot_blocks(n), chunks x R), one
+// chunk of one system per block, so every chunk's loads are in flight at
+// once.  Systems r (right-hand sides sharing an operator) are addressed by
+// the strides sV, sw, sP; system r is skipped when st[r] (optional) is done.
+__host__ __device__ inline int mdot_chunks(int nc) { return (nc + 7) / 8; }
+template <class T>
+__global__ void __launch_bounds__(MD_THREADS) k_mdot_part(const T* __restrict__ V, int64_t ldv, int ncols,
+                                                          int with_ww, const T* __restrict__ w, int64_t n,
+                                                          double* __restrict__ partial, const GmState* __restrict__ st,
+                                                          int64_t sV = 0, int64_t sw = 0, int64_t sP = 0)
+{
+    const int nc = ncols + with_ww, nch = mdot_chunks(nc);
+    const int r = blockIdx.y / nch, cb = 8 * (blockIdx.y % nch);
+    if (st && st[r].done) return;
+    mdot_chunk8(V + r * sV, ldv, ncols, with_ww, w + r * sw, n, partial + r * sP, cb);
 }
 
 // out[c] = sum_b partial[b][c]; one block
@@ -403,163 +411,152 @@ namespace pa {
 // ------------------------------------------------------------------ device-resident GMRES
 
 
-// relaxed read of the done flag (block 0 of k_gm_upd may set it while
-// other blocks of the same launch read it; either value is correct there,
-// as long as all threads of a block act on the same one)
-__device__ __forceinline__ int gm_done(const GmState* st)
-{
-    return __hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
 // One Arnoldi step after w = A v_j and the partials of <V_c, w> (c <= j)
-// and <w, w> (k_mdot_part), with one classical Gram-Schmidt pass.  Every
-// block sums the partials in the same fixed order (hc[c] = <V_c, w>, and
-// with orthonormal V ||w - V hc||^2 = <w,w> - |hc|^2) and writes its part of
-//   V_{j+1} = (w - V hc) / ||w - V hc||.
-// Block 0 also rotates column j of H by the previous Givens rotations,
-// makes the rotation that zeroes the subdiagonal and updates the residual
-// estimate |g[j+1]|.  When the projection cancels more than 99% of ||w||
-// (where one pass would lose orthogonality) the cycle is closed at this
-// column and the caller's true-residual check decides whether to restart.
-// V_{j+1} is written even when the cycle ends here; it is then unused.
-// Blocks cover the same MD_TILE ranges as k_mdot_part; each thread owns two
-// double2.  The loads of w and of the first GU_PRE basis columns are issued
-// before the partials are summed, so that their latency overlaps the
-// summation; later columns follow in groups of eight.  The partial sums are
-// spread over the threads as (column, row group): thread (c, g) adds rows g,
-// g + 8, ... of column c, then the 8 group sums of a column are added in
-// group order (the same order in every block).
-constexpr int GU_PRE = 16;   // basis columns loaded before the final sums
+// and <w, w> (k_mdot_part), with one classical Gram-Schmidt pass:
+//   V_{j+1} = (w - V hc) / ||w - V hc||,  hc[c] = <V_c, w>,
+//   ||w - V hc||^2 = <w, w> - |hc|^2 (V orthonormal).
+// Grid (gm_upd_blocks(n), R), one double2 of every column per thread.
+// Every block first issues the loads of w and of the first GU_COLS basis
+// columns, then sums the partial rows (thread (column c, row group g) adds
+// rows g, g + 8, ... of column c, GU_ROWS loads in flight; the 8 group sums
+// are added in group order -- the same bits in every block), then finishes
+// the update; later columns follow GU_COLS at a time, all added in column
+// order.  Block 0 also rotates column j of H by the previous Givens
+// rotations, makes the rotation that zeroes the subdiagonal and updates the
+// residual estimate |g[j+1]|.  When the projection cancels more than 99% of
+// ||w|| (where one pass would lose orthogonality) the cycle is closed at
+// this column and the caller's true-residual check decides whether to
+// restart.  Block 0 may set `done` while other blocks of the launch start:
+// each block reads it once (either value is correct there: V_{j+1} of a
+// closed cycle is never used).
+constexpr int GU_THREADS = 256;
+constexpr int GU_COLS = 16;    // basis columns loaded together
+constexpr int GU_ROWS = 8;     // partial rows loaded together per thread
+inline int64_t gm_upd_blocks(int64_t n) { return (n / 2 + GU_THREADS - 1) / GU_THREADS; }
 template <class T>
-__global__ void __launch_bounds__(MD_THREADS) k_gm_upd(const T* __restrict__ V, int64_t ldv, int j, int m,
+__global__ void __launch_bounds__(GU_THREADS) k_gm_upd(const T* __restrict__ V, int64_t ldv, int j, int m,
                                                        const T* __restrict__ w, int64_t n,
                                                        const double* __restrict__ partial, int nblk,
                                                        GmState* __restrict__ st, int64_t sV = 0, int64_t sw = 0,
                                                        int64_t sP = 0)
 {
-    {   // system r = blockIdx.y
-        const int r = blockIdx.y;
-        V += r * sV;
-        w += r * sw;
-        partial += r * sP;
-        st += r;
-    }
-    T* __restrict__ vnext = const_cast<T*>(V) + (int64_t)(j + 1) * ldv;
+    const int r = blockIdx.y;
+    V += r * sV;
+    w += r * sw;
+    partial += r * sP;
+    st += r;
     __shared__ int sdone;
-    if (threadIdx.x == 0) sdone = gm_done(st);   // one read per block, so that the whole block leaves or stays
+    const int tid = threadIdx.x;
+    if (tid == 0) sdone = __hip_atomic_load(&st->done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     __syncthreads();
     if (sdone) return;
     __shared__ double s1[GM_MAXM + 2];
     __shared__ double scs[GM_MAXM], ssn[GM_MAXM];
     __shared__ double col[GM_MAXM + 2];
-    __shared__ double red[MD_THREADS / 32][33];
+    __shared__ double red[GU_THREADS / 32][33];
+    __shared__ double sih;
     const int ncols = j + 1, nc = j + 2;
     const bool lead = blockIdx.x == 0;
-    const int tid = threadIdx.x;
-    const int64_t i0 = (int64_t)blockIdx.x * MD_TILE + 2 * tid, i1 = i0 + 2 * MD_THREADS;
-    const bool in0 = i0 < n, in1 = i1 < n;
-    const int64_t a0 = in0 ? i0 : 0, a1 = in1 ? i1 : 0;   // clamped (valid) addresses
-    double2 pa[GU_PRE], pb[GU_PRE];
+    const int64_t i = ((int64_t)blockIdx.x * GU_THREADS + tid) * 2;
+    const bool in = i < n;
+    const int64_t ia = in ? i : 0;   // clamped (valid) address
+    T* __restrict__ vnext = const_cast<T*>(V) + (int64_t)(j + 1) * ldv;
+    double2 pa[GU_COLS];
 #pragma unroll
-    for (int u = 0; u < GU_PRE; ++u) {
-        const T* vc = V + (int64_t)(u < ncols ? u : ncols - 1) * ldv;
-        pa[u] = ld2(vc + a0);
-        pb[u] = ld2(vc + a1);
-    }
-    const double2 wa = ld2(w + a0), wb = ld2(w + a1);
+    for (int u = 0; u < GU_COLS; ++u) pa[u] = ld2(V + (int64_t)(u < ncols ? u : ncols - 1) * ldv + ia);
+    const double2 wv = ld2(w + ia);
     if (lead)
-        for (int i = tid; i < j; i += blockDim.x) {
-            scs[i] = st->cs[i];
-            ssn[i] = st->sn[i];
+        for (int q = tid; q < j; q += GU_THREADS) {
+            scs[q] = st->cs[q];
+            ssn[q] = st->sn[q];
         }
     // final sums of the partials
     {
         const int cl = tid & 31, g = tid >> 5;
-        constexpr int NG = MD_THREADS / 32;
+        constexpr int NG = GU_THREADS / 32;
         for (int c0 = 0; c0 < nc; c0 += 32) {
             const int c = c0 + cl;
             double acc = 0.0;
-            if (c < nc)
-                for (int b = g; b < nblk; b += NG) acc += partial[(int64_t)b * nc + c];
+            if (c < nc) {
+                int b = g;
+                for (; b + (GU_ROWS - 1) * NG < nblk; b += GU_ROWS * NG) {
+                    double v[GU_ROWS];
+#pragma unroll
+                    for (int u = 0; u < GU_ROWS; ++u) v[u] = partial[(int64_t)(b + u * NG) * nc + c];
+#pragma unroll
+                    for (int u = 0; u < GU_ROWS; ++u) acc += v[u];
+                }
+                for (; b < nblk; b += NG) acc += partial[(int64_t)b * nc + c];
+            }
             red[g][cl] = acc;
             __syncthreads();
-            if (tid < 32 && c < nc) {
+            if (tid < 32 && c0 + tid < nc) {
                 double sum = 0.0;
 #pragma unroll
                 for (int gg = 0; gg < NG; ++gg) sum += red[gg][tid];
-                s1[c] = sum;
+                s1[c0 + tid] = sum;
             }
             __syncthreads();
         }
     }
-    double proj = 0.0;
-    for (int i = 0; i < ncols; ++i) proj += s1[i] * s1[i];
-    const double ww = s1[ncols], rem = ww - proj;
-    const double hn = rem > 0.0 ? sqrt(rem) : 0.0;
-    const double ih = hn > 0.0 ? 1.0 / hn : 0.0;
-    if (lead && tid == 0) {
-        const bool close = !(rem > 1e-4 * ww);
-        for (int i = 0; i < ncols; ++i) col[i] = s1[i];
-        col[j + 1] = hn;
-        for (int i = 0; i < j; ++i) {
-            double a = col[i], b = col[i + 1];
-            col[i] = scs[i] * a + ssn[i] * b;
-            col[i + 1] = -ssn[i] * a + scs[i] * b;
-        }
-        double a = col[j], b = col[j + 1];
-        double rr = sqrt(a * a + b * b);
-        double c = a / rr, sgn = b / rr;
-        col[j] = rr;
-        col[j + 1] = 0.0;
-        double gj = st->g[j];
-        double gj1 = -sgn * gj;
-        st->cs[j] = c;
-        st->sn[j] = sgn;
-        st->g[j] = c * gj;
-        st->g[j + 1] = gj1;
-        double res = fabs(gj1);
-        st->res = res;
-        if (!(res > st->tol) || hn == 0.0 || close || !(res == res)) {
-            st->its = j + 1;
-            __hip_atomic_store(&st->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-    }
-    if (lead) {
-        __syncthreads();
-        for (int i = tid; i <= j + 1; i += blockDim.x) {
-            st->H[i * m + j] = col[i];
-            if (i <= j) st->hc[i] = s1[i];
+    if (tid == 0) {
+        double proj = 0.0;
+        for (int q = 0; q < ncols; ++q) proj += s1[q] * s1[q];
+        const double ww = s1[ncols], rem = ww - proj;
+        const double hn = rem > 0.0 ? sqrt(rem) : 0.0;
+        sih = hn > 0.0 ? 1.0 / hn : 0.0;
+        if (lead) {
+            const bool close = !(rem > 1e-4 * ww);
+            for (int q = 0; q < ncols; ++q) col[q] = s1[q];
+            col[j + 1] = hn;
+            for (int q = 0; q < j; ++q) {
+                const double a = col[q], b = col[q + 1];
+                col[q] = scs[q] * a + ssn[q] * b;
+                col[q + 1] = -ssn[q] * a + scs[q] * b;
+            }
+            const double a = col[j], b = col[j + 1];
+            const double rr = sqrt(a * a + b * b);
+            const double c = a / rr, sgn = b / rr;
+            col[j] = rr;
+            col[j + 1] = 0.0;
+            const double gj = st->g[j];
+            const double gj1 = -sgn * gj;
+            st->cs[j] = c;
+            st->sn[j] = sgn;
+            st->g[j] = c * gj;
+            st->g[j + 1] = gj1;
+            const double res = fabs(gj1);
+            st->res = res;
+            if (!(res > st->tol) || hn == 0.0 || close || !(res == res)) {
+                st->its = j + 1;
+                __hip_atomic_store(&st->done, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            }
         }
     }
+    __syncthreads();
+    if (lead)
+        for (int q = tid; q <= j + 1; q += GU_THREADS) st->H[q * m + j] = col[q];
     // V_{j+1}
-    double2 s0 = make_double2(0.0, 0.0), s1v = make_double2(0.0, 0.0);
+    double sx = 0.0, sy = 0.0;
 #pragma unroll
-    for (int u = 0; u < GU_PRE; ++u) {
+    for (int u = 0; u < GU_COLS; ++u) {
         const double h = u < ncols ? s1[u] : 0.0;
-        s0.x += h * pa[u].x;
-        s0.y += h * pa[u].y;
-        s1v.x += h * pb[u].x;
-        s1v.y += h * pb[u].y;
+        sx += h * pa[u].x;
+        sy += h * pa[u].y;
     }
-    for (int cb = GU_PRE; cb < ncols; cb += 8) {
-        double2 a[8], b[8];
+    for (int c0 = GU_COLS; c0 < ncols; c0 += GU_COLS) {
+        double2 a[GU_COLS];
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const T* vc = V + (int64_t)(cb + u < ncols ? cb + u : ncols - 1) * ldv;
-            a[u] = ld2(vc + a0);
-            b[u] = ld2(vc + a1);
-        }
+        for (int u = 0; u < GU_COLS; ++u) a[u] = ld2(V + (int64_t)(c0 + u < ncols ? c0 + u : ncols - 1) * ldv + ia);
 #pragma unroll
-        for (int u = 0; u < 8; ++u) {
-            const double h = cb + u < ncols ? s1[cb + u] : 0.0;
-            s0.x += h * a[u].x;
-            s0.y += h * a[u].y;
-            s1v.x += h * b[u].x;
-            s1v.y += h * b[u].y;
+        for (int u = 0; u < GU_COLS; ++u) {
+            const double h = c0 + u < ncols ? s1[c0 + u] : 0.0;
+            sx += h * a[u].x;
+            sy += h * a[u].y;
         }
     }
-    if (in0) st2(vnext + i0, make_double2((wa.x - s0.x) * ih, (wa.y - s0.y) * ih));
-    if (in1) st2(vnext + i1, make_double2((wb.x - s1v.x) * ih, (wb.y - s1v.y) * ih));
+    const double ih = sih;
+    if (in) st2(vnext + i, make_double2((wv.x - sx) * ih, (wv.y - sy) * ih));
 }
 
 // start of a cycle from the partials of <r, r>: beta = ||r||, g = beta e_1,
@@ -651,16 +648,26 @@ namespace pa {
 // Transposed solves (left preconditioning): Ahat^T x = P^{-T} b.
 // Only the three off-diagonal blocks of a row are streamed per iteration.
 
-// P (diagonal blocks of A) and P^{-1}: LU with partial pivoting (largest
-// magnitude, lowest row on ties) of each diagonal block in LDS, one wave per
-// block, then the explicit inverse.
-//  - pivot search: lane i holds |a[i][k]| (i >= k) and the wave finds the
-//    largest by a butterfly of cross-lane exchanges;
-//  - row swap, multipliers and the trailing update run across the lanes
-//    (the update over the (B-k-1)^2 trailing entries);
-//  - inverse: lane j computes column j of P^{-1} = U^{-1} L^{-1} Pi e_j in
-//    registers (forward then back substitution, fully unrolled, the factor
-//    entries read from LDS as broadcasts) and writes it.
+// P (diagonal blocks of A) and P^{-1} by Gauss-Jordan elimination with
+// partial pivoting (largest magnitude, lowest row on ties), one wave per
+// block, the block held in registers: lane i owns row i.
+//  - step k: the pivot is the largest |a[i][k]| over the rows not yet
+//    pivotal, found by a butterfly of cross-lane exchanges; the pivot row is
+//    broadcast from its lane (readlane) and the in-place Gauss-Jordan update
+//    runs on every lane at once (row p: a[p][:] /= a[p][k] with a[p][k] =
+//    1 / pivot; row i != p: a[i][:] -= a[i][k] a[p][:], a[i][k] =
+//    -a[i][k] / pivot);
+//  - with rows taken in the pivot order p_0, p_1, ... this inverts the row-
+//    permuted block, so lane p_k ends with row k of P^{-1} with its columns
+//    in pivot order (entry c belongs to column p_c); the rows are put back
+//    in place through LDS and stored coalesced.
+__device__ __forceinline__ double bcast_lane(double x, int src)
+{
+    const long long v = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)v, src);
+    const int hi = __builtin_amdgcn_readlane((int)(v >> 32), src);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
 template <int NP>
 __global__ void __launch_bounds__(64) k_blockprep(int Ne, const double* __restrict__ area, const double* __restrict__ mh,
                                                   const double* __restrict__ J, double c, double* __restrict__ Pd,
@@ -668,24 +675,30 @@ __global__ void __launch_bounds__(64) k_blockprep(int Ne, const double* __restri
 {
     constexpr int B = 4 * NP, BB = B * B;
     static_assert(B <= 64, "one lane per row");
-    __shared__ double a[B][B + 1];
-    __shared__ int perm[B];
+    __shared__ double t[B][B + 1];
+    __shared__ int pc[B];
     const int K = blockIdx.x, lane = threadIdx.x;
     const double* src = J + (int64_t)K * 4 * BB;
     const double s2 = 2.0 * area[K];
     double* pd = Pd + (int64_t)K * BB;
-    for (int t = lane; t < BB; t += 64) {
-        int i = t / B, j = t % B;
-        double mm = ((i & 3) == (j & 3)) ? s2 * mh[(i >> 2) * NP + (j >> 2)] : 0.0;
-        double v = mm - c * src[t];
-        a[i][j] = v;
-        pd[t] = v;
+    for (int q = lane; q < BB; q += 64) {
+        const int i = q / B, j = q % B;
+        const double mm = ((i & 3) == (j & 3)) ? s2 * mh[(i >> 2) * NP + (j >> 2)] : 0.0;
+        const double v = mm - c * src[q];
+        t[i][j] = v;
+        pd[q] = v;
     }
-    if (lane < B) perm[lane] = lane;
     __syncthreads();
+    const int row = lane < B ? lane : B - 1;
+    double a[B];
+#pragma unroll
+    for (int j = 0; j < B; ++j) a[j] = t[row][j];
+    bool used = lane >= B;
+    int kpos = 0;
+    bool singular = false;
+#pragma clang loop unroll(full)
     for (int k = 0; k < B; ++k) {
-        // pivot: the largest |a[i][k]|, i >= k, lowest i on ties
-        double v = (lane >= k && lane < B) ? fabs(a[lane][k]) : -1.0;
+        double v = used ? -1.0 : fabs(a[k]);
         int idx = lane;
 #pragma unroll
         for (int off = 32; off > 0; off >>= 1) {
@@ -693,57 +706,31 @@ __global__ void __launch_bounds__(64) k_blockprep(int Ne, const double* __restri
             const int oi = __shfl_xor(idx, off, 64);
             if (ov > v || (ov == v && oi < idx)) { v = ov; idx = oi; }
         }
-        const int p = idx;
-        if (lane == 0 && v == 0.0) status[0] = 1;
-        if (p != k) {
-            if (lane < B) {
-                const double t = a[k][lane];
-                a[k][lane] = a[p][lane];
-                a[p][lane] = t;
-            }
-            if (lane == 0) {
-                const int t = perm[k];
-                perm[k] = perm[p];
-                perm[p] = t;
-            }
+        const int p = __builtin_amdgcn_readfirstlane(idx);
+        singular = singular || v == 0.0;
+        const double ipv = 1.0 / bcast_lane(a[k], p);
+        const bool me = lane == p;
+        const double f = a[k];
+        const double g = me ? 0.0 : f * ipv;   // multiple of the (unscaled) pivot row taken away
+        const double sc = me ? ipv : 1.0;      // the pivot row itself is scaled
+#pragma clang loop unroll(full)
+        for (int j = 0; j < B; ++j) {
+            if (j == k) continue;
+            const double apj = bcast_lane(a[j], p);
+            a[j] = (a[j] - g * apj) * sc;
         }
-        __syncthreads();
-        const double d = a[k][k];
-        if (lane > k && lane < B) a[lane][k] /= d;
-        __syncthreads();
-        const int w = B - k - 1;
-        for (int t = lane; t < w * w; t += 64) {
-            const int i = k + 1 + t / w, j = k + 1 + t % w;
-            a[i][j] -= a[i][k] * a[k][j];
-        }
-        __syncthreads();
+        a[k] = me ? ipv : -f * ipv;
+        if (me) { used = true; kpos = k; }
+        if (lane == 0) pc[k] = p;
     }
-    if (lane < B) {
-        const int col = lane;
-        double x[B];
-        // x = Pi e_col: row i of the permuted system is row perm[i] of P
+    if (lane == 0 && singular) status[0] = 1;
+    __syncthreads();
+    if (lane < B)
 #pragma unroll
-        for (int i = 0; i < B; ++i) x[i] = perm[i] == col ? 1.0 : 0.0;
-        // L (unit lower) forward substitution
-#pragma unroll
-        for (int i = 1; i < B; ++i) {
-            double s = x[i];
-#pragma unroll
-            for (int j = 0; j < i; ++j) s -= a[i][j] * x[j];
-            x[i] = s;
-        }
-        // U back substitution
-#pragma unroll
-        for (int i = B - 1; i >= 0; --i) {
-            double s = x[i];
-#pragma unroll
-            for (int j = i + 1; j < B; ++j) s -= a[i][j] * x[j];
-            x[i] = s / a[i][i];
-        }
-        double* dst = Pinv + (int64_t)K * BB;
-#pragma unroll
-        for (int i = 0; i < B; ++i) dst[i * B + col] = x[i];
-    }
+        for (int cc = 0; cc < B; ++cc) t[kpos][pc[cc]] = a[cc];
+    __syncthreads();
+    double* dst = Pinv + (int64_t)K * BB;
+    for (int q = lane; q < BB; q += 64) dst[q] = t[q / B][q % B];
 }
 
 template <int NP>
