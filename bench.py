@@ -37,8 +37,11 @@ apply tile timings), 'mixed' (the step with FP32 and BF16 operator copies),
 'batched' (instances on concurrent contexts), 'learned' (the learned warm
 start and the combined learned + mixed-precision + block-Krylov form), 'ttg'
 (the time to gradient on the 8x24 p=1 workload with a block-Krylov adjoint),
-'oracle-sweeps' (the oracle's sweeps on that workload on 1 and all host
-threads).  --solver-comparison runs only the shooting-solver comparison;
+'ttg32' (the time to gradient on the 32x96 p=3 workload, shooting from
+coarse orbits prolonged 8x24 p=1 -> 16x48 p=2 -> 32x96 p=3; several
+minutes), 'batched' (32 instances on the 16x48 p=2 workload with five
+right-hand sides each, by default), 'oracle-sweeps' (the oracle's sweeps on
+the 8x24 workload on 1 and all host threads).  --solver-comparison runs only the shooting-solver comparison;
 --spmv-only runs only the isolated applies used for hardware counters.
 
 Prints progress on stderr and one JSON line on stdout.  --gpus N > 1 is
@@ -60,11 +63,11 @@ os.environ.setdefault("PA_VERBOSE", "1")   # progress lines from the library (st
 from paper_1512_00616_amd import inputs  # noqa: E402
 
 HBM_PEAK_GBS = 8000.0
-# hardware-counter traffic per launch of the forward FP64 stage-operator apply
-# on the 32x96 p=3 workload (FETCH_SIZE and WRITE_SIZE calibrated against a
-# plain copy; profiles/k_ahat_fwd_32x96_p3.md); valid for that kernel as
-# measured, to be re-taken when it changes
-TRAFFIC_BYTES = {"pa::k_ahat_fwd<10, double, double, 0>": 243.2e6}
+# hardware-counter traffic per launch of the FP64 stage-operator applies on
+# the 32x96 p=3 workload (FETCH_SIZE and WRITE_SIZE calibrated against a
+# plain copy; profiles/k_ahat_32x96_p3.md); valid for those kernels as
+# measured, to be re-taken when they change
+TRAFFIC_BYTES = {"pa::k_ahat_fwd<10, double, double, 0>": 243.4e6, "pa::k_ahat_tr_m<10>": 254.2e6}
 # the forward apply as launched by the benchmark step: default tile shape
 # (four 16-byte chunks per lane task); pa_config.autotune picks among 1, 2, 4
 FWD_KERNEL = "pa::k_ahat_fwd<10, double, double, 0>"
@@ -129,7 +132,9 @@ def cpu_baseline(work, counts, mu):
 def time_to_gradient(pa, mu):
     """Full Alg. 4 on the 8x24 p=1, 20-step workload: shooting from the free
     stream (+ seeded N(0,1e-3) perturbation) to ||u^(Nt) - u0||_2 <= 1e-8, then
-    the periodic adjoint gradient of both QoIs at relative 1e-8."""
+    the periodic adjoint gradient of both QoIs at relative 1e-8; then the
+    same run with every stage solve in one workgroup (pa_config.wg_solve)
+    for comparison."""
     work = inputs.WORKLOADS["circle-8x24-p1-nt20"]
     s = pa.Solver(gmres_restart=30, lin_rtol=1e-10, newton_atol=1e-10, max_krylov=100, **work, **inputs.PHYSICS)
     s.set_params(mu)
@@ -155,6 +160,16 @@ def time_to_gradient(pa, mu):
     _, dJb, brep = b.adjoint_gradient(rtol=1e-8)
     tb = time.perf_counter() - tb
     b.close()
+    k = pa.Solver(gmres_restart=30, lin_rtol=1e-10, newton_atol=1e-10, max_krylov=100, wg_solve=1, **work,
+                  **inputs.PHYSICS)
+    k.set_params(mu)
+    k.set_freestream(inputs.perturbation(k.Nu, seed=1))
+    tk = time.perf_counter()
+    krep = k.shoot(tol=1e-8, eta=1e-3, maxit=30)
+    _, dJk, _ = k.adjoint_gradient(rtol=1e-8)
+    tk = time.perf_counter() - tk
+    k.close()
+    log("ttg: stage solves in one workgroup: %.1f s" % tk)
     return {"workload": "circle-8x24-p1-nt20", "seconds": t, "newton": rep.newton_its,
             "tangent_sweeps": rep.krylov_its, "periodicity": rep.res, "adjoint_krylov": list(arep.krylov_its),
             "counts": {"primal_sweeps": rep.primal_sweeps, "tangent_sweeps": rep.krylov_its,
@@ -163,7 +178,9 @@ def time_to_gradient(pa, mu):
             "block_adjoint": {"krylov": list(brep.krylov_its), "sweeps": brep.sweeps, "seconds": tb,
                               "rel_res": list(brep.rel_res),
                               "dJdmu_rel_diff": float(np.abs(dJb - dJ).max() / np.abs(dJ).max())},
-            "floquet_leading": [[float(z.real), float(z.imag)] for z in ritz[:4]]}
+            "floquet_leading": [[float(z.real), float(z.imag)] for z in ritz[:4]],
+            "workgroup_form": {"seconds": tk, "newton": krep.newton_its, "tangent_sweeps": krep.krylov_its,
+                               "dJdmu_rel_diff": float(np.abs(dJk - dJ).max() / np.abs(dJ).max())}}
 
 
 def solver_comparison(pa, mu, descent_maxit=150):
@@ -311,28 +328,96 @@ def learned(pa, args):
             "combined_setup_error": comb_err, "held_out": tests}
 
 
+def time_to_gradient_fine(pa, mu, args):
+    """Alg. 4 on the 32x96 p=3, 100-step workload from a coarse orbit: the
+    8x24 p=1 and 16x48 p=2 discretisations (same physics, same 100 steps per
+    period) are shot to periodicity in turn, each from the previous level's
+    periodic state prolonged to its nodes (the first from the free stream),
+    and the prolonged 16x48 orbit starts the 32x96 shooting to
+    ||u^(Nt) - u0||_2 <= 1e-8; then both QoIs' periodic adjoint gradients at
+    relative 1e-8.  Shooting eta 1e-3; stage solves block-Jacobi GMRES(30)
+    at 1e-10.  Times per level; the fine-level time to gradient is the
+    32x96 shooting plus its adjoint."""
+    levels = [dict(Nr=8, Nth=24, p=1), dict(Nr=16, Nth=48, p=2), dict(Nr=32, Nth=96, p=3)]
+    out = {"workload": "circle-32x96-p3-nt100", "levels": []}
+    prev, u_prev = None, None
+    t_all = time.perf_counter()
+    for k, lev in enumerate(levels):
+        cfgd = dict(lev, Nt=100, **inputs.PHYSICS)
+        s = pa.Solver(gmres_restart=30, lin_rtol=1e-10, newton_atol=1e-10, max_krylov=120, **cfgd)
+        s.set_params(mu)
+        t0 = time.perf_counter()
+        if prev is None:
+            s.set_freestream()
+        else:
+            s.set_state(s.prolong_from(prev, u_prev))
+        fine = k == len(levels) - 1
+        try:
+            rep = s.shoot(tol=1e-8, eta=1e-3, maxit=args.ttg32_maxit, allow_unconverged=True)
+        except pa.PaError as e:   # e.g. the line search finds no decrease: report where it stopped
+            out["levels"].append({"Nr": lev["Nr"], "Nth": lev["Nth"], "p": lev["p"], "Nu": s.Nu,
+                                  "shoot_s": time.perf_counter() - t0, "error": str(e)})
+            log("ttg32: level %dx%d p=%d: %s" % (lev["Nr"], lev["Nth"], lev["p"], e))
+            s.close()
+            break
+        t_shoot = time.perf_counter() - t0
+        res, kry, lam = rep.history()
+        entry = {"Nr": lev["Nr"], "Nth": lev["Nth"], "p": lev["p"], "Nu": s.Nu, "shoot_s": t_shoot,
+                 "newton": rep.newton_its, "tangent_sweeps": rep.krylov_its, "primal_sweeps": rep.primal_sweeps,
+                 "res0": rep.res0, "res": rep.res, "res_hist": res.tolist(), "krylov_hist": kry.tolist(),
+                 "step_hist": lam.tolist(), "stage_gmres": rep.stage_gmres_its}
+        log("ttg32: level %dx%d p=%d shot in %.1f s: %d Newton, %d tangent sweeps, |R| %.3e -> %.3e" %
+            (lev["Nr"], lev["Nth"], lev["p"], t_shoot, rep.newton_its, rep.krylov_its, rep.res0, rep.res))
+        if not rep.res <= 1e-8:
+            out["levels"].append(entry)
+            s.close()
+            break
+        if fine:
+            t1 = time.perf_counter()
+            q, dJ, arep = s.adjoint_gradient(rtol=1e-8)
+            t_adj = time.perf_counter() - t1
+            entry.update({"adjoint_s": t_adj, "adjoint_krylov": list(arep.krylov_its),
+                          "adjoint_rel_res": list(arep.rel_res), "qoi": q.tolist(), "dJdmu": dJ.tolist(),
+                          "converged": bool(rep.res <= 1e-8)})
+            out["fine_time_to_gradient_s"] = t_shoot + t_adj
+            log("ttg32: adjoint gradient in %.1f s" % t_adj)
+        else:
+            prev, u_prev = cfgd, s.get_state(0)
+        out["levels"].append(entry)
+        s.close()
+    out["total_s"] = time.perf_counter() - t_all
+    return out
+
+
 def batched(pa, args):
     """Many kinematic instances (seeded h0 ~ U[0.1,0.5], theta0 ~ U[0,30 deg],
     phi ~ U[0,pi]) on the 16x48 p=2, 60-step workload: the same bounded
     per-instance step as the main benchmark (one Newton-Krylov shooting step
-    with a 6-vector basis, then both QoIs' periodic adjoints and dJ/dmu), run
-    one after another on one context and by concurrent contexts inside the
-    library (pa_batch_gradients); instances per second of each."""
+    with a 6-vector basis), then five right-hand sides per instance: both
+    QoIs' periodic adjoints (one backward sweep carries both) and the three
+    parameter tangents of the direct gradient (one forward sweep carries all
+    three), at relative 1e-8; run one after another on one context and by
+    concurrent contexts inside the library (pa_batch_gradients); instances
+    per second of each."""
     name = "circle-16x48-p2-nt60"
     work = dict(inputs.WORKLOADS[name], **inputs.PHYSICS)
     mu = inputs.batch_params(args.batch, seed=4)
-    kw = dict(shoot_maxit=1, allow_unconverged=True, max_krylov=args.krylov, **work)
+    kw = dict(shoot_maxit=1, allow_unconverged=True, max_krylov=args.krylov, direct=True, **work)
     t0 = time.perf_counter()
-    q1, g1, _ = pa.batch_gradients(mu, workers=1, **kw)
+    q1, g1, _, d1 = pa.batch_gradients(mu, workers=1, **kw)
     t_seq = time.perf_counter() - t0
+    log("batched: %d instances one after another: %.1f s" % (args.batch, t_seq))
     t0 = time.perf_counter()
-    qb, gb, _ = pa.batch_gradients(mu, workers=args.batch_workers, **kw)
+    qb, gb, _, db = pa.batch_gradients(mu, workers=args.batch_workers, **kw)
     t_bat = time.perf_counter() - t0
+    log("batched: %d instances on %d concurrent contexts: %.1f s" % (args.batch, args.batch_workers, t_bat))
     return {"workload": name, "instances": args.batch, "workers": args.batch_workers,
-            "step": "1 NK shooting step (basis %d) + periodic adjoint gradient of both QoIs" % args.krylov,
+            "step": "1 NK shooting step (basis %d) + periodic adjoint gradient of both QoIs + direct gradient "
+                    "(3 parameter tangents): 5 right-hand sides per instance" % args.krylov,
             "sequential_s": t_seq, "batched_s": t_bat,
             "instances_per_s": args.batch / t_bat, "sequential_instances_per_s": args.batch / t_seq,
-            "speedup": t_seq / t_bat, "bitwise_equal": bool(np.array_equal(g1, gb) and np.array_equal(q1, qb))}
+            "speedup": t_seq / t_bat,
+            "bitwise_equal": bool(np.array_equal(g1, gb) and np.array_equal(q1, qb) and np.array_equal(d1, db))}
 
 
 def cpu_info():
@@ -398,7 +483,7 @@ def roofline_entry(name, ms, launches, skipped, nbytes):
             "frac": ach / HBM_PEAK_GBS, "avg_launch_us_all": ms / launches * 1e3}
 
 
-SECTIONS = ("tiles", "mixed", "batched", "learned", "ttg", "oracle-sweeps")
+SECTIONS = ("tiles", "mixed", "batched", "learned", "ttg", "ttg32", "oracle-sweeps")
 
 
 def main():
@@ -417,9 +502,11 @@ def main():
     ap.add_argument("--sections", default="",
                     help="comma-separated extra sections after the headline step: " + ", ".join(SECTIONS)
                          + " (or 'all'); none by default")
-    ap.add_argument("--batch", type=int, default=8,
+    ap.add_argument("--batch", type=int, default=32,
                     help="instances of the 16x48 p=2 batched comparison (section 'batched')")
     ap.add_argument("--batch-workers", type=int, default=4)
+    ap.add_argument("--ttg32-maxit", type=int, default=12,
+                    help="Newton steps allowed per level of section 'ttg32'")
     ap.add_argument("--learned-train", type=int, default=16,
                     help="periodic orbits that train the warm start on the 8x24 p=1 workload (section 'learned')")
     ap.add_argument("--learned-test", type=int, default=2, help="held-out parameter draws of the warm-start test")
@@ -486,6 +573,9 @@ def main():
     if "ttg" in sections:
         log("time to gradient on the 8x24 p=1 workload")
         out["time_to_gradient"] = time_to_gradient(pa, mu)
+    if "ttg32" in sections:
+        log("time to gradient on the 32x96 p=3 workload from prolonged coarse orbits")
+        out["time_to_gradient_32x96"] = time_to_gradient_fine(pa, mu, args)
     if "oracle-sweeps" in sections:
         log("oracle sweeps on the 8x24 p=1 workload (1 thread, all threads)")
         ci = cpu_info()
@@ -569,6 +659,7 @@ def run_step(pa, name, work, mu, args, precision):
            "blockinv")
     kt = {k: s.kernel_time(getattr(pa, "PA_K_" + k.upper())) for k in ids}
     ksk = {k: s.kernel_skipped(getattr(pa, "PA_K_" + k.upper())) for k in ids}
+    kvec = {k: s.kernel_vectors(getattr(pa, "PA_K_" + k.upper())) for k in ("mdot", "gmupd")}
     s.set_timing(False)
     nsteps = len(results)
     step_s = t_run / nsteps
@@ -595,10 +686,18 @@ def run_step(pa, name, work, mu, args, precision):
     full = (Nr, Nth, p) == (32, 96, 3)
     traffic = TRAFFIC_BYTES.get(dom["kernel"]) if full else None
     # the Krylov vector kernels: one pass over the basis columns each; their
-    # bytes depend on the column index, so only the mean per working launch
-    # is reported
-    vec = {k: {"total_ms": kt[k][0], "launches": kt[k][1], "launches_skipped": ksk[k],
-               "avg_launch_us": kt[k][0] / max(kt[k][1] - ksk[k], 1) * 1e3} for k in ("mdot", "gmupd")}
+    # bytes depend on the column index: the library counts the length-Nu
+    # vectors their working launches read or wrote, so the mean algorithmic
+    # bytes per working launch and the achieved bandwidth follow
+    vec = {}
+    for k in ("mdot", "gmupd"):
+        work_k = max(kt[k][1] - ksk[k], 1)
+        nbytes = kvec[k] * Nu * 8 / work_k
+        avg_us = kt[k][0] / work_k * 1e3
+        vec[k] = {"total_ms": kt[k][0], "launches": kt[k][1], "launches_skipped": ksk[k], "avg_launch_us": avg_us,
+                  "vectors": kvec[k], "bytes_per_launch": nbytes,
+                  "achieved_gbs": nbytes / (avg_us * 1e-6) / 1e9 if avg_us > 0 else None,
+                  "frac": nbytes / (avg_us * 1e-6) / 1e9 / HBM_PEAK_GBS if avg_us > 0 else None}
     lo_bytes = spmv_bytes(Nr, Nth, p, 4 if precision == pa.PREC_FP32 else 2, 4)
     ms_lo, n_lo = kt["spmv_lo"]
     work_lo = n_lo - ksk["spmv_lo"]

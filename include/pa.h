@@ -91,6 +91,17 @@ typedef struct pa_config {
     void* (*dev_alloc)(uint64_t bytes, void* user);
     void  (*dev_free)(void* ptr, void* user);
     void*   user;
+    /* FP64 stage solves of small meshes (N_u <= 16384, gmres_restart <= 64)
+     * as one kernel per solve: the whole restarted GMRES of each system in
+     * one workgroup, with no launch per iteration (the same algorithm and
+     * stopping test as the multi-kernel solve; sums in another fixed order).
+     * 0 (default): never; 1: always (PA_EINVAL at pa_create when the mesh is
+     * too large); -1: whenever the mesh is small enough.  One workgroup
+     * streams the operator through one compute unit, so this pays only where
+     * a solve's data is far smaller than the launch cost of its iterations
+     * (on the 8x24 p=1 mesh it is about 3x slower than the multi-kernel
+     * solve). */
+    int32_t wg_solve;
 } pa_config;
 
 /* Precision of the stage linear solves (Sec. 2.1 eq. dirk, each stage's
@@ -375,11 +386,16 @@ typedef struct pa_batch_opts {
  * per-instance trajectory storage (pa_device_bytes of one context).
  * Outputs (host, caller-owned): qoi[n][2], dJdmu[n][6], periodicity[n]
  * (||u^(Nt) - u0||_2 after shooting), states[n][N_u] (the initial state u0
- * after shooting, canonical order); any may be NULL.  Results are the same
+ * after shooting, canonical order), dJdmu_direct[n][6] (the same gradient
+ * by the direct method, pa_tangent_gradient: the three parameter tangents
+ * in the same forward sweeps, so that an instance carries five right-hand
+ * sides -- two adjoint, three tangent); any may be NULL (dJdmu_direct NULL:
+ * no tangent sweeps).  Results are the same
  * bits as the same instances run one after another on one context.  On
  * failure the first error is returned and pa_last_error(NULL) reports it. */
 pa_status pa_batch_gradients(const pa_config* cfg, int32_t n, const double* mu, const pa_batch_opts* opts,
-                             double* qoi, double* dJdmu, double* periodicity, double* states);
+                             double* qoi, double* dJdmu, double* periodicity, double* states,
+                             double* dJdmu_direct);
 
 /* ---- learned warm start ---- */
 typedef struct pa_ws_opts {
@@ -458,6 +474,14 @@ pa_status pa_kernel_time(pa_ctx* ctx, int32_t kernel, double* total_ms, int64_t*
  * its per-launch bytes times (launches - skipped).  0 for other kernels;
  * reset by pa_set_timing.  PA_EINVAL for a bad id or a NULL output. */
 pa_status pa_kernel_skipped(pa_ctx* ctx, int32_t kernel, int64_t* skipped);
+/* for the FP64 stage-GMRES vector kernels (PA_K_MDOT, PA_K_GMUPD): the
+ * number of length-N_u vectors their working launches read or wrote since
+ * timing was switched on (iteration j of a cycle: j + 2 in k_mdot_part --
+ * the basis columns 0..j and w --, j + 3 in the update, which also writes
+ * V_{j+1}); their algorithmic bytes are this count times 8 N_u.  0 for
+ * other kernels; reset by pa_set_timing.  PA_EINVAL for a bad id or a NULL
+ * output. */
+pa_status pa_kernel_vectors(pa_ctx* ctx, int32_t kernel, int64_t* vectors);
 /* averaged over reps launches of the preconditioned stage-operator apply
  * y = Ahat x (transposed: Ahat^T x) of the stored first stage, Ahat =
  * (M - dt a_11 J) P^{-1} with P its diagonal blocks (timed with HIP events on

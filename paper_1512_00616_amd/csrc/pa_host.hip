@@ -531,6 +531,7 @@ struct pa_ctx {
     virtual int32_t num_elems() const = 0;
     virtual int32_t block_size() const = 0;
     virtual int64_t device_bytes() const = 0;
+    virtual int64_t kernel_vectors(int k) = 0;
     virtual void get_mesh(int32_t*, int32_t*, int8_t*, double*) const = 0;
     virtual void set_params(const double mu[3]) = 0;
     virtual void set_state(const double* u0, int64_t n) = 0;
@@ -692,6 +693,7 @@ struct Solver final : pa_ctx {
         for (void* p : allocs) da.put(p);
         if (hstat) (void)hipHostFree(hstat);
         if (hstm) (void)hipHostFree(hstm);
+        if (hwgst) (void)hipHostFree(hwgst);
         for (auto& e : gm_ev)
             if (e) (void)hipEventDestroy(e);
         if (st && own_stream) (void)hipStreamDestroy(st);
@@ -908,6 +910,11 @@ struct Solver final : pa_ctx {
         nk_save = dalloc<double>(Nu);
         gms = dalloc<GmState>(1);
         HIPCHK(hipHostMalloc((void**)&hstat, 3 * sizeof(GmHost), hipHostMallocDefault));
+        use_wg = cfg.wg_solve == 1 || (cfg.wg_solve == -1 && Nu <= WG_MAXNU && restart <= WG_MAXM);
+        if (use_wg) {
+            wgst = dalloc<WgStatus>(GM_RMAX);
+            HIPCHK(hipHostMalloc((void**)&hwgst, GM_RMAX * sizeof(WgStatus), hipHostMallocDefault));
+        }
         for (auto& e : gm_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         set_jacobian_smem();
     }
@@ -930,6 +937,16 @@ struct Solver final : pa_ctx {
     void tskip(int k, int64_t n)
     {
         if (timing) kskip[k] += n;
+    }
+    // length-Nu vectors read or written by the working launches of the stage-
+    // GMRES vector kernels: iteration j of a cycle reads j + 1 basis columns
+    // and w in k_mdot_part, and also writes V_{j+1} in k_gm_upd
+    int64_t kvec[PA_K_COUNT] = { 0 };
+    void tvec_cycle(int64_t its)
+    {
+        if (!timing || its <= 0) return;
+        kvec[PA_K_MDOT] += its * (its + 3) / 2;    // sum over j < its of (j + 2)
+        kvec[PA_K_GMUPD] += its * (its + 5) / 2;   // sum over j < its of (j + 3)
     }
     void tstart(int k, hipEvent_t* out)
     {
@@ -970,7 +987,7 @@ struct Solver final : pa_ctx {
     {
         harvest();
         timing = on;
-        for (int k = 0; k < PA_K_COUNT; ++k) { ktime[k] = 0; kcount[k] = 0; tseen[k] = 0; kskip[k] = 0; }
+        for (int k = 0; k < PA_K_COUNT; ++k) { ktime[k] = 0; kcount[k] = 0; tseen[k] = 0; kskip[k] = 0; kvec[k] = 0; }
     }
     void kernel_time(int k, double* ms, int64_t* cnt) override
     {
@@ -989,6 +1006,11 @@ struct Solver final : pa_ctx {
     {
         if (k < 0 || k >= PA_K_COUNT) raise(PA_EINVAL, "bad kernel id %d", k);
         return kskip[k];
+    }
+    int64_t kernel_vectors(int k) override
+    {
+        if (k < 0 || k >= PA_K_COUNT) raise(PA_EINVAL, "bad kernel id %d", k);
+        return kvec[k];
     }
 
     // ---------------------------------------------------------------- motion
@@ -1288,9 +1310,43 @@ struct Solver final : pa_ctx {
     // copy only, so GM_CHECK iterations stay queued on the device while it
     // looks.  Iterations enqueued after convergence exit at once.
     static constexpr int GM_CHECK = 5;
+    // R systems sharing one stage operator, each solved by one workgroup
+    // (k_stage_gmres_wg): rhs and x hold R vectors; returns the largest
+    // iteration count
+    int stage_solve_wg(const StageOps& op, int tr, int R, const double* rhs, double* x, double* Vb, double* yb,
+                       double* wb)
+    {
+        const int m = restart, maxit = 20 * restart;
+        const double* b = rhs;
+        if (tr) {
+            double* bt = R == 1 ? gm_b : bm;
+            for (int r = 0; r < R; ++r) prec(op.Pinv, 1, rhs + r * Nu, bt + r * Nu);
+            b = bt;
+        }
+        k_stage_gmres_wg<NP><<<R, WG_THREADS, 0, st>>>(Ne, dm.enb, dm.etw, op.Ah, tr, b, yb, Vb, wb, m, maxit,
+                                                        cfg.lin_rtol, wgst, Nu, Nu, (int64_t)(m + 1) * Nu, Nu);
+        LAUNCHCHK();
+        HIPCHK(hipMemcpyAsync(hwgst, wgst, R * sizeof(WgStatus), hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        int its = 0;
+        for (int r = 0; r < R; ++r) {
+            if (hwgst[r].conv < 0) raise(PA_ENUMERIC, "NaN in stage GMRES");
+            if (hwgst[r].conv == 0)
+                raise(PA_ENOCONV, "stage GMRES did not converge in %d iterations: residual %.3e", hwgst[r].its,
+                      hwgst[r].res);
+            its = std::max(its, hwgst[r].its);
+            cnt_gmres += hwgst[r].its;
+        }
+        for (int r = 0; r < R; ++r) {
+            if (tr) copy(yb + r * Nu, x + r * Nu);
+            else prec(op.Pinv, 0, yb + r * Nu, x + r * Nu);
+        }
+        return its;
+    }
     int stage_solve(const StageOps& op, int tr, const double* rhs, double* x)
     {
         if (pmode != PA_PREC_FP64) return stage_solve_ir(op, tr, rhs, x);
+        if (use_wg) return stage_solve_wg(op, tr, 1, rhs, x, V, gm_y, we);
         const int m = restart, maxit = 20 * restart;
         const int* skip = &gms->done;
         const int nb = (int)mdot_blocks(Nu);
@@ -1352,6 +1408,7 @@ struct Solver final : pa_ctx {
             tskip(tr ? PA_K_SPMV_T : PA_K_SPMV, launched - (done ? hstat[2].its : m));
             tskip(PA_K_MDOT, launched - (done ? hstat[2].its : m));
             tskip(PA_K_GMUPD, launched - (done ? hstat[2].its : m));
+            tvec_cycle(done ? hstat[2].its : m);
             if (done && !std::isfinite(hstat[2].res)) raise(PA_ENUMERIC, "NaN in stage GMRES");
             if (!std::isfinite(rn)) raise(PA_ENUMERIC, "NaN in stage GMRES");
             if (done && rn <= 2.0 * tol) break;
@@ -1756,6 +1813,7 @@ struct Solver final : pa_ctx {
         }
         if (R > GM_RMAX) raise(PA_EINVAL, "at most %d right-hand sides", GM_RMAX);
         ensure_multi();
+        if (use_wg) return stage_solve_wg(op, tr, R, rhs, x, Vm, ym, wm);
         const int m = restart, maxit = 20 * restart;
         const int nb = (int)mdot_blocks(Nu);
         const int64_t sV = (int64_t)(m + 1) * Nu, sP = (int64_t)nb * (m + 2);
@@ -1788,10 +1846,15 @@ struct Solver final : pa_ctx {
             for (int j = 0; j < m; ++j) {
                 jlast = j;
                 ahat_m(op.Ah, tr, R, Vm + (int64_t)j * Nu, sV, wm, Nu, gmsm);
+                hipEvent_t e;
+                tstart(PA_K_MDOT, &e);
                 k_mdot_part<<<dim3(nb, mdot_chunks(j + 2) * R), MD_THREADS, 0, st>>>(Vm, Nu, j + 1, 1, wm, Nu, partm, gmsm,
                                                                                      sV, Nu, sP);
+                tstop(e);
+                tstart(PA_K_GMUPD, &e);
                 k_gm_upd<<<dim3((unsigned)gm_upd_blocks(Nu), R), GU_THREADS, 0, st>>>(Vm, Nu, j, m, wm, Nu, partm, nb,
                                                                                       gmsm, sV, Nu, sP);
+                tstop(e);
                 LAUNCHCHK();
                 if ((j + 1) % GM_CHECK == 0 && j < m - 1) {
                     if (pending >= 0) {
@@ -1820,14 +1883,18 @@ struct Solver final : pa_ctx {
                 const double rn = norm(rm + r * Nu);   // synchronises: hstm valid
                 if (!acc[r]) {
                     cyc = std::max(cyc, hstm[r].done ? hstm[r].its : m);
+                    tvec_cycle(hstm[r].done ? hstm[r].its : m);
                     if (!std::isfinite(rn) || !std::isfinite(hstm[r].res)) raise(PA_ENUMERIC, "NaN in stage GMRES");
                     if (hstm[r].done && rn <= 2.0 * tol[r]) { acc[r] = true; tl.t[r] = 1e300; }
                 }
                 all = all && acc[r];
             }
             total += cyc;
-            // the applies of the cycle return at once when every system is done
+            // the applies and vector kernels of the cycle return at once when
+            // every system is done
             tskip(tr ? PA_K_SPMV_TM : PA_K_SPMV_M, jlast + 1 - cyc);
+            tskip(PA_K_MDOT, jlast + 1 - cyc);
+            tskip(PA_K_GMUPD, jlast + 1 - cyc);
             if (!all && total >= maxit) raise(PA_ENOCONV, "stage GMRES (%d systems) did not converge in %d iterations", R, total);
         }
         for (int r = 0; r < R; ++r) {
@@ -1995,6 +2062,9 @@ struct Solver final : pa_ctx {
     }
     GmState* gms = nullptr;
     GmHost* hstat = nullptr;       // pinned: two check slots and the end-of-cycle status
+    bool use_wg = false;           // FP64 stage solves in one workgroup per system (small meshes)
+    WgStatus* wgst = nullptr;      // device [GM_RMAX]
+    WgStatus* hwgst = nullptr;     // pinned copy
     hipEvent_t gm_ev[2] = {nullptr, nullptr};
 
     // ---------------------------------------------------------------- setup
@@ -3197,6 +3267,7 @@ void pa_default_config(pa_config* c)
     c->autotune = 0;
     c->block_krylov = 0;
     c->device = 0;
+    c->wg_solve = 0;
 }
 
 static thread_local std::string g_create_err;
@@ -3207,9 +3278,19 @@ pa_status pa_create(const pa_config* cfg, pa_ctx** out)
     *out = nullptr;
     if (!cfg || cfg->Nr < 1 || cfg->Nth < 3 || cfg->p < 1 || cfg->p > 3 || cfg->Nt < 1 || cfg->gmres_restart < 1 ||
         cfg->gmres_restart > 64 || cfg->max_krylov < 1 || cfg->max_krylov > 126 || !(cfg->r_far > 1.0) ||
-        !(cfg->stretch > 0.0) || !(cfg->T > 0.0) || cfg->precision < PA_PREC_FP64 || cfg->precision > PA_PREC_BF16) {
+        !(cfg->stretch > 0.0) || !(cfg->T > 0.0) || cfg->precision < PA_PREC_FP64 || cfg->precision > PA_PREC_BF16 ||
+        cfg->wg_solve < -1 || cfg->wg_solve > 1) {
         g_create_err = "invalid configuration";
         return PA_EINVAL;
+    }
+    if (cfg->wg_solve == 1) {
+        const int64_t np_ = (int64_t)(cfg->p + 1) * (cfg->p + 2) / 2;
+        const int64_t nu = 2LL * cfg->Nr * cfg->Nth * 4 * np_;
+        if (nu > WG_MAXNU || cfg->gmres_restart > WG_MAXM) {
+            g_create_err = "wg_solve = 1 needs N_u <= " + std::to_string(WG_MAXNU) + " and gmres_restart <= " +
+                           std::to_string(WG_MAXM);
+            return PA_EINVAL;
+        }
     }
     try {
         pa_ctx* c = nullptr;
@@ -3838,7 +3919,7 @@ pa_status pa_dbg_mlp(int32_t in, int32_t width, int32_t out, int32_t batch, cons
 }
 
 pa_status pa_batch_gradients(const pa_config* cfg, int32_t n, const double* mu, const pa_batch_opts* o,
-                             double* qoi, double* dJ, double* per, double* states)
+                             double* qoi, double* dJ, double* per, double* states, double* dJd)
 {
     if (!cfg || !mu || !o || n < 0 || o->workers < 1 || o->shoot_maxit < 0) {
         g_create_err = "bad batch arguments";
@@ -3877,10 +3958,13 @@ pa_status pa_batch_gradients(const pa_config* cfg, int32_t n, const double* mu, 
             if (rc == PA_OK && states)
                 rc = pa_get_state(c, 0, states + (int64_t)i * pa_num_dofs(c), pa_num_dofs(c));
             if (rc == PA_OK) rc = pa_adjoint_gradient(c, o->adj_rtol, q, g, nullptr);
+            double gd[6];
+            if (rc == PA_OK && dJd) rc = pa_tangent_gradient(c, o->adj_rtol, gd, nullptr);
             if (rc != PA_OK && o->keep_going && rc != PA_EDEVICE && rc != PA_ENOMEM) {
                 const double nan = std::nan("");
                 if (qoi) qoi[2 * (int64_t)i] = qoi[2 * (int64_t)i + 1] = nan;
                 if (dJ) for (int k = 0; k < 6; ++k) dJ[6 * (int64_t)i + k] = nan;
+                if (dJd) for (int k = 0; k < 6; ++k) dJd[6 * (int64_t)i + k] = nan;
                 if (per) per[i] = nan;
                 continue;
             }
@@ -3890,6 +3974,7 @@ pa_status pa_batch_gradients(const pa_config* cfg, int32_t n, const double* mu, 
             }
             if (qoi) { qoi[2 * (int64_t)i] = q[0]; qoi[2 * (int64_t)i + 1] = q[1]; }
             if (dJ) for (int k = 0; k < 6; ++k) dJ[6 * (int64_t)i + k] = g[k];
+            if (dJd) for (int k = 0; k < 6; ++k) dJd[6 * (int64_t)i + k] = gd[k];
             if (per) per[i] = res;
         }
         pa_destroy(c);
@@ -4019,6 +4104,13 @@ pa_status pa_kernel_skipped(pa_ctx* c, int32_t k, int64_t* skipped)
     return guard(c, [&] {
         if (!skipped) raise(PA_EINVAL, "null output");
         *skipped = c->kernel_skipped(k);
+    });
+}
+pa_status pa_kernel_vectors(pa_ctx* c, int32_t k, int64_t* vectors)
+{
+    return guard(c, [&] {
+        if (!vectors) raise(PA_EINVAL, "null output");
+        *vectors = c->kernel_vectors(k);
     });
 }
 pa_status pa_bench_copy(pa_ctx* c, int32_t reps, double* avg, int64_t* bytes)

@@ -733,6 +733,232 @@ __global__ void __launch_bounds__(64) k_blockprep(int Ne, const double* __restri
     for (int q = lane; q < BB; q += 64) dst[q] = t[q / B][q % B];
 }
 
+// ------------------------------------------------------------------ one-workgroup stage solve
+// For meshes small enough that every kernel of an iteration is dominated by
+// its launch (N_u up to WG_MAXNU), the whole stage solve -- GMRES(m) on
+// Ahat y = b (or Ahat^T y = b) with restarts and the true-residual check --
+// runs in one workgroup of WG_THREADS threads per system (grid = systems,
+// strides sb, sy, sV, sw between them), with no kernel boundary inside it.
+// The same algorithm as the multi-kernel solve: x0 = 0, one classical
+// Gram-Schmidt pass per iteration (a column whose projection cancels more
+// than 99% of ||w|| closes the cycle), Givens rotations, a cycle accepted on
+// its true residual ||b - Ahat y|| <= 2 tol with tol = rtol ||b||, at most
+// maxit iterations.  Thread t owns rows t, t + WG_THREADS, ...; every sum
+// over rows is a fixed-order block reduction (bitwise reproducible).  The
+// apply reads the three stored blocks of a row (transposed: the neighbours'
+// twin blocks, by column) from L2, where the operator and the basis stay
+// across iterations at these sizes.
+constexpr int WG_THREADS = 512;
+constexpr int WG_MAXNU = 16384;
+constexpr int WG_MAXM = 64;
+struct WgStatus {
+    int its;        // GMRES iterations over all cycles
+    int conv;       // 1: converged; 0: iteration limit; -1: not finite
+    double res;     // final true residual norm
+};
+
+// fixed-order sum over the block of one value per thread; every thread gets it
+__device__ __forceinline__ double wg_sum(double v, double* sred)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    __syncthreads();
+    if (lane == 0) sred[wv] = v;
+    __syncthreads();
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < WG_THREADS / 64; ++k) s += sred[k];
+    return s;
+}
+
+template <int NP>
+__device__ __forceinline__ void wg_apply(int Ne, const int32_t* __restrict__ enb, const int8_t* __restrict__ etw,
+                                         const double* __restrict__ Ah, int tr, const double* x, double* out)
+{
+    constexpr int B = 4 * NP, BB = B * B;
+    const int64_t Nu = (int64_t)Ne * B;
+    for (int64_t rr = threadIdx.x; rr < Nu; rr += WG_THREADS) {
+        const int K = (int)(rr / B), i = (int)(rr % B);
+        double acc = x[rr];
+#pragma unroll
+        for (int f = 0; f < 3; ++f) {
+            const int nb = enb[3 * K + f];
+            if (nb < 0) continue;
+            const double* xn = x + (int64_t)nb * B;
+            if (!tr) {
+                const double* blk = Ah + ((int64_t)K * 3 + f) * BB + (int64_t)i * B;
+#pragma unroll
+                for (int j = 0; j < B; ++j) acc += blk[j] * xn[j];
+            } else {
+                const double* blk = Ah + ((int64_t)nb * 3 + etw[3 * K + f]) * BB + i;
+#pragma unroll
+                for (int j = 0; j < B; ++j) acc += blk[(int64_t)j * B] * xn[j];
+            }
+        }
+        out[rr] = acc;
+    }
+}
+
+template <int NP>
+__global__ void __launch_bounds__(WG_THREADS) k_stage_gmres_wg(int Ne, const int32_t* __restrict__ enb,
+                                                               const int8_t* __restrict__ etw,
+                                                               const double* __restrict__ Ah, int tr,
+                                                               const double* __restrict__ b, double* __restrict__ y,
+                                                               double* __restrict__ V, double* __restrict__ w,
+                                                               int m, int maxit, double rtol, WgStatus* status,
+                                                               int64_t sb, int64_t sy, int64_t sV, int64_t sw)
+{
+    constexpr int B = 4 * NP;
+    const int64_t Nu = (int64_t)Ne * B;
+    const int sys = blockIdx.x, tid = threadIdx.x;
+    b += sys * sb;
+    y += sys * sy;
+    V += sys * sV;
+    w += sys * sw;
+    status += sys;
+    __shared__ double sred[WG_THREADS / 64];
+    __shared__ double red[WG_THREADS / 64][33];
+    __shared__ double H[(WG_MAXM + 1) * WG_MAXM];
+    __shared__ double g[WG_MAXM + 1], cs[WG_MAXM], sn[WG_MAXM], hc[WG_MAXM + 2], yc[WG_MAXM], col[WG_MAXM + 2];
+    __shared__ double s_ih;
+    __shared__ int s_done;
+    double bb = 0.0;
+    for (int64_t rr = tid; rr < Nu; rr += WG_THREADS) {
+        const double v = b[rr];
+        bb += v * v;
+        y[rr] = 0.0;
+    }
+    const double bn = sqrt(wg_sum(bb, sred));
+    const double tol = rtol * bn;
+    int total = 0, conv = 0;
+    double rn = bn;
+    if (!(bn > 0.0)) {
+        if (tid == 0) { status->its = 0; status->conv = bn == 0.0 ? 1 : -1; status->res = bn; }
+        return;
+    }
+    // r = b - Ahat y lives in w at the start of each cycle (y = 0: r = b)
+    for (int64_t rr = tid; rr < Nu; rr += WG_THREADS) w[rr] = b[rr];
+    for (;;) {
+        // cycle start: V_0 = r / |r|, g = |r| e_1
+        const double ib = 1.0 / rn;
+        for (int64_t rr = tid; rr < Nu; rr += WG_THREADS) V[rr] = w[rr] * ib;
+        if (tid == 0) {
+            g[0] = rn;
+            s_done = 0;
+        }
+        __syncthreads();
+        int its = m;
+        for (int j = 0; j < m; ++j) {
+            const double* vj = V + (int64_t)j * Nu;
+            wg_apply<NP>(Ne, enb, etw, Ah, tr, vj, w);
+            // <V_c, w> (c <= j) and <w, w>: each thread reads only its own rows of w
+            const int nc = j + 2;
+            for (int c0 = 0; c0 < nc; c0 += 32) {
+                double p[MD_GROUP];
+#pragma unroll
+                for (int u = 0; u < MD_GROUP; ++u) p[u] = 0.0;
+                for (int64_t rr = tid; rr < Nu; rr += WG_THREADS) {
+                    const double wv = w[rr];
+#pragma unroll
+                    for (int u = 0; u < MD_GROUP; ++u) {
+                        const int c = c0 + u;
+                        if (c <= j) p[u] += V[(int64_t)c * Nu + rr] * wv;
+                        else if (c == j + 1) p[u] += wv * wv;
+                    }
+                }
+                wave_colsum32(p);
+                const int lane = tid & 63, wv = tid >> 6;
+                if ((lane & 1) == 0) red[wv][lane >> 1] = p[0];
+                __syncthreads();
+                if (tid < 32 && c0 + tid < nc) {
+                    double sum = 0.0;
+#pragma unroll
+                    for (int k = 0; k < WG_THREADS / 64; ++k) sum += red[k][tid];
+                    hc[c0 + tid] = sum;
+                }
+                __syncthreads();
+            }
+            if (tid == 0) {
+                double proj = 0.0;
+                for (int q = 0; q <= j; ++q) proj += hc[q] * hc[q];
+                const double ww = hc[j + 1], rem = ww - proj;
+                const double hn = rem > 0.0 ? sqrt(rem) : 0.0;
+                s_ih = hn > 0.0 ? 1.0 / hn : 0.0;
+                const bool close = !(rem > 1e-4 * ww);
+                for (int q = 0; q <= j; ++q) col[q] = hc[q];
+                col[j + 1] = hn;
+                for (int q = 0; q < j; ++q) {
+                    const double a = col[q], bq = col[q + 1];
+                    col[q] = cs[q] * a + sn[q] * bq;
+                    col[q + 1] = -sn[q] * a + cs[q] * bq;
+                }
+                const double a = col[j], bq = col[j + 1];
+                const double rr2 = sqrt(a * a + bq * bq);
+                cs[j] = a / rr2;
+                sn[j] = bq / rr2;
+                col[j] = rr2;
+                for (int q = 0; q <= j; ++q) H[q * WG_MAXM + j] = col[q];
+                const double gj = g[j];
+                g[j] = cs[j] * gj;
+                g[j + 1] = -sn[j] * gj;
+                const double res = fabs(g[j + 1]);
+                if (!(res > tol) || hn == 0.0 || close || !(res == res)) s_done = 1;
+            }
+            __syncthreads();
+            const bool done = s_done != 0;
+            if (!done) {
+                // V_{j+1} = (w - V hc) ih (V holds m + 1 columns)
+                const double ih = s_ih;
+                double* vn = V + (int64_t)(j + 1) * Nu;
+                for (int64_t rr = tid; rr < Nu; rr += WG_THREADS) {
+                    double sacc = 0.0;
+                    for (int c = 0; c <= j; ++c) sacc += hc[c] * V[(int64_t)c * Nu + rr];
+                    vn[rr] = (w[rr] - sacc) * ih;
+                }
+            }
+            __syncthreads();
+            if (done) {
+                its = j + 1;
+                break;
+            }
+        }
+        // y += V R^{-1} g over the cycle's columns
+        if (tid == 0)
+            for (int q = its - 1; q >= 0; --q) {
+                double sacc = g[q];
+                for (int c = q + 1; c < its; ++c) sacc -= H[q * WG_MAXM + c] * yc[c];
+                yc[q] = sacc / H[q * WG_MAXM + q];
+            }
+        __syncthreads();
+        for (int64_t rr = tid; rr < Nu; rr += WG_THREADS) {
+            double sacc = 0.0;
+            for (int c = 0; c < its; ++c) sacc += yc[c] * V[(int64_t)c * Nu + rr];
+            y[rr] += sacc;
+        }
+        __syncthreads();
+        total += its;
+        // true residual r = b - Ahat y, into w
+        wg_apply<NP>(Ne, enb, etw, Ah, tr, y, w);
+        double rr2 = 0.0;
+        for (int64_t rr = tid; rr < Nu; rr += WG_THREADS) {
+            const double v = b[rr] - w[rr];
+            w[rr] = v;
+            rr2 += v * v;
+        }
+        rn = sqrt(wg_sum(rr2, sred));
+        if (!(rn == rn)) { conv = -1; break; }
+        if (rn <= 2.0 * tol) { conv = 1; break; }
+        if (total >= maxit) break;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        status->its = total;
+        status->conv = conv;
+        status->res = rn;
+    }
+}
+
 template <int NP>
 __global__ void __launch_bounds__(64) k_form_ahat_mfma(int Ne, const int32_t* __restrict__ enb,
                                                        const double* __restrict__ J, double c,

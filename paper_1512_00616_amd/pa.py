@@ -24,7 +24,7 @@ EXPORTED = [
     "pa_ws_train", "pa_ws_predict", "pa_ws_pod", "pa_prolong", "pa_ws_shoot", "pa_ws_save", "pa_ws_load", "pa_dbg_mlp", "pa_mlp_grad_noalloc", "pa_tangent_sweep",
     "pa_adjoint_sweep", "pa_dbg_gbar", "pa_dbg_dgbar", "pa_dbg_residual", "pa_dbg_jacobian", "pa_dbg_dr_dmu",
     "pa_dbg_qoi", "pa_dbg_bsr_apply", "pa_dbg_blockinv", "pa_dbg_stage_solve", "pa_dbg_traj", "pa_dbg_hess_eig", "pa_dbg_sym_eig", "pa_optimize", "pa_dbg_qp3", "pa_set_timing",
-    "pa_kernel_time", "pa_kernel_skipped", "pa_bench_spmv", "pa_bench_spmv_m", "pa_bench_spmv_lo", "pa_bench_copy", "pa_tuning",
+    "pa_kernel_time", "pa_kernel_skipped", "pa_kernel_vectors", "pa_bench_spmv", "pa_bench_spmv_m", "pa_bench_spmv_lo", "pa_bench_copy", "pa_tuning",
 ]
 
 
@@ -38,6 +38,7 @@ class pa_config(C.Structure):
         ("newton_atol", C.c_double), ("newton_maxit", C.c_int32), ("max_krylov", C.c_int32),
         ("device", C.c_int32), ("precision", C.c_int32), ("autotune", C.c_int32), ("block_krylov", C.c_int32),
         ("stream", C.c_void_p), ("dev_alloc", C.c_void_p), ("dev_free", C.c_void_p), ("user", C.c_void_p),
+        ("wg_solve", C.c_int32),
     ]
 
 
@@ -153,7 +154,7 @@ def lib():
             "pa_get_state": [P, C.c_int32, P, C.c_int64],
             "pa_primal_period": [P, P, P],
             "pa_shoot": [P, C.c_double, C.c_double, C.c_int32, P],
-            "pa_batch_gradients": [P, C.c_int32, P, P, P, P, P, P],
+            "pa_batch_gradients": [P, C.c_int32, P, P, P, P, P, P, P],
             "pa_floquet": [P, C.c_int32, C.c_uint64, P, P, P, P],
             "pa_ws_train": [P, P, P, C.c_int32, P, P],
             "pa_ws_predict": [P, P],
@@ -188,6 +189,7 @@ def lib():
             "pa_set_timing": [P, C.c_int32],
             "pa_kernel_time": [P, C.c_int32, P, P],
             "pa_kernel_skipped": [P, C.c_int32, P],
+            "pa_kernel_vectors": [P, C.c_int32, P],
             "pa_bench_spmv": [P, C.c_int32, C.c_int32, P],
             "pa_bench_spmv_m": [P, C.c_int32, C.c_int32, C.c_int32, P],
             "pa_bench_spmv_lo": [P, C.c_int32, C.c_int32, P],
@@ -221,11 +223,13 @@ def default_config(**kw):
 
 
 def batch_gradients(mu, workers=4, shoot_maxit=30, shoot_tol=1e-8, shoot_eta=1e-3, allow_unconverged=False,
-                    adj_rtol=1e-8, return_states=False, keep_going=False, **cfg_kw):
+                    adj_rtol=1e-8, return_states=False, keep_going=False, direct=False, **cfg_kw):
     """Alg. 4 for every row of mu (n x 3) on one configuration, run by
     `workers` concurrent contexts inside the library; returns qoi (n x 2),
-    dJ/dmu (n x 2 x 3), the final periodicity residuals (n) and, with
-    return_states, the periodic initial states (n x N_u)."""
+    dJ/dmu (n x 2 x 3), the final periodicity residuals (n), with
+    return_states the periodic initial states (n x N_u) and with direct the
+    direct-method dJ/dmu (n x 2 x 3; three parameter tangents per
+    instance besides the two adjoints)."""
     mu = np.ascontiguousarray(np.asarray(mu, dtype=np.float64).reshape(-1, 3))
     n = mu.shape[0]
     cfg = default_config(**cfg_kw)
@@ -237,12 +241,17 @@ def batch_gradients(mu, workers=4, shoot_maxit=30, shoot_tol=1e-8, shoot_eta=1e-
     if return_states:
         np_ = (cfg.p + 1) * (cfg.p + 2) // 2
         states = np.zeros((n, 2 * cfg.Nr * cfg.Nth * 4 * np_))
-    rc = lib().pa_batch_gradients(C.byref(cfg), n, _ptr(mu), C.byref(o), _ptr(q), _ptr(g), _ptr(per), _ptr(states))
+    gd = np.zeros((n, 6)) if direct else None
+    rc = lib().pa_batch_gradients(C.byref(cfg), n, _ptr(mu), C.byref(o), _ptr(q), _ptr(g), _ptr(per), _ptr(states),
+                                  _ptr(gd))
     if rc != PA_OK:
         raise PaError(rc, lib().pa_last_error(None).decode())
+    out = (q, g.reshape(n, 2, 3), per)
     if return_states:
-        return q, g.reshape(n, 2, 3), per, states
-    return q, g.reshape(n, 2, 3), per
+        out = out + (states,)
+    if direct:
+        out = out + (gd.reshape(n, 2, 3),)
+    return out
 
 
 def dbg_mlp(params, X, T, width):
@@ -652,6 +661,14 @@ class Solver:
         because their GMRES systems had already converged"""
         n = C.c_int64()
         self._chk(lib().pa_kernel_skipped(self._c, k, C.byref(n)))
+        return n.value
+
+    def kernel_vectors(self, k):
+        """length-Nu vectors read or written by the working launches of the
+        stage-GMRES vector kernel k (PA_K_MDOT, PA_K_GMUPD) since
+        set_timing(True)"""
+        n = C.c_int64()
+        self._chk(lib().pa_kernel_vectors(self._c, k, C.byref(n)))
         return n.value
 
     def bench_copy(self, reps=20):

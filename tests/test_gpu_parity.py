@@ -30,9 +30,12 @@ def libs():
     return pa, O
 
 
-def make_pair(libs, gpu_kw=None, orc_kw=None, **kw):
+def make_pair(libs, gpu_kw=None, orc_kw=None, wg=0, **kw):
+    """GPU context and oracle on the same discretisation; wg selects the
+    GPU's stage-solve form (0: one kernel per GMRES step, 1: one workgroup
+    per solve)."""
     pa, O = libs
-    g = pa.Solver(**dict(kw, **(gpu_kw or {})))
+    g = pa.Solver(**dict(kw, wg_solve=wg, **(gpu_kw or {})))
     o = O.Oracle(**dict(kw, **(orc_kw or {})))
     g.set_params(MU)
     o.set_params(MU)
@@ -140,9 +143,10 @@ def test_blockinv_inverts_diagonal_blocks(libs, p):
         assert np.abs(D @ inv[K] - eye).max() <= 1e-11
 
 
+@pytest.mark.parametrize("wg", [0, 1])
 @pytest.mark.parametrize("tr", [False, True])
-def test_stage_solve_parity(libs, tr):
-    g, o = make_pair(libs, Nr=3, Nth=8, p=2, Nt=2, gpu_kw=dict(lin_rtol=1e-13), orc_kw=dict(lin_solver=0))
+def test_stage_solve_parity(libs, tr, wg):
+    g, o = make_pair(libs, Nr=3, Nth=8, p=2, Nt=2, gpu_kw=dict(lin_rtol=1e-13), orc_kw=dict(lin_solver=0), wg=wg)
     u = o.freestream(inputs.perturbation(o.Nu, seed=18, sigma=1e-2))
     J = o.jacobian(1, 2, u)
     c = 0.5 * 0.4358665215084590
@@ -184,9 +188,9 @@ TIGHT_G = dict(lin_rtol=1e-13, newton_atol=1e-12)
 TIGHT_O = dict(lin_solver=0, newton_atol=1e-12)
 
 
-@pytest.fixture(scope="module")
-def period_pair(libs):
-    g, o = make_pair(libs, gpu_kw=TIGHT_G, orc_kw=TIGHT_O, Nr=2, Nth=6, p=2, Nt=8)
+@pytest.fixture(scope="module", params=[0, 1], ids=["kernels", "workgroup"])
+def period_pair(libs, request):
+    g, o = make_pair(libs, gpu_kw=TIGHT_G, orc_kw=TIGHT_O, Nr=2, Nth=6, p=2, Nt=8, wg=request.param)
     pert = inputs.perturbation(g.Nu, seed=1)
     g.set_freestream(pert)
     u0 = o.freestream(pert)
@@ -226,11 +230,12 @@ def test_tangent_and_adjoint_sweep_parity(period_pair):
         assert rel(gg, go) <= 1e-10
 
 
-def test_shoot_and_periodic_gradient_parity(libs):
+@pytest.mark.parametrize("wg", [0, 1])
+def test_shoot_and_periodic_gradient_parity(libs, wg):
     """Alg. 4 end to end at the plain-path bar: shooting to 1e-12 on both
     sides from the same start, then both QoIs' periodic adjoint gradients and
     the direct gradients (oracle: exact stage solves)."""
-    g, o = make_pair(libs, gpu_kw=TIGHT_G, orc_kw=TIGHT_O, Nr=2, Nth=6, p=1, Nt=4)
+    g, o = make_pair(libs, gpu_kw=TIGHT_G, orc_kw=TIGHT_O, Nr=2, Nth=6, p=1, Nt=4, wg=wg)
     pert = inputs.perturbation(g.Nu, seed=1)
     g.set_freestream(pert)
     rep = g.shoot(tol=1e-12, eta=1e-12, maxit=20)

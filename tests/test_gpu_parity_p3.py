@@ -25,11 +25,13 @@ def rel(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
-@pytest.fixture(scope="module")
-def pair():
+@pytest.fixture(scope="module", params=[0, 1], ids=["kernels", "workgroup"])
+def pair(request):
+    """wg_solve 0: the several-system applies k_ahat_tr_m / k_ahat_fwd_m
+    and the GMRES vector kernels; 1: one workgroup per system and solve"""
     from paper_1512_00616_amd import pa
     from oracle.oracle import Oracle
-    g = pa.Solver(lin_rtol=1e-13, newton_atol=1e-12, **KW)
+    g = pa.Solver(lin_rtol=1e-13, newton_atol=1e-12, wg_solve=request.param, **KW)
     o = Oracle(lin_solver=1, lin_rtol=1e-13, newton_atol=1e-12, **KW)
     g.set_params(MU)
     o.set_params(MU)
