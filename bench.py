@@ -498,6 +498,8 @@ def main():
     ap.add_argument("--warmup-budget-s", type=float, default=45.0,
                     help="the same budget for the warm-up steps (at least one when --warmup > 0)")
     ap.add_argument("--krylov", type=int, default=6, help="outer Krylov basis cap of the step")
+    ap.add_argument("--lin-guess", type=int, default=0, choices=(0, 1),
+                    help="tangent and adjoint stage solves start from the neighbouring step's solution")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--sections", default="",
                     help="comma-separated extra sections after the headline step: " + ", ".join(SECTIONS)
@@ -631,7 +633,7 @@ def run_step(pa, name, work, mu, args, precision):
     report and dJ/dmu of the last step."""
     t_setup = time.perf_counter()
     s = pa.Solver(gmres_restart=30, lin_rtol=1e-10, newton_atol=1e-10, max_krylov=args.krylov,
-                  precision=precision, **work, **inputs.PHYSICS)
+                  precision=precision, lin_guess=args.lin_guess, **work, **inputs.PHYSICS)
     s.set_params(mu)
     setup_s = time.perf_counter() - t_setup
     log("setup %.1f s, %.1f GB on the device" % (setup_s, s.device_bytes / 1e9))
@@ -718,7 +720,8 @@ def run_step(pa, name, work, mu, args, precision):
         "dtype": "f64" if precision == pa.PREC_FP64 else ("f32+f64" if precision == pa.PREC_FP32 else "bf16+f32+f64"),
         "data": "synthetic",
         "config": {"workload": name, **work, "mu": list(mu), "stage_gmres": "block-Jacobi GMRES(30) rtol 1e-10",
-                   "newton_atol": 1e-10, "outer_krylov_cap": args.krylov, "shoot_eta": 1e-3, "adj_rtol": 1e-8},
+                   "newton_atol": 1e-10, "outer_krylov_cap": args.krylov, "shoot_eta": 1e-3, "adj_rtol": 1e-8,
+                   "lin_guess": args.lin_guess},
         "roofline": {"bound": "hbm", "achieved": dom["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": dom["frac"], "traffic": traffic, **dom},
         "applies": cand,

@@ -102,6 +102,12 @@ typedef struct pa_config {
      * (on the 8x24 p=1 mesh it is about 3x slower than the multi-kernel
      * solve). */
     int32_t wg_solve;
+    /* 1: every stage solve of a tangent or adjoint sweep starts from the
+     * same stage's solution at the neighbouring step already swept (the
+     * previous step forward, the next one backward), kept when its residual
+     * is below |b|; the stopping test stays lin_rtol |b|.  0 (default): from
+     * zero.  Newton corrections always start from zero. */
+    int32_t lin_guess;
 } pa_config;
 
 /* Precision of the stage linear solves (Sec. 2.1 eq. dirk, each stage's

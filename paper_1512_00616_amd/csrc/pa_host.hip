@@ -305,7 +305,7 @@ struct MlpShape {
 inline void mlp_gemm(int M, int N, int K, const float* A, int tA, const float* B, int tB, float* C, hipStream_t st)
 {
     dim3 grid((N + GT - 1) / GT, (M + GT - 1) / GT);
-    k_gemm_f32<<<grid, GT * GT, 0, st>>>(M, N, K, 1.0f, A, tA, B, tB, 0.0f, C);
+    k_gemm_mfma_f32<<<grid, 64, 0, st>>>(M, N, K, A, tA, B, tB, C);
     LAUNCHCHK();
 }
 inline void mlp_forward(const MlpShape& sh, const float* p, const float* X, float* const H[4], int S, hipStream_t st)
@@ -634,6 +634,7 @@ struct Solver final : pa_ctx {
     double *qtmp = nullptr, *qdu = nullptr, *qdmu = nullptr;
     double *rg4 = nullptr, *kg4 = nullptr;                         // GCL work [3][4][nn]
     int64_t cnt_newton = 0, cnt_gmres = 0;
+    int64_t cnt_guess_try = 0, cnt_guess_used = 0;   // stage solves offered an initial guess / that kept it
 
     // timing
     bool timing = false;
@@ -1343,7 +1344,10 @@ struct Solver final : pa_ctx {
         }
         return its;
     }
-    int stage_solve(const StageOps& op, int tr, const double* rhs, double* x)
+    // x0 (optional, may alias x): initial guess in the stage unknowns; it is
+    // used when its residual is below |b|, else the solve starts from zero.
+    // The stopping test stays relative to |b|.
+    int stage_solve(const StageOps& op, int tr, const double* rhs, double* x, const double* x0 = nullptr)
     {
         if (pmode != PA_PREC_FP64) return stage_solve_ir(op, tr, rhs, x);
         if (use_wg) return stage_solve_wg(op, tr, 1, rhs, x, V, gm_y, we);
@@ -1353,15 +1357,26 @@ struct Solver final : pa_ctx {
         const double* b = rhs;
         if (tr) { prec(op.Pinv, 1, rhs, gm_b); b = gm_b; }
         const double bn = norm(b);
-        zero(x);
-        if (bn == 0.0) return 0;
+        if (bn == 0.0) { zero(x); return 0; }
         const double tol = cfg.lin_rtol * bn;
         double* r = we;
         double* w = we;
         double* y = gm_y;
-        zero(y);
         int total = 0;
-        copy(b, r);
+        bool guessed = false;
+        if (x0) {   // y0 = P x0 (forward) or x0 (transposed), r0 = b - Ahat y0
+            if (tr) copy(x0, y);
+            else prec(op.Pd, 0, x0, y);
+            ahat(op.Ah, tr, y, w);
+            lincomb(1.0, b, -1.0, w, r);
+            guessed = norm(r) < bn;
+            ++cnt_guess_try;
+            if (guessed) ++cnt_guess_used;
+        }
+        if (!guessed) {
+            zero(y);
+            copy(b, r);
+        }
         for (;;) {
             k_mdot_part<<<nb, MD_THREADS, 0, st>>>(r, 0, 1, 0, r, Nu, part, nullptr);
             k_gm_begin<<<nb, MD_THREADS, 0, st>>>(r, V, Nu, part, nb, GmTol{ { tol } }, gms);
@@ -1804,11 +1819,12 @@ struct Solver final : pa_ctx {
             HIPCHK(hipMemcpyAsync(&hstm[r], &gmsm[r].res, sizeof(GmHost), hipMemcpyDeviceToHost, st));
     }
     // x_r solves op(A) x_r = rhs_r, r < R; rhs and x hold R vectors at stride Nu
-    int stage_solve_multi(const StageOps& op, int tr, int R, const double* rhs, double* x)
+    int stage_solve_multi(const StageOps& op, int tr, int R, const double* rhs, double* x,
+                          const double* x0 = nullptr)
     {
         if (R == 1 || pmode != PA_PREC_FP64) {
             int tot = 0;
-            for (int r = 0; r < R; ++r) tot += stage_solve(op, tr, rhs + r * Nu, x + r * Nu);
+            for (int r = 0; r < R; ++r) tot += stage_solve(op, tr, rhs + r * Nu, x + r * Nu, x0 ? x0 + r * Nu : nullptr);
             return tot;
         }
         if (R > GM_RMAX) raise(PA_EINVAL, "at most %d right-hand sides", GM_RMAX);
@@ -1831,8 +1847,26 @@ struct Solver final : pa_ctx {
             acc[r] = bn[r] == 0.0;
             tl.t[r] = acc[r] ? 1e300 : tol[r];
         }
-        zero(ym, R * Nu);
-        HIPCHK(hipMemcpyAsync(rm, b, sizeof(double) * R * Nu, hipMemcpyDeviceToDevice, st));
+        if (x0) {   // per system: the guess when its residual is below |b_r|, else zero
+            for (int r = 0; r < R; ++r) {
+                if (tr) copy(x0 + r * Nu, ym + r * Nu);
+                else prec(op.Pd, 0, x0 + r * Nu, ym + r * Nu);
+            }
+            ahat_m(op.Ah, tr, R, ym, Nu, wm, Nu);
+            for (int r = 0; r < R; ++r) {
+                lincomb(1.0, b + r * Nu, -1.0, wm + r * Nu, rm + r * Nu);
+                ++cnt_guess_try;
+                if (norm(rm + r * Nu) < bn[r]) {
+                    ++cnt_guess_used;
+                } else {
+                    zero(ym + r * Nu);
+                    copy(b + r * Nu, rm + r * Nu);
+                }
+            }
+        } else {
+            zero(ym, R * Nu);
+            HIPCHK(hipMemcpyAsync(rm, b, sizeof(double) * R * Nu, hipMemcpyDeviceToDevice, st));
+        }
         int total = 0;
         bool all = true;
         for (int r = 0; r < R; ++r) all = all && acc[r];
@@ -1959,7 +1993,7 @@ struct Solver final : pa_ctx {
                     for (int r = 0; r < R; ++r)
                         if (mu_dir[r] >= 0) axpby(dt, drmm + (int64_t)mu_dir[r] * Nu, 1.0, rhs + r * Nu);
                 }
-                stage_solve_multi(ops(s), 0, R, rhs, DK(i - 1, 0));
+                stage_solve_multi(ops(s), 0, R, rhs, DK(i - 1, 0), cfg.lin_guess && n > 1 ? DK(i - 1, 0) : nullptr);
                 if (dq) {
                     qoi_grad(n, i, stU(s), 0, qg, qtmp);
                     qoi_grad(n, i, stU(s), 1, qg + Nu, qtmp);
@@ -1994,7 +2028,7 @@ struct Solver final : pa_ctx {
         if (R > GM_RMAX) raise(PA_EINVAL, "at most %d right-hand sides", GM_RMAX);
         double* lam = lamm;
         double* rhs = rhsm;
-        double* kap = kapm;
+        if (!kap3m) kap3m = dalloc<double>((int64_t)3 * GM_RMAX * Nu);
         auto SK = [&](int i, int r) { return skm + ((int64_t)i * R + r) * Nu; };
         auto FP = [&](int i, int r) { return fpm + ((int64_t)i * R + r) * Nu; };
         HIPCHK(hipMemcpyAsync(lam, lamNt, sizeof(double) * R * Nu, hipMemcpyDeviceToDevice, st));
@@ -2022,7 +2056,8 @@ struct Solver final : pa_ctx {
                     if (fq[r] >= 0)
                         for (int j = i; j <= 3; ++j) axpby(sc * rk.b[j - 1] * rk.A[j - 1][i - 1], FP(j - 1, r), 1.0, rr);
                 }
-                stage_solve_multi(ops(s), 1, R, rhs, kap);
+                double* kap = kap3m + (int64_t)(i - 1) * R * Nu;   // this stage's multipliers (the guess)
+                stage_solve_multi(ops(s), 1, R, rhs, kap, cfg.lin_guess && n < Nt ? kap : nullptr);
                 // dt J^T kap_r into the stage slots (contiguous per stage)
                 stage_jprod_tr_multi(ops(s), R, kap, SK(i - 1, 0));
                 if (anyf) {
@@ -2063,6 +2098,8 @@ struct Solver final : pa_ctx {
     GmState* gms = nullptr;
     GmHost* hstat = nullptr;       // pinned: two check slots and the end-of-cycle status
     bool use_wg = false;           // FP64 stage solves in one workgroup per system (small meshes)
+    double* kap3 = nullptr;        // adjoint sweep: the multipliers of the three stages of a step
+    double* kap3m = nullptr;       // the same for several systems [3][GM_RMAX][Nu]
     WgStatus* wgst = nullptr;      // device [GM_RMAX]
     WgStatus* hwgst = nullptr;     // pinned copy
     hipEvent_t gm_ev[2] = {nullptr, nullptr};
@@ -2314,7 +2351,9 @@ struct Solver final : pa_ctx {
                 copy(du, w);
                 for (int j = 1; j < i; ++j) axpby(rk.A[i - 1][j - 1], sk3 + (int64_t)(j - 1) * Nu, 1.0, w);
                 stage_jprod(ops(s), 0, w, rhs, gm_b, gm_y);
-                stage_solve(ops(s), 0, rhs, sk3 + (int64_t)(i - 1) * Nu);
+                // guess: the same stage's slope one step earlier (still in sk3)
+                double* ki = sk3 + (int64_t)(i - 1) * Nu;
+                stage_solve(ops(s), 0, rhs, ki, cfg.lin_guess && n > 1 ? ki : nullptr);
             }
             for (int i = 0; i < 3; ++i) axpby(rk.b[i], sk3 + (int64_t)i * Nu, 1.0, du);
         }
@@ -2327,7 +2366,7 @@ struct Solver final : pa_ctx {
         if (!have_traj) raise(PA_ESTATE, "no trajectory");
         double* lam = wa;
         double* rhs = wb;
-        double* kap = wc;
+        if (!kap3) kap3 = dalloc<double>(3 * Nu);
         copy(lamNt, lam);
         double g[3] = { 0, 0, 0 };
         const double sc = dt / cfg.T;
@@ -2347,7 +2386,9 @@ struct Solver final : pa_ctx {
                 if (fq >= 0)
                     for (int j = i; j <= 3; ++j)
                         axpby(sc * rk.b[j - 1] * rk.A[j - 1][i - 1], fp3 + (int64_t)(j - 1) * Nu, 1.0, rhs);
-                stage_solve(ops(s), 1, rhs, kap);
+                // guess: the same stage's multiplier one step later
+                double* kap = kap3 + (int64_t)(i - 1) * Nu;
+                stage_solve(ops(s), 1, rhs, kap, cfg.lin_guess && n < Nt ? kap : nullptr);
                 stage_jprod(ops(s), 1, kap, sk3 + (int64_t)(i - 1) * Nu, gm_b, gm_y);
                 if (fq >= 0) {
                     dr_dmu(n, i, stU(s), drm);
@@ -3279,7 +3320,7 @@ pa_status pa_create(const pa_config* cfg, pa_ctx** out)
     if (!cfg || cfg->Nr < 1 || cfg->Nth < 3 || cfg->p < 1 || cfg->p > 3 || cfg->Nt < 1 || cfg->gmres_restart < 1 ||
         cfg->gmres_restart > 64 || cfg->max_krylov < 1 || cfg->max_krylov > 126 || !(cfg->r_far > 1.0) ||
         !(cfg->stretch > 0.0) || !(cfg->T > 0.0) || cfg->precision < PA_PREC_FP64 || cfg->precision > PA_PREC_BF16 ||
-        cfg->wg_solve < -1 || cfg->wg_solve > 1) {
+        cfg->wg_solve < -1 || cfg->wg_solve > 1 || cfg->lin_guess < 0 || cfg->lin_guess > 1) {
         g_create_err = "invalid configuration";
         return PA_EINVAL;
     }

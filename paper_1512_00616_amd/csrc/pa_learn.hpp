@@ -15,41 +15,32 @@ namespace pa {
 
 constexpr int GT = 16;   // GEMM tile edge
 
-// C[M][N] = alpha * op(A)[M][K] op(B)[K][N] + beta * C, row-major storage;
-// op(A) = A (A is M x K, lda = K) or A^T (A is K x M, lda = M), likewise B.
-// 16 x 16 output tile per 256-thread block, K staged through LDS in tiles of
-// 16; accumulation in FP32 in a fixed order.
-__global__ void __launch_bounds__(GT * GT) k_gemm_f32(int M, int N, int K, float alpha, const float* __restrict__ A,
-                                                      int transA, const float* __restrict__ B, int transB,
-                                                      float beta, float* __restrict__ C)
+// C[M][N] = op(A)[M][K] op(B)[K][N], row-major storage; op(A) = A (A is
+// M x K, lda = K) or A^T (A is K x M, lda = M), likewise B.  One wave per
+// 16 x 16 tile of C on the FP32 matrix cores (v_mfma_f32_16x16x4f32): in
+// each step of 4 along K, lane l supplies A[row0 + l % 16][k0 + l / 16] and
+// B[k0 + l / 16][col0 + l % 16] (zero outside the matrices) and receives
+// C[row0 + 4 (l / 16) + r][col0 + l % 16] in accumulator register r.  FP32
+// accumulation in a fixed order.
+typedef float mf_f4 __attribute__((ext_vector_type(4)));
+__global__ void __launch_bounds__(64) k_gemm_mfma_f32(int M, int N, int K, const float* __restrict__ A, int transA,
+                                                      const float* __restrict__ B, int transB, float* __restrict__ C)
 {
-    __shared__ float sa[GT][GT + 1], sb[GT][GT + 1];
-    const int tx = threadIdx.x % GT, ty = threadIdx.x / GT;
-    const int row = blockIdx.y * GT + ty, col = blockIdx.x * GT + tx;
-    float acc = 0.0f;
-    for (int k0 = 0; k0 < K; k0 += GT) {
-        // sa[ty][tx] = op(A)[blockIdx.y*GT + ty][k0 + tx]
-        {
-            const int r = blockIdx.y * GT + ty, k = k0 + tx;
-            float v = 0.0f;
-            if (r < M && k < K) v = transA ? A[(int64_t)k * M + r] : A[(int64_t)r * K + k];
-            sa[ty][tx] = v;
-        }
-        // sb[ty][tx] = op(B)[k0 + ty][blockIdx.x*GT + tx]
-        {
-            const int k = k0 + ty, c = blockIdx.x * GT + tx;
-            float v = 0.0f;
-            if (k < K && c < N) v = transB ? B[(int64_t)c * K + k] : B[(int64_t)k * N + c];
-            sb[ty][tx] = v;
-        }
-        __syncthreads();
-#pragma unroll
-        for (int k = 0; k < GT; ++k) acc += sa[ty][k] * sb[k][tx];
-        __syncthreads();
+    const int lane = threadIdx.x, li = lane & 15, lk = lane >> 4;
+    const int row0 = blockIdx.y * GT, col0 = blockIdx.x * GT;
+    const int r = row0 + li, c = col0 + li;
+    mf_f4 acc = { 0.0f, 0.0f, 0.0f, 0.0f };
+    for (int k0 = 0; k0 < K; k0 += 4) {
+        const int k = k0 + lk;
+        float a = 0.0f, b = 0.0f;
+        if (r < M && k < K) a = transA ? A[(int64_t)k * M + r] : A[(int64_t)r * K + k];
+        if (k < K && c < N) b = transB ? B[(int64_t)c * K + k] : B[(int64_t)k * N + c];
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
     }
-    if (row < M && col < N) {
-        float* c = C + (int64_t)row * N + col;
-        *c = alpha * acc + (beta == 0.0f ? 0.0f : beta * *c);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int rr = row0 + 4 * lk + q;
+        if (rr < M && c < N) C[(int64_t)rr * N + c] = acc[q];
     }
 }
 

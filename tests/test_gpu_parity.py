@@ -30,12 +30,13 @@ def libs():
     return pa, O
 
 
-def make_pair(libs, gpu_kw=None, orc_kw=None, wg=0, **kw):
+def make_pair(libs, gpu_kw=None, orc_kw=None, wg=0, guess=0, **kw):
     """GPU context and oracle on the same discretisation; wg selects the
     GPU's stage-solve form (0: one kernel per GMRES step, 1: one workgroup
-    per solve)."""
+    per solve), guess whether the linear sweeps' stage solves start from the
+    neighbouring step's solution (pa_config.lin_guess)."""
     pa, O = libs
-    g = pa.Solver(**dict(kw, wg_solve=wg, **(gpu_kw or {})))
+    g = pa.Solver(**dict(kw, wg_solve=wg, lin_guess=guess, **(gpu_kw or {})))
     o = O.Oracle(**dict(kw, **(orc_kw or {})))
     g.set_params(MU)
     o.set_params(MU)
@@ -188,9 +189,10 @@ TIGHT_G = dict(lin_rtol=1e-13, newton_atol=1e-12)
 TIGHT_O = dict(lin_solver=0, newton_atol=1e-12)
 
 
-@pytest.fixture(scope="module", params=[0, 1], ids=["kernels", "workgroup"])
+@pytest.fixture(scope="module", params=[(0, 0), (1, 0), (0, 1)], ids=["kernels", "workgroup", "guess"])
 def period_pair(libs, request):
-    g, o = make_pair(libs, gpu_kw=TIGHT_G, orc_kw=TIGHT_O, Nr=2, Nth=6, p=2, Nt=8, wg=request.param)
+    wg, guess = request.param
+    g, o = make_pair(libs, gpu_kw=TIGHT_G, orc_kw=TIGHT_O, Nr=2, Nth=6, p=2, Nt=8, wg=wg, guess=guess)
     pert = inputs.perturbation(g.Nu, seed=1)
     g.set_freestream(pert)
     u0 = o.freestream(pert)
@@ -230,12 +232,12 @@ def test_tangent_and_adjoint_sweep_parity(period_pair):
         assert rel(gg, go) <= 1e-10
 
 
-@pytest.mark.parametrize("wg", [0, 1])
-def test_shoot_and_periodic_gradient_parity(libs, wg):
+@pytest.mark.parametrize("wg,guess", [(0, 0), (1, 0), (0, 1)])
+def test_shoot_and_periodic_gradient_parity(libs, wg, guess):
     """Alg. 4 end to end at the plain-path bar: shooting to 1e-12 on both
     sides from the same start, then both QoIs' periodic adjoint gradients and
     the direct gradients (oracle: exact stage solves)."""
-    g, o = make_pair(libs, gpu_kw=TIGHT_G, orc_kw=TIGHT_O, Nr=2, Nth=6, p=1, Nt=4, wg=wg)
+    g, o = make_pair(libs, gpu_kw=TIGHT_G, orc_kw=TIGHT_O, Nr=2, Nth=6, p=1, Nt=4, wg=wg, guess=guess)
     pert = inputs.perturbation(g.Nu, seed=1)
     g.set_freestream(pert)
     rep = g.shoot(tol=1e-12, eta=1e-12, maxit=20)
