@@ -1960,7 +1960,7 @@ struct Solver final : pa_ctx {
         LAUNCHCHK();
     }
     // tangent sweeps of R systems together: out_r = Phi v_r, plus (mu_dir[r]
-    // >= 0) the forcing dt dr/dmu_k of a parameter tangent (Sec. 2.3 eq.
+    // >= 0) the forcing dt dr/dmu_k of a parameter tangent (Sec. 2.2 eq.
     // dirk-sens-mvp with the parameter term), and (dq != NULL) the tangent of
     // both time-averaged QoIs: dq[2 r + q] = sum_n sum_i dt b_i / T
     // (df_q/du(u_i) du_i + df_q/dmu_k), du_i = w_i + a_ii dk_i
