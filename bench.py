@@ -266,7 +266,8 @@ def learned(pa, args):
     ok = np.isfinite(per)
     s = pa.Solver(**work)
     t0 = time.perf_counter()
-    loss = s.ws_train(mu_tr[ok], states[ok], modes=16, width=256, epochs=3000, lr=1e-3, seed=5)
+    modes = min(args.learned_modes, int(ok.sum()) - 1)
+    loss = s.ws_train(mu_tr[ok], states[ok], modes=modes, width=256, epochs=3000, lr=1e-3, seed=5)
     t_train = time.perf_counter() - t0
     comb, comb_err = None, None
     try:
@@ -323,7 +324,8 @@ def learned(pa, args):
         comb.close()
     return {"workload": name, "training_orbits": int(ok.sum()), "training_draws": args.learned_train,
             "generation_s": t_gen, "train_s": t_train, "final_loss": loss,
-            "model": "POD 16 modes + MLP 3-256-256-256-16 (tanh, FP32, Adam 3000 full-batch steps)",
+            "model": "POD %d modes + MLP 4-256-256-256-%d (inputs h0, theta0, phi, Mach; tanh, FP32, MFMA "
+                     "layer products, Adam 3000 full-batch steps)" % (modes, modes),
             "combined_form": "learned warm start + FP32 mixed-precision stage solves + block Krylov adjoint",
             "combined_setup_error": comb_err, "held_out": tests}
 
@@ -512,6 +514,7 @@ def main():
     ap.add_argument("--learned-train", type=int, default=16,
                     help="periodic orbits that train the warm start on the 8x24 p=1 workload (section 'learned')")
     ap.add_argument("--learned-test", type=int, default=2, help="held-out parameter draws of the warm-start test")
+    ap.add_argument("--learned-modes", type=int, default=16, help="POD modes of the warm-start model")
     ap.add_argument("--spmv-only", action="store_true",
                     help="short run for hardware counters: a 3-stage period on the 32x96 p=3 mesh, then timed "
                          "launches of the preconditioned stage operator and of a plain copy")
