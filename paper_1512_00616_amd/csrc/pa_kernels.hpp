@@ -352,7 +352,7 @@ struct JacSmem {
     double x[4][NP][2], v[4][NP][2];
     // face data, point index j in the lower-index side's orientation
     double UL[3][NF][4], UR[3][NF][4], gUL[3][NF][4][2];
-    double gL[3][NF], gR[3][NF];
+    double gL[3][NF], gR[3][NF];        // 1 / gbar at the face points of either side
     double GL[3][NF][2][2], vGL[3][NF][2];
     double lift[3][NP][4];
     double LamL[3][NP][NP], LamR[3][NP][NP];
@@ -419,18 +419,20 @@ __global__ void __launch_bounds__(320) k_jacobian(DevMesh M, const Ref<P>* __res
             point_geom<NP, double>(S.x[Ls], S.v[Ls], R->phf[fL][j], gx, G, vG);
             double gl = 0, dgl[2] = { 0, 0 };
             for (int a = 0; a < NP; ++a) { gl += R->phf[fL][j][a] * S.g[Ls][a]; dgl[0] += gx[a][0] * S.g[Ls][a]; dgl[1] += gx[a][1] * S.g[Ls][a]; }
+            const double igl = 1.0 / gl, igl2 = igl * igl;   // one division per point
             for (int b = 0; b < NP; ++b) {
-                S.BuL[f][j][b] = R->phf[fL][j][b] / gl;
-                S.PsiL[f][j][b][0] = gx[b][0] / gl - R->phf[fL][j][b] * dgl[0] / (gl * gl);
-                S.PsiL[f][j][b][1] = gx[b][1] / gl - R->phf[fL][j][b] * dgl[1] / (gl * gl);
+                S.BuL[f][j][b] = R->phf[fL][j][b] * igl;
+                S.PsiL[f][j][b][0] = gx[b][0] * igl - R->phf[fL][j][b] * dgl[0] * igl2;
+                S.PsiL[f][j][b][1] = gx[b][1] * igl - R->phf[fL][j][b] * dgl[1] * igl2;
             }
             grad_X<NP>(M.jit + 4 * Rr, R->dphr[fR][j], gx);
             point_state<NP, double>(S.U[Rs], S.g[Rs], R->phr[fR][j], gx, UR, nullptr);
             double gr = 0;
             for (int a = 0; a < NP; ++a) gr += R->phr[fR][j][a] * S.g[Rs][a];
-            for (int b = 0; b < NP; ++b) S.BuR[f][j][b] = R->phr[fR][j][b] / gr;
-            S.gL[f][j] = gl;
-            S.gR[f][j] = gr;
+            const double igr = 1.0 / gr;
+            for (int b = 0; b < NP; ++b) S.BuR[f][j][b] = R->phr[fR][j][b] * igr;
+            S.gL[f][j] = igl;   // the lifting operators use the reciprocals
+            S.gR[f][j] = igr;
             for (int m = 0; m < 4; ++m) {
                 S.UL[f][j][m] = UL[m];
                 S.UR[f][j][m] = UR[m];
@@ -444,10 +446,11 @@ __global__ void __launch_bounds__(320) k_jacobian(DevMesh M, const Ref<P>* __res
             point_geom<NP, double>(S.x[0], S.v[0], R->phf[f][j], gx, G, vG);
             double gl = 0, dgl[2] = { 0, 0 };
             for (int a = 0; a < NP; ++a) { gl += R->phf[f][j][a] * S.g[0][a]; dgl[0] += gx[a][0] * S.g[0][a]; dgl[1] += gx[a][1] * S.g[0][a]; }
+            const double igl = 1.0 / gl, igl2 = igl * igl;
             for (int b = 0; b < NP; ++b) {
-                S.BuL[f][j][b] = R->phf[f][j][b] / gl;
-                S.PsiL[f][j][b][0] = gx[b][0] / gl - R->phf[f][j][b] * dgl[0] / (gl * gl);
-                S.PsiL[f][j][b][1] = gx[b][1] / gl - R->phf[f][j][b] * dgl[1] / (gl * gl);
+                S.BuL[f][j][b] = R->phf[f][j][b] * igl;
+                S.PsiL[f][j][b][0] = gx[b][0] * igl - R->phf[f][j][b] * dgl[0] * igl2;
+                S.PsiL[f][j][b][1] = gx[b][1] * igl - R->phf[f][j][b] * dgl[1] * igl2;
             }
             for (int m = 0; m < 4; ++m) {
                 S.UL[f][j][m] = U[m];
@@ -468,10 +471,11 @@ __global__ void __launch_bounds__(320) k_jacobian(DevMesh M, const Ref<P>* __res
         point_geom<NP, double>(S.x[0], S.v[0], R->phq[q], S.gphq[q], G, vG);
         double gg = 0, dg[2] = { 0, 0 };
         for (int a = 0; a < NP; ++a) { gg += R->phq[q][a] * S.g[0][a]; dg[0] += S.gphq[q][a][0] * S.g[0][a]; dg[1] += S.gphq[q][a][1] * S.g[0][a]; }
+        const double igg = 1.0 / gg, igg2 = igg * igg;
         for (int b = 0; b < NP; ++b) {
-            S.Buq[q][b] = R->phq[q][b] / gg;
-            S.Psi0[q][b][0] = S.gphq[q][b][0] / gg - R->phq[q][b] * dg[0] / (gg * gg);
-            S.Psi0[q][b][1] = S.gphq[q][b][1] / gg - R->phq[q][b] * dg[1] / (gg * gg);
+            S.Buq[q][b] = R->phq[q][b] * igg;
+            S.Psi0[q][b][0] = S.gphq[q][b][0] * igg - R->phq[q][b] * dg[0] * igg2;
+            S.Psi0[q][b][1] = S.gphq[q][b][1] * igg - R->phq[q][b] * dg[1] * igg2;
         }
         for (int m = 0; m < 4; ++m) { S.Uq[q][m] = U[m]; S.qq[q][m][0] = gU[m][0]; S.qq[q][m][1] = gU[m][1]; }
         for (int a = 0; a < 2; ++a) { S.Gq[q][a][0] = G[a][0]; S.Gq[q][a][1] = G[a][1]; S.vGq[q][a] = vG[a]; }
@@ -492,25 +496,41 @@ __global__ void __launch_bounds__(320) k_jacobian(DevMesh M, const Ref<P>* __res
         }
         S.lift[f][c][m] = s * acc;
     }
-    for (int t = tid; t < 3 * NP * NP; t += nth) {
-        int f = t / (NP * NP), c = (t / NP) % NP, b = t % NP;
-        if (nb[f] < 0) continue;
-        bool KL = K < nb[f];
-        int L = KL ? K : nb[f], fL = KL ? f : tw[f], fR = KL ? tw[f] : f;
-        double s = -M.elen[3 * K + f] / (2.0 * M.area[L]);
-        double aL = 0, aR = 0;
-        for (int cp = 0; cp < NP; ++cp) {
-            double tL = 0, tR = 0;
-            for (int j = 0; j < NF; ++j) {
-                double w = R->wf[j] * R->phf[fL][j][cp];
-                tL += w * R->phf[fL][j][b] / S.gL[f][j];
-                tR += w * R->phr[fR][j][b] / S.gR[f][j];
+    // lifting operators Lam = +-s Mhat^{-1} T with T[cp][b] = sum_j wf_j
+    // phi_cp(j) phi_b(j) / gbar(j) on either side: T first (one face point sum
+    // per entry), then the product with the inverse reference mass matrix.
+    // T lives in the element-data arrays, which no later phase reads.
+    {
+        double* Tt = &S.U[0][0][0];   // 3 NP^2 doubles (U, g, x, v are contiguous and dead here)
+        static_assert(sizeof(S.U) + sizeof(S.g) + sizeof(S.x) + sizeof(S.v) >= 3 * NP * NP * sizeof(double),
+                      "room for the lifting sums");
+        for (int side = 0; side < 2; ++side) {
+            for (int t = tid; t < 3 * NP * NP; t += nth) {
+                const int f = t / (NP * NP), cp = (t / NP) % NP, b = t % NP;
+                if (nb[f] < 0) continue;
+                const bool KL = K < nb[f];
+                const int fL = KL ? f : tw[f], fR = KL ? tw[f] : f;
+                double acc = 0.0;
+                for (int j = 0; j < NF; ++j) {
+                    const double w = R->wf[j] * R->phf[fL][j][cp];
+                    acc += side == 0 ? w * R->phf[fL][j][b] * S.gL[f][j] : w * R->phr[fR][j][b] * S.gR[f][j];
+                }
+                Tt[t] = acc;
             }
-            aL += R->mhi[c][cp] * tL;
-            aR += R->mhi[c][cp] * tR;
+            __syncthreads();
+            for (int t = tid; t < 3 * NP * NP; t += nth) {
+                const int f = t / (NP * NP), c = (t / NP) % NP, b = t % NP;
+                if (nb[f] < 0) continue;
+                const bool KL = K < nb[f];
+                const int L = KL ? K : nb[f];
+                const double s = -M.elen[3 * K + f] / (2.0 * M.area[L]);
+                double a = 0.0;
+                for (int cp = 0; cp < NP; ++cp) a += R->mhi[c][cp] * Tt[(f * NP + cp) * NP + b];
+                if (side == 0) S.LamL[f][c][b] = s * a;
+                else S.LamR[f][c][b] = -s * a;
+            }
+            __syncthreads();
         }
-        S.LamL[f][c][b] = s * aL;
-        S.LamR[f][c][b] = -s * aR;
     }
     __syncthreads();
     // lifting contributions to the trace and volume gradient operators
@@ -568,6 +588,34 @@ __global__ void __launch_bounds__(320) k_jacobian(DevMesh M, const Ref<P>* __res
         S.gUL[f][j][m][1] += l * N[1];
     }
     __syncthreads();
+    // test-side (A) values of the contraction, formed once: the volume ones
+    // in place of the basis gradients (w2K wq[q] grad phi_a(q), which only the
+    // contraction reads from here on), the face ones in the dead lifting-
+    // operator storage (-sign |e| wf[j] phi_a at the face point, from K's
+    // side of the face)
+    {
+        const double w2K = 2.0 * M.area[K];
+        for (int t = tid; t < NQ * NP; t += nth) {
+            const int q = t / NP, a = t % NP;
+            const double wq = w2K * R->wq[q];
+            S.gphq[q][a][0] *= wq;
+            S.gphq[q][a][1] *= wq;
+        }
+        double* Af = &S.LamL[0][0][0];   // [3][NF][NP]
+        for (int t = tid; t < 3 * NF * NP; t += nth) {
+            const int ff = t / (NF * NP), j = (t / NP) % NF, a = t % NP;
+            const double len = M.elen[3 * K + ff];
+            double v;
+            if (nb[ff] >= 0) {
+                const bool KL = K < nb[ff];
+                const double sg = (KL ? 1.0 : -1.0) * len;
+                v = -sg * R->wf[j] * (KL ? R->phf[ff][j][a] : R->phr[ff][j][a]);
+            } else {
+                v = -len * R->wf[j] * R->phf[ff][j][a];
+            }
+            Af[t] = v;
+        }
+    }
     // phase 3: pointwise Jacobians (one dual direction per thread)
     for (int t = tid; t < NQ * 12; t += nth) {
         int q = t / 12, sd = t % 12;
@@ -645,7 +693,7 @@ __global__ void __launch_bounds__(320) k_jacobian(DevMesh M, const Ref<P>* __res
     // result (lane / 16 + 4 r, lane % 16) in register r.  Tasks: (block s,
     // column tile), spread over the waves.
     {
-        const double w2K = 2.0 * M.area[K];
+        const double* Af = &S.LamL[0][0][0];   // face A values, [3][NF][NP]
         const int wave = tid >> 6, nwaves = nth >> 6, lane = tid & 63;
         const int li = lane & 15, lk = lane >> 4;
         // a task is two column tiles of one block: they share the test-side
@@ -677,7 +725,7 @@ __global__ void __launch_bounds__(320) k_jacobian(DevMesh M, const Ref<P>* __res
                     double av = 0.0, bv[2] = { 0.0, 0.0 };
                     if (kk < 2 * NQ) {
                         const int q = kk >> 1, d = kk & 1;
-                        if (li < NP) av = w2K * R->wq[q] * S.gphq[q][li][d];
+                        if (li < NP) av = S.gphq[q][li][d];
 #pragma unroll
                         for (int t = 0; t < 2; ++t) {
                             const int m = mm[t], n = nn[t], b = bb[t];
@@ -700,12 +748,10 @@ __global__ void __launch_bounds__(320) k_jacobian(DevMesh M, const Ref<P>* __res
                 double av = 0.0, bv[2] = { 0.0, 0.0 };
                 if (kk < npts) {
                     const int ff = s_ == 0 ? kk / NF : f, j = s_ == 0 ? kk % NF : kk;
-                    const double len = M.elen[3 * K + ff];
                     if (nb[ff] >= 0) {
                         const bool KL = K < nb[ff];
                         const int L = KL ? K : nb[ff], fL = KL ? ff : tw[ff];
                         const double* N = M.enrm + 2 * (3 * L + fL);
-                        const double sg = (KL ? 1.0 : -1.0) * len;
                         // the diagonal block takes K's own trace, a neighbour block the other side's
                         const bool own = (s_ == 0) == KL;
 #pragma unroll
@@ -720,7 +766,7 @@ __global__ void __launch_bounds__(320) k_jacobian(DevMesh M, const Ref<P>* __res
                                         (S.E[ff][j][m][8 + 2 * n] * N[0] + S.E[ff][j][m][9 + 2 * n] * N[1]) *
                                             S.LRf[ff][j][b];
                         }
-                        if (li < NP) av = -sg * R->wf[j] * (KL ? R->phf[ff][j][li] : R->phr[ff][j][li]);
+                        if (li < NP) av = Af[(ff * NF + j) * NP + li];
                     } else {
 #pragma unroll
                         for (int t = 0; t < 2; ++t) {
@@ -728,7 +774,7 @@ __global__ void __launch_bounds__(320) k_jacobian(DevMesh M, const Ref<P>* __res
                             bv[t] = S.E[ff][j][m][n] * S.BuL[ff][j][b] + S.E[ff][j][m][4 + 2 * n] * S.PsiL[ff][j][b][0] +
                                     S.E[ff][j][m][5 + 2 * n] * S.PsiL[ff][j][b][1];
                         }
-                        if (li < NP) av = -len * R->wf[j] * R->phf[ff][j][li];
+                        if (li < NP) av = Af[(ff * NF + j) * NP + li];
                     }
                 }
                 acc0 = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv[0], acc0, 0, 0, 0);
