@@ -134,7 +134,8 @@ def time_to_gradient(pa, mu):
     stream (+ seeded N(0,1e-3) perturbation) to ||u^(Nt) - u0||_2 <= 1e-8, then
     the periodic adjoint gradient of both QoIs at relative 1e-8; then the
     same run with every stage solve in one workgroup (pa_config.wg_solve)
-    for comparison."""
+    and with the stage-GMRES iterations replayed from captured graphs
+    (pa_config.graph) for comparison."""
     work = inputs.WORKLOADS["circle-8x24-p1-nt20"]
     s = pa.Solver(gmres_restart=30, lin_rtol=1e-10, newton_atol=1e-10, max_krylov=100, **work, **inputs.PHYSICS)
     s.set_params(mu)
@@ -170,6 +171,18 @@ def time_to_gradient(pa, mu):
     tk = time.perf_counter() - tk
     k.close()
     log("ttg: stage solves in one workgroup: %.1f s" % tk)
+    # the same run with the stage-GMRES iterations replayed from captured
+    # graphs (pa_config.graph): the same kernels, bitwise equal results
+    h = pa.Solver(gmres_restart=30, lin_rtol=1e-10, newton_atol=1e-10, max_krylov=100, graph=1, **work,
+                  **inputs.PHYSICS)
+    h.set_params(mu)
+    h.set_freestream(inputs.perturbation(h.Nu, seed=1))
+    th = time.perf_counter()
+    hrep = h.shoot(tol=1e-8, eta=1e-3, maxit=30)
+    _, dJh, _ = h.adjoint_gradient(rtol=1e-8)
+    th = time.perf_counter() - th
+    h.close()
+    log("ttg: stage-GMRES iterations replayed from graphs: %.1f s" % th)
     return {"workload": "circle-8x24-p1-nt20", "seconds": t, "newton": rep.newton_its,
             "tangent_sweeps": rep.krylov_its, "periodicity": rep.res, "adjoint_krylov": list(arep.krylov_its),
             "counts": {"primal_sweeps": rep.primal_sweeps, "tangent_sweeps": rep.krylov_its,
@@ -180,7 +193,9 @@ def time_to_gradient(pa, mu):
                               "dJdmu_rel_diff": float(np.abs(dJb - dJ).max() / np.abs(dJ).max())},
             "floquet_leading": [[float(z.real), float(z.imag)] for z in ritz[:4]],
             "workgroup_form": {"seconds": tk, "newton": krep.newton_its, "tangent_sweeps": krep.krylov_its,
-                               "dJdmu_rel_diff": float(np.abs(dJk - dJ).max() / np.abs(dJ).max())}}
+                               "dJdmu_rel_diff": float(np.abs(dJk - dJ).max() / np.abs(dJ).max())},
+            "graph_form": {"seconds": th, "newton": hrep.newton_its, "tangent_sweeps": hrep.krylov_its,
+                           "dJdmu_bitwise_equal": bool(np.array_equal(dJh, dJ))}}
 
 
 def solver_comparison(pa, mu, descent_maxit=150):

@@ -108,6 +108,18 @@ typedef struct pa_config {
      * is below |b|; the stopping test stays lin_rtol |b|.  0 (default): from
      * zero.  Newton corrections always start from zero. */
     int32_t lin_guess;
+    /* 1: the FP64 stage-GMRES iterations between two convergence checks
+     * (5 iterations of apply, multi-dot and basis update, one or several
+     * systems) are captured once per context as HIP graphs and replayed;
+     * the applies then read the stage operator's address from a device slot
+     * set before each solve.  The same kernels in the same order: results
+     * are bitwise equal to graph = 0.  It pays where launch costs dominate
+     * (small meshes); the sampled kernel times of pa_kernel_time do not
+     * cover replayed launches.  Needs gmres_restart a multiple of 5, FP64
+     * precision and wg_solve = 0 (else PA_EINVAL at pa_create), and a
+     * stream that can be captured (not the legacy null stream).
+     * 0 (default): every launch from the host. */
+    int32_t graph;
 } pa_config;
 
 /* Precision of the stage linear solves (Sec. 2.1 eq. dirk, each stage's

@@ -690,6 +690,7 @@ struct Solver final : pa_ctx {
     ~Solver() override
     {
         if (st) (void)hipStreamSynchronize(st);
+        free_graphs();
         for (auto& e : evpool) { (void)hipEventDestroy(e.a); (void)hipEventDestroy(e.b); }
         for (void* p : allocs) da.put(p);
         if (hstat) (void)hipHostFree(hstat);
@@ -912,6 +913,8 @@ struct Solver final : pa_ctx {
         gms = dalloc<GmState>(1);
         HIPCHK(hipHostMalloc((void**)&hstat, 3 * sizeof(GmHost), hipHostMallocDefault));
         use_wg = cfg.wg_solve == 1 || (cfg.wg_solve == -1 && Nu <= WG_MAXNU && restart <= WG_MAXM);
+        use_graph = cfg.graph == 1;
+        if (use_graph) ahp = dalloc<const double*>(1);
         if (use_wg) {
             wgst = dalloc<WgStatus>(GM_RMAX);
             HIPCHK(hipHostMalloc((void**)&hwgst, GM_RMAX * sizeof(WgStatus), hipHostMallocDefault));
@@ -1077,17 +1080,19 @@ struct Solver final : pa_ctx {
     }
     // forward FP64 apply with the tile shape q (chunks per task; 0 = default)
     int fwd_q = 0;
-    void launch_fwd(int q, const double* Ah, const double* x, double* y, const int* skip)
+    // (Ahp: optional device slot holding the operator's address, read by the kernel)
+    void launch_fwd(int q, const double* Ah, const double* x, double* y, const int* skip,
+                    const double* const* Ahp = nullptr)
     {
         if (q == 1 && ahat_fwd_valid<NP, double>(1))
-            k_ahat_fwd<NP, double, double, 1><<<Ne, 64, 0, st>>>(Ne, nb4f, Ah, x, y, skip);
+            k_ahat_fwd<NP, double, double, 1><<<Ne, 64, 0, st>>>(Ne, nb4f, Ah, x, y, skip, Ahp);
         else if (q == 2 && ahat_fwd_valid<NP, double>(2))
-            k_ahat_fwd<NP, double, double, 2><<<Ne, 64, 0, st>>>(Ne, nb4f, Ah, x, y, skip);
+            k_ahat_fwd<NP, double, double, 2><<<Ne, 64, 0, st>>>(Ne, nb4f, Ah, x, y, skip, Ahp);
         else if (q == 4 && ahat_fwd_valid<NP, double>(4)) {
             if constexpr (ahat_fwd_valid<NP, double>(4))
-                k_ahat_fwd<NP, double, double, 4><<<Ne, 64, 0, st>>>(Ne, nb4f, Ah, x, y, skip);
+                k_ahat_fwd<NP, double, double, 4><<<Ne, 64, 0, st>>>(Ne, nb4f, Ah, x, y, skip, Ahp);
         } else
-            k_ahat_fwd<NP, double, double><<<Ne, 64, 0, st>>>(Ne, nb4f, Ah, x, y, skip);
+            k_ahat_fwd<NP, double, double><<<Ne, 64, 0, st>>>(Ne, nb4f, Ah, x, y, skip, Ahp);
     }
     // autotune (pa_config.autotune): time each valid tile shape on the first
     // stored stage operator (after its formation, 10 launches each, HIP
@@ -1311,6 +1316,88 @@ struct Solver final : pa_ctx {
     // copy only, so GM_CHECK iterations stay queued on the device while it
     // looks.  Iterations enqueued after convergence exit at once.
     static constexpr int GM_CHECK = 5;
+
+    // pa_config.graph: the GM_CHECK iterations between two checks (apply,
+    // multi-dot, update; one system or R sharing the operator), for one
+    // transpose flag, system count and first column, are captured on the
+    // stream once and replayed.  Every launch of such a graph names the
+    // context's own fixed buffers (basis, work vector, partial sums, GMRES
+    // states); only the stage operator changes between solves, and the
+    // applies read its address from the device slot ahp, set on the stream
+    // before each solve.  A replay runs the kernels a host loop would
+    // launch, with the same arguments, in the same order.
+    bool use_graph = false;
+    const double** ahp = nullptr;
+    hipGraphExec_t gx[2][GM_RMAX + 1][GM_MAXM / GM_CHECK] = {};
+    int gx_q = -1;   // forward tile shape the graphs were captured with
+    void set_graph_op(const double* Ah)
+    {
+        k_set_ptr<<<1, 64, 0, st>>>(ahp, Ah);
+        LAUNCHCHK();
+    }
+    void free_graphs()
+    {
+        for (auto& a : gx)
+            for (auto& b : a)
+                for (auto& g : b)
+                    if (g) {
+                        (void)hipGraphExecDestroy(g);
+                        g = nullptr;
+                    }
+    }
+    // iteration j of the stage solve (R == 1: the buffers of stage_solve;
+    // R > 1: those of stage_solve_multi), with the operator from the slot
+    void gm_iter_slot(int tr, int R, int j)
+    {
+        const int m = restart, nb = (int)mdot_blocks(Nu);
+        if (R == 1) {
+            const double* vj = V + (int64_t)j * Nu;
+            if (tr) k_ahat_tr<NP, double, double><<<Ne, 64, 0, st>>>(Ne, nb4t, nullptr, vj, we, &gms->done, ahp);
+            else launch_fwd(fwd_q, nullptr, vj, we, &gms->done, ahp);
+            k_mdot_part<<<dim3(nb, mdot_chunks(j + 2)), MD_THREADS, 0, st>>>(V, Nu, j + 1, 1, we, Nu, part, gms);
+            k_gm_upd<<<(unsigned)gm_upd_blocks(Nu), GU_THREADS, 0, st>>>(V, Nu, j, m, we, Nu, part, nb, gms);
+        } else {
+            const int64_t sV = (int64_t)(m + 1) * Nu, sP = (int64_t)nb * (m + 2);
+            ahat_m(nullptr, tr, R, Vm + (int64_t)j * Nu, sV, wm, Nu, gmsm, ahp);
+            k_mdot_part<<<dim3(nb, mdot_chunks(j + 2) * R), MD_THREADS, 0, st>>>(Vm, Nu, j + 1, 1, wm, Nu, partm,
+                                                                                 gmsm, sV, Nu, sP);
+            k_gm_upd<<<dim3((unsigned)gm_upd_blocks(Nu), R), GU_THREADS, 0, st>>>(Vm, Nu, j, m, wm, Nu, partm, nb,
+                                                                                  gmsm, sV, Nu, sP);
+        }
+    }
+    // the graph of iterations c GM_CHECK .. (c + 1) GM_CHECK - 1, captured on first use
+    hipGraphExec_t gm_graph(int tr, int R, int c)
+    {
+        if (gx_q != fwd_q) {
+            free_graphs();
+            gx_q = fwd_q;
+        }
+        hipGraphExec_t& g = gx[tr][R][c];
+        if (g) return g;
+        (void)hipGetLastError();
+        HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+        hipGraph_t gr = nullptr;
+        try {
+            for (int j = c * GM_CHECK; j < (c + 1) * GM_CHECK; ++j) gm_iter_slot(tr, R, j);
+        } catch (...) {   // leave the stream out of capture mode
+            if (hipStreamEndCapture(st, &gr) == hipSuccess && gr) (void)hipGraphDestroy(gr);
+            throw;
+        }
+        const hipError_t el = hipGetLastError();
+        const hipError_t ec = hipStreamEndCapture(st, &gr);
+        if (el != hipSuccess || ec != hipSuccess || !gr) {
+            if (gr) (void)hipGraphDestroy(gr);
+            raise(PA_EDEVICE, "stage-GMRES graph capture failed: %s",
+                  hipGetErrorString(el != hipSuccess ? el : ec));
+        }
+        const hipError_t ei = hipGraphInstantiate(&g, gr, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(gr);
+        if (ei != hipSuccess) {
+            g = nullptr;
+            raise(PA_EDEVICE, "stage-GMRES graph instantiation failed: %s", hipGetErrorString(ei));
+        }
+        return g;
+    }
     // R systems sharing one stage operator, each solved by one workgroup
     // (k_stage_gmres_wg): rhs and x hold R vectors; returns the largest
     // iteration count
@@ -1377,24 +1464,31 @@ struct Solver final : pa_ctx {
             zero(y);
             copy(b, r);
         }
+        if (use_graph) set_graph_op(op.Ah);
         for (;;) {
             k_mdot_part<<<nb, MD_THREADS, 0, st>>>(r, 0, 1, 0, r, Nu, part, nullptr);
             k_gm_begin<<<nb, MD_THREADS, 0, st>>>(r, V, Nu, part, nb, GmTol{ { tol } }, gms);
             LAUNCHCHK();
             int pending = -1, slot = 0, launched = 0;
             for (int j = 0; j < m; ++j) {
-                double* vj = V + (int64_t)j * Nu;
-                ahat(op.Ah, tr, vj, w, skip);
+                if (use_graph) {
+                    // iterations j .. j + GM_CHECK - 1 (m is a multiple of GM_CHECK)
+                    if (j % GM_CHECK == 0) HIPCHK(hipGraphLaunch(gm_graph(tr, 1, j / GM_CHECK), st));
+                } else {
+                    double* vj = V + (int64_t)j * Nu;
+                    ahat(op.Ah, tr, vj, w, skip);
+                    // one classical Gram-Schmidt pass; the cycle closes on cancellation
+                    hipEvent_t e;
+                    tstart(PA_K_MDOT, &e);
+                    k_mdot_part<<<dim3(nb, mdot_chunks(j + 2)), MD_THREADS, 0, st>>>(V, Nu, j + 1, 1, w, Nu, part,
+                                                                                     gms);
+                    tstop(e);
+                    tstart(PA_K_GMUPD, &e);
+                    k_gm_upd<<<(unsigned)gm_upd_blocks(Nu), GU_THREADS, 0, st>>>(V, Nu, j, m, w, Nu, part, nb, gms);
+                    tstop(e);
+                    LAUNCHCHK();
+                }
                 ++launched;
-                // one classical Gram-Schmidt pass; the cycle closes on cancellation
-                hipEvent_t e;
-                tstart(PA_K_MDOT, &e);
-                k_mdot_part<<<dim3(nb, mdot_chunks(j + 2)), MD_THREADS, 0, st>>>(V, Nu, j + 1, 1, w, Nu, part, gms);
-                tstop(e);
-                tstart(PA_K_GMUPD, &e);
-                k_gm_upd<<<(unsigned)gm_upd_blocks(Nu), GU_THREADS, 0, st>>>(V, Nu, j, m, w, Nu, part, nb, gms);
-                tstop(e);
-                LAUNCHCHK();
                 if ((j + 1) % GM_CHECK == 0 && j < m - 1) {
                     if (pending >= 0) {
                         HIPCHK(hipEventSynchronize(gm_ev[pending]));
@@ -1795,16 +1889,18 @@ struct Solver final : pa_ctx {
         HIPCHK(hipHostMalloc((void**)&hstm, R * sizeof(GmHost), hipHostMallocDefault));
         RM = R;
     }
+    // (Ahp: optional device slot holding the operator's address; such
+    // launches, meant for graph capture, are not timed)
     void ahat_m(const double* Ah, int tr, int R, const double* x, int64_t sx, double* y, int64_t sy,
-                const GmState* skip = nullptr)
+                const GmState* skip = nullptr, const double* const* Ahp = nullptr)
     {
-        hipEvent_t e;
-        tstart(tr ? PA_K_SPMV_TM : PA_K_SPMV_M, &e);
+        hipEvent_t e = nullptr;
+        if (!Ahp) tstart(tr ? PA_K_SPMV_TM : PA_K_SPMV_M, &e);
         switch (R) {
 #define PA_AHAT_M(RR)                                                                                         \
     case RR:                                                                                                  \
-        if (tr) k_ahat_tr_m<NP, RR><<<Ne, 64, 0, st>>>(Ne, nb4t, Ah, x, sx, y, sy, skip);                     \
-        else k_ahat_fwd_m<NP, RR><<<Ne, 64, 0, st>>>(Ne, nb4f, Ah, x, sx, y, sy, skip);                       \
+        if (tr) k_ahat_tr_m<NP, RR><<<Ne, 64, 0, st>>>(Ne, nb4t, Ah, x, sx, y, sy, skip, Ahp);                \
+        else k_ahat_fwd_m<NP, RR><<<Ne, 64, 0, st>>>(Ne, nb4f, Ah, x, sx, y, sy, skip, Ahp);                  \
         break;
             PA_AHAT_M(1) PA_AHAT_M(2) PA_AHAT_M(3) PA_AHAT_M(4) PA_AHAT_M(5) PA_AHAT_M(6) PA_AHAT_M(7) PA_AHAT_M(8)
 #undef PA_AHAT_M
@@ -1870,6 +1966,7 @@ struct Solver final : pa_ctx {
         int total = 0;
         bool all = true;
         for (int r = 0; r < R; ++r) all = all && acc[r];
+        if (use_graph && !all) set_graph_op(op.Ah);
         while (!all) {
             const dim3 g2(nb, R);
             k_mdot_part<<<g2, MD_THREADS, 0, st>>>(rm, 0, 1, 0, rm, Nu, partm, nullptr, Nu, Nu, sP);
@@ -1879,17 +1976,22 @@ struct Solver final : pa_ctx {
             hipEvent_t ev_p = nullptr;
             for (int j = 0; j < m; ++j) {
                 jlast = j;
-                ahat_m(op.Ah, tr, R, Vm + (int64_t)j * Nu, sV, wm, Nu, gmsm);
-                hipEvent_t e;
-                tstart(PA_K_MDOT, &e);
-                k_mdot_part<<<dim3(nb, mdot_chunks(j + 2) * R), MD_THREADS, 0, st>>>(Vm, Nu, j + 1, 1, wm, Nu, partm, gmsm,
-                                                                                     sV, Nu, sP);
-                tstop(e);
-                tstart(PA_K_GMUPD, &e);
-                k_gm_upd<<<dim3((unsigned)gm_upd_blocks(Nu), R), GU_THREADS, 0, st>>>(Vm, Nu, j, m, wm, Nu, partm, nb,
-                                                                                      gmsm, sV, Nu, sP);
-                tstop(e);
-                LAUNCHCHK();
+                if (use_graph) {
+                    // iterations j .. j + GM_CHECK - 1 (m is a multiple of GM_CHECK)
+                    if (j % GM_CHECK == 0) HIPCHK(hipGraphLaunch(gm_graph(tr, R, j / GM_CHECK), st));
+                } else {
+                    ahat_m(op.Ah, tr, R, Vm + (int64_t)j * Nu, sV, wm, Nu, gmsm);
+                    hipEvent_t e;
+                    tstart(PA_K_MDOT, &e);
+                    k_mdot_part<<<dim3(nb, mdot_chunks(j + 2) * R), MD_THREADS, 0, st>>>(Vm, Nu, j + 1, 1, wm, Nu,
+                                                                                         partm, gmsm, sV, Nu, sP);
+                    tstop(e);
+                    tstart(PA_K_GMUPD, &e);
+                    k_gm_upd<<<dim3((unsigned)gm_upd_blocks(Nu), R), GU_THREADS, 0, st>>>(Vm, Nu, j, m, wm, Nu, partm,
+                                                                                          nb, gmsm, sV, Nu, sP);
+                    tstop(e);
+                    LAUNCHCHK();
+                }
                 if ((j + 1) % GM_CHECK == 0 && j < m - 1) {
                     if (pending >= 0) {
                         HIPCHK(hipEventSynchronize(ev_p));
@@ -3309,6 +3411,8 @@ void pa_default_config(pa_config* c)
     c->block_krylov = 0;
     c->device = 0;
     c->wg_solve = 0;
+    c->lin_guess = 0;
+    c->graph = 0;
 }
 
 static thread_local std::string g_create_err;
@@ -3320,8 +3424,13 @@ pa_status pa_create(const pa_config* cfg, pa_ctx** out)
     if (!cfg || cfg->Nr < 1 || cfg->Nth < 3 || cfg->p < 1 || cfg->p > 3 || cfg->Nt < 1 || cfg->gmres_restart < 1 ||
         cfg->gmres_restart > 64 || cfg->max_krylov < 1 || cfg->max_krylov > 126 || !(cfg->r_far > 1.0) ||
         !(cfg->stretch > 0.0) || !(cfg->T > 0.0) || cfg->precision < PA_PREC_FP64 || cfg->precision > PA_PREC_BF16 ||
-        cfg->wg_solve < -1 || cfg->wg_solve > 1 || cfg->lin_guess < 0 || cfg->lin_guess > 1) {
+        cfg->wg_solve < -1 || cfg->wg_solve > 1 || cfg->lin_guess < 0 || cfg->lin_guess > 1 || cfg->graph < 0 ||
+        cfg->graph > 1) {
         g_create_err = "invalid configuration";
+        return PA_EINVAL;
+    }
+    if (cfg->graph == 1 && (cfg->gmres_restart % Solver<1>::GM_CHECK != 0 || cfg->precision != PA_PREC_FP64 || cfg->wg_solve != 0)) {
+        g_create_err = "graph = 1 needs gmres_restart a multiple of 5, FP64 precision and wg_solve = 0";
         return PA_EINVAL;
     }
     if (cfg->wg_solve == 1) {

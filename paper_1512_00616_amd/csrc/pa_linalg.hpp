@@ -418,8 +418,10 @@ namespace pa {
 // Grid (gm_upd_blocks(n), R), one double2 of every column per thread.
 // Every block first issues the loads of w and of the first GU_COLS basis
 // columns, then sums the partial rows (thread (column c, row group g) adds
-// rows g, g + 8, ... of column c, GU_ROWS loads in flight; the 8 group sums
-// are added in group order -- the same bits in every block), then finishes
+// rows g, g + ng, ... of column c, the loads of up to GU_ROWS rows issued
+// before the first add, so that one load latency is paid per GU_ROWS rows;
+// the ng group sums are added in group order -- the same bits in every
+// block), then finishes
 // the update; later columns follow GU_COLS at a time, all added in column
 // order.  Block 0 also rotates column j of H by the previous Givens
 // rotations, makes the rotation that zeroes the subdiagonal and updates the
@@ -430,11 +432,11 @@ namespace pa {
 // each block reads it once (either value is correct there: V_{j+1} of a
 // closed cycle is never used).
 constexpr int GU_THREADS = 256;
-constexpr int GU_COLS = 16;    // basis columns loaded together
-constexpr int GU_ROWS = 8;     // partial rows loaded together per thread
+constexpr int GU_COLS = 12;    // basis columns loaded together
+constexpr int GU_ROWS = 16;    // partial rows loaded together per thread
 inline int64_t gm_upd_blocks(int64_t n) { return (n / 2 + GU_THREADS - 1) / GU_THREADS; }
 template <class T>
-__global__ void __launch_bounds__(GU_THREADS) k_gm_upd(const T* __restrict__ V, int64_t ldv, int j, int m,
+__global__ void __launch_bounds__(GU_THREADS, 4) k_gm_upd(const T* __restrict__ V, int64_t ldv, int j, int m,
                                                        const T* __restrict__ w, int64_t n,
                                                        const double* __restrict__ partial, int nblk,
                                                        GmState* __restrict__ st, int64_t sV = 0, int64_t sw = 0,
@@ -453,7 +455,7 @@ __global__ void __launch_bounds__(GU_THREADS) k_gm_upd(const T* __restrict__ V, 
     __shared__ double s1[GM_MAXM + 2];
     __shared__ double scs[GM_MAXM], ssn[GM_MAXM];
     __shared__ double col[GM_MAXM + 2];
-    __shared__ double red[GU_THREADS / 32][33];
+    __shared__ double red[GU_THREADS];
     __shared__ double sih;
     const int ncols = j + 1, nc = j + 2;
     const bool lead = blockIdx.x == 0;
@@ -470,30 +472,34 @@ __global__ void __launch_bounds__(GU_THREADS) k_gm_upd(const T* __restrict__ V, 
             scs[q] = st->cs[q];
             ssn[q] = st->sn[q];
         }
-    // final sums of the partials
+    // final sums of the partials: ncp columns per pass (8, 16 or 32, the
+    // fewest that cover nc), the 256 threads as ncp columns x ng row groups
     {
-        const int cl = tid & 31, g = tid >> 5;
-        constexpr int NG = GU_THREADS / 32;
-        for (int c0 = 0; c0 < nc; c0 += 32) {
+        const int ncp = nc <= 8 ? 8 : nc <= 16 ? 16 : 32, ng = GU_THREADS / ncp;
+        const int cl = tid % ncp, g = tid / ncp;
+        for (int c0 = 0; c0 < nc; c0 += ncp) {
             const int c = c0 + cl;
             double acc = 0.0;
-            if (c < nc) {
-                int b = g;
-                for (; b + (GU_ROWS - 1) * NG < nblk; b += GU_ROWS * NG) {
+            if (c < nc)
+                for (int b0 = g; b0 < nblk; b0 += GU_ROWS * ng) {
+                    // all GU_ROWS loads issued before the first add (rows
+                    // past nblk read the last row and add zero)
+                    const double* pc = partial + c;
                     double v[GU_ROWS];
 #pragma unroll
-                    for (int u = 0; u < GU_ROWS; ++u) v[u] = partial[(int64_t)(b + u * NG) * nc + c];
+                    for (int u = 0; u < GU_ROWS; ++u) {
+                        const int b = b0 + u * ng;
+                        v[u] = pc[(b < nblk ? b : nblk - 1) * nc];
+                    }
+                    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-                    for (int u = 0; u < GU_ROWS; ++u) acc += v[u];
+                    for (int u = 0; u < GU_ROWS; ++u) acc += b0 + u * ng < nblk ? v[u] : 0.0;
                 }
-                for (; b < nblk; b += NG) acc += partial[(int64_t)b * nc + c];
-            }
-            red[g][cl] = acc;
+            red[tid] = acc;
             __syncthreads();
-            if (tid < 32 && c0 + tid < nc) {
+            if (tid < ncp && c0 + tid < nc) {
                 double sum = 0.0;
-#pragma unroll
-                for (int gg = 0; gg < NG; ++gg) sum += red[gg][tid];
+                for (int gg = 0; gg < ng; ++gg) sum += red[gg * ncp + tid];
                 s1[c0 + tid] = sum;
             }
             __syncthreads();
@@ -1178,11 +1184,14 @@ constexpr bool ahat_fwd_valid(int Q)
 // 16-byte chunks lying in one row; lane l holds tasks l, l + 64, ... of the
 // three blocks in registers (every load issued before any arithmetic, no
 // matrix entry through LDS), leaves one partial per task in LDS, and lane i
-// adds row i's partials to x_i.
+// adds row i's partials to x_i.  With Ahp (optional, in every apply
+// kernel) the blocks' address is read from device memory at the start: a
+// launch captured once in a graph then serves whichever stored operator the
+// slot names when it is replayed.
 template <int NP, class TM, class TV, int QT = 0>
 __global__ void __launch_bounds__(64) k_ahat_fwd(int Ne, const int4* __restrict__ nb4, const TM* __restrict__ Ah,
                                                  const TV* __restrict__ x, TV* __restrict__ y,
-                                                 const int* __restrict__ skip)
+                                                 const int* __restrict__ skip, const TM* const* __restrict__ Ahp = nullptr)
 {
     constexpr int B = 4 * NP, BB = B * B;
     constexpr int EPL = 16 / sizeof(TM);              // entries per 16-byte chunk
@@ -1195,6 +1204,7 @@ __global__ void __launch_bounds__(64) k_ahat_fwd(int Ne, const int4* __restrict_
     __shared__ TV sp[3][TPR][B + 1];
     __shared__ TV sx[3][B];
     if (skip && *skip) return;
+    if (Ahp) Ah = *Ahp;
     const int K = blockIdx.x, lane = threadIdx.x;
     const int4 t4 = nb4[K];
     int nbs[3];
@@ -1353,9 +1363,10 @@ __device__ __forceinline__ void ahat_tr_body(int K, const int4* __restrict__ tb4
 template <int NP, class TM, class TV>
 __global__ void __launch_bounds__(64) k_ahat_tr(int Ne, const int4* __restrict__ tb4, const TM* __restrict__ Ah,
                                                 const TV* __restrict__ x, TV* __restrict__ y,
-                                                const int* __restrict__ skip)
+                                                const int* __restrict__ skip, const TM* const* __restrict__ Ahp = nullptr)
 {
     if (skip && *skip) return;
+    if (Ahp) Ah = *Ahp;
     ahat_tr_body<NP, TM, TV, 1>(blockIdx.x, tb4, Ah, x, 0, y, 0);
 }
 
@@ -1374,7 +1385,8 @@ __device__ __forceinline__ bool all_done(const GmState* __restrict__ st, int R)
 template <int NP, int RT>
 __global__ void __launch_bounds__(64) k_ahat_fwd_m(int Ne, const int4* __restrict__ nb4, const double* __restrict__ Ah,
                                                    const double* __restrict__ x, int64_t sx, double* __restrict__ y,
-                                                   int64_t sy, const GmState* __restrict__ st)
+                                                   int64_t sy, const GmState* __restrict__ st,
+                                                   const double* const* __restrict__ Ahp = nullptr)
 {
     constexpr int R = RT;
     constexpr int B = 4 * NP, BB = B * B, EPL = 2;
@@ -1387,6 +1399,7 @@ __global__ void __launch_bounds__(64) k_ahat_fwd_m(int Ne, const int4* __restric
         for (int r = 0; r < R; ++r) all = all && st[r].done;
         if (all) return;
     }
+    if (Ahp) Ah = *Ahp;
     const int K = blockIdx.x, lane = threadIdx.x;
     const int4 t4 = nb4[K];
     int nbs[3];
@@ -1446,10 +1459,18 @@ __global__ void __launch_bounds__(64) k_ahat_fwd_m(int Ne, const int4* __restric
 template <int NP, int R>
 __global__ void __launch_bounds__(64) k_ahat_tr_m(int Ne, const int4* __restrict__ tb4, const double* __restrict__ Ah,
                                                   const double* __restrict__ x, int64_t sx, double* __restrict__ y,
-                                                  int64_t sy, const GmState* __restrict__ st)
+                                                  int64_t sy, const GmState* __restrict__ st,
+                                                  const double* const* __restrict__ Ahp = nullptr)
 {
     if (all_done(st, R)) return;
+    if (Ahp) Ah = *Ahp;
     ahat_tr_body<NP, double, double, R>(blockIdx.x, tb4, Ah, x, sx, y, sy);
+}
+
+// *slot = p: the operator address that captured apply launches read
+__global__ void k_set_ptr(const double** __restrict__ slot, const double* p)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) *slot = p;
 }
 
 // z = a * x (FP64 -> FP32), y += a * x (FP32 -> FP64)

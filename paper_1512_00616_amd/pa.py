@@ -38,7 +38,7 @@ class pa_config(C.Structure):
         ("newton_atol", C.c_double), ("newton_maxit", C.c_int32), ("max_krylov", C.c_int32),
         ("device", C.c_int32), ("precision", C.c_int32), ("autotune", C.c_int32), ("block_krylov", C.c_int32),
         ("stream", C.c_void_p), ("dev_alloc", C.c_void_p), ("dev_free", C.c_void_p), ("user", C.c_void_p),
-        ("wg_solve", C.c_int32), ("lin_guess", C.c_int32),
+        ("wg_solve", C.c_int32), ("lin_guess", C.c_int32), ("graph", C.c_int32),
     ]
 
 

@@ -53,3 +53,19 @@ def test_bench_refuses_more_than_one_gpu():
     assert r.returncode == 2
     assert "one GPU" in r.stderr
     assert r.stdout == ""
+
+
+def test_create_rejects_configurations_before_touching_the_device():
+    # pa_create validates the configuration first (no device call), so the
+    # refusals below hold without a GPU
+    import pytest
+    from paper_1512_00616_amd import pa
+    base = dict(Nr=2, Nth=6, p=1, Nt=2)
+    for bad in (dict(graph=1, gmres_restart=32),          # a graph covers the 5 iterations between checks
+                dict(graph=1, precision=pa.PREC_FP32),    # FP64 stage solves only
+                dict(graph=1, wg_solve=1),                # exclusive with the one-workgroup solve
+                dict(graph=2), dict(lin_guess=2), dict(wg_solve=2), dict(gmres_restart=65)):
+        with pytest.raises(pa.PaError) as e:
+            pa.Solver(**dict(base, **bad))
+        assert e.value.code == pa.PA_EINVAL, bad
+    assert pa.default_config().graph == 0

@@ -30,13 +30,14 @@ def libs():
     return pa, O
 
 
-def make_pair(libs, gpu_kw=None, orc_kw=None, wg=0, guess=0, **kw):
+def make_pair(libs, gpu_kw=None, orc_kw=None, wg=0, guess=0, graph=0, **kw):
     """GPU context and oracle on the same discretisation; wg selects the
     GPU's stage-solve form (0: one kernel per GMRES step, 1: one workgroup
     per solve), guess whether the linear sweeps' stage solves start from the
-    neighbouring step's solution (pa_config.lin_guess)."""
+    neighbouring step's solution (pa_config.lin_guess), graph whether the
+    GMRES iterations are replayed from captured graphs (pa_config.graph)."""
     pa, O = libs
-    g = pa.Solver(**dict(kw, wg_solve=wg, lin_guess=guess, **(gpu_kw or {})))
+    g = pa.Solver(**dict(kw, wg_solve=wg, lin_guess=guess, graph=graph, **(gpu_kw or {})))
     o = O.Oracle(**dict(kw, **(orc_kw or {})))
     g.set_params(MU)
     o.set_params(MU)
@@ -144,10 +145,11 @@ def test_blockinv_inverts_diagonal_blocks(libs, p):
         assert np.abs(D @ inv[K] - eye).max() <= 1e-11
 
 
-@pytest.mark.parametrize("wg", [0, 1])
+@pytest.mark.parametrize("wg,graph", [(0, 0), (1, 0), (0, 1)], ids=["kernels", "workgroup", "graph"])
 @pytest.mark.parametrize("tr", [False, True])
-def test_stage_solve_parity(libs, tr, wg):
-    g, o = make_pair(libs, Nr=3, Nth=8, p=2, Nt=2, gpu_kw=dict(lin_rtol=1e-13), orc_kw=dict(lin_solver=0), wg=wg)
+def test_stage_solve_parity(libs, tr, wg, graph):
+    g, o = make_pair(libs, Nr=3, Nth=8, p=2, Nt=2, gpu_kw=dict(lin_rtol=1e-13), orc_kw=dict(lin_solver=0), wg=wg,
+                     graph=graph)
     u = o.freestream(inputs.perturbation(o.Nu, seed=18, sigma=1e-2))
     J = o.jacobian(1, 2, u)
     c = 0.5 * 0.4358665215084590
@@ -189,10 +191,11 @@ TIGHT_G = dict(lin_rtol=1e-13, newton_atol=1e-12)
 TIGHT_O = dict(lin_solver=0, newton_atol=1e-12)
 
 
-@pytest.fixture(scope="module", params=[(0, 0), (1, 0), (0, 1)], ids=["kernels", "workgroup", "guess"])
+@pytest.fixture(scope="module", params=[(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)],
+                ids=["kernels", "workgroup", "guess", "graph"])
 def period_pair(libs, request):
-    wg, guess = request.param
-    g, o = make_pair(libs, gpu_kw=TIGHT_G, orc_kw=TIGHT_O, Nr=2, Nth=6, p=2, Nt=8, wg=wg, guess=guess)
+    wg, guess, graph = request.param
+    g, o = make_pair(libs, gpu_kw=TIGHT_G, orc_kw=TIGHT_O, Nr=2, Nth=6, p=2, Nt=8, wg=wg, guess=guess, graph=graph)
     pert = inputs.perturbation(g.Nu, seed=1)
     g.set_freestream(pert)
     u0 = o.freestream(pert)
@@ -232,12 +235,13 @@ def test_tangent_and_adjoint_sweep_parity(period_pair):
         assert rel(gg, go) <= 1e-10
 
 
-@pytest.mark.parametrize("wg,guess", [(0, 0), (1, 0), (0, 1)])
-def test_shoot_and_periodic_gradient_parity(libs, wg, guess):
+@pytest.mark.parametrize("wg,guess,graph", [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)],
+                         ids=["kernels", "workgroup", "guess", "graph"])
+def test_shoot_and_periodic_gradient_parity(libs, wg, guess, graph):
     """Alg. 4 end to end at the plain-path bar: shooting to 1e-12 on both
     sides from the same start, then both QoIs' periodic adjoint gradients and
     the direct gradients (oracle: exact stage solves)."""
-    g, o = make_pair(libs, gpu_kw=TIGHT_G, orc_kw=TIGHT_O, Nr=2, Nth=6, p=1, Nt=4, wg=wg, guess=guess)
+    g, o = make_pair(libs, gpu_kw=TIGHT_G, orc_kw=TIGHT_O, Nr=2, Nth=6, p=1, Nt=4, wg=wg, guess=guess, graph=graph)
     pert = inputs.perturbation(g.Nu, seed=1)
     g.set_freestream(pert)
     rep = g.shoot(tol=1e-12, eta=1e-12, maxit=20)

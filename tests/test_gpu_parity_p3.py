@@ -25,16 +25,18 @@ def rel(a, b):
     return np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
 
 
-@pytest.fixture(scope="module", params=[(0, 0), (1, 0), (0, 1)], ids=["kernels", "workgroup", "guess"])
+@pytest.fixture(scope="module", params=[(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)],
+                ids=["kernels", "workgroup", "guess", "graph"])
 def pair(request):
     """wg_solve 0: the several-system applies k_ahat_tr_m / k_ahat_fwd_m
     and the GMRES vector kernels; 1: one workgroup per system and solve;
     guess: the linear sweeps start each stage solve from the neighbouring
-    step's solution"""
+    step's solution; graph: the GMRES iterations replayed from captured
+    graphs"""
     from paper_1512_00616_amd import pa
     from oracle.oracle import Oracle
-    wg, guess = request.param
-    g = pa.Solver(lin_rtol=1e-13, newton_atol=1e-12, wg_solve=wg, lin_guess=guess, **KW)
+    wg, guess, graph = request.param
+    g = pa.Solver(lin_rtol=1e-13, newton_atol=1e-12, wg_solve=wg, lin_guess=guess, graph=graph, **KW)
     o = Oracle(lin_solver=1, lin_rtol=1e-13, newton_atol=1e-12, **KW)
     g.set_params(MU)
     o.set_params(MU)
