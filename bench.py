@@ -36,13 +36,15 @@ Extra sections (--sections, comma-separated, or 'all'): 'tiles' (forward
 apply tile timings), 'mixed' (the step with FP32 and BF16 operator copies),
 'batched' (instances on concurrent contexts), 'learned' (the learned warm
 start and the combined learned + mixed-precision + block-Krylov form), 'ttg'
-(the time to gradient on the 8x24 p=1 workload with a block-Krylov adjoint),
+(the time to gradient on the 8x24 p=1 workload, compared with a
+block-Krylov adjoint, one-workgroup stage solves and graph replay),
 'ttg32' (the time to gradient on the 32x96 p=3 workload, shooting from
 coarse orbits prolonged 8x24 p=1 -> 16x48 p=2 -> 32x96 p=3; several
 minutes), 'batched' (32 instances on the 16x48 p=2 workload with five
 right-hand sides each, by default), 'oracle-sweeps' (the oracle's sweeps on
 the 8x24 workload on 1 and all host threads).  --solver-comparison runs only the shooting-solver comparison;
---spmv-only runs only the isolated applies used for hardware counters.
+--spmv-only runs only the isolated applies used for hardware counters;
+--ttg-only [--graph 1] only the plain 8x24 time to gradient (for profiling).
 
 Prints progress on stderr and one JSON line on stdout.  --gpus N > 1 is
 refused: the benchmark measures one GPU.
@@ -196,6 +198,25 @@ def time_to_gradient(pa, mu):
                                "dJdmu_rel_diff": float(np.abs(dJk - dJ).max() / np.abs(dJ).max())},
             "graph_form": {"seconds": th, "newton": hrep.newton_its, "tangent_sweeps": hrep.krylov_its,
                            "dJdmu_bitwise_equal": bool(np.array_equal(dJh, dJ))}}
+
+
+def ttg_only(pa, mu, graph):
+    """The plain Alg. 4 run of time_to_gradient alone (8x24 p=1, 20 steps;
+    graph = pa_config.graph), with its counts."""
+    work = inputs.WORKLOADS["circle-8x24-p1-nt20"]
+    s = pa.Solver(gmres_restart=30, lin_rtol=1e-10, newton_atol=1e-10, max_krylov=100, graph=graph, **work,
+                  **inputs.PHYSICS)
+    s.set_params(mu)
+    s.set_freestream(inputs.perturbation(s.Nu, seed=1))
+    t0 = time.perf_counter()
+    rep = s.shoot(tol=1e-8, eta=1e-3, maxit=30)
+    q, dJ, arep = s.adjoint_gradient(rtol=1e-8)
+    t = time.perf_counter() - t0
+    s.close()
+    return {"workload": "circle-8x24-p1-nt20", "graph": graph, "seconds": t, "newton": rep.newton_its,
+            "tangent_sweeps": rep.krylov_its, "shoot_stage_gmres": rep.stage_gmres_its,
+            "adjoint_stage_gmres": arep.stage_gmres_its, "adjoint_krylov": list(arep.krylov_its),
+            "dJdmu": dJ.tolist()}
 
 
 def solver_comparison(pa, mu, descent_maxit=150):
@@ -530,6 +551,10 @@ def main():
                     help="periodic orbits that train the warm start on the 8x24 p=1 workload (section 'learned')")
     ap.add_argument("--learned-test", type=int, default=2, help="held-out parameter draws of the warm-start test")
     ap.add_argument("--learned-modes", type=int, default=16, help="POD modes of the warm-start model")
+    ap.add_argument("--ttg-only", action="store_true",
+                    help="only the plain Alg. 4 on the 8x24 p=1 workload (for profiling), then exit")
+    ap.add_argument("--graph", type=int, default=0, choices=(0, 1),
+                    help="with --ttg-only: replay the stage-GMRES iterations from captured graphs")
     ap.add_argument("--spmv-only", action="store_true",
                     help="short run for hardware counters: a 3-stage period on the 32x96 p=3 mesh, then timed "
                          "launches of the preconditioned stage operator and of a plain copy")
@@ -557,6 +582,9 @@ def main():
         return 0
     if args.spmv_only:
         print(json.dumps(spmv_only(pa, work)), flush=True)
+        return 0
+    if args.ttg_only:
+        print(json.dumps(ttg_only(pa, mu, args.graph)), flush=True)
         return 0
 
     out, dJ64 = run_step(pa, name, work, mu, args, pa.PREC_FP64)

@@ -113,8 +113,10 @@ typedef struct pa_config {
      * systems) are captured once per context as HIP graphs and replayed;
      * the applies then read the stage operator's address from a device slot
      * set before each solve.  The same kernels in the same order: results
-     * are bitwise equal to graph = 0.  It pays where launch costs dominate
-     * (small meshes); the sampled kernel times of pa_kernel_time do not
+     * are bitwise equal to graph = 0.  It removes the host's cost per
+     * launch, not the kernels' own durations (on the 8x24 p=1 mesh, where
+     * the GPU is busy most of the time, it changes the time to gradient by
+     * a few percent); the sampled kernel times of pa_kernel_time do not
      * cover replayed launches.  Needs gmres_restart a multiple of 5, FP64
      * precision and wg_solve = 0 (else PA_EINVAL at pa_create), and a
      * stream that can be captured (not the legacy null stream).
