@@ -20,8 +20,9 @@ at least one step is timed) and the warm-up steps likewise within
 --warmup-budget-s.  The JSON line reports the steps actually run.
 
 The roofline object names the stage-operator apply with the largest total
-time over the timed steps (HIP events on the library stream, every 8th
-launch bracketed); the other applies and the stage-GMRES vector kernels are
+time over the timed steps (HIP events on the library stream that every 8th
+launch records at its kernel's start and end); the other applies and the
+stage-GMRES vector kernels are
 reported beside it.  The oracle is timed on the host on a bounded sample
 (one residual, one Jacobian, one stage solve at the same size) and composed
 with the step's counts.

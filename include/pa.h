@@ -481,9 +481,15 @@ enum {
     PA_K_GMUPD = 10,    /* stage GMRES: final sums, Givens update and next basis vector */
     PA_K_COUNT = 11
 };
-/* when on, every 8th launch of each listed kernel is bracketed by HIP events
- * on the library's stream; pa_kernel_time returns the launch count since
- * timing was switched on and the sampled mean duration times that count */
+/* when on, every 8th launch of each listed kernel carries a pair of HIP
+ * events that the launch itself records (hipExtLaunchKernelGGL) at the
+ * kernel's start and end on the library's stream, so a sample is the
+ * kernel's execution time without the dispatch latency ahead of it
+ * (PA_K_BLOCKINV: from the start of the block-factor kernel to the end of
+ * the operator formation that follows it); pa_kernel_time returns the
+ * launch count since timing was switched on and the sampled mean duration
+ * times that count.  Launches replayed from graphs (pa_config.graph) are
+ * not counted. */
 pa_status pa_set_timing(pa_ctx* ctx, int32_t on);
 pa_status pa_kernel_time(pa_ctx* ctx, int32_t kernel, double* total_ms, int64_t* launches);
 /* of those launches, the stage-operator applies (PA_K_SPMV, PA_K_SPMV_T,

@@ -18,6 +18,7 @@
 #include "pa_linalg.hpp"
 #include "pa_learn.hpp"
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -952,11 +953,15 @@ struct Solver final : pa_ctx {
         kvec[PA_K_MDOT] += its * (its + 3) / 2;    // sum over j < its of (j + 2)
         kvec[PA_K_GMUPD] += its * (its + 5) / 2;   // sum over j < its of (j + 3)
     }
-    void tstart(int k, hipEvent_t* out)
+    // Every TSTRIDE-th launch of a kind (k >= 0) is sampled: its start and
+    // stop events are recorded by the launch itself (hipExtLaunchKernelGGL),
+    // so they bracket the kernel's execution and not the dispatch latency
+    // ahead of it.  Unsampled launches are plain launches.
+    bool tsample(int k, hipEvent_t* a, hipEvent_t* b)
     {
-        *out = nullptr;
-        if (!timing) return;
-        if ((tseen[k]++ % TSTRIDE) != 0) return;
+        *a = *b = nullptr;
+        if (!timing || k < 0) return false;
+        if ((tseen[k]++ % TSTRIDE) != 0) return false;
         if (evused >= 4096) harvest();   // every recorded pair is closed here
         if (evused == evpool.size()) {
             EvPair e;
@@ -964,16 +969,28 @@ struct Solver final : pa_ctx {
             HIPCHK(hipEventCreate(&e.b));
             evpool.push_back(e);
         }
-        EvPair& e = evpool[evused];
+        EvPair& e = evpool[evused++];
         e.k = k;
-        HIPCHK(hipEventRecord(e.a, st));
-        *out = e.b;
-        ++evused;
+        *a = e.a;
+        *b = e.b;
+        return true;
     }
-    void tstop(hipEvent_t b)
+    // kern<<<g, b, sm, st>>>(args...), with the kernel's start and/or stop
+    // recorded into ea / eb when given
+    template <class... Pm, class... Ar>
+    void klaunch_ev(hipEvent_t ea, hipEvent_t eb, void (*kern)(Pm...), dim3 g, dim3 b, uint32_t sm, Ar... args)
     {
-        if (!timing || !b) return;
-        HIPCHK(hipEventRecord(b, st));
+        if (ea || eb) hipExtLaunchKernelGGL(kern, g, b, sm, st, ea, eb, 0, static_cast<Pm>(args)...);
+        else kern<<<g, b, sm, st>>>(static_cast<Pm>(args)...);
+        LAUNCHCHK();
+    }
+    // the same, sampled for timing as kind k (k < 0: never)
+    template <class... Pm, class... Ar>
+    void klaunch(int k, void (*kern)(Pm...), dim3 g, dim3 b, uint32_t sm, Ar... args)
+    {
+        hipEvent_t ea, eb;
+        tsample(k, &ea, &eb);
+        klaunch_ev(ea, eb, kern, g, b, sm, args...);
     }
     void harvest()
     {
@@ -1052,11 +1069,8 @@ struct Solver final : pa_ctx {
     // ---------------------------------------------------------------- kernels
     void residual(int n, int i, const double* u, double* r)
     {
-        hipEvent_t e;
-        tstart(PA_K_RESIDUAL, &e);
-        k_residual<P, double><<<Ne, 64, 0, st>>>(dm, dref, ph, motion(stage_time(n, i)), u, gbs(n, i), nullptr, r, Nu);
-        LAUNCHCHK();
-        tstop(e);
+        klaunch(PA_K_RESIDUAL, k_residual<P, double>, dim3(Ne), dim3(64), 0, dm, dref, ph, motion(stage_time(n, i)), u,
+                gbs(n, i), nullptr, r, Nu);
     }
     void dr_dmu(int n, int i, const double* u, double* out)
     {
@@ -1066,11 +1080,8 @@ struct Solver final : pa_ctx {
     }
     void jacobian(int n, int i, const double* u, double* J)
     {
-        hipEvent_t e;
-        tstart(PA_K_JACOBIAN, &e);
-        k_jacobian<P><<<Ne, 320, sizeof(JacSmem<P>), st>>>(dm, dref, ph, motion(stage_time(n, i)), u, gbs(n, i), J);
-        LAUNCHCHK();
-        tstop(e);
+        klaunch(PA_K_JACOBIAN, k_jacobian<P>, dim3(Ne), dim3(320), (uint32_t)sizeof(JacSmem<P>), dm, dref, ph,
+                motion(stage_time(n, i)), u, gbs(n, i), J);
     }
     // y = alpha M x + beta op(J) x
     void bsr(const double* J, double alpha, double beta, int tr, const double* x, double* y, const int* skip = nullptr)
@@ -1080,19 +1091,21 @@ struct Solver final : pa_ctx {
     }
     // forward FP64 apply with the tile shape q (chunks per task; 0 = default)
     int fwd_q = 0;
-    // (Ahp: optional device slot holding the operator's address, read by the kernel)
+    // (Ahp: optional device slot holding the operator's address, read by
+    // the kernel; k: timing kind, < 0 for none)
     void launch_fwd(int q, const double* Ah, const double* x, double* y, const int* skip,
-                    const double* const* Ahp = nullptr)
+                    const double* const* Ahp = nullptr, int k = -1)
     {
+        const dim3 g(Ne), b(64);
         if (q == 1 && ahat_fwd_valid<NP, double>(1))
-            k_ahat_fwd<NP, double, double, 1><<<Ne, 64, 0, st>>>(Ne, nb4f, Ah, x, y, skip, Ahp);
+            klaunch(k, k_ahat_fwd<NP, double, double, 1>, g, b, 0, Ne, nb4f, Ah, x, y, skip, Ahp);
         else if (q == 2 && ahat_fwd_valid<NP, double>(2))
-            k_ahat_fwd<NP, double, double, 2><<<Ne, 64, 0, st>>>(Ne, nb4f, Ah, x, y, skip, Ahp);
+            klaunch(k, k_ahat_fwd<NP, double, double, 2>, g, b, 0, Ne, nb4f, Ah, x, y, skip, Ahp);
         else if (q == 4 && ahat_fwd_valid<NP, double>(4)) {
             if constexpr (ahat_fwd_valid<NP, double>(4))
-                k_ahat_fwd<NP, double, double, 4><<<Ne, 64, 0, st>>>(Ne, nb4f, Ah, x, y, skip, Ahp);
+                klaunch(k, k_ahat_fwd<NP, double, double, 4>, g, b, 0, Ne, nb4f, Ah, x, y, skip, Ahp);
         } else
-            k_ahat_fwd<NP, double, double><<<Ne, 64, 0, st>>>(Ne, nb4f, Ah, x, y, skip, Ahp);
+            klaunch(k, k_ahat_fwd<NP, double, double>, g, b, 0, Ne, nb4f, Ah, x, y, skip, Ahp);
     }
     // autotune (pa_config.autotune): time each valid tile shape on the first
     // stored stage operator (after its formation, 10 launches each, HIP
@@ -1138,42 +1151,35 @@ struct Solver final : pa_ctx {
     }
     void ahat(const double* Ah, int tr, const double* x, double* y, const int* skip = nullptr)
     {
-        hipEvent_t e;
-        tstart(tr ? PA_K_SPMV_T : PA_K_SPMV, &e);
-        if (tr) k_ahat_tr<NP, double, double><<<Ne, 64, 0, st>>>(Ne, nb4t, Ah, x, y, skip);
-        else launch_fwd(fwd_q, Ah, x, y, skip);
-        LAUNCHCHK();
-        tstop(e);
+        const double* const* noslot = nullptr;
+        if (tr) klaunch(PA_K_SPMV_T, k_ahat_tr<NP, double, double>, dim3(Ne), dim3(64), 0, Ne, nb4t, Ah, x, y, skip, noslot);
+        else launch_fwd(fwd_q, Ah, x, y, skip, nullptr, PA_K_SPMV);
     }
     void ahat_lo(const void* Al, int tr, const float* x, float* y, const int* skip = nullptr)
     {
-        hipEvent_t e;
-        tstart(PA_K_SPMV_LO, &e);
+        const int k = PA_K_SPMV_LO;
+        const dim3 g(Ne), b(64);
+        const float* const* nof = nullptr;
+        const bf16_t* const* nob = nullptr;
         if (tr) {
             if (pmode == PA_PREC_FP32)
-                k_ahat_tr<NP, float, float><<<Ne, 64, 0, st>>>(Ne, nb4t, (const float*)Al, x, y, skip);
+                klaunch(k, k_ahat_tr<NP, float, float>, g, b, 0, Ne, nb4t, (const float*)Al, x, y, skip, nof);
             else if constexpr (B % 8 == 0)
-                k_ahat_tr<NP, bf16_t, float><<<Ne, 64, 0, st>>>(Ne, nb4t, (const bf16_t*)Al, x, y, skip);
+                klaunch(k, k_ahat_tr<NP, bf16_t, float>, g, b, 0, Ne, nb4t, (const bf16_t*)Al, x, y, skip, nob);
             else   // 16-byte BF16 chunks would straddle rows
-                k_ahat_apply_lo<NP, bf16_t><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, (const bf16_t*)Al, x, y, tr, skip);
+                klaunch(k, k_ahat_apply_lo<NP, bf16_t>, g, b, 0, Ne, dm.enb, dm.etw, (const bf16_t*)Al, x, y, tr, skip);
         } else {
             if (pmode == PA_PREC_FP32)
-                k_ahat_fwd<NP, float, float><<<Ne, 64, 0, st>>>(Ne, nb4f, (const float*)Al, x, y, skip);
+                klaunch(k, k_ahat_fwd<NP, float, float>, g, b, 0, Ne, nb4f, (const float*)Al, x, y, skip, nof);
             else if constexpr (B % 8 == 0)
-                k_ahat_fwd<NP, bf16_t, float><<<Ne, 64, 0, st>>>(Ne, nb4f, (const bf16_t*)Al, x, y, skip);
+                klaunch(k, k_ahat_fwd<NP, bf16_t, float>, g, b, 0, Ne, nb4f, (const bf16_t*)Al, x, y, skip, nob);
             else   // 16-byte BF16 chunks would straddle rows
-                k_ahat_apply_lo<NP, bf16_t><<<Ne, 64, 0, st>>>(Ne, dm.enb, dm.etw, (const bf16_t*)Al, x, y, tr, skip);
+                klaunch(k, k_ahat_apply_lo<NP, bf16_t>, g, b, 0, Ne, dm.enb, dm.etw, (const bf16_t*)Al, x, y, tr, skip);
         }
-        LAUNCHCHK();
-        tstop(e);
     }
     void prec(const double* Ai, int tr, const double* x, double* z, const int* skip = nullptr)
     {
-        hipEvent_t e;
-        tstart(PA_K_PRECOND, &e);
-        k_block_apply<NP><<<Ne, 64, 0, st>>>(Ne, Ai, x, z, tr, skip);
-        LAUNCHCHK();
-        tstop(e);
+        klaunch(PA_K_PRECOND, k_block_apply<NP>, dim3(Ne), dim3(64), 0, Ne, Ai, x, z, tr, skip);
     }
     void axpby(double a, const double* x, double b, double* y)
     {
@@ -1478,15 +1484,10 @@ struct Solver final : pa_ctx {
                     double* vj = V + (int64_t)j * Nu;
                     ahat(op.Ah, tr, vj, w, skip);
                     // one classical Gram-Schmidt pass; the cycle closes on cancellation
-                    hipEvent_t e;
-                    tstart(PA_K_MDOT, &e);
-                    k_mdot_part<<<dim3(nb, mdot_chunks(j + 2)), MD_THREADS, 0, st>>>(V, Nu, j + 1, 1, w, Nu, part,
-                                                                                     gms);
-                    tstop(e);
-                    tstart(PA_K_GMUPD, &e);
-                    k_gm_upd<<<(unsigned)gm_upd_blocks(Nu), GU_THREADS, 0, st>>>(V, Nu, j, m, w, Nu, part, nb, gms);
-                    tstop(e);
-                    LAUNCHCHK();
+                    klaunch(PA_K_MDOT, k_mdot_part<double>, dim3(nb, mdot_chunks(j + 2)), dim3(MD_THREADS), 0, V, Nu,
+                            j + 1, 1, w, Nu, part, gms, 0, 0, 0);
+                    klaunch(PA_K_GMUPD, k_gm_upd<double>, dim3((unsigned)gm_upd_blocks(Nu)), dim3(GU_THREADS), 0, V,
+                            Nu, j, m, w, Nu, part, nb, gms, 0, 0, 0);
                 }
                 ++launched;
                 if ((j + 1) % GM_CHECK == 0 && j < m - 1) {
@@ -1894,20 +1895,17 @@ struct Solver final : pa_ctx {
     void ahat_m(const double* Ah, int tr, int R, const double* x, int64_t sx, double* y, int64_t sy,
                 const GmState* skip = nullptr, const double* const* Ahp = nullptr)
     {
-        hipEvent_t e = nullptr;
-        if (!Ahp) tstart(tr ? PA_K_SPMV_TM : PA_K_SPMV_M, &e);
+        const int k = Ahp ? -1 : tr ? PA_K_SPMV_TM : PA_K_SPMV_M;
         switch (R) {
 #define PA_AHAT_M(RR)                                                                                         \
     case RR:                                                                                                  \
-        if (tr) k_ahat_tr_m<NP, RR><<<Ne, 64, 0, st>>>(Ne, nb4t, Ah, x, sx, y, sy, skip, Ahp);                \
-        else k_ahat_fwd_m<NP, RR><<<Ne, 64, 0, st>>>(Ne, nb4f, Ah, x, sx, y, sy, skip, Ahp);                  \
+        if (tr) klaunch(k, k_ahat_tr_m<NP, RR>, dim3(Ne), dim3(64), 0, Ne, nb4t, Ah, x, sx, y, sy, skip, Ahp); \
+        else klaunch(k, k_ahat_fwd_m<NP, RR>, dim3(Ne), dim3(64), 0, Ne, nb4f, Ah, x, sx, y, sy, skip, Ahp);   \
         break;
             PA_AHAT_M(1) PA_AHAT_M(2) PA_AHAT_M(3) PA_AHAT_M(4) PA_AHAT_M(5) PA_AHAT_M(6) PA_AHAT_M(7) PA_AHAT_M(8)
 #undef PA_AHAT_M
         default: raise(PA_EINVAL, "%d right-hand sides per apply (1..%d)", R, GM_RMAX);
         }
-        LAUNCHCHK();
-        tstop(e);
     }
     void poll_multi(int R)
     {
@@ -1981,16 +1979,10 @@ struct Solver final : pa_ctx {
                     if (j % GM_CHECK == 0) HIPCHK(hipGraphLaunch(gm_graph(tr, R, j / GM_CHECK), st));
                 } else {
                     ahat_m(op.Ah, tr, R, Vm + (int64_t)j * Nu, sV, wm, Nu, gmsm);
-                    hipEvent_t e;
-                    tstart(PA_K_MDOT, &e);
-                    k_mdot_part<<<dim3(nb, mdot_chunks(j + 2) * R), MD_THREADS, 0, st>>>(Vm, Nu, j + 1, 1, wm, Nu,
-                                                                                         partm, gmsm, sV, Nu, sP);
-                    tstop(e);
-                    tstart(PA_K_GMUPD, &e);
-                    k_gm_upd<<<dim3((unsigned)gm_upd_blocks(Nu), R), GU_THREADS, 0, st>>>(Vm, Nu, j, m, wm, Nu, partm,
-                                                                                          nb, gmsm, sV, Nu, sP);
-                    tstop(e);
-                    LAUNCHCHK();
+                    klaunch(PA_K_MDOT, k_mdot_part<double>, dim3(nb, mdot_chunks(j + 2) * R), dim3(MD_THREADS), 0, Vm,
+                            Nu, j + 1, 1, wm, Nu, partm, gmsm, sV, Nu, sP);
+                    klaunch(PA_K_GMUPD, k_gm_upd<double>, dim3((unsigned)gm_upd_blocks(Nu), R), dim3(GU_THREADS), 0, Vm,
+                            Nu, j, m, wm, Nu, partm, nb, gmsm, sV, Nu, sP);
                 }
                 if ((j + 1) % GM_CHECK == 0 && j < m - 1) {
                     if (pending >= 0) {
@@ -2322,12 +2314,13 @@ struct Solver final : pa_ctx {
     }
     void prepare_ops(const double* J, double c, int s)
     {
-        hipEvent_t e;
-        tstart(PA_K_BLOCKINV, &e);
-        k_blockprep<NP><<<Ne, 64, 0, st>>>(Ne, dm.area, dmh, J, c, tPd + (int64_t)s * Isz, tAi + (int64_t)s * Isz,
-                                          dstatus);
-        k_form_ahat_mfma<NP><<<Ne * 3, 64, 0, st>>>(Ne, dm.enb, J, c, tAi + (int64_t)s * Isz, tAh + (int64_t)s * 3 * Isz);
-        LAUNCHCHK();
+        // timed from the start of the first kernel to the end of the second
+        hipEvent_t ea, eb;
+        tsample(PA_K_BLOCKINV, &ea, &eb);
+        klaunch_ev(ea, nullptr, k_blockprep<NP>, dim3(Ne), dim3(64), 0, Ne, dm.area, dmh, J, c, tPd + (int64_t)s * Isz,
+                   tAi + (int64_t)s * Isz, dstatus);
+        klaunch_ev(nullptr, eb, k_form_ahat_mfma<NP>, dim3(Ne * 3), dim3(64), 0, Ne, dm.enb, J, c,
+                   tAi + (int64_t)s * Isz, tAh + (int64_t)s * 3 * Isz);
         if (cfg.autotune && !fwd_tuned) tune_fwd(tAh + (int64_t)s * 3 * Isz);
         const int64_t n3 = 3 * Isz;
         if (pmode == PA_PREC_FP32)
@@ -2335,7 +2328,6 @@ struct Solver final : pa_ctx {
         else if (pmode == PA_PREC_BF16)
             k_to_lo<bf16_t><<<grid1(n3), 256, 0, st>>>(tAh + s * n3, (bf16_t*)tAl + s * n3, n3);
         LAUNCHCHK();
-        tstop(e);
     }
     double* stK(int s) { return tk + (int64_t)s * Nu; }
     double* stU(int s) { return tui + (int64_t)s * Nu; }
