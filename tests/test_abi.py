@@ -69,3 +69,36 @@ def test_create_rejects_configurations_before_touching_the_device():
             pa.Solver(**dict(base, **bad))
         assert e.value.code == pa.PA_EINVAL, bad
     assert pa.default_config().graph == 0
+
+
+def test_binding_structs_match_the_header_layout(tmp_path):
+    # every struct the binding mirrors has the size and field offsets that
+    # the C compiler gives the header's declaration
+    import ctypes as C
+    import shutil
+    import subprocess
+    import pytest
+    from paper_1512_00616_amd import pa
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = [pa.pa_config, pa.pa_shoot_report, pa.pa_adjoint_report, pa.pa_batch_opts, pa.pa_opt_opts,
+               pa.pa_opt_report, pa.pa_ws_opts]
+    lines = ['#include <stddef.h>', '#include <stdio.h>', '#include "pa.h"', 'int main(void) {']
+    for S in structs:
+        n = S.__name__
+        lines.append('printf("%s size %%zu\\n", sizeof(%s));' % (n, n))
+        for f in S._fields_:
+            lines.append('printf("%s %s %%zu\\n", offsetof(%s, %s));' % (n, f[0], n, f[0]))
+    lines += ['return 0;', '}']
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run([cc, "-std=c11", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for S in structs:
+        n = S.__name__
+        assert got[(n, "size")] == C.sizeof(S), n
+        for f in S._fields_:
+            assert got[(n, f[0])] == getattr(S, f[0]).offset, (n, f[0])
