@@ -687,12 +687,26 @@ __global__ void __launch_bounds__(64) k_blockprep(int Ne, const double* __restri
     const double* src = J + (int64_t)K * 4 * BB;
     const double s2 = 2.0 * area[K];
     double* pd = Pd + (int64_t)K * BB;
-    for (int q = lane; q < BB; q += 64) {
-        const int i = q / B, j = q % B;
-        const double mm = ((i & 3) == (j & 3)) ? s2 * mh[(i >> 2) * NP + (j >> 2)] : 0.0;
-        const double v = mm - c * src[q];
-        t[i][j] = v;
-        pd[q] = v;
+    // every load (the Jacobian block's and the mass entries') issued before
+    // the first use
+    constexpr int NL = (BB + 63) / 64;
+    double sv[NL], mv[NL];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+        const int q = lane + 64 * u < BB ? lane + 64 * u : BB - 1;
+        sv[u] = src[q];
+        mv[u] = mh[(q / B >> 2) * NP + (q % B >> 2)];
+    }
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+        const int q = lane + 64 * u;
+        if (q < BB) {
+            const int i = q / B, j = q % B;
+            const double mm = ((i & 3) == (j & 3)) ? s2 * mv[u] : 0.0;
+            const double v = mm - c * sv[u];
+            t[i][j] = v;
+            pd[q] = v;
+        }
     }
     __syncthreads();
     const int row = lane < B ? lane : B - 1;
@@ -982,9 +996,26 @@ __global__ void __launch_bounds__(64) k_form_ahat_mfma(int Ne, const int32_t* __
     }
     const double* js = J + ((int64_t)K * 4 + 1 + f) * BB;
     const double* ps = Pinv + (int64_t)nb * BB;
-    for (int t = lane; t < BB; t += 64) {
-        sj[t / B][t % B] = -c * js[t];
-        sp[t / B][t % B] = ps[t];
+    // both blocks as double2 (B is even: a pair never straddles rows), every
+    // load issued before the first LDS store
+    constexpr int H2 = BB / 2, NL = (H2 + 63) / 64;
+    double2 vj[NL], vp[NL];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+        const int t2 = lane + 64 * u < H2 ? lane + 64 * u : H2 - 1;
+        vj[u] = reinterpret_cast<const double2*>(js)[t2];
+        vp[u] = reinterpret_cast<const double2*>(ps)[t2];
+    }
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+        const int t2 = lane + 64 * u;
+        if (t2 < H2) {
+            const int i = 2 * t2 / B, j = 2 * t2 % B;
+            sj[i][j] = -c * vj[u].x;
+            sj[i][j + 1] = -c * vj[u].y;
+            sp[i][j] = vp[u].x;
+            sp[i][j + 1] = vp[u].y;
+        }
     }
     __syncthreads();
     const int li = lane % 16, lk = lane / 16;
