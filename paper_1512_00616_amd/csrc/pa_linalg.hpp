@@ -91,13 +91,22 @@ __global__ void __launch_bounds__(64) k_block_apply(int Ne, const double* __rest
     if (skip && *skip) return;
     const int K = blockIdx.x, lane = threadIdx.x;
     const double2* blk2 = reinterpret_cast<const double2*>(Ainv + (int64_t)K * BB);
-    for (int t = lane; t < BB / 2; t += 64) {
-        double2 v = blk2[t];
-        int e = 2 * t;
-        sblk[e / B][e % B] = v.x;
-        sblk[(e + 1) / B][(e + 1) % B] = v.y;
+    // every load issued before the first LDS store
+    constexpr int H2 = BB / 2, NL = (H2 + 63) / 64;
+    double2 v[NL];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) v[u] = blk2[lane + 64 * u < H2 ? lane + 64 * u : H2 - 1];
+    const double xv = x[(int64_t)K * B + (lane < B ? lane : 0)];
+#pragma unroll
+    for (int u = 0; u < NL; ++u) {
+        const int t = lane + 64 * u;
+        if (t < H2) {
+            const int e = 2 * t;
+            sblk[e / B][e % B] = v[u].x;
+            sblk[(e + 1) / B][(e + 1) % B] = v[u].y;
+        }
     }
-    if (lane < B) sx[lane] = x[(int64_t)K * B + lane];
+    if (lane < B) sx[lane] = xv;
     __syncthreads();
     if (lane < B) {
         double a = 0.0;
