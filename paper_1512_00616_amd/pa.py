@@ -208,8 +208,30 @@ def lib():
 def _ptr(a):
     if a is None:
         return None
-    assert a.flags["C_CONTIGUOUS"]
+    if not a.flags["C_CONTIGUOUS"]:
+        raise ValueError("array arguments must be C-contiguous")
     return a.ctypes.data_as(C.c_void_p)
+
+
+def _sized(a, n, dtype, what):
+    """a as a contiguous array of exactly n entries of dtype (the library
+    reads and writes that many through the pointer)"""
+    a = np.ascontiguousarray(a, dtype=dtype)
+    if a.size != n:
+        raise ValueError("%s: expected %d entries, got %d" % (what, n, a.size))
+    return a
+
+
+def _square(a, what):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if a.ndim != 2 or a.shape[0] != a.shape[1]:
+        raise ValueError("%s: expected a square matrix, got shape %s" % (what, a.shape))
+    return a
+
+
+def mlp_param_count(n_in, width, n_out):
+    """entries of the perceptron's flat parameter vector [W1 b1 .. W4 b4]"""
+    return n_in * width + width + 2 * (width * width + width) + width * n_out + n_out
 
 
 def default_config(**kw):
@@ -257,9 +279,11 @@ def batch_gradients(mu, workers=4, shoot_maxit=30, shoot_tol=1e-8, shoot_eta=1e-
 def dbg_mlp(params, X, T, width):
     """One device forward/backward pass of the warm-start perceptron
     (X [in][batch], T [out][batch]); returns (loss, grads)."""
-    params = np.ascontiguousarray(params, dtype=np.float32)
     X = np.ascontiguousarray(X, dtype=np.float32)
     T = np.ascontiguousarray(T, dtype=np.float32)
+    if X.ndim != 2 or T.ndim != 2 or X.shape[1] != T.shape[1]:
+        raise ValueError("X [in][batch] and T [out][batch] need the same batch, got %s and %s" % (X.shape, T.shape))
+    params = _sized(params, mlp_param_count(X.shape[0], width, T.shape[0]), np.float32, "params")
     grads = np.zeros_like(params)
     loss = np.zeros(1, dtype=np.float32)
     rc = lib().pa_dbg_mlp(X.shape[0], width, T.shape[0], X.shape[1], _ptr(params), _ptr(X), _ptr(T), _ptr(loss),
@@ -294,7 +318,7 @@ def mlp_grad_noalloc(n_in, width, n_out, batch, params, X, T, loss, grads, strea
 def dbg_hess_eig(H):
     """Eigenvalues (complex, by decreasing modulus) of an upper Hessenberg
     matrix by the library's host-side shifted QR (no device work)."""
-    H = np.ascontiguousarray(H, dtype=np.float64)
+    H = _square(H, "H")
     n = H.shape[0]
     re = np.zeros(n)
     im = np.zeros(n)
@@ -307,7 +331,7 @@ def dbg_hess_eig(H):
 def dbg_sym_eig(A):
     """(eigenvalues descending, eigenvectors as columns) of a symmetric
     matrix by the library's host-side cyclic Jacobi (no device work)."""
-    A = np.ascontiguousarray(A, dtype=np.float64)
+    A = _square(A, "A")
     n = A.shape[0]
     w = np.zeros(n)
     V = np.zeros((n, n))
@@ -409,9 +433,7 @@ class Solver:
             raise PaError(rc, lib().pa_last_error(self._c).decode())
 
     def _vec(self, x, n=None):
-        x = np.ascontiguousarray(x, dtype=np.float64)
-        assert x.size == (self.Nu if n is None else n)
-        return x
+        return _sized(x, self.Nu if n is None else n, np.float64, "vector")
 
     @property
     def device_bytes(self):
@@ -478,8 +500,7 @@ class Solver:
                         shoot_maxit=shoot_maxit, adj_rtol=adj_rtol)
         o.lo[:] = [float(v) for v in lo]
         o.hi[:] = [float(v) for v in hi]
-        mu = np.array(mu0, dtype=np.float64).copy()
-        assert mu.size == 3
+        mu = _sized(np.array(mu0, dtype=np.float64), 3, np.float64, "mu0")
         rep = pa_opt_report()
         rep.attach_history(maxit + 1)
         self._chk(lib().pa_optimize(self._c, C.byref(o), _ptr(mu), C.byref(rep)))
@@ -531,8 +552,7 @@ class Solver:
         return float(loss[0])
 
     def ws_predict(self, mu):
-        mu = np.ascontiguousarray(mu, dtype=np.float64)
-        self._chk(lib().pa_ws_predict(self._c, _ptr(mu)))
+        self._chk(lib().pa_ws_predict(self._c, _ptr(self._vec(mu, 3))))
 
     def ws_pod(self, kmax=128):
         """(mean deviation [Nu], modes [k][Nu], Gram eigenvalues [k])"""
@@ -549,7 +569,8 @@ class Solver:
         """a state of the discretisation `coarse` (dict of pa_config fields)
         evaluated at this context's nodes"""
         cfg = default_config(**coarse)
-        u_coarse = np.ascontiguousarray(u_coarse, dtype=np.float64)
+        n_coarse = 2 * cfg.Nr * cfg.Nth * 4 * ((cfg.p + 1) * (cfg.p + 2) // 2)
+        u_coarse = _sized(u_coarse, n_coarse, np.float64, "u_coarse")
         out = np.zeros(self.Nu)
         self._chk(lib().pa_prolong(C.byref(cfg), _ptr(u_coarse), self._c, _ptr(out)))
         return out

@@ -102,3 +102,36 @@ def test_binding_structs_match_the_header_layout(tmp_path):
         assert got[(n, "size")] == C.sizeof(S), n
         for f in S._fields_:
             assert got[(n, f[0])] == getattr(S, f[0]).offset, (n, f[0])
+
+
+def test_binding_checks_array_sizes_before_the_call():
+    # the library reads and writes a fixed number of entries through each
+    # pointer, so the binding refuses an array of another size before any
+    # library call (no context and no device needed)
+    import numpy as np
+    import pytest
+    from paper_1512_00616_amd import pa
+    s = pa.Solver.__new__(pa.Solver)
+    s._c = None
+    s.Nu, s.Ne, s.b = 48, 4, 12
+    for call in (lambda: s.set_params([0.25, 0.1]),
+                 lambda: s.set_state(np.zeros(47)),
+                 lambda: s.set_freestream(np.zeros(49)),
+                 lambda: s.ws_predict(np.zeros(4)),
+                 lambda: s.tangent_sweep(np.zeros((2, 48))),
+                 lambda: s.bsr_apply(np.zeros(4 * 4 * 144 - 1), np.zeros(48)),
+                 lambda: s.optimize([0.2, 0.1]),
+                 lambda: s.prolong_from(dict(Nr=2, Nth=6, p=1), np.zeros(2 * 2 * 6 * 4 * 3 + 1))):
+        with pytest.raises(ValueError, match="expected"):
+            call()
+    with pytest.raises(ValueError, match="C-contiguous"):
+        pa._ptr(np.zeros((4, 4))[:, 0])
+    with pytest.raises(ValueError, match="square"):
+        pa.dbg_hess_eig(np.zeros((3, 4)))
+    with pytest.raises(ValueError, match="square"):
+        pa.dbg_sym_eig(np.zeros(9))
+    X, T = np.zeros((3, 5), np.float32), np.zeros((16, 5), np.float32)
+    with pytest.raises(ValueError, match="params"):
+        pa.dbg_mlp(np.zeros(pa.mlp_param_count(3, 32, 16) - 1), X, T, 32)
+    with pytest.raises(ValueError, match="batch"):
+        pa.dbg_mlp(np.zeros(pa.mlp_param_count(3, 32, 16)), X, T[:, :4], 32)
