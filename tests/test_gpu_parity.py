@@ -235,29 +235,47 @@ def test_tangent_and_adjoint_sweep_parity(period_pair):
         assert rel(gg, go) <= 1e-10
 
 
+@pytest.fixture(scope="module")
+def oracle_alg4(libs):
+    """The oracle's side of Alg. 4 on the 2x6 p=1 Nt=4 workload, computed
+    once (it does not depend on the GPU's execution form, which the test
+    below varies): the orbit shot to 1e-12 from the perturbed free stream,
+    its QoIs, both QoIs' periodic adjoint gradients and the direct (tangent)
+    gradient, all with exact stage solves."""
+    _, O = libs
+    o = O.Oracle(Nr=2, Nth=6, p=1, Nt=4, **TIGHT_O)
+    o.set_params(MU)
+    pert = inputs.perturbation(o.Nu, seed=1)
+    us, _ = o.shoot(o.freestream(pert), tol=1e-12, eta=1e-12, maxit=20, max_krylov=300)
+    _, qo, _ = o.primal_period(us)
+    go = np.stack([o.periodic_adjoint(q, rtol=1e-13)[0] for q in (0, 1)])
+    to = o.tangent_gradient(rtol=1e-13)
+    o.close()
+    return us, qo, go, to
+
+
 @pytest.mark.parametrize("wg,guess,graph", [(0, 0, 0), (1, 0, 0), (0, 1, 0), (0, 0, 1)],
                          ids=["kernels", "workgroup", "guess", "graph"])
-def test_shoot_and_periodic_gradient_parity(libs, wg, guess, graph):
+def test_shoot_and_periodic_gradient_parity(libs, oracle_alg4, wg, guess, graph):
     """Alg. 4 end to end at the plain-path bar: shooting to 1e-12 on both
     sides from the same start, then both QoIs' periodic adjoint gradients and
     the direct gradients (oracle: exact stage solves)."""
-    g, o = make_pair(libs, gpu_kw=TIGHT_G, orc_kw=TIGHT_O, Nr=2, Nth=6, p=1, Nt=4, wg=wg, guess=guess, graph=graph)
-    pert = inputs.perturbation(g.Nu, seed=1)
-    g.set_freestream(pert)
+    pa, _ = libs
+    us, qo, go, to = oracle_alg4
+    g = pa.Solver(Nr=2, Nth=6, p=1, Nt=4, wg_solve=wg, lin_guess=guess, graph=graph, **TIGHT_G)
+    g.set_params(MU)
+    g.set_freestream(inputs.perturbation(g.Nu, seed=1))
     rep = g.shoot(tol=1e-12, eta=1e-12, maxit=20)
     assert rep.res <= 1e-12
-    us, orep = o.shoot(o.freestream(pert), tol=1e-12, eta=1e-12, maxit=20, max_krylov=300)
     assert rel(g.get_state(0), us) <= 1e-10
     qg, dJ, arep = g.adjoint_gradient(rtol=1e-13)
-    _, qo, _ = o.primal_period(us)
     assert rel(qg, qo) <= 1e-10
-    go = np.stack([o.periodic_adjoint(q, rtol=1e-13)[0] for q in (0, 1)])
     assert rel(dJ, go) <= 1e-10
     # and against the oracle's independent direct (tangent) gradient
-    to = o.tangent_gradient(rtol=1e-13)
     assert rel(dJ, to) <= 1e-10
     # the GPU direct method (three parameter tangents in the same sweeps)
     tg, its = g.tangent_gradient(rtol=1e-13)
     assert all(its > 0)
     assert rel(tg, to) <= 1e-10
     assert rel(tg, dJ) <= 1e-10
+    g.close()

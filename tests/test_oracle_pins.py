@@ -348,6 +348,38 @@ def test_adjoint_gradient_matches_central_differences(oracle_mod, tiny_periodic)
     assert np.linalg.norm(G - FD) <= 1e-6 * np.linalg.norm(FD), (G, FD)
 
 
+@pytest.mark.slow
+def test_finite_difference_error_falls_as_tau_squared_then_rises(tiny_periodic):
+    """Sec. 4.1's step sweep of the gradient verification, along one seeded
+    direction d in mu: the central-difference error of the periodic QoIs
+    against the adjoint gradient G d falls as tau^2 (truncation) to about
+    1e-10 of |G d|, then grows as tau shrinks further (the periodic solves'
+    tolerance divided by tau).  A gradient wrong by more than ~1e-9 would
+    show as a floor above the bottom of the V."""
+    o, us, _ = tiny_periodic
+    o.set_params(MU)
+    o.primal_period(us)
+    G = np.stack([o.periodic_adjoint(q, rtol=1e-13)[0] for q in (0, 1)])
+    d = np.random.default_rng(3).standard_normal(3)
+    d /= np.linalg.norm(d)
+    Gd = G @ d
+
+    def J(m):
+        o.set_params(m)
+        u, _ = o.shoot(us, tol=1e-12, eta=1e-11, maxit=20, max_krylov=300)
+        return o.primal_period(u)[1]
+
+    err = {}
+    for tau in (1e-3, 1e-4, 1e-6, 1e-9):
+        fd = (J(MU + tau * d) - J(MU - tau * d)) / (2 * tau)
+        err[tau] = np.linalg.norm(fd - Gd) / np.linalg.norm(Gd)
+    o.set_params(MU)
+    o.primal_period(us)
+    assert 50 <= err[1e-3] / err[1e-4] <= 200, err      # second order: 100
+    assert err[1e-6] <= 1e-8, err
+    assert err[1e-9] >= 10 * err[1e-6], err
+
+
 # ---------------------------------------------------------------- dense monolithic solve
 def test_trajectory_solves_the_monolithic_system(tiny_periodic):
     """The shot orbit satisfies every row of Sec. 3 eq. abs-govern-disc
