@@ -31,7 +31,7 @@ def test_hessenberg_eigenvalues_of_a_companion_matrix():
     assert np.all(np.diff(np.abs(ev)) <= 1e-12)       # by decreasing modulus
 
 
-@pytest.mark.parametrize("n,seed", [(40, 1), (7, 2), (1, 3)])
+@pytest.mark.parametrize("n,seed", [(40, 1), (7, 2), (1, 3), (200, 5)])   # 200: the Floquet count
 def test_hessenberg_eigenvalues_match_numpy(n, seed):
     g = np.random.default_rng(seed)
     H = np.triu(g.standard_normal((n, n)), -1)
@@ -52,6 +52,25 @@ def test_symmetric_eigenpairs():
     assert np.allclose(w, np.sort(np.linalg.eigvalsh(A))[::-1], rtol=0, atol=1e-11 * w[0])
     assert np.abs(V.T @ V - np.eye(30)).max() <= 1e-12
     assert np.abs(A @ V - V * w).max() <= 1e-11 * w[0]
+
+
+def test_symmetric_eigenpairs_of_a_graded_gram_matrix():
+    """The POD's Gram matrix at scale: 256 snapshots whose eigenvalues fall
+    geometrically over 12 decades, as a snapshot set's do.  The leading 64
+    eigenpairs (the warm start's largest basis) come out to 1e-10 relative
+    each, with their modes."""
+    g = np.random.default_rng(5)
+    n, k = 256, 64
+    Q = np.linalg.qr(g.standard_normal((n, n)))[0]
+    lam = 1e4 * 10.0 ** (-np.linspace(0, 12, n))
+    A = (Q * lam) @ Q.T
+    A = (A + A.T) / 2
+    w, V = pa.dbg_sym_eig(A)
+    assert np.all(np.diff(w) <= 0)
+    assert (np.abs(w[:k] - lam[:k]) / lam[:k]).max() <= 1e-10
+    assert np.abs(np.sum(V[:, :k] * Q[:, :k], axis=0)).min() >= 1 - 1e-10
+    assert np.abs(V.T @ V - np.eye(n)).max() <= 1e-12
+    assert np.abs(A @ V - V * w).max() <= 1e-12 * lam[0]
 
 
 def test_bad_arguments_raise():
