@@ -1,0 +1,97 @@
+"""The oracle's pins catch plausible mistakes.
+
+Each case plants one slip in a copy of oracle/oracle.c, compiles the copy
+into a temporary library (the committed oracle is untouched), loads it
+through a separate instance of the oracle's binding, and runs the pin that
+should catch the slip: that pin must then fail.  The slips are the ones a
+reader checking the code against the paper could miss:
+- the bulk viscosity coefficient of Stokes' hypothesis (Sec. 4, eq. ns);
+- the heat flux built from (gamma - 1) instead of gamma;
+- the sign and the scale of the compact-DG lifting;
+- a dropped stage coupling in the tangent sweep (eq. dirk-sens-mvp);
+- a transposed tableau index and a missing transpose in the backward sweep
+  (eq. uns-disc-adj-dirk-sens-mvp), caught by the duality theorem of the
+  appendix.
+A control copy with no slip, built the same way, passes every one of these
+pins, so a failure below is the slip's and not the harness's."""
+import importlib.util
+import os
+import subprocess
+
+import pytest
+
+import test_oracle_flux_pins as F
+import test_oracle_pins as P
+from paper_1512_00616_amd import inputs
+
+ORACLE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle")
+
+
+def _mutant(tmp_path, old, new):
+    src = open(os.path.join(ORACLE, "oracle.c")).read()
+    assert src.count(old) == 1, old
+    c = tmp_path / "oracle.c"
+    c.write_text(src.replace(old, new))
+    so = tmp_path / "liboracle_mutant.so"
+    subprocess.check_call(["gcc", "-O1", "-fopenmp", "-fPIC", "-shared", "-std=gnu11", "-Wl,-Bsymbolic",
+                           "-I", ORACLE, str(c), "-o", str(so), "-lm"])
+    spec = importlib.util.spec_from_file_location("oracle_mutant_" + tmp_path.name,
+                                                  os.path.join(ORACLE, "oracle.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    mod._LIB_PATH = str(so)
+    mod.lib()
+    return mod
+
+
+def _duality(mod):
+    """the appendix's duality pin about a one-period trajectory (the theorem
+    holds about any trajectory, periodic or not)"""
+    o = mod.Oracle(Nr=2, Nth=6, p=1, Nt=4, lin_solver=0, newton_atol=1e-12)
+    o.set_params(P.MU)
+    u0 = o.freestream(inputs.perturbation(o.Nu, seed=1))
+    try:
+        P.test_adjoint_sweep_is_transpose_of_tangent_sweep((o, u0, None))
+    finally:
+        o.close()
+
+
+PINS = {
+    "dilatation": F.test_uniform_dilatation_stokes_hypothesis,
+    "fourier": F.test_fourier_heat_conduction_at_rest,
+    "lifting": lambda m: F.test_lifting_of_a_constant_jump(m, 1),
+    "tangent": P.test_tangent_sweep_is_derivative_of_flow_map,
+    "duality": _duality,
+}
+
+SLIPS = [
+    ("bulk-viscosity", "dilatation",
+     "(i == j ? 2.0 / 3.0 * div : 0.0)", "(i == j ? 1.0 / 3.0 * div : 0.0)"),
+    ("heat-flux-gamma-minus-one", "fourier",
+     "cplx dh = c->gam * (dE[d]", "cplx dh = (c->gam - 1.0) * (dE[d]"),
+    ("lifting-sign", "lifting",
+     "double s = -len / (2.0 * c->area[L]);", "double s = len / (2.0 * c->area[L]);"),
+    ("lifting-scale", "lifting",
+     "double s = -len / (2.0 * c->area[L]);", "double s = -len / c->area[L];"),
+    ("tangent-drops-stage-coupling", "tangent",
+     "acc += c->A[i - 1][j - 1] * dk[(int64_t)(j - 1) * Nu + q];",
+     "acc += 0.0 * dk[(int64_t)(j - 1) * Nu + q];"),
+    ("adjoint-tableau-index-transposed", "duality",
+     "acc += c->A[j - 1][i - 1] * z[(int64_t)(j - 1) * Nu + q];",
+     "acc += c->A[i - 1][j - 1] * z[(int64_t)(j - 1) * Nu + q];"),
+    ("adjoint-missing-transpose", "duality",
+     "pao_bsr_apply(c, J, 1, kap, zi);", "pao_bsr_apply(c, J, 0, kap, zi);"),
+]
+
+
+def test_control_copy_passes_every_pin(tmp_path):
+    mod = _mutant(tmp_path, "double s = -len / (2.0 * c->area[L]);", "double s = -len / (2.0 * c->area[L]);")
+    for pin in PINS.values():
+        pin(mod)
+
+
+@pytest.mark.parametrize("name,pin,old,new", SLIPS, ids=[s[0] for s in SLIPS])
+def test_pin_fails_on_the_planted_slip(tmp_path, name, pin, old, new):
+    mod = _mutant(tmp_path, old, new)
+    with pytest.raises(AssertionError):     # caught by the pin's assertion, not by an error
+        PINS[pin](mod)
