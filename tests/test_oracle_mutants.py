@@ -11,7 +11,14 @@ reader checking the code against the paper could miss:
 - a dropped stage coupling in the tangent sweep (eq. dirk-sens-mvp);
 - a transposed tableau index and a missing transpose in the backward sweep
   (eq. uns-disc-adj-dirk-sens-mvp), caught by the duality theorem of the
-  appendix.
+  appendix;
+- a GCL stage value that leaves out its own stage's slope (an explicit
+  instead of the diagonally implicit recurrence), caught by the third-order
+  pin;
+- the sign of Alg. 3's right-hand side (the paper's printed residual and
+  update disagree in sign), caught by the dense solve;
+- the time step dropped from the gradient sum (eq. funcl-grad-nosens-dirk),
+  caught by the direct method.
 A control copy with no slip, built the same way, passes every one of these
 pins, so a failure below is the slip's and not the harness's."""
 import importlib.util
@@ -33,7 +40,7 @@ def _mutant(tmp_path, old, new):
     c = tmp_path / "oracle.c"
     c.write_text(src.replace(old, new))
     so = tmp_path / "liboracle_mutant.so"
-    subprocess.check_call(["gcc", "-O1", "-fopenmp", "-fPIC", "-shared", "-std=gnu11", "-Wl,-Bsymbolic",
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=gnu11", "-Wl,-Bsymbolic",
                            "-I", ORACLE, str(c), "-o", str(so), "-lm"])
     spec = importlib.util.spec_from_file_location("oracle_mutant_" + tmp_path.name,
                                                   os.path.join(ORACLE, "oracle.py"))
@@ -44,24 +51,31 @@ def _mutant(tmp_path, old, new):
     return mod
 
 
-def _duality(mod):
-    """the appendix's duality pin about a one-period trajectory (the theorem
-    holds about any trajectory, periodic or not)"""
-    o = mod.Oracle(Nr=2, Nth=6, p=1, Nt=4, lin_solver=0, newton_atol=1e-12)
-    o.set_params(P.MU)
-    u0 = o.freestream(inputs.perturbation(o.Nu, seed=1))
-    try:
-        P.test_adjoint_sweep_is_transpose_of_tangent_sweep((o, u0, None))
-    finally:
-        o.close()
+def _about_one_period(pin):
+    """a pin of the sweeps or of the periodic boundary-value problem, run
+    about a one-period trajectory from the perturbed free stream instead of
+    the shot orbit: the identities it checks (duality, the dense solve of
+    Alg. 3, adjoint = direct gradient) hold about any trajectory"""
+    def run(mod):
+        o = mod.Oracle(Nr=2, Nth=6, p=1, Nt=4, lin_solver=0, newton_atol=1e-12)
+        o.set_params(P.MU)
+        u0 = o.freestream(inputs.perturbation(o.Nu, seed=1))
+        try:
+            pin((o, u0, None))
+        finally:
+            o.close()
+    return run
 
 
 PINS = {
     "dilatation": F.test_uniform_dilatation_stokes_hypothesis,
     "fourier": F.test_fourier_heat_conduction_at_rest,
     "lifting": lambda m: F.test_lifting_of_a_constant_jump(m, 1),
+    "gcl-order": P.test_gcl_field_third_order_in_time,
     "tangent": P.test_tangent_sweep_is_derivative_of_flow_map,
-    "duality": _duality,
+    "duality": _about_one_period(P.test_adjoint_sweep_is_transpose_of_tangent_sweep),
+    "dense-alg3": _about_one_period(P.test_periodic_adjoint_matches_dense_solve),
+    "adjoint-vs-direct": _about_one_period(P.test_adjoint_gradient_equals_tangent_gradient),
 }
 
 SLIPS = [
@@ -81,6 +95,13 @@ SLIPS = [
      "acc += c->A[i - 1][j - 1] * z[(int64_t)(j - 1) * Nu + q];"),
     ("adjoint-missing-transpose", "duality",
      "pao_bsr_apply(c, J, 1, kap, zi);", "pao_bsr_apply(c, J, 0, kap, zi);"),
+    ("gcl-stage-value-without-its-own-slope", "gcl-order",
+     "for (int j = 1; j <= i; ++j) s += c->A[i - 1][j - 1] * kg[(int64_t)(j - 1) * nn + k];",
+     "for (int j = 1; j < i; ++j) s += c->A[i - 1][j - 1] * kg[(int64_t)(j - 1) * nn + k];"),
+    ("alg3-right-hand-side-sign", "dense-alg3",
+     "for (int64_t k = 0; k < Nu; ++k) gF[k] = -gF[k];", "for (int64_t k = 0; k < Nu; ++k) gF[k] = gF[k];"),
+    ("gradient-sum-without-dt", "adjoint-vs-direct",
+     "g[k] += c->dt * dot(Nu, kap, dr + (int64_t)k * Nu);", "g[k] += dot(Nu, kap, dr + (int64_t)k * Nu);"),
 ]
 
 
