@@ -18,7 +18,10 @@ reader checking the code against the paper could miss:
 - the sign of Alg. 3's right-hand side (the paper's printed residual and
   update disagree in sign), caught by the dense solve;
 - the time step dropped from the gradient sum (eq. funcl-grad-nosens-dirk),
-  caught by the direct method.
+  caught by the direct method;
+- the power built with the velocity components swapped, and the force of
+  the body on the fluid in place of the fluid's on the body (Sec. 4 eq.
+  qoi), caught by the QoIs' closed forms.
 A control copy with no slip, built the same way, passes every one of these
 pins, so a failure below is the slip's and not the harness's."""
 import importlib.util
@@ -72,6 +75,7 @@ PINS = {
     "fourier": F.test_fourier_heat_conduction_at_rest,
     "lifting": lambda m: F.test_lifting_of_a_constant_jump(m, 1),
     "gcl-order": P.test_gcl_field_third_order_in_time,
+    "qoi-closed-form": lambda m: P.test_qois_of_a_linear_pressure_field_in_heave(m, 1),
     "tangent": P.test_tangent_sweep_is_derivative_of_flow_map,
     "duality": _about_one_period(P.test_adjoint_sweep_is_transpose_of_tangent_sweep),
     "dense-alg3": _about_one_period(P.test_periodic_adjoint_matches_dense_solve),
@@ -100,6 +104,11 @@ SLIPS = [
      "for (int j = 1; j < i; ++j) s += c->A[i - 1][j - 1] * kg[(int64_t)(j - 1) * nn + k];"),
     ("alg3-right-hand-side-sign", "dense-alg3",
      "for (int64_t k = 0; k < Nu; ++k) gF[k] = -gF[k];", "for (int64_t k = 0; k < Nu; ++k) gF[k] = gF[k];"),
+    ("power-with-swapped-velocity-components", "qoi-closed-form",
+     "f[0] += w * (Fh[j * 4 + 1] * vG[0] + Fh[j * 4 + 2] * vG[1]);",
+     "f[0] += w * (Fh[j * 4 + 1] * vG[1] + Fh[j * 4 + 2] * vG[0]);"),
+    ("force-of-the-body-on-the-fluid", "qoi-closed-form",
+     "f[1] += w * Fh[j * 4 + 1];", "f[1] -= w * Fh[j * 4 + 1];"),
     ("gradient-sum-without-dt", "adjoint-vs-direct",
      "g[k] += c->dt * dot(Nu, kap, dr + (int64_t)k * Nu);", "g[k] += dot(Nu, kap, dr + (int64_t)k * Nu);"),
 ]

@@ -193,6 +193,36 @@ def test_force_on_closed_body_at_rest_is_zero(oracle_mod):
     assert np.abs(f).max() < 1e-12
 
 
+@pytest.mark.parametrize("p", [1, 3])
+def test_qois_of_a_linear_pressure_field_in_heave(oracle_mod, p):
+    """Closed forms of both QoIs (Sec. 4 eq. qoi with reading 8: f the force
+    of the fluid on the body, power f . xdot with xdot the wall velocity).
+    Pure heave (theta0 = 0), so the first ring of elements moves rigidly
+    with the wall; the fluid moves with it (u = (0, hdot)) and its pressure
+    is linear, p = p0 + g . X.  Then the wall flux is pressure only, and the
+    force on the inscribed N_th-gon of area A is -g A (the divergence
+    theorem), so the x-force is -g_x A and the power -g_y A hdot."""
+    Nth = 24
+    o = make(oracle_mod, Nr=8, Nth=Nth, p=p)
+    _, _, c = oracle_mod.dirk_tableau()
+    o.set_params(np.array([0.25, 0.0, 0.0]))
+    n, i = 1, 2
+    t = (n - 1 + c[i - 1]) / o.Nt
+    hdot = 2 * math.pi * 0.25 * math.cos(2 * math.pi * t)
+    X, _ = o.nodes()
+    gx, gy = 0.8, -0.3
+    pres = 17.0 + gx * X[..., 0] + gy * X[..., 1]
+    U = np.zeros((o.Ne, o.np, 4))
+    U[..., 0] = 1.0
+    U[..., 2] = hdot
+    U[..., 3] = pres / 0.4 + 0.5 * hdot ** 2
+    u = (U * o.gbar(n, i).reshape(o.Ne, o.np)[..., None]).ravel()
+    f = o.qoi(n, i, u)
+    A = 0.5 * Nth * math.sin(2 * math.pi / Nth)
+    assert abs(f[1] - (-gx * A)) <= 1e-12 * gx * A
+    assert abs(f[0] - (-gy * A * hdot)) <= 1e-12 * abs(gy * A * hdot)
+
+
 # ---------------------------------------------------------------- derivatives
 @pytest.mark.parametrize("p", [1, 3])
 def test_jacobian_matches_central_differences(oracle_mod, p):
