@@ -5,6 +5,8 @@ into a temporary library (the committed oracle is untouched), loads it
 through a separate instance of the oracle's binding, and runs the pin that
 should catch the slip: that pin must then fail.  The slips are the ones a
 reader checking the code against the paper could miss:
+- the radial stretching and a twin-face index of the O-grid;
+- the sign of the grid-velocity flux of the ALE form;
 - the bulk viscosity coefficient of Stokes' hypothesis (Sec. 4, eq. ns);
 - the heat flux built from (gamma - 1) instead of gamma;
 - the sign and the scale of the compact-DG lifting;
@@ -71,6 +73,8 @@ def _about_one_period(pin):
 
 
 PINS = {
+    "mesh": P.test_mesh_connectivity_and_orientation,
+    "moving-face": F.test_flux_through_a_face_moving_with_the_fluid_is_pressure_only,
     "dilatation": F.test_uniform_dilatation_stokes_hypothesis,
     "fourier": F.test_fourier_heat_conduction_at_rest,
     "lifting": lambda m: F.test_lifting_of_a_constant_jump(m, 1),
@@ -83,6 +87,12 @@ PINS = {
 }
 
 SLIPS = [
+    ("stretching-per-mesh-instead-of-per-cell", "mesh",
+     "double q = pow(c->cfg.stretch, 8.0 / Nr);", "double q = pow(c->cfg.stretch, 1.0 / Nr);"),
+    ("twin-face-index", "mesh",
+     "c->enb[3 * B] = A; c->etw[3 * B] = 2;", "c->enb[3 * B] = A; c->etw[3 * B] = 1;"),
+    ("grid-velocity-flux-sign", "moving-face",
+     "H[m] = F[m][0] * n[0] + F[m][1] * n[1] - U[m] * vn;", "H[m] = F[m][0] * n[0] + F[m][1] * n[1] + U[m] * vn;"),
     ("bulk-viscosity", "dilatation",
      "(i == j ? 2.0 / 3.0 * div : 0.0)", "(i == j ? 1.0 / 3.0 * div : 0.0)"),
     ("heat-flux-gamma-minus-one", "fourier",
