@@ -23,7 +23,9 @@ reader checking the code against the paper could miss:
   caught by the direct method;
 - the power built with the velocity components swapped, and the force of
   the body on the fluid in place of the fluid's on the body (Sec. 4 eq.
-  qoi), caught by the QoIs' closed forms.
+  qoi), caught by the QoIs' closed forms;
+- the period average weighted with the stage times instead of the
+  quadrature weights, caught by the solver-consistent QoI pin.
 A control copy with no slip, built the same way, passes every one of these
 pins, so a failure below is the slip's and not the harness's."""
 import importlib.util
@@ -80,6 +82,7 @@ PINS = {
     "lifting": lambda m: F.test_lifting_of_a_constant_jump(m, 1),
     "gcl-order": P.test_gcl_field_third_order_in_time,
     "qoi-closed-form": lambda m: P.test_qois_of_a_linear_pressure_field_in_heave(m, 1),
+    "qoi-quadrature": P.test_period_qois_are_the_dirk_quadrature_of_the_stage_qois,
     "tangent": P.test_tangent_sweep_is_derivative_of_flow_map,
     "duality": _about_one_period(P.test_adjoint_sweep_is_transpose_of_tangent_sweep),
     "dense-alg3": _about_one_period(P.test_periodic_adjoint_matches_dense_solve),
@@ -119,6 +122,8 @@ SLIPS = [
      "f[0] += w * (Fh[j * 4 + 1] * vG[1] + Fh[j * 4 + 2] * vG[0]);"),
     ("force-of-the-body-on-the-fluid", "qoi-closed-form",
      "f[1] += w * Fh[j * 4 + 1];", "f[1] -= w * Fh[j * 4 + 1];"),
+    ("period-average-with-the-stage-times", "qoi-quadrature",
+     "Jq[0] += c->dt * c->bw[i - 1] * f[0] / c->cfg.T;", "Jq[0] += c->dt * c->cc[i - 1] * f[0] / c->cfg.T;"),
     ("gradient-sum-without-dt", "adjoint-vs-direct",
      "g[k] += c->dt * dot(Nu, kap, dr + (int64_t)k * Nu);", "g[k] += dot(Nu, kap, dr + (int64_t)k * Nu);"),
 ]

@@ -193,6 +193,19 @@ def test_force_on_closed_body_at_rest_is_zero(oracle_mod):
     assert np.abs(f).max() < 1e-12
 
 
+def test_period_qois_are_the_dirk_quadrature_of_the_stage_qois(oracle_mod):
+    """Reading 10 (solver-consistent QoIs): the time average over a period
+    is (1/T) sum_n sum_i dt b_i f(u_i^(n)), the DIRK's own quadrature with
+    the stored stage states."""
+    o = make(oracle_mod, Nr=2, Nth=6, p=1, Nt=4, lin_solver=0, newton_atol=1e-12)
+    o.set_params(MU)
+    _, J, _ = o.primal_period(o.freestream(inputs.perturbation(o.Nu, seed=1)))
+    _, b, _ = oracle_mod.dirk_tableau()
+    dt = 1.0 / o.Nt     # T = 1
+    acc = sum(dt * b[i - 1] * o.qoi(n, i, o.traj(0, n, i)) for n in range(1, o.Nt + 1) for i in (1, 2, 3))
+    assert np.allclose(J, acc, rtol=1e-13, atol=0)
+
+
 @pytest.mark.parametrize("p", [1, 3])
 def test_qois_of_a_linear_pressure_field_in_heave(oracle_mod, p):
     """Closed forms of both QoIs (Sec. 4 eq. qoi with reading 8: f the force
