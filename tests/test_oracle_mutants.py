@@ -64,7 +64,7 @@ def _about_one_period(pin):
     the shot orbit: the identities it checks (duality, the dense solve of
     Alg. 3, adjoint = direct gradient) hold about any trajectory"""
     def run(mod):
-        o = mod.Oracle(Nr=2, Nth=6, p=1, Nt=4, lin_solver=0, newton_atol=1e-12)
+        o = mod.Oracle(Nr=2, Nth=6, p=1, Nt=2, lin_solver=0, newton_atol=1e-12)
         o.set_params(P.MU)
         u0 = o.freestream(inputs.perturbation(o.Nu, seed=1))
         try:
