@@ -7,6 +7,10 @@ should catch the slip: that pin must then fail.  The slips are the ones a
 reader checking the code against the paper could miss:
 - the radial stretching and a twin-face index of the O-grid;
 - the sign of the grid-velocity flux of the ALE form;
+- in the primal sweep: the time step dropped from the stage equation, the
+  stage sum with the tableau transposed and the state update weighted with
+  the stage times (Sec. 2.1 eq. dirk), caught by the rows of eq.
+  abs-govern-disc;
 - the bulk viscosity coefficient of Stokes' hypothesis (Sec. 4, eq. ns);
 - the heat flux built from (gamma - 1) instead of gamma;
 - the sign and the scale of the compact-DG lifting;
@@ -83,6 +87,7 @@ PINS = {
     "gcl-order": P.test_gcl_field_third_order_in_time,
     "qoi-closed-form": lambda m: P.test_qois_of_a_linear_pressure_field_in_heave(m, 1),
     "qoi-quadrature": P.test_period_qois_are_the_dirk_quadrature_of_the_stage_qois,
+    "period-rows": P.test_one_period_solves_the_update_and_stage_rows,
     "tangent": P.test_tangent_sweep_is_derivative_of_flow_map,
     "duality": _about_one_period(P.test_adjoint_sweep_is_transpose_of_tangent_sweep),
     "dense-alg3": _about_one_period(P.test_periodic_adjoint_matches_dense_solve),
@@ -104,6 +109,14 @@ SLIPS = [
      "double s = -len / (2.0 * c->area[L]);", "double s = len / (2.0 * c->area[L]);"),
     ("lifting-scale", "lifting",
      "double s = -len / (2.0 * c->area[L]);", "double s = -len / c->area[L];"),
+    ("stage-equation-without-dt", "period-rows",
+     "R[q] -= c->dt * r[q];", "R[q] -= r[q];"),
+    ("stage-sum-with-transposed-tableau", "period-rows",
+     "acc += c->A[i - 1][j - 1] * c->tk[(int64_t)(s - i + j) * Nu + q];",
+     "acc += c->A[j - 1][i - 1] * c->tk[(int64_t)(s - i + j) * Nu + q];"),
+    ("state-update-with-the-stage-times", "period-rows",
+     "acc += c->bw[i] * c->tk[(int64_t)((n - 1) * 3 + i) * Nu + q];",
+     "acc += c->cc[i] * c->tk[(int64_t)((n - 1) * 3 + i) * Nu + q];"),
     ("tangent-drops-stage-coupling", "tangent",
      "acc += c->A[i - 1][j - 1] * dk[(int64_t)(j - 1) * Nu + q];",
      "acc += 0.0 * dk[(int64_t)(j - 1) * Nu + q];"),
@@ -138,5 +151,7 @@ def test_control_copy_passes_every_pin(tmp_path):
 @pytest.mark.parametrize("name,pin,old,new", SLIPS, ids=[s[0] for s in SLIPS])
 def test_pin_fails_on_the_planted_slip(tmp_path, name, pin, old, new):
     mod = _mutant(tmp_path, old, new)
-    with pytest.raises(AssertionError):     # caught by the pin's assertion, not by an error
+    # caught by the pin's assertion, or by the oracle itself refusing to go on
+    # (a stage Newton that no longer converges), never by a crash
+    with pytest.raises((AssertionError, mod.OracleError)):
         PINS[pin](mod)

@@ -465,6 +465,26 @@ def test_trajectory_solves_the_monolithic_system(tiny_periodic):
     assert np.abs(r).max() <= 1e-10
 
 
+def test_one_period_solves_the_update_and_stage_rows(oracle_mod):
+    """One primal period (A6) from the perturbed free stream satisfies the
+    state-update and stage rows of eq. abs-govern-disc (all but the
+    periodicity row), with every stored stage state equal to
+    u^(n-1) + sum_{j<=i} a_ij k_j^(n) (Sec. 2.1 eq. dirk)."""
+    from oracle import monolithic
+    o = make(oracle_mod, Nr=2, Nth=6, p=1, Nt=4, lin_solver=0, newton_atol=1e-12)
+    o.set_params(MU)
+    o.primal_period(o.freestream(inputs.perturbation(o.Nu, seed=1)))
+    r = monolithic.residual(o)[o.Nu:]
+    assert np.abs(r).max() <= 1e-11
+    A, _, _ = oracle_mod.dirk_tableau()
+    for n in range(1, o.Nt + 1):
+        k = [o.traj(1, n, j) for j in (1, 2, 3)]
+        for i in (1, 2, 3):
+            ui = o.traj(2, n - 1) + sum(A[i - 1, j] * k[j] for j in range(i))
+            assert np.abs(o.traj(0, n, i) - ui).max() <= 1e-13 * np.abs(ui).max()
+    o.close()
+
+
 def test_periodic_adjoint_matches_dense_monolithic_solve(tiny_periodic):
     """Alg. 3 + eq. funcl-grad-nosens-dirk (sweeps, matrix-free GMRES on
     (Phi^T - I)) against one dense LU solve of the transposed Jacobian of the
