@@ -14,6 +14,9 @@ reader checking the code against the paper could miss:
 - the bulk viscosity coefficient of Stokes' hypothesis (Sec. 4, eq. ns);
 - the heat flux built from (gamma - 1) instead of gamma;
 - the sign and the scale of the compact-DG lifting;
+- a neighbour's Jacobian block stored in the wrong block slot, and the
+  parameter derivatives taken in the wrong parameter (caught by central
+  differences);
 - a dropped stage coupling in the tangent sweep (eq. dirk-sens-mvp);
 - a transposed tableau index and a missing transpose in the backward sweep
   (eq. uns-disc-adj-dirk-sens-mvp), caught by the duality theorem of the
@@ -88,6 +91,8 @@ PINS = {
     "qoi-closed-form": lambda m: P.test_qois_of_a_linear_pressure_field_in_heave(m, 1),
     "qoi-quadrature": P.test_period_qois_are_the_dirk_quadrature_of_the_stage_qois,
     "period-rows": P.test_one_period_solves_the_update_and_stage_rows,
+    "jacobian": lambda m: P.test_jacobian_matches_central_differences(m, 1),
+    "dr-dmu": P.test_dr_dmu_and_dqoi_match_central_differences,
     "tangent": P.test_tangent_sweep_is_derivative_of_flow_map,
     "duality": _about_one_period(P.test_adjoint_sweep_is_transpose_of_tangent_sweep),
     "dense-alg3": _about_one_period(P.test_periodic_adjoint_matches_dense_solve),
@@ -117,6 +122,10 @@ SLIPS = [
     ("state-update-with-the-stage-times", "period-rows",
      "acc += c->bw[i] * c->tk[(int64_t)((n - 1) * 3 + i) * Nu + q];",
      "acc += c->cc[i] * c->tk[(int64_t)((n - 1) * 3 + i) * Nu + q];"),
+    ("jacobian-neighbour-block-in-the-wrong-slot", "jacobian",
+     "int slot = 1 + c->etw[3 * Kp + f];", "int slot = 1 + f;"),
+    ("parameter-derivatives-shifted-by-one", "dr-dmu",
+     "if (dir > 0) mu[dir - 1] += I * CSTEP;", "if (dir > 0) mu[dir % 3] += I * CSTEP;"),
     ("tangent-drops-stage-coupling", "tangent",
      "acc += c->A[i - 1][j - 1] * dk[(int64_t)(j - 1) * Nu + q];",
      "acc += 0.0 * dk[(int64_t)(j - 1) * Nu + q];"),
