@@ -33,16 +33,22 @@ reader checking the code against the paper could miss:
   qoi), caught by the QoIs' closed forms;
 - the period average weighted with the stage times instead of the
   quadrature weights, caught by the solver-consistent QoI pin.
+The same is done for the plain-numpy references of the learned form: the
+tanh derivative of the perceptron's back-propagation, and the centring and
+the mode scaling of the POD.
 A control copy with no slip, built the same way, passes every one of these
 pins, so a failure below is the slip's and not the harness's."""
 import importlib.util
 import os
 import subprocess
+import types
 
 import pytest
 
+import test_mlp_oracle as M
 import test_oracle_flux_pins as F
 import test_oracle_pins as P
+import test_oracle_pod_pins as D
 from paper_1512_00616_amd import inputs
 
 ORACLE = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "oracle")
@@ -164,3 +170,35 @@ def test_pin_fails_on_the_planted_slip(tmp_path, name, pin, old, new):
     # (a stage Newton that no longer converges), never by a crash
     with pytest.raises((AssertionError, mod.OracleError)):
         PINS[pin](mod)
+
+
+# ---------------------------------------------------------------- the Python references
+def _py_mutant(name, old, new):
+    path = os.path.join(ORACLE, name + ".py")
+    src = open(path).read()
+    assert src.count(old) == 1, old
+    mod = types.ModuleType("oracle_%s_mutant" % name)
+    exec(compile(src.replace(old, new), path, "exec"), mod.__dict__)
+    return mod
+
+
+PY_SLIPS = [
+    ("tanh-derivative", "mlp", "(1.0 - acts[l] ** 2)", "(1.0 - acts[l])",
+     M, "mlp", M.test_deep_gradient_matches_central_differences),
+    ("pod-without-centring", "pod", "D = X - mean", "D = X",
+     D, "pod", D.test_pod_recovers_constructed_modes),
+    ("pod-modes-scaled-by-the-eigenvalue", "pod",
+     "modes = (V[:, :k].T @ D) / np.sqrt(lam[:k])[:, None]", "modes = (V[:, :k].T @ D) / lam[:k][:, None]",
+     D, "pod", D.test_modes_orthonormal_and_snapshots_reconstructed),
+]
+
+
+@pytest.mark.parametrize("name,module,old,new,tmod,attr,pin", PY_SLIPS, ids=[s[0] for s in PY_SLIPS])
+def test_reference_pin_fails_on_the_planted_slip(monkeypatch, name, module, old, new, tmod, attr, pin):
+    # the perceptron and POD references (plain numpy): the slip is planted in
+    # a copy of the module's source; an unmodified copy passes the same pin
+    monkeypatch.setattr(tmod, attr, _py_mutant(module, old, old))
+    pin()
+    monkeypatch.setattr(tmod, attr, _py_mutant(module, old, new))
+    with pytest.raises(AssertionError):
+        pin()
