@@ -14,6 +14,8 @@ reader checking the code against the paper could miss:
 - the bulk viscosity coefficient of Stokes' hypothesis (Sec. 4, eq. ns);
 - the heat flux built from (gamma - 1) instead of gamma;
 - the sign and the scale of the compact-DG lifting;
+- the transposed block product with untransposed blocks (caught by the
+  stage systems' adjoint identity);
 - a neighbour's Jacobian block stored in the wrong block slot, and the
   parameter derivatives taken in the wrong parameter (caught by central
   differences);
@@ -97,6 +99,7 @@ PINS = {
     "qoi-closed-form": lambda m: P.test_qois_of_a_linear_pressure_field_in_heave(m, 1),
     "qoi-quadrature": P.test_period_qois_are_the_dirk_quadrature_of_the_stage_qois,
     "period-rows": P.test_one_period_solves_the_update_and_stage_rows,
+    "stage-systems": lambda m: P.test_stage_solves_satisfy_their_systems(m, 0),
     "jacobian": lambda m: P.test_jacobian_matches_central_differences(m, 1),
     "dr-dmu": P.test_dr_dmu_and_dqoi_match_central_differences,
     "tangent": P.test_tangent_sweep_is_derivative_of_flow_map,
@@ -128,6 +131,9 @@ SLIPS = [
     ("state-update-with-the-stage-times", "period-rows",
      "acc += c->bw[i] * c->tk[(int64_t)((n - 1) * 3 + i) * Nu + q];",
      "acc += c->cc[i] * c->tk[(int64_t)((n - 1) * 3 + i) * Nu + q];"),
+    ("transposed-product-without-transposed-blocks", "stage-systems",
+     "for (int i = 0; i < b; ++i) acc += B[i * b + j] * x[(int64_t)K * b + i];",
+     "for (int i = 0; i < b; ++i) acc += B[j * b + i] * x[(int64_t)K * b + i];"),
     ("jacobian-neighbour-block-in-the-wrong-slot", "jacobian",
      "int slot = 1 + c->etw[3 * Kp + f];", "int slot = 1 + f;"),
     ("parameter-derivatives-shifted-by-one", "dr-dmu",

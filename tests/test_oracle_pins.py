@@ -236,6 +236,31 @@ def test_qois_of_a_linear_pressure_field_in_heave(oracle_mod, p):
     assert abs(f[0] - (-gy * A * hdot)) <= 1e-12 * abs(gy * A * hdot)
 
 
+# ---------------------------------------------------------------- stage solves
+@pytest.mark.parametrize("lin_solver", [0, 1], ids=["dense-lu", "block-jacobi-gmres"])
+def test_stage_solves_satisfy_their_systems(oracle_mod, lin_solver):
+    """The stage operator A = M - a_ii dt J of rows A5 and A9: the block
+    product and its transpose are adjoint (<w, J v> = <J^T w, v>), and the
+    solutions of A x = b and A^T y = b (M is symmetric) satisfy them when
+    checked with explicit products, for the dense LU and for the
+    block-Jacobi GMRES at 1e-13."""
+    o = make(oracle_mod, Nr=2, Nth=6, p=2, lin_solver=lin_solver, lin_rtol=1e-13)
+    o.set_params(MU)
+    u = o.freestream(inputs.perturbation(o.Nu, seed=5, sigma=1e-2))
+    J = o.jacobian(1, 2, u)
+    v, w = inputs.random_vectors(o.Nu, 2, seed=7)
+    lhs = w @ o.bsr_apply(J, v)
+    assert abs(lhs - o.bsr_apply(J, w, transpose=True) @ v) <= 1e-13 * abs(lhs)
+    adt = 0.4358665215084590 / o.Nt
+    b = o.mass(v)
+    bar = 1e-13 if lin_solver == 0 else 1e-11
+    x = o.stage_solve(J, adt, b)
+    assert np.linalg.norm(o.mass(x) - adt * o.bsr_apply(J, x) - b) <= bar * np.linalg.norm(b)
+    y = o.stage_solve(J, adt, b, transpose=True)
+    assert np.linalg.norm(o.mass(y) - adt * o.bsr_apply(J, y, transpose=True) - b) <= bar * np.linalg.norm(b)
+    o.close()
+
+
 # ---------------------------------------------------------------- derivatives
 @pytest.mark.parametrize("p", [1, 3])
 def test_jacobian_matches_central_differences(oracle_mod, p):
