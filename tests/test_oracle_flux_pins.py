@@ -79,8 +79,8 @@ def test_uniform_shear_stress(oracle_mod):
 
 def test_uniform_dilatation_stokes_hypothesis(oracle_mod):
     """u = a x (pure expansion, div u = 2a): with the bulk viscosity -2 mu / 3
-    of eq. ns the normal stresses are mu (2a - 2/3 * 2a) = 2 mu a / 3 and the
-    shear stress is zero."""
+    of the stress tensor of Sec. 4 the normal stresses are
+    mu (2a - 2/3 * 2a) = 2 mu a / 3 and the shear stress is zero."""
     o = make(oracle_mod)
     a = -1.7
     U, dU = conservative(gu=[[a, 0.0], [0.0, a]], ge=(0.0, 0.0), **STATE)

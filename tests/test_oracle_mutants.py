@@ -11,7 +11,7 @@ reader checking the code against the paper could miss:
   stage sum with the tableau transposed and the state update weighted with
   the stage times (Sec. 2.1 eq. dirk), caught by the rows of eq.
   abs-govern-disc;
-- the bulk viscosity coefficient of Stokes' hypothesis (Sec. 4, eq. ns);
+- the bulk viscosity coefficient of Stokes' hypothesis (Sec. 4, eqs. ns1-ns5);
 - the heat flux built from (gamma - 1) instead of gamma;
 - the sign and the scale of the compact-DG lifting;
 - the transposed block product with untransposed blocks (caught by the
