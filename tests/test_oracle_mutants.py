@@ -29,7 +29,9 @@ reader checking the code against the paper could miss:
 - the sign of Alg. 3's right-hand side (the paper's printed residual and
   update disagree in sign), caught by the dense solve;
 - the time step dropped from the gradient sum (eq. funcl-grad-nosens-dirk),
-  caught by the direct method;
+  the QoI forcing of the backward stages without its tableau factor and the
+  explicit parameter term without the quadrature weights, caught by the
+  direct method;
 - the power built with the velocity components swapped, and the force of
   the body on the fluid in place of the fluid's on the body (Sec. 4 eq.
   qoi), caught by the QoIs' closed forms;
@@ -158,6 +160,12 @@ SLIPS = [
      "f[1] += w * Fh[j * 4 + 1];", "f[1] -= w * Fh[j * 4 + 1];"),
     ("period-average-with-the-stage-times", "qoi-quadrature",
      "Jq[0] += c->dt * c->bw[i - 1] * f[0] / c->cfg.T;", "Jq[0] += c->dt * c->cc[i - 1] * f[0] / c->cfg.T;"),
+    ("adjoint-stage-forcing-without-the-tableau", "adjoint-vs-direct",
+     "for (int j = i; j <= 3; ++j) acc += sc * c->bw[j - 1] * c->A[j - 1][i - 1] * fp[(int64_t)(j - 1) * Nu + q];",
+     "for (int j = i; j <= 3; ++j) acc += sc * c->bw[j - 1] * fp[(int64_t)(j - 1) * Nu + q];"),
+    ("explicit-parameter-term-without-quadrature-weights", "adjoint-vs-direct",
+     "for (int k = 0; k < 3; ++k) g[k] += sc * c->bw[i - 1] * fm[3 * fq + k];",
+     "for (int k = 0; k < 3; ++k) g[k] += sc * fm[3 * fq + k];"),
     ("gradient-sum-without-dt", "adjoint-vs-direct",
      "g[k] += c->dt * dot(Nu, kap, dr + (int64_t)k * Nu);", "g[k] += dot(Nu, kap, dr + (int64_t)k * Nu);"),
 ]
