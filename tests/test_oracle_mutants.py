@@ -32,6 +32,9 @@ reader checking the code against the paper could miss:
   the QoI forcing of the backward stages without its tableau factor and the
   explicit parameter term without the quadrature weights, caught by the
   direct method;
+- the wall's reflected state built about a wall at rest instead of the
+  moving wall (reading of the no-slip wall), caught by the QoIs' closed
+  forms, whose fluid moves with the wall;
 - the power built with the velocity components swapped, and the force of
   the body on the fluid in place of the fluid's on the body (Sec. 4 eq.
   qoi), caught by the QoIs' closed forms;
@@ -153,6 +156,8 @@ SLIPS = [
      "for (int j = 1; j < i; ++j) s += c->A[i - 1][j - 1] * kg[(int64_t)(j - 1) * nn + k];"),
     ("alg3-right-hand-side-sign", "dense-alg3",
      "for (int64_t k = 0; k < Nu; ++k) gF[k] = -gF[k];", "for (int64_t k = 0; k < Nu; ++k) gF[k] = gF[k];"),
+    ("wall-reflects-the-velocity-about-zero", "qoi-closed-form",
+     "cplx bx = 2.0 * vG[0] - ux, by = 2.0 * vG[1] - uy;", "cplx bx = vG[0] - ux, by = vG[1] - uy;"),
     ("power-with-swapped-velocity-components", "qoi-closed-form",
      "f[0] += w * (Fh[j * 4 + 1] * vG[0] + Fh[j * 4 + 2] * vG[1]);",
      "f[0] += w * (Fh[j * 4 + 1] * vG[1] + Fh[j * 4 + 2] * vG[0]);"),
